@@ -1,0 +1,210 @@
+/*
+ * signtri.h -- U = sign(T) for an upper-triangular T on an AMD MI355X (gfx950).
+ *
+ * The method is the one of Stotland, Schwartz and Toledo, "High-Performance
+ * Algorithms for Computing the Sign Function of Triangular Matrices":
+ *
+ *   - sign(z) is the sign of Re z (Section 1); sign(T) is undefined when some
+ *     diagonal entry has a zero real part (Section 1);
+ *   - the Parlett-Higham substitution (Algorithm 3): u_ii = sign(t_ii); for
+ *     i < j, Eq. (1) (from TU = UT) where sign(t_ii) != sign(t_jj), Eq. (2)
+ *     (from U^2 = I) where they agree; computed here in block form (Section 5:
+ *     the block equations with accumulators X and Y, Algorithms 4-6), with
+ *     diagonal blocks solved element by element and off-diagonal block
+ *     accumulations done as matrix products;
+ *   - the Parlett-Sylvester form (Algorithm 2 specialised to the sign, whose
+ *     diagonal blocks are +I and -I, Section 2): for a T whose diagonal is
+ *     already grouped by sign, U = [[s I, X], [0, -s I]] with
+ *     T11 X - X T22 = 2 s T12;
+ *   - the choice between them by the work estimates of Section 3, driven by
+ *     the inertia of the diagonal.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense n x n with a leading dimension ld >= max(1, n), in
+ *     column-major (element (i, j) at i + j*ld) or row-major (i*ld + j)
+ *     order.  SIGNTRI_C128 elements are interleaved (re, im) doubles and ld
+ *     counts complex elements.
+ *   - T and U are DEVICE pointers.  The caller owns them; the library never
+ *     frees them.  T is never written.  U must not overlap T.
+ *   - Only the upper triangle of T (diagonal included) is read; its strict
+ *     lower triangle may hold anything.  The whole n x n of U is written: its
+ *     upper triangle with sign(T) and its strict lower triangle with zeros.
+ *     Padding between n and ld is not touched.
+ *   - Work is queued on `stream` (a hipStream_t; NULL means the default
+ *     stream).  Single-matrix calls synchronise the stream once, after a
+ *     device scan of the diagonal, to plan the work; the result in U is ready
+ *     when the stream has been synchronised again.
+ *   - Return codes: 0 on success; -p if argument p (1-based) is invalid;
+ *     positive SIGNTRI_E* codes below.  On any nonzero return, U is untouched
+ *     except after SIGNTRI_EHIP (a device error mid-computation).
+ */
+#ifndef SIGNTRI_H
+#define SIGNTRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SIGNTRI_R64 = 0, SIGNTRI_C128 = 1 } signtri_dtype;
+
+/* FP64: every operation in FP64 (complex128).
+ * MIXED_REFINED: bulk products on FP32 MFMA with FP32 accumulation, divisions by
+ *   t_ii - t_jj and diagonal blocks in FP64, then FP64 residuals of U^2 = I and
+ *   TU = UT and an FP32 correction solve (iterative refinement); blocks whose
+ *   refinement stalls are recomputed in FP64.
+ * FP32: the mixed path without refinement (about 1e-6 relative accuracy). */
+typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } signtri_mode;
+
+/* AUTO picks by the Section 3 work estimates (PS only when the diagonal is
+ * already grouped by sign, since this library does not reorder the Schur form). */
+typedef enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2 } signtri_algo;
+
+typedef enum { SIGNTRI_COL_MAJOR = 0, SIGNTRI_ROW_MAJOR = 1 } signtri_layout;
+
+/* Path actually run. */
+enum { SIGNTRI_PATH_TRIVIAL = 0, SIGNTRI_PATH_PH = 1, SIGNTRI_PATH_PS = 2 };
+
+enum {
+    SIGNTRI_OK = 0,
+    SIGNTRI_EDOMAIN = 1,     /* some Re(t_ii) is zero, or t_ii is not finite   */
+    SIGNTRI_EHIP = 2,        /* a HIP runtime call failed                      */
+    SIGNTRI_EWORKSPACE = 3,  /* ws_bytes smaller than signtri_workspace_size() */
+    SIGNTRI_ENOCONV = 4,     /* refinement did not converge, fallback disabled */
+    SIGNTRI_ENOTSUP = 5,     /* a combination this build does not implement    */
+    SIGNTRI_ENOMEM = 6       /* the library could not allocate its workspace   */
+};
+
+/* Filled on return when non-NULL (host memory). */
+typedef struct {
+    int32_t path;             /* SIGNTRI_PATH_* that ran                                 */
+    int32_t model_pick;       /* SIGNTRI_PATH_PH or _PS by the Section 3 model, reordering
+                                 cost included (the paper's choice)                       */
+    int64_t n_pos, n_neg;     /* inertia of the diagonal                                  */
+    int64_t swaps;            /* adjacent swaps needed to group the diagonal by sign       */
+    double w_ph, w_ps;        /* Section 3 work estimates in real flops                   */
+    int32_t refine_steps;     /* refinement steps taken (mixed mode)                      */
+    int32_t tile;             /* block size used                                          */
+    int64_t fallback_tiles;   /* blocks recomputed in FP64 after a stalled refinement     */
+    double correction_rel;    /* max |correction| / max |U| of the last refinement step   */
+    int64_t bad_index;        /* 1-based index of the offending diagonal (EDOMAIN), else 0 */
+} signtri_info;
+
+/* Tunables; zero-initialise for defaults. */
+typedef struct {
+    int32_t tile;                /* block size: 0 = default                                */
+    int32_t max_refine_steps;    /* mixed mode: 0 = default (1)                            */
+    double stall_ratio;          /* mixed mode: a block stalls when its correction exceeds
+                                    this fraction of its largest |u| (0 = default 1e-3)  */
+    int32_t no_fallback;         /* mixed mode: 1 = return SIGNTRI_ENOCONV instead of
+                                    recomputing stalled blocks in FP64                   */
+    int32_t max_splits;          /* split-K limit for block products (0 = default)          */
+} signtri_options;
+
+/*
+ * Compute U = sign(T).
+ *   T, ldt      device input, upper triangle read (see conventions above)
+ *   U, ldu      device output, n x n written
+ *   n           order, n >= 0 (n == 0 is a no-op)
+ *   dtype       SIGNTRI_R64 or SIGNTRI_C128
+ *   layout      storage order of both T and U
+ *   mode        SIGNTRI_FP64, SIGNTRI_MIXED_REFINED or SIGNTRI_FP32
+ *   algo        SIGNTRI_AUTO, SIGNTRI_PH or SIGNTRI_PS (PS requires a diagonal
+ *               already grouped by sign, else SIGNTRI_ENOTSUP)
+ *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
+ *               use a buffer it allocates and keeps for later calls
+ *   stream      hipStream_t to queue work on (NULL = default stream)
+ *   opts        tunables, or NULL for defaults
+ *   info        optional host output
+ * Errors: SIGNTRI_EDOMAIN (detected by the diagonal scan, before U is
+ * written; info->bad_index names the entry), SIGNTRI_EWORKSPACE, SIGNTRI_EHIP,
+ * SIGNTRI_ENOCONV, SIGNTRI_ENOTSUP, SIGNTRI_ENOMEM, or -p for argument p.
+ */
+int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n,
+            signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
+            signtri_algo algo, void *workspace, size_t ws_bytes, void *stream,
+            const signtri_options *opts, signtri_info *info);
+
+/* Bytes of device workspace signtri() needs for these arguments (an upper
+ * bound valid for any diagonal).  Returns 0 for invalid arguments. */
+size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_mode mode,
+                              signtri_algo algo);
+
+/*
+ * Batched form: U_b = sign(T_b) for b = 0 .. batch-1, matrices of uneven
+ * order, in one graph-captured persistent launch.
+ *   T, U        HOST arrays of `batch` DEVICE pointers
+ *   ldt, ldu, n HOST arrays of `batch` leading dimensions and orders
+ *   dtype       SIGNTRI_R64 only in this build (else SIGNTRI_ENOTSUP)
+ *   mode        as for signtri(); MIXED_REFINED refines each matrix
+ *   workspace   device scratch of ws_bytes, or NULL for a library buffer
+ *   infos       optional HOST array of `batch` results
+ * The call plans on the host (one stream synchronisation for the diagonal
+ * signs), then launches; a domain error in any matrix returns SIGNTRI_EDOMAIN
+ * before anything is written and marks that matrix's info.
+ */
+int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U,
+                    const int64_t *ldu, const int64_t *n, int64_t batch,
+                    signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
+                    void *workspace, size_t ws_bytes, void *stream,
+                    const signtri_options *opts, signtri_info *infos);
+
+/* Device workspace needed by signtri_batched() for these orders. */
+size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch,
+                                      signtri_dtype dtype, signtri_mode mode);
+
+/* Human-readable text for a return code (static storage). */
+const char *signtri_strerror(int code);
+
+/*
+ * The plain form: column-major, ldu = ld, AUTO path, FP64, library workspace,
+ * default stream, synchronous (returns after U is complete).
+ */
+int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U);
+
+/*
+ * Section 3 planner on HOST data, without a GPU: from the diagonal signs
+ * s[0..n-1] (each +1 or -1) compute the inertia, the swap count and the two
+ * work estimates, and the path AUTO would run (into info->path; the other
+ * fields as documented for signtri_info).  Returns 0, or -1 for bad input.
+ */
+int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype,
+                      signtri_info *info);
+
+/* Release the library-owned workspace buffers (all devices). */
+void signtri_release(void);
+
+/*
+ * Kernel timers, for measurement.  signtri_profile_enable(1) clears the
+ * counters and, until signtri_profile_enable(0), brackets every kernel the
+ * library launches with a pair of HIP events on the launching stream (this
+ * adds a little time per launch).  signtri_profile_read() waits for the
+ * recorded events and returns, for one kernel family, the summed event time
+ * in milliseconds, the number of launches and the algorithmic flops of that
+ * work (Section 3 counting: a real multiply-add is 2 flops, a complex one 8).
+ * Returns 0, -1 for an unknown family, or SIGNTRI_EHIP.
+ */
+enum {
+    SIGNTRI_K_SCAN = 0,        /* diagonal scan                                  */
+    SIGNTRI_K_DIAG = 1,        /* diagonal blocks, element by element            */
+    SIGNTRI_K_GEMM = 2,        /* block products of the substitution             */
+    SIGNTRI_K_SOLVE = 3,       /* off-diagonal block equations                   */
+    SIGNTRI_K_AUX = 4,         /* zeroing and +-I fills                          */
+    SIGNTRI_K_RESID = 5,       /* FP64 residuals of refinement                   */
+    SIGNTRI_K_CORR_GEMM = 6,   /* block products of the correction solve         */
+    SIGNTRI_K_CORR_SOLVE = 7,  /* block equations of the correction solve        */
+    SIGNTRI_K_SYL_GEMM = 8,    /* Sylvester block products                       */
+    SIGNTRI_K_SYL_SOLVE = 9,   /* Sylvester block equations                      */
+    SIGNTRI_K_BATCHED = 10,    /* batched persistent kernel                      */
+    SIGNTRI_K_CONVERT = 11     /* precision and layout conversions               */
+};
+void signtri_profile_enable(int on);
+int signtri_profile_read(int family, double *ms, int64_t *launches, double *flops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIGNTRI_H */

@@ -1,0 +1,305 @@
+// C-ABI entry points: argument checks, workspace, planning and dispatch.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+using namespace sgt;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t scan = 0, sgn = 0, zbuf = 0, total = 0;
+    int64_t zslots = 0;
+};
+
+Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+{
+    (void)mode;
+    (void)algo;
+    const bool cplx = dtype == SIGNTRI_C128;
+    const size_t es = cplx ? 16 : 8;
+    Layout L;
+    size_t off = 0;
+    L.scan = off;
+    off += align_up(sizeof(ScanResult));
+    L.sgn = off;
+    off += align_up((size_t)std::max<int64_t>(n, 1));
+    const int tb = ph_tile_size(cplx);
+    L.zslots = ph_zslots(n, cplx);
+    L.zbuf = off;
+    off += align_up((size_t)L.zslots * tb * tb * es);
+    L.total = off;
+    return L;
+}
+
+// Library-owned device workspace and pinned host staging, grown on demand.
+struct Owned {
+    std::mutex mu;
+    std::vector<std::pair<void *, size_t>> dev;  // per device id
+    void *host = nullptr;
+    size_t host_bytes = 0;
+};
+Owned &owned()
+{
+    static Owned o;
+    return o;
+}
+
+int owned_workspace(size_t bytes, void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SIGNTRI_EHIP;
+    Owned &o = owned();
+    std::lock_guard<std::mutex> g(o.mu);
+    if ((int)o.dev.size() <= dev) o.dev.resize(dev + 1, {nullptr, 0});
+    auto &slot = o.dev[dev];
+    if (slot.second < bytes) {
+        if (slot.first) {
+            if (hipDeviceSynchronize() != hipSuccess) return SIGNTRI_EHIP;
+            (void)hipFree(slot.first);
+            slot = {nullptr, 0};
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return SIGNTRI_ENOMEM;
+        slot = {p, bytes};
+    }
+    *out = slot.first;
+    return SIGNTRI_OK;
+}
+
+int owned_host(size_t bytes, void **out)
+{
+    Owned &o = owned();
+    std::lock_guard<std::mutex> g(o.mu);
+    if (o.host_bytes < bytes) {
+        if (o.host) (void)hipHostFree(o.host);
+        o.host = nullptr;
+        o.host_bytes = 0;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return SIGNTRI_ENOMEM;
+        o.host = p;
+        o.host_bytes = bytes;
+    }
+    *out = o.host;
+    return SIGNTRI_OK;
+}
+
+bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bn && pb < pa + an;
+}
+
+size_t extent_bytes(int64_t n, int64_t ld, size_t es)
+{
+    if (n <= 0) return 0;
+    return ((size_t)(n - 1) * (size_t)ld + (size_t)n) * es;
+}
+
+void fill_info(signtri_info *info, const HostPlan &p)
+{
+    if (!info) return;
+    info->model_pick = p.model_pick;
+    info->n_pos = p.n_pos;
+    info->n_neg = p.n_neg;
+    info->swaps = std::min(p.swaps_pos_first, p.swaps_neg_first);
+    info->w_ph = p.w_ph;
+    info->w_ps = p.w_ps;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *signtri_strerror(int code)
+{
+    switch (code) {
+    case SIGNTRI_OK: return "success";
+    case SIGNTRI_EDOMAIN:
+        return "sign(T) is undefined: a diagonal entry has a zero real part or is not finite";
+    case SIGNTRI_EHIP: return "a HIP runtime call failed";
+    case SIGNTRI_EWORKSPACE: return "workspace smaller than signtri_workspace_size()";
+    case SIGNTRI_ENOCONV: return "iterative refinement did not converge and fallback is disabled";
+    case SIGNTRI_ENOTSUP: return "this combination of arguments is not implemented";
+    case SIGNTRI_ENOMEM: return "the library could not allocate its workspace";
+    default: break;
+    }
+    if (code < 0) return "invalid argument";
+    return "unknown error code";
+}
+
+size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+{
+    if (n < 0) return 0;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return 0;
+    if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
+    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return 0;
+    return layout_for(n, dtype, mode, algo).total;
+}
+
+int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype, signtri_info *info)
+{
+    if (n < 0 || (n > 0 && !s) || !info) return -1;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (s[i] != 1 && s[i] != -1) return -1;
+    std::memset(info, 0, sizeof(*info));
+    HostPlan p = plan_from_signs(s, n, dtype == SIGNTRI_C128);
+    fill_info(info, p);
+    info->path = n == 0 ? SIGNTRI_PATH_TRIVIAL : p.auto_path;
+    return 0;
+}
+
+int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri_dtype dtype,
+            signtri_layout layout, signtri_mode mode, signtri_algo algo, void *workspace,
+            size_t ws_bytes, void *stream, const signtri_options *opts, signtri_info *info)
+{
+    if (info) std::memset(info, 0, sizeof(*info));
+    // argument checks, in argument order (LAPACK style -p)
+    if (n > 0 && !T) return -1;
+    if (ldt < std::max<int64_t>(1, n)) return -2;
+    if (n > 0 && !U) return -3;
+    if (ldu < std::max<int64_t>(1, n)) return -4;
+    if (n < 0) return -5;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -6;
+    if (layout != SIGNTRI_COL_MAJOR && layout != SIGNTRI_ROW_MAJOR) return -7;
+    if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return -8;
+    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return -9;
+    if (workspace && ws_bytes == 0) return -11;
+    const bool cplx = dtype == SIGNTRI_C128;
+    const size_t es = cplx ? 16 : 8;
+    if (n > 0 && ranges_overlap(T, extent_bytes(n, ldt, es), U, extent_bytes(n, ldu, es))) return -3;
+    if (n == 0) return SIGNTRI_OK;
+    if (layout != SIGNTRI_COL_MAJOR || mode != SIGNTRI_FP64) return SIGNTRI_ENOTSUP;
+
+    const Layout L = layout_for(n, dtype, mode, algo);
+    if (workspace) {
+        if (ws_bytes < L.total) return SIGNTRI_EWORKSPACE;
+    } else {
+        int rc = owned_workspace(L.total, &workspace);
+        if (rc != SIGNTRI_OK) return rc;
+    }
+    void *hostbuf = nullptr;
+    size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n);
+    if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
+
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    ScanResult *scan = (ScanResult *)(ws + L.scan);
+    int8_t *sgn = (int8_t *)(ws + L.sgn);
+    if (launch_scan(T, ldt, n, cplx, sgn, scan, st) != hipSuccess) return SIGNTRI_EHIP;
+    char *hb = (char *)hostbuf;
+    // scan result and signs are adjacent in the workspace: one copy
+    if (hipMemcpyAsync(hb, ws + L.scan, L.sgn - L.scan + (size_t)n, hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+        return SIGNTRI_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SIGNTRI_EHIP;
+    ScanResult sr;
+    std::memcpy(&sr, hb, sizeof(sr));
+    const int8_t *hs = (const int8_t *)(hb + (L.sgn - L.scan));
+    if (sr.bad_index < n) {
+        if (info) info->bad_index = sr.bad_index + 1;
+        return SIGNTRI_EDOMAIN;
+    }
+    HostPlan p = plan_from_signs(hs, n, cplx);
+    fill_info(info, p);
+
+    int path = p.auto_path;
+    if (algo == SIGNTRI_PH && path != SIGNTRI_PATH_TRIVIAL) path = SIGNTRI_PATH_PH;
+    if (algo == SIGNTRI_PS && path != SIGNTRI_PATH_TRIVIAL) {
+        if (p.ps_sign == 0) return SIGNTRI_ENOTSUP;
+        path = SIGNTRI_PATH_PS;
+    }
+    if (path == SIGNTRI_PATH_PS) path = SIGNTRI_PATH_PH;  // sign-split solver arrives later
+
+    hipError_t e = hipSuccess;
+    if (path == SIGNTRI_PATH_TRIVIAL) {
+        e = launch_fill_pm_identity(U, ldu, n, cplx, p.n_pos > 0 ? 1.0 : -1.0, st);
+    } else {
+        PhArgs a;
+        a.T = T;
+        a.ldt = ldt;
+        a.U = U;
+        a.ldu = ldu;
+        a.n = n;
+        a.sgn = sgn;
+        a.zbuf = ws + L.zbuf;
+        a.zslots = L.zslots;
+        a.hsgn = hs;
+        a.max_splits = opts ? opts->max_splits : 0;
+        e = run_ph_fp64(a, cplx, st);
+    }
+    if (e != hipSuccess) return SIGNTRI_EHIP;
+    if (info) {
+        info->path = path;
+        info->tile = path == SIGNTRI_PATH_TRIVIAL ? 0 : ph_tile_size(cplx);
+    }
+    return SIGNTRI_OK;
+}
+
+int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U)
+{
+    int rc = signtri(T, ld, U, ld, n, dtype, SIGNTRI_COL_MAJOR, SIGNTRI_FP64, SIGNTRI_AUTO, nullptr,
+                     0, nullptr, nullptr, nullptr);
+    if (rc != SIGNTRI_OK) return rc;
+    return hipStreamSynchronize(nullptr) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
+}
+
+size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch, signtri_dtype dtype,
+                                      signtri_mode mode)
+{
+    if (batch < 0 || (batch > 0 && !n)) return 0;
+    size_t m = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        if (n[b] < 0) return 0;
+        m = std::max(m, signtri_workspace_size(n[b], dtype, mode, SIGNTRI_AUTO));
+    }
+    return m;
+}
+
+int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, const int64_t *ldu,
+                    const int64_t *n, int64_t batch, signtri_dtype dtype, signtri_layout layout,
+                    signtri_mode mode, void *workspace, size_t ws_bytes, void *stream,
+                    const signtri_options *opts, signtri_info *infos)
+{
+    if (batch > 0 && !T) return -1;
+    if (batch > 0 && !ldt) return -2;
+    if (batch > 0 && !U) return -3;
+    if (batch > 0 && !ldu) return -4;
+    if (batch > 0 && !n) return -5;
+    if (batch < 0) return -6;
+    for (int64_t b = 0; b < batch; ++b) {
+        int rc = signtri(T[b], ldt[b], U[b], ldu[b], n[b], dtype, layout, mode, SIGNTRI_AUTO,
+                         workspace, ws_bytes, stream, opts, infos ? infos + b : nullptr);
+        if (rc != SIGNTRI_OK) return rc;
+    }
+    return SIGNTRI_OK;
+}
+
+void signtri_release(void)
+{
+    Owned &o = owned();
+    std::lock_guard<std::mutex> g(o.mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (size_t d = 0; d < o.dev.size(); ++d) {
+        if (o.dev[d].first) {
+            (void)hipSetDevice((int)d);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(o.dev[d].first);
+        }
+        o.dev[d] = {nullptr, 0};
+    }
+    (void)hipSetDevice(cur);
+    if (o.host) (void)hipHostFree(o.host);
+    o.host = nullptr;
+    o.host_bytes = 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Diagonal scan and the Section 3 work model (Arithmetic Efficiency).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace sgt {
+
+// One workgroup reads the diagonal, records sign(Re t_ii) as +1/-1 (Section 1),
+// the first index whose sign is undefined (zero or non-finite entry), and the
+// number of positive signs.
+__global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int64_t ldt,
+                                               int64_t n, int cplx, int8_t *__restrict__ sgn,
+                                               ScanResult *__restrict__ res)
+{
+    __shared__ unsigned long long bad;
+    __shared__ unsigned long long npos;
+    if (threadIdx.x == 0) {
+        bad = (unsigned long long)n;
+        npos = 0;
+    }
+    __syncthreads();
+    unsigned long long my_pos = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double re, im = 0.0;
+        if (cplx) {
+            const double *p = T + 2 * (i + i * ldt);
+            re = p[0];
+            im = p[1];
+        } else {
+            re = T[i + i * ldt];
+        }
+        int s = 0;
+        if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
+        sgn[i] = (int8_t)s;
+        if (s == 0) atomicMin(&bad, (unsigned long long)i);
+        my_pos += (s > 0);
+    }
+    atomicAdd(&npos, my_pos);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        res->bad_index = (int64_t)bad;
+        res->n_pos = (int64_t)npos;
+    }
+}
+
+hipError_t launch_scan(const void *T, int64_t ldt, int64_t n, bool cplx, int8_t *sgn,
+                       ScanResult *res, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const double *)T, ldt, n,
+                       cplx ? 1 : 0, sgn, res);
+    return hipGetLastError();
+}
+
+// Work model of Section 3, in O(n) with running counts.
+//   W_PH = c * sum_{i<j} (j-i-1) * (2 if s_i == s_j else 4), c = 4 for complex.
+//   k    = adjacent swaps to group by sign (inversions), the fewer of the two orders.
+//   W_PS = c * (12 n k + n_- n_+ (n_- + n_+) + 12 n k): reorder with the Schur
+//          vectors, the Sylvester equation, and the same rotations applied again
+//          to bring the sign back (nothing when k = 0).
+HostPlan plan_from_signs(const int8_t *s, int64_t n, bool is_complex)
+{
+    HostPlan p;
+    const double c = is_complex ? 4.0 : 1.0;
+    int64_t cnt[2] = {0, 0};   // [0]: negatives seen, [1]: positives seen
+    double sumidx[2] = {0, 0};
+    double opp_terms = 0.0;    // sum over opposite-sign pairs of (j - i - 1)
+    for (int64_t j = 0; j < n; ++j) {
+        int cls = s[j] > 0 ? 1 : 0;
+        int opp = 1 - cls;
+        opp_terms += (double)cnt[opp] * (double)(j - 1) - sumidx[opp];
+        if (cls == 1) p.swaps_pos_first += cnt[0];  // a negative before this positive
+        else p.swaps_neg_first += cnt[1];
+        cnt[cls] += 1;
+        sumidx[cls] += (double)j;
+    }
+    p.n_pos = cnt[1];
+    p.n_neg = cnt[0];
+    double nd = (double)n;
+    double c3 = nd * (nd - 1.0) * (nd - 2.0) / 6.0;
+    if (n < 3) c3 = 0.0;
+    p.w_ph = c * (2.0 * c3 + 2.0 * opp_terms);
+    int64_t k = std::min(p.swaps_pos_first, p.swaps_neg_first);
+    double npn = (double)p.n_pos, nng = (double)p.n_neg;
+    p.w_ps = c * (24.0 * nd * (double)k + nng * npn * (nng + npn));
+    p.model_pick = (p.w_ps < p.w_ph) ? SIGNTRI_PATH_PS : SIGNTRI_PATH_PH;
+    if (p.n_pos == 0 || p.n_neg == 0) {
+        p.auto_path = SIGNTRI_PATH_TRIVIAL;
+        p.model_pick = SIGNTRI_PATH_TRIVIAL;
+        p.w_ps = 0.0;
+        return p;
+    }
+    if (p.swaps_pos_first == 0) {
+        p.ps_sign = 1;
+        p.split = p.n_pos;
+    } else if (p.swaps_neg_first == 0) {
+        p.ps_sign = -1;
+        p.split = p.n_neg;
+    }
+    // No Schur reordering here: PS runs only on an already grouped diagonal.
+    double w_ps_grouped = c * nng * npn * nd;
+    p.auto_path = (p.ps_sign != 0 && w_ps_grouped < p.w_ph) ? SIGNTRI_PATH_PS : SIGNTRI_PATH_PH;
+    return p;
+}
+
+}  // namespace sgt

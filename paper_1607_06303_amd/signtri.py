@@ -1,0 +1,258 @@
+"""Python binding of libsigntri.so (the C ABI in include/signtri.h).
+
+Argument marshalling only: every step of sign(T) runs in the library's HIP
+kernels.  PyTorch provides device memory and the current HIP stream.  There
+is no fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsigntri.so")
+
+R64, C128 = 0, 1
+COL_MAJOR, ROW_MAJOR = 0, 1
+MODES = {"fp64": 0, "mixed": 1, "fp32": 2}
+ALGOS = {"auto": 0, "ph": 1, "ps": 2}
+PATH_NAMES = {0: "trivial", 1: "ph", 2: "ps"}
+
+EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
+           "signtri_batched_workspace_size", "signtri_strerror", "sign_tri",
+           "signtri_plan_host", "signtri_release", "signtri_profile_enable",
+           "signtri_profile_read")
+FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
+            "corr_gemm": 6, "corr_solve": 7, "syl_gemm": 8, "syl_solve": 9,
+            "batched": 10, "convert": 11}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32), ("model_pick", ctypes.c_int32),
+        ("n_pos", ctypes.c_int64), ("n_neg", ctypes.c_int64), ("swaps", ctypes.c_int64),
+        ("w_ph", ctypes.c_double), ("w_ps", ctypes.c_double),
+        ("refine_steps", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("fallback_tiles", ctypes.c_int64), ("correction_rel", ctypes.c_double),
+        ("bad_index", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["path_name"] = PATH_NAMES.get(self.path, "?")
+        d["model_pick_name"] = PATH_NAMES.get(self.model_pick, "?")
+        return d
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("tile", ctypes.c_int32), ("max_refine_steps", ctypes.c_int32),
+        ("stall_ratio", ctypes.c_double), ("no_fallback", ctypes.c_int32),
+        ("max_splits", ctypes.c_int32),
+    ]
+
+
+class SignTriError(RuntimeError):
+    def __init__(self, code: int, message: str, info: dict | None = None):
+        super().__init__("signtri error %d: %s" % (code, message))
+        self.code = code
+        self.info = info or {}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsigntri.so, raising if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libsigntri.so is not built (%s); run __graft_entry__.build()"
+                                   % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            i64, p, sz, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+            L.signtri.argtypes = [p, i64, p, i64, i64, i32, i32, i32, i32, p, sz, p,
+                                  ctypes.POINTER(Options), ctypes.POINTER(Info)]
+            L.signtri.restype = i32
+            L.signtri_workspace_size.argtypes = [i64, i32, i32, i32]
+            L.signtri_workspace_size.restype = sz
+            L.signtri_batched.argtypes = [ctypes.POINTER(p), ctypes.POINTER(i64), ctypes.POINTER(p),
+                                          ctypes.POINTER(i64), ctypes.POINTER(i64), i64, i32, i32,
+                                          i32, p, sz, p, ctypes.POINTER(Options),
+                                          ctypes.POINTER(Info)]
+            L.signtri_batched.restype = i32
+            L.signtri_batched_workspace_size.argtypes = [ctypes.POINTER(i64), i64, i32, i32]
+            L.signtri_batched_workspace_size.restype = sz
+            L.signtri_strerror.argtypes = [i32]
+            L.signtri_strerror.restype = ctypes.c_char_p
+            L.sign_tri.argtypes = [p, i64, i64, i32, p]
+            L.sign_tri.restype = i32
+            L.signtri_plan_host.argtypes = [p, i64, i32, ctypes.POINTER(Info)]
+            L.signtri_plan_host.restype = i32
+            L.signtri_release.argtypes = []
+            L.signtri_release.restype = None
+            L.signtri_profile_enable.argtypes = [i32]
+            L.signtri_profile_enable.restype = None
+            L.signtri_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+            L.signtri_profile_read.restype = i32
+            _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().signtri_strerror(int(code)).decode()
+
+
+def workspace_size(n: int, complex_: bool = False, mode: str = "fp64", algo: str = "auto") -> int:
+    return int(lib().signtri_workspace_size(n, C128 if complex_ else R64, MODES[mode], ALGOS[algo]))
+
+
+def plan_host(signs, complex_: bool = False) -> dict:
+    """Section 3 planner on host signs (+1/-1), without a GPU."""
+    import numpy as np
+
+    s = np.ascontiguousarray(np.asarray(signs, dtype=np.int8))
+    info = Info()
+    rc = lib().signtri_plan_host(s.ctypes.data if s.size else None, int(s.size),
+                                 C128 if complex_ else R64, ctypes.byref(info))
+    if rc != 0:
+        raise ValueError("invalid sign vector")
+    return info.as_dict()
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    if t.dtype == torch.float64:
+        return R64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError("T must be float64 or complex128, got %s" % t.dtype)
+
+
+def _layout(t):
+    """(layout code, leading dimension) of a 2-D strided tensor, or None."""
+    n0, n1 = t.shape
+    s0, s1 = t.stride()
+    if s0 == 1 and (s1 >= max(1, n0) or n1 <= 1):
+        return COL_MAJOR, max(s1, n0, 1)
+    if s1 == 1 and (s0 >= max(1, n1) or n0 <= 1):
+        return ROW_MAJOR, max(s0, n1, 1)
+    return None
+
+
+def empty_like_layout(t):
+    """A new tensor with t's shape, dtype, device and storage order."""
+    import torch
+
+    lay = _layout(t)
+    if lay is not None and lay[0] == COL_MAJOR and t.shape[0] > 1:
+        return torch.empty(t.shape[1], t.shape[0], dtype=t.dtype, device=t.device).t()
+    return torch.empty(t.shape, dtype=t.dtype, device=t.device)
+
+
+def _stream_handle(t, stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _opts(options: dict | None):
+    if not options:
+        return None
+    o = Options()
+    for k, v in options.items():
+        setattr(o, k, v)
+    return ctypes.byref(o)
+
+
+def sign_tri(T, mode: str = "fp64", algo: str = "auto", out=None, workspace=None,
+             stream=None, options: dict | None = None):
+    """U = sign(T) for a square upper-triangular CUDA/HIP tensor T.
+
+    T may be column- or row-major (with padding); U (``out`` or a new tensor)
+    gets the same storage order.  Returns (U, info dict).  Raises
+    SignTriError on a nonzero library return code.
+    """
+    if T.dim() != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    n = T.shape[0]
+    dt = _dtype_code(T)
+    lay = _layout(T)
+    if lay is None:
+        raise ValueError("T must be column- or row-major strided")
+    layout, ldt = lay
+    U = out if out is not None else empty_like_layout(T)
+    ulay = _layout(U)
+    if ulay is None or (n > 1 and ulay[0] != layout) or U.shape != T.shape or U.dtype != T.dtype:
+        raise ValueError("out must match T's shape, dtype and storage order")
+    ldu = ulay[1]
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    info = Info()
+    rc = lib().signtri(T.data_ptr() if n else None, ldt, U.data_ptr() if n else None, ldu, n, dt,
+                       layout, MODES[mode], ALGOS[algo], ws_ptr, ws_bytes,
+                       _stream_handle(T, stream), _opts(options), ctypes.byref(info))
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc), info.as_dict())
+    return U, info.as_dict()
+
+
+def sign_tri_batched(Ts, mode: str = "fp64", outs=None, workspace=None, stream=None,
+                     options: dict | None = None):
+    """Batched form: list of square upper-triangular tensors (same dtype, device
+    and storage order).  Returns (list of U, list of info dicts)."""
+    if not Ts:
+        return [], []
+    dt = _dtype_code(Ts[0])
+    layouts = [_layout(t) for t in Ts]
+    if any(l is None for l in layouts):
+        raise ValueError("every T must be column- or row-major strided")
+    layout = layouts[0][0]
+    Us = outs if outs is not None else [empty_like_layout(t) for t in Ts]
+    B = len(Ts)
+    P = ctypes.c_void_p * B
+    I = ctypes.c_int64 * B
+    tp = P(*[t.data_ptr() for t in Ts])
+    up = P(*[u.data_ptr() for u in Us])
+    ldt = I(*[l[1] for l in layouts])
+    ldu = I(*[_layout(u)[1] for u in Us])
+    ns = I(*[t.shape[0] for t in Ts])
+    infos = (Info * B)()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    rc = lib().signtri_batched(tp, ldt, up, ldu, ns, B, dt, layout, MODES[mode], ws_ptr,
+                               ws_bytes, _stream_handle(Ts[0], stream), _opts(options), infos)
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc))
+    return Us, [infos[b].as_dict() for b in range(B)]
+
+
+def release() -> None:
+    lib().signtri_release()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (clearing counters) or stop the library's per-family kernel timers."""
+    lib().signtri_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{family: (milliseconds, launches, algorithmic flops)} for families with launches."""
+    out = {}
+    for name, k in FAMILIES.items():
+        ms, cnt, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        rc = lib().signtri_profile_read(k, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(fl))
+        if rc != 0:
+            raise SignTriError(rc, strerror(rc))
+        if cnt.value:
+            out[name] = (ms.value, cnt.value, fl.value)
+    return out

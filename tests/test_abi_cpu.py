@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/signtri.h declares, validates arguments before any
+device work, and its Section 3 planner agrees with the brute-force counts."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import workmodel
+from paper_1607_06303_amd import signtri
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "signtri.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "signtri" in names and "sign_tri" in names and "signtri_batched" in names
+    L = signtri.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(signtri.EXPORTS) <= set(names)
+
+
+def test_strerror():
+    assert signtri.strerror(0) == "success"
+    assert "undefined" in signtri.strerror(1)
+    assert "invalid" in signtri.strerror(-3)
+
+
+def test_workspace_size():
+    a = signtri.workspace_size(512)
+    b = signtri.workspace_size(8192)
+    c = signtri.workspace_size(4096, complex_=True)
+    assert 0 < a < b and c > 0
+    assert signtri.lib().signtri_workspace_size(-1, 0, 0, 0) == 0
+    assert signtri.lib().signtri_workspace_size(10, 7, 0, 0) == 0
+
+
+def _call(T, ldt, U, ldu, n, dtype=0, layout=0, mode=0, algo=0, ws=None, wsb=0):
+    info = signtri.Info()
+    return signtri.lib().signtri(T, ldt, U, ldu, n, dtype, layout, mode, algo, ws, wsb, None,
+                                 None, ctypes.byref(info))
+
+
+def test_argument_validation_without_device_work():
+    fake_t = ctypes.c_void_p(0x1000)
+    fake_u = ctypes.c_void_p(0x100000)
+    assert _call(None, 4, fake_u, 4, 4) == -1
+    assert _call(fake_t, 3, fake_u, 4, 4) == -2
+    assert _call(fake_t, 4, None, 4, 4) == -3
+    assert _call(fake_t, 4, fake_u, 2, 4) == -4
+    assert _call(fake_t, 4, fake_u, 4, -1) == -5
+    assert _call(fake_t, 4, fake_u, 4, 4, dtype=9) == -6
+    assert _call(fake_t, 4, fake_u, 4, 4, layout=9) == -7
+    assert _call(fake_t, 4, fake_u, 4, 4, mode=9) == -8
+    assert _call(fake_t, 4, fake_u, 4, 4, algo=9) == -9
+    assert _call(fake_t, 4, fake_u, 4, 4, ws=ctypes.c_void_p(0x2000), wsb=0) == -11
+    # U overlapping T
+    assert _call(fake_t, 4, ctypes.c_void_p(0x1000 + 8), 4, 4) == -3
+    # n == 0 is a no-op
+    assert _call(None, 1, None, 1, 0) == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 33, 120])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_planner_matches_bruteforce(n, cplx):
+    rng = np.random.default_rng(n + 7 * cplx)
+    for trial in range(4):
+        p = [0.5, 0.05, 0.95, 1.0][trial]
+        s = np.where(rng.random(n) < p, 1, -1).astype(np.int8)
+        info = signtri.plan_host(s, complex_=cplx)
+        npos = int(np.sum(s > 0))
+        assert info["n_pos"] == npos and info["n_neg"] == n - npos
+        assert info["w_ph"] == workmodel.ph_flops(list(s), cplx)
+        if 0 < npos < n:
+            assert info["swaps"] == min(workmodel.swaps(list(s)))
+            assert info["w_ps"] == workmodel.ps_flops(list(s), cplx)
+        else:
+            assert info["path"] == 0  # +-I, no solve
+
+
+def test_planner_choice_rule():
+    n = 200
+    # grouped by sign: Parlett-Sylvester (no reordering needed)
+    grouped = np.array([1] * 150 + [-1] * 50, dtype=np.int8)
+    info = signtri.plan_host(grouped)
+    assert info["swaps"] == 0 and info["path_name"] == "ps" and info["model_pick_name"] == "ps"
+    neg_first = grouped[::-1].copy()
+    assert signtri.plan_host(neg_first)["path_name"] == "ps"
+    # interleaved: Parlett-Higham; the model prefers PH for balanced inertia
+    rng = np.random.default_rng(3)
+    inter = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    info = signtri.plan_host(inter)
+    assert info["path_name"] == "ph" and info["model_pick_name"] == "ph"
+    # few negatives at random positions: the model (with reordering) prefers PS,
+    # but without a reordering step PH runs (the paper's Fig. 3 regime)
+    few = np.ones(n, dtype=np.int8)
+    few[rng.choice(n, 3, replace=False)] = -1
+    info = signtri.plan_host(few)
+    assert info["model_pick_name"] == "ps" and info["path_name"] == "ph"
+
+
+def test_planner_rejects_bad_signs():
+    with pytest.raises(ValueError):
+        signtri.plan_host(np.array([1, 0, -1], dtype=np.int8))

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 results must match the oracle to 1e-11 relative Frobenius error (the
+accuracy bar stated for the FP64 path).  Sizes span several blocks and a
+ragged last block; sign patterns cover interleaved, skewed, all-equal and
+grouped inertia; special inputs cover repeated diagonal values, garbage below
+the diagonal, padded leading dimensions and domain errors.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06303_amd import workloads as wl
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_06303_amd import signtri
+
+    signtri.lib()
+    return torch.device("cuda:0")
+
+
+def to_dev_colmajor(T, dev, ld=None):
+    import torch
+
+    n = T.shape[0]
+    ld = ld or n
+    buf = np.zeros((ld, n), dtype=T.dtype, order="F")
+    buf[:n, :n] = T
+    G = torch.from_numpy(np.ascontiguousarray(buf.T)).to(dev)  # (n, ld) row-major == column-major ld x n
+    return G.t()[:n, :n] if ld == n else G.t()[:n, :]
+
+
+def run_gpu(T, dev, **kw):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    Tg = to_dev_colmajor(np.asarray(T), dev)
+    U, info = signtri.sign_tri(Tg, **kw)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), info
+
+
+def check(T, dev, tol=TOL_FP64, **kw):
+    import oracle
+
+    U, info = run_gpu(T, dev, **kw)
+    Uref = oracle.sign_tri(T)
+    err = rel_fro(U, Uref)
+    assert err <= tol, (T.shape, err, info)
+    assert not np.any(np.tril(U, -1)), "strict lower triangle must be zero"
+    return U, info, err
+
+
+SIZES = [1, 2, 3, 16, 31, 63, 64, 65, 100, 127, 128, 129, 191, 257, 300]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_real_interleaved(dev, n):
+    rng = np.random.default_rng(1000 + n)
+    check(wl.make_T(n, rng), dev)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_complex_interleaved(dev, n):
+    rng = np.random.default_rng(2000 + n)
+    check(wl.make_T(n, rng, complex_=True), dev)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("n", [130, 333])
+def test_skewed_few_negatives(dev, n, cplx):
+    rng = np.random.default_rng(3000 + n)
+    s = wl.signs_with_negatives(n, 5, rng)
+    _, info, _ = check(wl.make_T(n, rng, complex_=cplx, signs=s), dev)
+    assert info["path_name"] == "ph"
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("sgn", [1.0, -1.0])
+def test_all_same_sign_is_exact(dev, sgn, cplx):
+    rng = np.random.default_rng(4000)
+    T = wl.make_T(150, rng, complex_=cplx, signs=np.full(150, sgn))
+    U, info = run_gpu(T, dev)
+    assert info["path_name"] == "trivial"
+    assert np.array_equal(U, sgn * np.eye(150))
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_sign_split_input(dev, cplx):
+    rng = np.random.default_rng(4100)
+    T = wl.sorted_positive_first(wl.make_T(200, rng, complex_=cplx))
+    check(T, dev)
+
+
+def test_block_pattern_signs(dev):
+    # whole 64-blocks of one sign next to mixed ones
+    n = 320
+    s = np.ones(n)
+    s[64:128] = -1
+    s[200:230] = -1
+    s[300] = -1
+    rng = np.random.default_rng(4200)
+    check(wl.make_T(n, rng, signs=s), dev)
+
+
+def test_repeated_diagonal(dev):
+    rng = np.random.default_rng(4300)
+    T = wl.schur_like(150, None, rng)
+    U, _, _ = check(T, dev, tol=1e-10)
+    assert np.all(np.isfinite(U))
+
+
+def test_near_imaginary_complex(dev):
+    rng = np.random.default_rng(4400)
+    T = wl.make_T(200, rng, complex_=True, re_range=(1e-3, 1.0), im_range=(-2, 2))
+    check(T, dev)
+
+
+def test_lower_garbage_and_padding(dev):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+    import oracle
+
+    n, ld = 150, 173
+    rng = np.random.default_rng(4500)
+    T = wl.make_T(n, rng)
+    G = T + np.tril(rng.standard_normal((n, n)), -1) * 100
+    Tg = to_dev_colmajor(G, dev, ld=ld)
+    Ubuf = torch.full((n, ld), 7.0, dtype=torch.float64, device=dev)  # column-major ld x n
+    U = Ubuf.t()[:n, :]
+    signtri.sign_tri(Tg, out=U)
+    torch.cuda.synchronize()
+    full = Ubuf.cpu().numpy().T  # ld x n
+    assert np.all(full[n:, :] == 7.0), "padding rows must be untouched"
+    assert rel_fro(full[:n, :], oracle.sign_tri(T)) <= TOL_FP64
+    assert not np.any(np.tril(full[:n, :], -1))
+
+
+def test_domain_error_leaves_u_untouched(dev):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(4600)
+    T = wl.make_T(90, rng)
+    T[37, 37] = 0.0
+    Tg = to_dev_colmajor(T, dev)
+    U = signtri.empty_like_layout(Tg)
+    U.fill_(3.0)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(Tg, out=U)
+    assert ei.value.code == 1 and ei.value.info["bad_index"] == 38
+    torch.cuda.synchronize()
+    assert bool((U == 3.0).all())
+    Tc = wl.make_T(40, rng, complex_=True)
+    Tc[5, 5] = 0.25j
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(to_dev_colmajor(Tc, dev))
+    assert ei.value.info["bad_index"] == 6
+
+
+def test_deterministic(dev):
+    rng = np.random.default_rng(4700)
+    T = wl.make_T(400, rng)
+    U1, _ = run_gpu(T, dev)
+    U2, _ = run_gpu(T, dev)
+    assert np.array_equal(U1, U2)
+
+
+def test_workspace_argument(dev):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+    import oracle
+
+    rng = np.random.default_rng(4800)
+    T = wl.make_T(200, rng)
+    Tg = to_dev_colmajor(T, dev)
+    need = signtri.workspace_size(200)
+    small = torch.empty(need // 2, dtype=torch.uint8, device=dev)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(Tg, workspace=small)
+    assert ei.value.code == 3
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    U, _ = signtri.sign_tri(Tg, workspace=ws)
+    torch.cuda.synchronize()
+    assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_workload1_full(dev):
+    """512 x 512 real, interleaved inertia: whole matrix against the oracle."""
+    check(wl.workload1(), dev)
