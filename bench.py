@@ -39,13 +39,14 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--check-block", type=int, default=1536)
+    ap.add_argument("--tile", type=int, default=0, help="block size 32 or 64 (0: library default)")
     return ap.parse_args()
 
 
-def time_mode(signtri, torch, Tg, mode, steps, warmup):
+def time_mode(signtri, torch, Tg, mode, steps, warmup, opts):
     U = signtri.empty_like_layout(Tg)
     for _ in range(warmup):
-        signtri.sign_tri(Tg, mode=mode, out=U)
+        signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -54,7 +55,7 @@ def time_mode(signtri, torch, Tg, mode, steps, warmup):
     start.record()
     info = None
     for _ in range(steps):
-        _, info = signtri.sign_tri(Tg, mode=mode, out=U)
+        _, info = signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
     stop.record()
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
@@ -103,10 +104,11 @@ def main():
     torch.cuda.synchronize()
     n3 = n ** 3 / 3.0
 
+    opts = {"tile": args.tile} if args.tile else None
     results = {}
     for mode in [m for m in args.modes.split(",") if m]:
         try:
-            U, info, ms = time_mode(signtri, torch, Tg, mode, args.steps, args.warmup)
+            U, info, ms = time_mode(signtri, torch, Tg, mode, args.steps, args.warmup, opts)
         except signtri.SignTriError as e:
             log("mode %s unavailable: %s" % (mode, e))
             continue
@@ -121,7 +123,7 @@ def main():
                 % (mode, err, inv1, inv2))
         # kernel timers over one more step (HIP events on the library's stream)
         signtri.profile_enable(True)
-        signtri.sign_tri(Tg, mode=mode, out=U)
+        signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
         torch.cuda.synchronize()
         r["kernels"] = signtri.profile_read()
         signtri.profile_enable(False)
@@ -182,7 +184,7 @@ def main():
         "modes": {m: {"ms_per_step": r["ms"], "gflops": r["gflops"],
                       "err_sampled": r.get("err_sampled"), "inv_u2": r.get("inv_u2"),
                       "inv_comm": r.get("inv_comm"), "path": r["info"]["path_name"],
-                      "refine_steps": r["info"]["refine_steps"],
+                      "refine_steps": r["info"]["refine_steps"], "tile": r["info"]["tile"],
                       "fallback_tiles": r["info"]["fallback_tiles"],
                       "kernels_ms": {k: v[0] for k, v in r["kernels"].items()}}
                   for m, r in results.items()},

@@ -14,11 +14,11 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t scan = 0, sgn = 0, zbuf = 0, total = 0;
+    size_t scan = 0, sgn = 0, zbuf = 0, zbufs[2] = {0, 0}, ebuf = 0, total = 0;
     int64_t zslots = 0;
 };
 
-Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo, int tb)
 {
     (void)mode;
     (void)algo;
@@ -30,12 +30,28 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_alg
     off += align_up(sizeof(ScanResult));
     L.sgn = off;
     off += align_up((size_t)std::max<int64_t>(n, 1));
-    const int tb = ph_tile_size(cplx);
-    L.zslots = ph_zslots(n, cplx);
+    L.zslots = ph_zslots(n, tb);
     L.zbuf = off;
     off += align_up((size_t)L.zslots * tb * tb * es);
+    if (!cplx) {
+        static_assert(kLookahead - 1 <= 2, "bulk buffer count");
+        for (int b = 0; b < kLookahead - 1; ++b) {
+            L.zbufs[b] = off;
+            off += align_up((size_t)L.zslots * tb * tb * es);
+        }
+        L.ebuf = off;
+        off += align_up((size_t)ph_real_edge_slots(n, tb) * tb * tb * es);
+    }
     L.total = off;
     return L;
+}
+
+// Workspace valid for every block size the call may choose.
+size_t max_total(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+{
+    size_t m = layout_for(n, dtype, mode, algo, 32).total;
+    if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, mode, algo, 64).total);
+    return m;
 }
 
 // Library-owned device workspace and pinned host staging, grown on demand.
@@ -102,6 +118,83 @@ size_t extent_bytes(int64_t n, int64_t ld, size_t es)
     return ((size_t)(n - 1) * (size_t)ld + (size_t)n) * es;
 }
 
+// Captured launch sequences of the blocked sweep.  Every launch shape depends
+// only on the arguments in the key (the kernels read the signs from device
+// memory), so one graph serves every T of that shape.  Capture runs on a
+// library-owned stream; the graph is then launched on the caller's stream.
+struct GraphKey {
+    const void *T;
+    int64_t ldt;
+    void *U;
+    int64_t ldu;
+    int64_t n;
+    int dtype, tile, max_splits, device;
+    void *ws;
+    bool operator==(const GraphKey &o) const
+    {
+        return T == o.T && ldt == o.ldt && U == o.U && ldu == o.ldu && n == o.n &&
+               dtype == o.dtype && tile == o.tile && max_splits == o.max_splits &&
+               device == o.device && ws == o.ws;
+    }
+};
+struct GraphCache {
+    std::mutex mu;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> entries;  // most recent last
+    std::vector<hipStream_t> capture_streams;                 // per device
+};
+GraphCache &graphs()
+{
+    static GraphCache g;
+    return g;
+}
+constexpr size_t kGraphCacheSize = 8;
+
+bool graphs_enabled()
+{
+    const char *v = getenv("SIGNTRI_NO_GRAPH");
+    return !(v && *v && *v != '0');
+}
+
+// Launch the sweep described by `a` on `st`, through a cached graph when possible.
+hipError_t launch_ph(const PhArgs &a, bool cplx, hipStream_t st, int device)
+{
+    if (!graphs_enabled() || prof_on()) return run_ph_fp64(a, cplx, st);
+    GraphKey key{a.T, a.ldt, a.U, a.ldu, a.n, cplx ? 1 : 0, a.tile, a.max_splits, device,
+                 a.zbuf};
+    GraphCache &g = graphs();
+    std::lock_guard<std::mutex> lk(g.mu);
+    for (size_t k = 0; k < g.entries.size(); ++k)
+        if (g.entries[k].first == key) {
+            auto hit = g.entries[k];
+            g.entries.erase(g.entries.begin() + k);
+            g.entries.push_back(hit);
+            return hipGraphLaunch(hit.second, st);
+        }
+    if ((int)g.capture_streams.size() <= device) g.capture_streams.resize(device + 1, nullptr);
+    hipStream_t &cs = g.capture_streams[device];
+    hipError_t e;
+    if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+    hipError_t run = run_ph_fp64(a, cplx, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (run != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return run;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (g.entries.size() >= kGraphCacheSize) {
+        (void)hipGraphExecDestroy(g.entries.front().second);
+        g.entries.erase(g.entries.begin());
+    }
+    g.entries.push_back({key, exec});
+    return hipGraphLaunch(exec, st);
+}
+
 void fill_info(signtri_info *info, const HostPlan &p)
 {
     if (!info) return;
@@ -140,7 +233,7 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_mode mode,
     if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return 0;
     if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
     if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return 0;
-    return layout_for(n, dtype, mode, algo).total;
+    return max_total(n, dtype, mode, algo);
 }
 
 int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype, signtri_info *info)
@@ -178,11 +271,13 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     if (n == 0) return SIGNTRI_OK;
     if (layout != SIGNTRI_COL_MAJOR || mode != SIGNTRI_FP64) return SIGNTRI_ENOTSUP;
 
-    const Layout L = layout_for(n, dtype, mode, algo);
+    if (opts && opts->tile != 0 && opts->tile != 32 && opts->tile != 64) return -13;
+    const int tb = ph_tile_size(cplx, opts ? opts->tile : 0);
+    const Layout L = layout_for(n, dtype, mode, algo, tb);
     if (workspace) {
-        if (ws_bytes < L.total) return SIGNTRI_EWORKSPACE;
+        if (ws_bytes < max_total(n, dtype, mode, algo)) return SIGNTRI_EWORKSPACE;
     } else {
-        int rc = owned_workspace(L.total, &workspace);
+        int rc = owned_workspace(max_total(n, dtype, mode, algo), &workspace);
         if (rc != SIGNTRI_OK) return rc;
     }
     void *hostbuf = nullptr;
@@ -230,15 +325,21 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         a.n = n;
         a.sgn = sgn;
         a.zbuf = ws + L.zbuf;
+        a.zbufs[0] = ws + L.zbufs[0];
+        a.zbufs[1] = ws + L.zbufs[1];
+        a.ebuf = ws + L.ebuf;
         a.zslots = L.zslots;
         a.hsgn = hs;
         a.max_splits = opts ? opts->max_splits : 0;
-        e = run_ph_fp64(a, cplx, st);
+        a.tile = tb;
+        int device = 0;
+        if (hipGetDevice(&device) != hipSuccess) return SIGNTRI_EHIP;
+        e = launch_ph(a, cplx, st, device);
     }
     if (e != hipSuccess) return SIGNTRI_EHIP;
     if (info) {
         info->path = path;
-        info->tile = path == SIGNTRI_PATH_TRIVIAL ? 0 : ph_tile_size(cplx);
+        info->tile = path == SIGNTRI_PATH_TRIVIAL ? 0 : tb;
     }
     return SIGNTRI_OK;
 }
@@ -300,6 +401,10 @@ void signtri_release(void)
     if (o.host) (void)hipHostFree(o.host);
     o.host = nullptr;
     o.host_bytes = 0;
+    GraphCache &gc = graphs();
+    std::lock_guard<std::mutex> lk(gc.mu);
+    for (auto &kv : gc.entries) (void)hipGraphExecDestroy(kv.second);
+    gc.entries.clear();
 }
 
 }  // extern "C"

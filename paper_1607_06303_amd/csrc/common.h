@@ -5,10 +5,13 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/signtri.h"
 
 namespace sgt {
+
+constexpr int kLookahead = 3;  // bulk products run kLookahead-1 superdiagonals ahead
 
 // ---------------------------------------------------------------------------
 // Scalars.  Complex numbers are interleaved (re, im) doubles, as in the ABI.
@@ -66,6 +69,54 @@ typedef float fx4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int mfma64_row(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ inline int mfma32_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+// Sum over aligned groups of 8 consecutive lanes with DPP moves (no LDS):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror.
+template <int CTRL> __device__ inline float dppf(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ inline double dppd(double v)
+{
+    long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double group8_sum(double v)
+{
+    v += dppd<0xB1>(v);
+    v += dppd<0x4E>(v);
+    v += dppd<0x141>(v);
+    return v;
+}
+__device__ inline float group8_sum(float v)
+{
+    v += dppf<0xB1>(v);
+    v += dppf<0x4E>(v);
+    v += dppf<0x141>(v);
+    return v;
+}
+// Sum over aligned groups of L consecutive lanes (L = 4, 8 or 16); every lane
+// of a group receives the group's sum.  16: the 8-lane sums are combined with
+// row_mirror (lane i and lane 15 - i lie in different halves).
+template <int L, typename V> __device__ inline V group_sum(V v)
+{
+    static_assert(L == 4 || L == 8 || L == 16, "group size");
+    if constexpr (sizeof(V) == 8) {
+        v += dppd<0xB1>(v);
+        v += dppd<0x4E>(v);
+        if constexpr (L >= 8) v += dppd<0x141>(v);
+        if constexpr (L >= 16) v += dppd<0x140>(v);
+    } else {
+        v += dppf<0xB1>(v);
+        v += dppf<0x4E>(v);
+        if constexpr (L >= 8) v += dppf<0x141>(v);
+        if constexpr (L >= 16) v += dppf<0x140>(v);
+    }
+    return v;
+}
 
 __device__ inline dx4 mfma_f64(double a, double b, dx4 c)
 {
@@ -139,11 +190,116 @@ struct PhArgs {
     const int8_t *sgn;
     const int8_t *hsgn;  // the same signs in host memory (flop accounting)
     void *zbuf;          // block accumulators: zslots * tile * tile scalars
+    void *zbufs[2];      // further bulk buffers (real path)
+    void *ebuf;          // edge partials (real path)
     int64_t zslots;
     int max_splits;
+    int tile;            // block size: 64 or 32 (real), 32 (complex)
 };
-int ph_tile_size(bool cplx);
-int64_t ph_zslots(int64_t n, bool cplx);
+
+// Algorithmic flops (Section 3 counting) per launch family, from host signs: a
+// pair (i, j), i < j, costs 2 (equal signs) or 4 (opposite) real flops per k
+// strictly between them (x4 for complex).  Its k are attributed to the block
+// products when they lie in blocks strictly between I and J (bulk: I+2 .. J-2,
+// edge: I+1 and J-1) and to the solve kernels when they lie inside I or J.
+struct FlopCounter {
+    const int8_t *s;
+    int64_t n;
+    int tb;
+    double c;  // 1 real, 4 complex
+
+    void counts(int64_t i0, int len, int64_t &pos, int64_t &neg) const
+    {
+        pos = neg = 0;
+        for (int t = 0; t < len; ++t) (s[i0 + t] > 0 ? pos : neg)++;
+    }
+    // flops of the middle K blocks of superdiagonal D, per K block
+    double per_k_block(int D) const
+    {
+        const int64_t nb = (n + tb - 1) / tb;
+        double f = 0.0;
+        for (int64_t I = 0; I + D < nb; ++I) {
+            int64_t J = I + D;
+            int bj = (int)((n - J * tb) < tb ? (n - J * tb) : tb);
+            int64_t rp, rn, cp, cn;
+            counts(I * tb, tb, rp, rn);
+            counts(J * tb, bj, cp, cn);
+            double same = (double)(rp * cp + rn * cn), opp = (double)(rp * cn + rn * cp);
+            f += (2.0 * same + 4.0 * opp) * (double)tb;
+        }
+        return c * f;
+    }
+    // middle K blocks of block (I, I+D) split into bulk (I+L .. J-L) and edge (the rest)
+    double gemm_bulk(int D, int L) const
+    {
+        const int nb = D - 2 * L + 1;
+        return nb > 0 ? per_k_block(D) * nb : 0.0;
+    }
+    double gemm_edge(int D, int L) const
+    {
+        const int ne = D <= 1 ? 0 : (D - 1 < 2 * (L - 1) ? D - 1 : 2 * (L - 1));
+        return ne > 0 ? per_k_block(D) * ne : 0.0;
+    }
+    double solve(int D) const
+    {
+        const int64_t nb = (n + tb - 1) / tb;
+        double f = 0.0;
+        for (int64_t I = 0; I + D < nb; ++I) {
+            int64_t J = I + D;
+            int bj = (int)((n - J * tb) < tb ? (n - J * tb) : tb);
+            for (int i = 0; i < tb; ++i)
+                for (int j = 0; j < bj; ++j) {
+                    double w = (double)((tb - 1 - i) + j);
+                    f += (s[I * tb + i] == s[J * tb + j] ? 2.0 : 4.0) * w;
+                }
+        }
+        return c * f;
+    }
+    double diag() const
+    {
+        double f = 0.0;
+        for (int64_t r0 = 0; r0 < n; r0 += tb) {
+            int bt = (int)((n - r0) < tb ? (n - r0) : tb);
+            for (int j = 0; j < bt; ++j)
+                for (int i = 0; i < j; ++i)
+                    f += (s[r0 + i] == s[r0 + j] ? 2.0 : 4.0) * (double)(j - i - 1);
+        }
+        return c * f;
+    }
+};
+
+// One real blocked sweep (64 x 64 blocks): bulk products on a side stream,
+// edge products and solves on the caller's stream.
+struct RealSweep {
+    const double *T;
+    int64_t ldt;
+    double *U;
+    int64_t ldu;
+    int64_t n;
+    const int8_t *sgn;
+    double *zbuf[kLookahead];   // bulk partials, by superdiagonal mod kLookahead
+    double *ebuf;               // edge partials
+    int64_t zslots;
+    int max_splits;
+    int tile;                   // 32 or 64
+    const FlopCounter *flops;   // null unless timers are on
+    std::vector<int> bulk_nm;   // bulk slices used per superdiagonal
+};
+hipError_t run_ph_real(RealSweep &w, hipStream_t st);
+int64_t ph_real_edge_slots(int64_t n, int tb);
+// Right-hand sides of block superdiagonal D (real, 64 x 64 blocks): nmid_split
+// slices of the middle K blocks plus one slice for the diagonal-block terms,
+// into Z[(tile * (nmid_split + 1) + slice) * 64 * 64 + i * 64 + j].
+template <typename F>
+hipError_t launch_wave_gemm(int tb, const F *T, int64_t ldt, const F *U, int64_t ldu, int64_t n,
+                            const int8_t *sgn, int D, int ntiles, int edge, int nmid_split, int L,
+                            F *Z, hipStream_t st);
+int wave_gemm_mid_splits(int D, int L, int ntiles, int max_splits, int64_t zslots);
+int wave_gemm_edge_slices(int D, int L);
+
+// block size used for a request (0 = default), and bulk partial-sum slots
+int ph_tile_size(bool cplx, int requested);
+int64_t ph_zslots(int64_t n, int tb);
 hipError_t run_ph_fp64(const PhArgs &a, bool cplx, hipStream_t st);
 
 }  // namespace sgt

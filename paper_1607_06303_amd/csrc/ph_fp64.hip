@@ -119,151 +119,6 @@ __device__ inline GroupSigns group_signs(const int8_t *s, int g0, int lim)
 enum KKind { K_MID = 0, K_SPEC_I = 1, K_SPEC_J = 2 };
 
 // ---------------------------------------------------------------------------
-// Right-hand sides of diagonal D, real FP64, 64 x 64 blocks.  Wave w owns the
-// 32 x 32 quarter (w / 2, w % 2) as 2 x 2 MFMA pieces of 16 x 16.
-// Block (I, J) = (I0 + blockIdx.x, I + D); blockIdx.y is the K split.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_gemm_r64(const double *__restrict__ T, int64_t ldt,
-                                                       const double *__restrict__ U, int64_t ldu,
-                                                       int64_t n, const int8_t *__restrict__ sgn,
-                                                       int D, int I0, int nsplit,
-                                                       double *__restrict__ Z)
-{
-    constexpr int TB = 64, KC = 16, LDB = TB + 1;
-    __shared__ double sAU[KC][TB];
-    __shared__ double sAT[KC][TB];
-    __shared__ double sBU[KC][LDB];
-    __shared__ double sBT[KC][LDB];
-    __shared__ int8_t rs[TB], cs[TB];
-    __shared__ int tile_any_x;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int I = I0 + blockIdx.x, J = I + D, split = blockIdx.y;
-    const int64_t r0 = (int64_t)I * TB, c0 = (int64_t)J * TB;
-    const int bj = (int)min((int64_t)TB, n - c0);
-    if (tid < TB) {
-        rs[tid] = sgn[r0 + tid];
-        cs[tid] = tid < bj ? sgn[c0 + tid] : 0;
-    }
-    if (tid == 0) tile_any_x = 0;
-    __syncthreads();
-
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    bool needY[2][2], needX[2][2];
-    bool wave_x = false;
-    {
-        GroupSigns rg[2], cg[2];
-        for (int b = 0; b < 2; ++b) {
-            rg[b] = group_signs(rs, wr + 16 * b, TB);
-            cg[b] = group_signs(cs, wc + 16 * b, bj);
-        }
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                needY[a][b] = (rg[a].pos && cg[b].pos) || (rg[a].neg && cg[b].neg);
-                needX[a][b] = (rg[a].pos && cg[b].neg) || (rg[a].neg && cg[b].pos);
-                wave_x |= needX[a][b];
-            }
-    }
-    if (wave_x && lane == 0) atomicOr(&tile_any_x, 1);
-    __syncthreads();
-    const bool any_x = tile_any_x != 0;
-
-    dx4 accY[2][2], accX[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            accY[a][b] = dx4{0, 0, 0, 0};
-            accX[a][b] = dx4{0, 0, 0, 0};
-        }
-
-    const int nmid = D - 1;
-    const int chunk = (nmid + nsplit - 1) / nsplit;
-    const int kb = I + 1 + split * chunk;
-    const int ke = min(J, kb + chunk);
-    const bool specials = any_x && (split == nsplit - 1);
-
-    // Thread roles for the global -> LDS copies.
-    const int am = tid & 63, akq = tid >> 6;   // A: row am, k = akq + 4t
-    const int bkk = tid & 15, bjq = tid >> 4;  // B: k = bkk, col = bjq + 16t
-
-    auto run = [&](int kind, int K) {
-        // A operand columns / B operand rows in global index space.
-        int64_t acol = 0, brow = 0;
-        int klim = TB;
-        if (kind == K_MID) {
-            acol = (int64_t)K * TB;
-            brow = (int64_t)K * TB;
-        } else if (kind == K_SPEC_I) {
-            acol = r0;  // U_II
-            brow = r0;  // T_IJ
-        } else {
-            acol = c0;  // T_IJ
-            brow = c0;  // U_JJ
-            klim = bj;
-        }
-        for (int k0 = 0; k0 < klim; k0 += KC) {
-            // A tiles
-            for (int kk = akq; kk < KC; kk += 4) {
-                bool ok = (k0 + kk) < klim;
-                int64_t col = acol + k0 + kk;
-                if (kind != K_SPEC_J) sAU[kk][am] = ldg_or_zero(U + (r0 + am) + col * ldu, ok);
-                if ((kind == K_MID && any_x) || kind == K_SPEC_J)
-                    sAT[kk][am] = ldg_or_zero(T + (r0 + am) + col * ldt, ok);
-            }
-            // B tiles
-            for (int j = bjq; j < TB; j += 16) {
-                bool ok = (j < bj) && (k0 + bkk) < klim;
-                int64_t row = brow + k0 + bkk;
-                if (kind != K_SPEC_I) sBU[bkk][j] = ldg_or_zero(U + row + (c0 + j) * ldu, ok);
-                if ((kind == K_MID && any_x) || kind == K_SPEC_I)
-                    sBT[bkk][j] = ldg_or_zero(T + row + (c0 + j) * ldt, ok);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k4 = 0; k4 < KC / 4; ++k4) {
-                const int kr = k4 * 4 + (lane >> 4);
-                double aU[2], aT[2], bU[2], bT[2];
-                for (int a = 0; a < 2; ++a) {
-                    aU[a] = sAU[kr][wr + 16 * a + (lane & 15)];
-                    aT[a] = -sAT[kr][wr + 16 * a + (lane & 15)];
-                    bU[a] = sBU[kr][wc + 16 * a + (lane & 15)];
-                    bT[a] = sBT[kr][wc + 16 * a + (lane & 15)];
-                }
-                for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 2; ++b) {
-                        if (kind == K_MID) {
-                            if (needY[a][b]) accY[a][b] = mfma_f64(aU[a], bU[b], accY[a][b]);
-                            if (needX[a][b]) {
-                                accX[a][b] = mfma_f64(aU[a], bT[b], accX[a][b]);
-                                accX[a][b] = mfma_f64(aT[a], bU[b], accX[a][b]);
-                            }
-                        } else if (kind == K_SPEC_I) {
-                            if (needX[a][b]) accX[a][b] = mfma_f64(aU[a], bT[b], accX[a][b]);
-                        } else {
-                            if (needX[a][b]) accX[a][b] = mfma_f64(aT[a], bU[b], accX[a][b]);
-                        }
-                    }
-            }
-            __syncthreads();
-        }
-    };
-
-    for (int K = kb; K < ke; ++K) run(K_MID, K);
-    if (specials) {
-        run(K_SPEC_I, I);
-        run(K_SPEC_J, J);
-    }
-
-    double *Zt = Z + ((int64_t)blockIdx.x * nsplit + split) * TB * TB;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int r = 0; r < 4; ++r) {
-                int i = wr + 16 * a + mfma64_row(lane, r);
-                int j = wc + 16 * b + (lane & 15);
-                Zt[i * TB + j] = (rs[i] == cs[j]) ? accY[a][b][r] : accX[a][b][r];
-            }
-}
-
-// ---------------------------------------------------------------------------
 // Right-hand sides of diagonal D, complex128, 32 x 32 blocks: wave w owns the
 // 16 x 16 piece (w / 2, w % 2); each complex product is four real MFMAs.
 // ---------------------------------------------------------------------------
@@ -399,20 +254,26 @@ __global__ __launch_bounds__(kThreads) void k_gemm_c128(const cd *__restrict__ T
 // Block solve for diagonal D: each block's own equations (see top of file),
 // entry by entry along anti-diagonals from the bottom-left corner.  Row i of
 // the block is handled by LPR lanes; at step a it owns entry (i, a - (TB-1-i)).
-// Diagonal blocks are kept packed: U_II, T_II row-wise (rows read), U_JJ, T_JJ
-// column-wise (columns read).
+// The right-hand side (the sum of the K-split partial products) is staged in
+// the block's LDS tile and each entry is overwritten by its solution.
+// Diagonal blocks are kept packed: U_II, T_II row-wise (rows are read),
+// U_JJ, T_JJ column-wise (columns are read); index 0 = U, 1 = T.
 // ---------------------------------------------------------------------------
+constexpr int kSolveThreads = 512;
+
 template <typename S, int TB>
-__global__ __launch_bounds__(kThreads) void k_solve(const S *__restrict__ T, int64_t ldt,
-                                                    S *__restrict__ U, int64_t ldu, int64_t n,
-                                                    const int8_t *__restrict__ sgn, int D, int I0,
-                                                    int nsplit, const S *__restrict__ Z)
+__global__ __launch_bounds__(kSolveThreads) void k_solve(const S *__restrict__ T, int64_t ldt,
+                                                         S *__restrict__ U, int64_t ldu, int64_t n,
+                                                         const int8_t *__restrict__ sgn, int D,
+                                                         int I0, int nsplit,
+                                                         const S *__restrict__ Z)
 {
     using tr = scalar_traits<S>;
+    constexpr int NT = kSolveThreads;
     constexpr int LD = TB + 1;
-    constexpr int LPR = kThreads / TB;
+    constexpr int LPR = NT / TB;
     constexpr int P = TB * (TB + 1) / 2;
-    __shared__ S Lu[P], Lt[P], Ru[P], Rt[P];
+    __shared__ S sL[2 * P], sR[2 * P];
     __shared__ S X[TB * LD];
     __shared__ S dI[TB], dJ[TB];
     __shared__ int8_t rs[TB], cs[TB];
@@ -423,17 +284,25 @@ __global__ __launch_bounds__(kThreads) void k_solve(const S *__restrict__ T, int
     const int bj = (int)min((int64_t)TB, n - c0);
     // packed row-major upper: row i starts at i*TB - i*(i-1)/2, entry (i,k) at +k-i
     // packed column-major upper: column j starts at j*(j+1)/2, entry (k,j) at +k
-    for (int e = tid; e < TB * TB; e += kThreads) {
+    for (int e = tid; e < TB * TB; e += NT) {
         int i = e % TB, j = e / TB;
         if (i <= j) {
             int pr = i * TB - (i * (i - 1)) / 2 + (j - i);
-            Lu[pr] = U[(r0 + i) + (r0 + j) * ldu];
-            Lt[pr] = T[(r0 + i) + (r0 + j) * ldt];
+            sL[pr] = U[(r0 + i) + (r0 + j) * ldu];
+            sL[P + pr] = T[(r0 + i) + (r0 + j) * ldt];
             bool in = j < bj;
             int pc = (j * (j + 1)) / 2 + i;
-            Ru[pc] = ldg_or_zero(U + (c0 + i) + (c0 + j) * ldu, in);
-            Rt[pc] = ldg_or_zero(T + (c0 + i) + (c0 + j) * ldt, in);
+            sR[pc] = ldg_or_zero(U + (c0 + i) + (c0 + j) * ldu, in);
+            sR[P + pc] = ldg_or_zero(T + (c0 + i) + (c0 + j) * ldt, in);
         }
+    }
+    // right-hand sides: partial products summed in split order
+    const S *Zb = Z + (int64_t)blockIdx.x * nsplit * TB * TB;
+    for (int e = tid; e < TB * TB; e += NT) {
+        int i = e / TB, j = e % TB;
+        S z = tr::zero();
+        for (int s = 0; s < nsplit; ++s) z = z + Zb[(int64_t)s * TB * TB + e];
+        X[i + j * LD] = z;
     }
     if (tid < TB) {
         rs[tid] = sgn[r0 + tid];
@@ -445,36 +314,47 @@ __global__ __launch_bounds__(kThreads) void k_solve(const S *__restrict__ T, int
 
     const int i = tid / LPR, q = tid % LPR;
     const int rowstart = i * TB - (i * (i - 1)) / 2 - i;  // + k gives (i, k)
-    const S *Zt = Z + (int64_t)blockIdx.x * nsplit * TB * TB + i * TB;
     const int steps = (TB - 1) + bj;
     for (int a = 0; a < steps; ++a) {
         const int j = a - (TB - 1 - i);
         if (j >= 0 && j < bj) {
-            S rhs = tr::zero();
-            if (q == 0)
-                for (int s = 0; s < nsplit; ++s) rhs = rhs + Zt[(int64_t)s * TB * TB + j];
             const bool same = rs[i] == cs[j];
-            const S *L = same ? Lu : Lt;
-            const S *R = same ? Ru : Rt;
+            const int sel = same ? 0 : P;
+            // Y: u = -(rhs + col + row) * s_i / 2;  X: u = (rhs - col + row) / (t_ii - t_jj)
+            const S scale = same ? tr::from_real(-0.5 * (double)rs[i])
+                                 : tr::from_real(1.0) / (dI[i] - dJ[j]);
+            const double csign = same ? 1.0 : -1.0;
             const int colstart = (j * (j + 1)) / 2;
+            // fixed trip counts with predication, so that all LDS loads of a
+            // step are issued back to back
             S col = tr::zero(), row = tr::zero();
-            for (int k = i + 1 + q; k < TB; k += LPR) col = col + L[rowstart + k] * X[k + j * LD];
-            for (int k = q; k < j; k += LPR) row = row + X[i + k * LD] * R[colstart + k];
+            S lv[TB / LPR], xv[TB / LPR];
 #pragma unroll
-            for (int m = 1; m < LPR; m <<= 1) {
-                col = col + tr::shfl_xor(col, m);
-                row = row + tr::shfl_xor(row, m);
+            for (int t = 0; t < TB / LPR; ++t) {
+                const int k = i + 1 + q + t * LPR;
+                const int kk = k < TB ? k : TB - 1;
+                lv[t] = k < TB ? sL[sel + rowstart + kk] : tr::zero();
+                xv[t] = X[kk + j * LD];
             }
-            if (q == 0) {
-                S u;
-                if (same) u = (rhs + col + row) * (-0.5 * (double)rs[i]);
-                else u = (rhs - col + row) / (dI[i] - dJ[j]);
-                X[i + j * LD] = u;
+#pragma unroll
+            for (int t = 0; t < TB / LPR; ++t) col = col + lv[t] * xv[t];
+#pragma unroll
+            for (int t = 0; t < TB / LPR; ++t) {
+                const int k = q + t * LPR;
+                const int kk = k < j ? k : 0;
+                xv[t] = k < j ? X[i + kk * LD] : tr::zero();
+                lv[t] = sR[sel + colstart + kk];
             }
+#pragma unroll
+            for (int t = 0; t < TB / LPR; ++t) row = row + xv[t] * lv[t];
+            S tot = col * csign + row;
+#pragma unroll
+            for (int m = 1; m < LPR; m <<= 1) tot = tot + tr::shfl_xor(tot, m);
+            if (q == 0) X[i + j * LD] = (X[i + j * LD] + tot) * scale;
         }
         __syncthreads();
     }
-    for (int e = tid; e < TB * TB; e += kThreads) {
+    for (int e = tid; e < TB * TB; e += NT) {
         int ii = e % TB, jj = e / TB;
         if (jj < bj) U[(r0 + ii) + (c0 + jj) * ldu] = X[ii + jj * LD];
     }
@@ -492,78 +372,25 @@ int choose_splits(int D, int ntiles, int max_splits, int64_t zslots)
     return s;
 }
 
-// Algorithmic flops (Section 3 counting) of each launch family, from the host
-// signs: a pair (i, j) with i < j costs 2 (equal signs) or 4 (opposite) real
-// flops per k strictly between them; its k are split into those inside blocks
-// I and J (solve kernels) and those in blocks strictly between (products).
-struct FlopCounter {
-    const int8_t *s;
-    int64_t n;
-    int tb;
-    double c;  // 1 real, 4 complex
-
-    void counts(int64_t i0, int len, int64_t &pos, int64_t &neg) const
-    {
-        pos = neg = 0;
-        for (int t = 0; t < len; ++t) (s[i0 + t] > 0 ? pos : neg)++;
-    }
-    double gemm(int D) const
-    {
-        const int64_t nb = (n + tb - 1) / tb;
-        double f = 0.0;
-        for (int64_t I = 0; I + D < nb; ++I) {
-            int64_t J = I + D;
-            int bj = (int)std::min<int64_t>(tb, n - J * tb);
-            int64_t rp, rn, cp, cn;
-            counts(I * tb, tb, rp, rn);
-            counts(J * tb, bj, cp, cn);
-            double same = (double)(rp * cp + rn * cn), opp = (double)(rp * cn + rn * cp);
-            f += (2.0 * same + 4.0 * opp) * (double)tb * (double)(D - 1);
-        }
-        return c * f;
-    }
-    double solve(int D) const
-    {
-        const int64_t nb = (n + tb - 1) / tb;
-        double f = 0.0;
-        for (int64_t I = 0; I + D < nb; ++I) {
-            int64_t J = I + D;
-            int bj = (int)std::min<int64_t>(tb, n - J * tb);
-            for (int i = 0; i < tb; ++i)
-                for (int j = 0; j < bj; ++j) {
-                    double w = (double)((tb - 1 - i) + j);
-                    f += (s[I * tb + i] == s[J * tb + j] ? 2.0 : 4.0) * w;
-                }
-        }
-        return c * f;
-    }
-    double diag() const
-    {
-        double f = 0.0;
-        for (int64_t r0 = 0; r0 < n; r0 += tb) {
-            int bt = (int)std::min<int64_t>(tb, n - r0);
-            for (int j = 0; j < bt; ++j)
-                for (int i = 0; i < j; ++i)
-                    f += (s[r0 + i] == s[r0 + j] ? 2.0 : 4.0) * (double)(j - i - 1);
-        }
-        return c * f;
-    }
-};
-
 }  // namespace
 
-int ph_tile_size(bool cplx) { return cplx ? 32 : 64; }
-
-int64_t ph_zslots(int64_t n, bool cplx)
+int ph_tile_size(bool cplx, int requested)
 {
-    int tb = ph_tile_size(cplx);
+    if (cplx) return 32;
+    return requested == 64 ? 64 : 32;
+}
+
+int64_t ph_zslots(int64_t n, int tb)
+{
     int64_t nb = (n + tb - 1) / tb;
-    return nb + kTargetWorkgroups + 64;
+    return 2 * nb + kTargetWorkgroups + 128;
 }
 
 hipError_t run_ph_fp64(const PhArgs &a, bool cplx, hipStream_t st)
 {
-    const int tb = ph_tile_size(cplx);
+    const int tb = a.tile;
+    if (tb != 32 && tb != 64) return hipErrorInvalidValue;
+    if (cplx && tb != 32) return hipErrorInvalidValue;
     const int64_t nb = (a.n + tb - 1) / tb;
     const bool prof = prof_on() && a.hsgn;
     const FlopCounter fc{a.hsgn, a.n, tb, cplx ? 4.0 : 1.0};
@@ -575,35 +402,46 @@ hipError_t run_ph_fp64(const PhArgs &a, bool cplx, hipStream_t st)
     if (cplx) {
         hipLaunchKernelGGL((k_diag_tiles<cd, 32>), dim3(nb), dim3(kThreads), 0, st,
                            (const cd *)a.T, a.ldt, (cd *)a.U, a.ldu, a.n, a.sgn);
-    } else {
+    } else if (tb == 64) {
         hipLaunchKernelGGL((k_diag_tiles<double, 64>), dim3(nb), dim3(kThreads), 0, st,
+                           (const double *)a.T, a.ldt, (double *)a.U, a.ldu, a.n, a.sgn);
+    } else {
+        hipLaunchKernelGGL((k_diag_tiles<double, 32>), dim3(nb), dim3(kThreads), 0, st,
                            (const double *)a.T, a.ldt, (double *)a.U, a.ldu, a.n, a.sgn);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_end(st, PK_DIAG, prof ? fc.diag() : 0.0);
+    if (!cplx) {
+        RealSweep w;
+        w.T = (const double *)a.T;
+        w.ldt = a.ldt;
+        w.U = (double *)a.U;
+        w.ldu = a.ldu;
+        w.n = a.n;
+        w.sgn = a.sgn;
+        w.zbuf[0] = (double *)a.zbuf;
+        for (int b = 1; b < kLookahead; ++b) w.zbuf[b] = (double *)a.zbufs[b - 1];
+        w.ebuf = (double *)a.ebuf;
+        w.zslots = a.zslots;
+        w.max_splits = a.max_splits;
+        w.tile = tb;
+        w.flops = prof ? &fc : nullptr;
+        w.bulk_nm.assign(nb + 2, 0);
+        return run_ph_real(w, st);
+    }
     for (int D = 1; D < nb; ++D) {
         const int ntiles = (int)(nb - D);
+        // ns K slices, the diagonal-block terms in the last one
         const int ns = (D == 1) ? 1 : choose_splits(D, ntiles, a.max_splits, a.zslots);
         prof_begin(st);
-        if (cplx)
-            hipLaunchKernelGGL(k_gemm_c128, dim3(ntiles, ns), dim3(kThreads), 0, st,
-                               (const cd *)a.T, a.ldt, (const cd *)a.U, a.ldu, a.n, a.sgn, D, 0,
-                               ns, (cd *)a.zbuf);
-        else
-            hipLaunchKernelGGL(k_gemm_r64, dim3(ntiles, ns), dim3(kThreads), 0, st,
-                               (const double *)a.T, a.ldt, (const double *)a.U, a.ldu, a.n,
-                               a.sgn, D, 0, ns, (double *)a.zbuf);
+        hipLaunchKernelGGL(k_gemm_c128, dim3(ntiles, ns), dim3(kThreads), 0, st, (const cd *)a.T,
+                           a.ldt, (const cd *)a.U, a.ldu, a.n, a.sgn, D, 0, ns, (cd *)a.zbuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        prof_end(st, PK_GEMM, prof ? fc.gemm(D) : 0.0);
+        prof_end(st, PK_GEMM, prof ? fc.per_k_block(D) * (D - 1) : 0.0);
         prof_begin(st);
-        if (cplx)
-            hipLaunchKernelGGL((k_solve<cd, 32>), dim3(ntiles), dim3(kThreads), 0, st,
-                               (const cd *)a.T, a.ldt, (cd *)a.U, a.ldu, a.n, a.sgn, D, 0, ns,
-                               (const cd *)a.zbuf);
-        else
-            hipLaunchKernelGGL((k_solve<double, 64>), dim3(ntiles), dim3(kThreads), 0, st,
-                               (const double *)a.T, a.ldt, (double *)a.U, a.ldu, a.n, a.sgn, D,
-                               0, ns, (const double *)a.zbuf);
+        hipLaunchKernelGGL((k_solve<cd, 32>), dim3(ntiles), dim3(kSolveThreads), 0, st,
+                           (const cd *)a.T, a.ldt, (cd *)a.U, a.ldu, a.n, a.sgn, D, 0, ns,
+                           (const cd *)a.zbuf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         prof_end(st, PK_SOLVE, prof ? fc.solve(D) : 0.0);
     }

@@ -202,3 +202,18 @@ def test_workspace_argument(dev):
 def test_workload1_full(dev):
     """512 x 512 real, interleaved inertia: whole matrix against the oracle."""
     check(wl.workload1(), dev)
+
+
+@pytest.mark.parametrize("tile", [32, 64])
+@pytest.mark.parametrize("n", [63, 64, 65, 200, 321])
+def test_real_block_sizes(dev, n, tile):
+    rng = np.random.default_rng(5000 + n + tile)
+    _, info, _ = check(wl.make_T(n, rng), dev, options={"tile": tile})
+    assert info["tile"] == tile
+
+
+@pytest.mark.parametrize("tile", [32, 64])
+def test_real_skewed_block_sizes(dev, tile):
+    rng = np.random.default_rng(5100 + tile)
+    s = wl.signs_with_negatives(700, 6, rng)
+    check(wl.make_T(700, rng, signs=s), dev, options={"tile": tile})
