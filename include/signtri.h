@@ -33,7 +33,11 @@
  *   - Work is queued on `stream` (a hipStream_t; NULL means the default
  *     stream).  Single-matrix calls synchronise the stream once, after a
  *     device scan of the diagonal, to plan the work; the result in U is ready
- *     when the stream has been synchronised again.
+ *     when the stream has been synchronised again.  Calls that also wait for
+ *     their result before returning: MIXED_REFINED (its convergence test runs
+ *     on the host), and any real call with a non-NULL `info` (it then also
+ *     reports SIGNTRI_EHIP if a dependency wait of the dataflow sweep hit its
+ *     safety bound, which does not happen in a correct run).
  *   - Return codes: 0 on success; -p if argument p (1-based) is invalid;
  *     positive SIGNTRI_E* codes below.  On any nonzero return, U is untouched
  *     except after SIGNTRI_EHIP (a device error mid-computation).
@@ -94,13 +98,20 @@ typedef struct {
 
 /* Tunables; zero-initialise for defaults. */
 typedef struct {
-    int32_t tile;                /* block size: 0 = default                                */
-    int32_t max_refine_steps;    /* mixed mode: 0 = default (1)                            */
-    double stall_ratio;          /* mixed mode: a block stalls when its correction exceeds
-                                    this fraction of its largest |u| (0 = default 1e-3)  */
+    int32_t tile;                /* block size: 0 = default (32); 64 selects, for real FP64
+                                    only, the two-stream superdiagonal sweep             */
+    int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2)   */
+    double stall_ratio;          /* mixed mode: a block stalls when a step leaves its
+                                    residual above this fraction of the previous one
+                                    (0 = default 0.5)                                    */
     int32_t no_fallback;         /* mixed mode: 1 = return SIGNTRI_ENOCONV instead of
                                     recomputing stalled blocks in FP64                   */
-    int32_t max_splits;          /* split-K limit for block products (0 = default)          */
+    int32_t max_splits;          /* split-K limit for block products of the superdiagonal
+                                    sweeps (0 = default)                                 */
+    int64_t force_stall;         /* testing: treat block (I, J) of the 32 x 32 grid as
+                                    stalled when this is 1 + I * nb + J (nb = block count
+                                    of the row index space), every block when -1, none
+                                    when 0                                               */
 } signtri_options;
 
 /*
@@ -111,8 +122,9 @@ typedef struct {
  *   dtype       SIGNTRI_R64 or SIGNTRI_C128
  *   layout      storage order of both T and U
  *   mode        SIGNTRI_FP64, SIGNTRI_MIXED_REFINED or SIGNTRI_FP32
- *   algo        SIGNTRI_AUTO, SIGNTRI_PH or SIGNTRI_PS (PS requires a diagonal
- *               already grouped by sign, else SIGNTRI_ENOTSUP)
+ *   algo        SIGNTRI_AUTO, SIGNTRI_PH or SIGNTRI_PS (PS requires a real T
+ *               whose diagonal is already grouped by sign, else SIGNTRI_ENOTSUP)
+ *   Complex T supports mode SIGNTRI_FP64 only in this build (else SIGNTRI_ENOTSUP).
  *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
  *               use a buffer it allocates and keeps for later calls
  *   stream      hipStream_t to queue work on (NULL = default stream)
@@ -129,8 +141,8 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n,
 
 /* Bytes of device workspace signtri() needs for these arguments (an upper
  * bound valid for any diagonal).  Returns 0 for invalid arguments. */
-size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_mode mode,
-                              signtri_algo algo);
+size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout layout,
+                              signtri_mode mode, signtri_algo algo);
 
 /*
  * Batched form: U_b = sign(T_b) for b = 0 .. batch-1, matrices of uneven
@@ -187,18 +199,17 @@ void signtri_release(void);
  * Returns 0, -1 for an unknown family, or SIGNTRI_EHIP.
  */
 enum {
-    SIGNTRI_K_SCAN = 0,        /* diagonal scan                                  */
-    SIGNTRI_K_DIAG = 1,        /* diagonal blocks, element by element            */
-    SIGNTRI_K_GEMM = 2,        /* block products of the substitution             */
-    SIGNTRI_K_SOLVE = 3,       /* off-diagonal block equations                   */
-    SIGNTRI_K_AUX = 4,         /* zeroing and +-I fills                          */
-    SIGNTRI_K_RESID = 5,       /* FP64 residuals of refinement                   */
-    SIGNTRI_K_CORR_GEMM = 6,   /* block products of the correction solve         */
-    SIGNTRI_K_CORR_SOLVE = 7,  /* block equations of the correction solve        */
-    SIGNTRI_K_SYL_GEMM = 8,    /* Sylvester block products                       */
-    SIGNTRI_K_SYL_SOLVE = 9,   /* Sylvester block equations                      */
-    SIGNTRI_K_BATCHED = 10,    /* batched persistent kernel                      */
-    SIGNTRI_K_CONVERT = 11     /* precision and layout conversions               */
+    SIGNTRI_K_SCAN = 0,        /* diagonal scan                                       */
+    SIGNTRI_K_DIAG = 1,        /* diagonal blocks, element by element                 */
+    SIGNTRI_K_GEMM = 2,        /* block products of the superdiagonal sweeps          */
+    SIGNTRI_K_SOLVE = 3,       /* block equations of the superdiagonal sweeps         */
+    SIGNTRI_K_AUX = 4,         /* zeroing, fills, task lists                          */
+    SIGNTRI_K_RESID = 5,       /* FP64 residuals of refinement                        */
+    SIGNTRI_K_CORR = 6,        /* correction sweep of refinement (products + solves)  */
+    SIGNTRI_K_SYL = 7,         /* Sylvester dataflow sweep (products + solves)        */
+    SIGNTRI_K_FLOW = 8,        /* Parlett-Higham dataflow sweep (products + solves)   */
+    SIGNTRI_K_BATCHED = 9,     /* batched persistent sweep                            */
+    SIGNTRI_K_CONVERT = 10     /* precision and layout conversions                    */
 };
 void signtri_profile_enable(int on);
 int signtri_profile_read(int family, double *ms, int64_t *launches, double *flops);

@@ -14,13 +14,19 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t scan = 0, sgn = 0, zbuf = 0, zbufs[2] = {0, 0}, ebuf = 0, total = 0;
+    size_t scan = 0, sgn = 0, dg = 0, flow = 0, tcopy = 0, ucopy = 0;
+    size_t zbuf = 0, zbufs[2] = {0, 0}, ebuf = 0, total = 0;
     int64_t zslots = 0;
+    bool flow_path = false;  // real, 32 x 32 blocks: the dataflow sweeps
 };
 
-Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo, int tb)
+// Real matrices run the dataflow sweeps (32 x 32 blocks) unless the two-stream
+// 64 x 64 sweep is requested; complex matrices run the superdiagonal sweep.
+bool uses_flow(signtri_dtype dtype, int tb) { return dtype == SIGNTRI_R64 && tb == 32; }
+
+Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
+                  signtri_algo algo, int tb)
 {
-    (void)mode;
     (void)algo;
     const bool cplx = dtype == SIGNTRI_C128;
     const size_t es = cplx ? 16 : 8;
@@ -30,27 +36,47 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_alg
     off += align_up(sizeof(ScanResult));
     L.sgn = off;
     off += align_up((size_t)std::max<int64_t>(n, 1));
-    L.zslots = ph_zslots(n, tb);
-    L.zbuf = off;
-    off += align_up((size_t)L.zslots * tb * tb * es);
-    if (!cplx) {
-        static_assert(kLookahead - 1 <= 2, "bulk buffer count");
-        for (int b = 0; b < kLookahead - 1; ++b) {
-            L.zbufs[b] = off;
-            off += align_up((size_t)L.zslots * tb * tb * es);
+    L.dg = off;
+    off += align_up((size_t)std::max<int64_t>(n, 1) * sizeof(double));
+    L.flow_path = uses_flow(dtype, tb);
+    if (L.flow_path) {
+        size_t fb = 0;
+        (void)flow_ws_layout(nullptr, n, mode != SIGNTRI_FP64, &fb);
+        L.flow = off;
+        off += align_up(fb);
+    } else {
+        L.zslots = ph_zslots(n, tb);
+        L.zbuf = off;
+        off += align_up((size_t)L.zslots * tb * tb * es);
+        if (!cplx) {
+            static_assert(kLookahead - 1 <= 2, "bulk buffer count");
+            for (int b = 0; b < kLookahead - 1; ++b) {
+                L.zbufs[b] = off;
+                off += align_up((size_t)L.zslots * tb * tb * es);
+            }
+            L.ebuf = off;
+            off += align_up((size_t)ph_real_edge_slots(n, tb) * tb * tb * es);
         }
-        L.ebuf = off;
-        off += align_up((size_t)ph_real_edge_slots(n, tb) * tb * tb * es);
+    }
+    if (layout == SIGNTRI_ROW_MAJOR) {
+        // column-major copies of T and U (leading dimension n)
+        const size_t mat = (size_t)std::max<int64_t>(n, 1) * std::max<int64_t>(n, 1) * es;
+        L.tcopy = off;
+        off += align_up(mat);
+        L.ucopy = off;
+        off += align_up(mat);
     }
     L.total = off;
     return L;
 }
 
 // Workspace valid for every block size the call may choose.
-size_t max_total(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
+                 signtri_algo algo)
 {
-    size_t m = layout_for(n, dtype, mode, algo, 32).total;
-    if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, mode, algo, 64).total);
+    size_t m = layout_for(n, dtype, layout, mode, algo, 32).total;
+    if (dtype == SIGNTRI_R64 && mode == SIGNTRI_FP64)
+        m = std::max(m, layout_for(n, dtype, layout, mode, algo, 64).total);
     return m;
 }
 
@@ -195,6 +221,29 @@ hipError_t launch_ph(const PhArgs &a, bool cplx, hipStream_t st, int device)
     return hipGraphLaunch(exec, st);
 }
 
+// Algorithmic flops of the dataflow launches (Section 3 counting, real).
+SweepFlops sweep_flops(const int8_t *s, int64_t n, const HostPlan &p)
+{
+    SweepFlops f;
+    const FlopCounter fc{s, n, kFlowTile, 1.0};
+    f.diag = fc.diag();
+    f.flow = p.w_ph - f.diag;
+    const double dn = (double)n, np = (double)p.n_pos, nn = (double)p.n_neg;
+    // correction sweep: two products (4 flops) per k strictly between i and j,
+    // off the diagonal blocks
+    double cdiag = 0.0;
+    for (int64_t r0 = 0; r0 < n; r0 += kFlowTile) {
+        const double b = (double)std::min<int64_t>(kFlowTile, n - r0);
+        cdiag += b * (b - 1) * (b - 2) / 6.0;
+    }
+    f.corr = 4.0 * (dn * (dn - 1) * (dn - 2) / 6.0 - cdiag);
+    // residual: k = i .. j, i.e. two more terms per entry than the sweep
+    f.resid = f.flow + 2.0 * (2.0 * dn * (dn - 1) / 2.0 + 2.0 * np * nn);
+    // Sylvester: (p - 1 - i) + (j - p) multiply-adds per entry of X
+    f.syl = np * nn * (dn - 2.0);
+    return f;
+}
+
 void fill_info(signtri_info *info, const HostPlan &p)
 {
     if (!info) return;
@@ -227,13 +276,15 @@ const char *signtri_strerror(int code)
     return "unknown error code";
 }
 
-size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_mode mode, signtri_algo algo)
+size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout layout,
+                              signtri_mode mode, signtri_algo algo)
 {
     if (n < 0) return 0;
     if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return 0;
+    if (layout != SIGNTRI_COL_MAJOR && layout != SIGNTRI_ROW_MAJOR) return 0;
     if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
     if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return 0;
-    return max_total(n, dtype, mode, algo);
+    return max_total(n, dtype, layout, mode, algo);
 }
 
 int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype, signtri_info *info)
@@ -268,28 +319,46 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     const bool cplx = dtype == SIGNTRI_C128;
     const size_t es = cplx ? 16 : 8;
     if (n > 0 && ranges_overlap(T, extent_bytes(n, ldt, es), U, extent_bytes(n, ldu, es))) return -3;
-    if (n == 0) return SIGNTRI_OK;
-    if (layout != SIGNTRI_COL_MAJOR || mode != SIGNTRI_FP64) return SIGNTRI_ENOTSUP;
-
     if (opts && opts->tile != 0 && opts->tile != 32 && opts->tile != 64) return -13;
-    const int tb = ph_tile_size(cplx, opts ? opts->tile : 0);
-    const Layout L = layout_for(n, dtype, mode, algo, tb);
+    if (n == 0) return SIGNTRI_OK;
+    if (cplx && mode != SIGNTRI_FP64) return SIGNTRI_ENOTSUP;
+
+    int tb = ph_tile_size(cplx, opts ? opts->tile : 0);
+    if (mode != SIGNTRI_FP64) tb = 32;  // reduced precision runs on the dataflow sweeps
+    const Layout L = layout_for(n, dtype, layout, mode, algo, tb);
+    const size_t need = max_total(n, dtype, layout, mode, algo);
     if (workspace) {
-        if (ws_bytes < max_total(n, dtype, mode, algo)) return SIGNTRI_EWORKSPACE;
+        if (ws_bytes < need) return SIGNTRI_EWORKSPACE;
     } else {
-        int rc = owned_workspace(max_total(n, dtype, mode, algo), &workspace);
+        int rc = owned_workspace(need, &workspace);
         if (rc != SIGNTRI_OK) return rc;
     }
     void *hostbuf = nullptr;
-    size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n);
+    const size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n) +
+                              (L.flow_path ? flow_host_bytes(n) : 0);
     if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
+    char *hb = (char *)hostbuf;
+    void *hflow = hb + align_up(sizeof(ScanResult)) + align_up((size_t)n);
 
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
     ScanResult *scan = (ScanResult *)(ws + L.scan);
     int8_t *sgn = (int8_t *)(ws + L.sgn);
-    if (launch_scan(T, ldt, n, cplx, sgn, scan, st) != hipSuccess) return SIGNTRI_EHIP;
-    char *hb = (char *)hostbuf;
+    double *dg = (double *)(ws + L.dg);
+
+    // row-major arguments run on column-major copies
+    const void *Tc = T;
+    void *Uc = U;
+    int64_t ldtc = ldt, lduc = ldu;
+    if (layout == SIGNTRI_ROW_MAJOR) {
+        Tc = ws + L.tcopy;
+        Uc = ws + L.ucopy;
+        ldtc = lduc = n;
+        if (launch_transpose(T, ldt, (void *)Tc, n, n, cplx, st) != hipSuccess) return SIGNTRI_EHIP;
+    }
+
+    if (launch_scan(Tc, ldtc, n, cplx, sgn, cplx ? nullptr : dg, scan, st) != hipSuccess)
+        return SIGNTRI_EHIP;
     // scan result and signs are adjacent in the workspace: one copy
     if (hipMemcpyAsync(hb, ws + L.scan, L.sgn - L.scan + (size_t)n, hipMemcpyDeviceToHost, st) !=
         hipSuccess)
@@ -311,17 +380,39 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         if (p.ps_sign == 0) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PS;
     }
-    if (path == SIGNTRI_PATH_PS) path = SIGNTRI_PATH_PH;  // sign-split solver arrives later
+    if (path == SIGNTRI_PATH_PS && !L.flow_path) {
+        if (algo == SIGNTRI_PS) return SIGNTRI_ENOTSUP;
+        path = SIGNTRI_PATH_PH;  // the Sylvester form runs on the real dataflow sweeps
+    }
 
+    int rc = SIGNTRI_OK;
     hipError_t e = hipSuccess;
+    bool waited = false;
+    FlowWs fw{};
+    if (L.flow_path) fw = flow_ws_layout(ws + L.flow, n, mode != SIGNTRI_FP64, nullptr);
     if (path == SIGNTRI_PATH_TRIVIAL) {
-        e = launch_fill_pm_identity(U, ldu, n, cplx, p.n_pos > 0 ? 1.0 : -1.0, st);
+        e = launch_fill_pm_identity(Uc, lduc, n, cplx, p.n_pos > 0 ? 1.0 : -1.0, st);
+    } else if (L.flow_path) {
+        const double *Td = (const double *)Tc;
+        double *Ud = (double *)Uc;
+        const int64_t split = path == SIGNTRI_PATH_PS ? p.split : 0;
+        const SweepFlops fl = prof_on() ? sweep_flops(hs, n, p) : SweepFlops();
+        if (mode == SIGNTRI_FP64) {
+            if (path == SIGNTRI_PATH_PS)
+                e = sweep_ps_fp64(Td, ldtc, Ud, lduc, n, split, p.ps_sign, dg, fw, fl, st);
+            else
+                e = sweep_ph_fp64(Td, ldtc, Ud, lduc, n, sgn, dg, fw, fl, st);
+        } else {
+            rc = sweep_mixed(Td, ldtc, Ud, lduc, n, sgn, dg, split, p.ps_sign,
+                             mode == SIGNTRI_MIXED_REFINED, opts, fw, hflow, fl, st, info);
+            waited = mode == SIGNTRI_MIXED_REFINED;
+        }
     } else {
         PhArgs a;
-        a.T = T;
-        a.ldt = ldt;
-        a.U = U;
-        a.ldu = ldu;
+        a.T = Tc;
+        a.ldt = ldtc;
+        a.U = Uc;
+        a.ldu = lduc;
         a.n = n;
         a.sgn = sgn;
         a.zbuf = ws + L.zbuf;
@@ -337,6 +428,18 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         e = launch_ph(a, cplx, st, device);
     }
     if (e != hipSuccess) return SIGNTRI_EHIP;
+    if (rc != SIGNTRI_OK) return rc;
+    if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    // with info requested, wait and report a dependency-wait timeout of the sweep
+    if (info && L.flow_path && path != SIGNTRI_PATH_TRIVIAL && !waited) {
+        int *herr = (int *)hflow;
+        if (hipMemcpyAsync(herr, fw.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SIGNTRI_EHIP;
+        if (herr[1]) return SIGNTRI_EHIP;
+    }
     if (info) {
         info->path = path;
         info->tile = path == SIGNTRI_PATH_TRIVIAL ? 0 : tb;
@@ -359,7 +462,7 @@ size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch, signtri_d
     size_t m = 0;
     for (int64_t b = 0; b < batch; ++b) {
         if (n[b] < 0) return 0;
-        m = std::max(m, signtri_workspace_size(n[b], dtype, mode, SIGNTRI_AUTO));
+        m = std::max(m, signtri_workspace_size(n[b], dtype, SIGNTRI_COL_MAJOR, mode, SIGNTRI_AUTO));
     }
     return m;
 }

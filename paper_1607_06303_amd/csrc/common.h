@@ -153,18 +153,17 @@ HostPlan plan_from_signs(const int8_t *s, int64_t n, bool is_complex);
 // algorithmic flops (Section 3 counting) of the work it does.
 // ---------------------------------------------------------------------------
 enum ProfKind {
-    PK_SCAN = 0,
-    PK_DIAG = 1,
-    PK_GEMM = 2,
-    PK_SOLVE = 3,
-    PK_AUX = 4,
-    PK_RESID = 5,
-    PK_CORR_GEMM = 6,
-    PK_CORR_SOLVE = 7,
-    PK_SYL_GEMM = 8,
-    PK_SYL_SOLVE = 9,
-    PK_BATCHED = 10,
-    PK_CONVERT = 11,
+    PK_SCAN = SIGNTRI_K_SCAN,
+    PK_DIAG = SIGNTRI_K_DIAG,
+    PK_GEMM = SIGNTRI_K_GEMM,
+    PK_SOLVE = SIGNTRI_K_SOLVE,
+    PK_AUX = SIGNTRI_K_AUX,
+    PK_RESID = SIGNTRI_K_RESID,
+    PK_CORR = SIGNTRI_K_CORR,
+    PK_SYL = SIGNTRI_K_SYL,
+    PK_FLOW = SIGNTRI_K_FLOW,
+    PK_BATCHED = SIGNTRI_K_BATCHED,
+    PK_CONVERT = SIGNTRI_K_CONVERT,
     PK_COUNT = 16
 };
 bool prof_on();
@@ -174,11 +173,13 @@ void prof_end(hipStream_t st, int kind, double flops);
 // ---------------------------------------------------------------------------
 // Launchers (each in its own translation unit).
 // ---------------------------------------------------------------------------
-hipError_t launch_scan(const void *T, int64_t ldt, int64_t n, bool cplx, int8_t *sgn,
+hipError_t launch_scan(const void *T, int64_t ldt, int64_t n, bool cplx, int8_t *sgn, double *dg,
                        ScanResult *res, hipStream_t st);
 hipError_t launch_zero_lower(void *U, int64_t ldu, int64_t n, bool cplx, hipStream_t st);
 hipError_t launch_fill_pm_identity(void *U, int64_t ldu, int64_t n, bool cplx, double s,
                                    hipStream_t st);
+hipError_t launch_transpose(const void *src, int64_t lds, void *dst, int64_t ldd, int64_t n,
+                            bool cplx, hipStream_t st);
 
 // Parlett-Higham block sweep, FP64 (real: tile 64, complex: tile 32).
 struct PhArgs {
@@ -296,6 +297,105 @@ hipError_t launch_wave_gemm(int tb, const F *T, int64_t ldt, const F *U, int64_t
                             F *Z, hipStream_t st);
 int wave_gemm_mid_splits(int D, int L, int ntiles, int max_splits, int64_t zslots);
 int wave_gemm_edge_slices(int D, int L);
+
+// ---------------------------------------------------------------------------
+// Persistent dataflow sweep (flow.hip): 32 x 32 blocks, one workgroup per block
+// task, completion flags between tasks.
+// ---------------------------------------------------------------------------
+constexpr int kFlowTile = 32;
+enum FlowKind { FLOW_MAIN = 0, FLOW_CORR = 1, FLOW_SYL = 2 };
+
+// One real triangular system of a sweep; column-major device arrays.
+//   MAIN: V = U (its diagonal blocks already computed), products of V and T.
+//   CORR: V holds the residual on entry and the correction E on exit; C = U0.
+//   SYL:  the unknown X = V(0:split, split:n), A = T(0:split, 0:split),
+//         B = T(split:n, split:n), right-hand side rhs_scale * Rh(0:split, split:n)
+//         (Rh = T for the Parlett-Sylvester equation, a residual for its correction).
+template <typename F> struct FlowMat {
+    const F *T;
+    int64_t ldt;
+    const F *C;
+    int64_t ldc;
+    F *V;
+    int64_t ldv;
+    const F *Rh;
+    int64_t ldrh;
+    const double *dg;    // FP64 diagonal of T (n entries)
+    const int8_t *sgn;   // sign(Re t_ii) as +1 / -1 (n entries)
+    int n;
+    int split;           // SYL: order of T11
+    int nbr, nbc;        // blocks in the row and column index spaces of the unknown
+    int64_t flag0;       // this matrix's first completion flag (flags are I * nbc + J)
+    double rhs_scale;    // SYL: 2 s
+};
+template <typename F> struct FlowArgs {
+    FlowMat<F> m0;             // the matrix, when mats is null
+    const FlowMat<F> *mats;    // per-matrix table (batched), or null
+    const int2 *tasks;         // (matrix, I << 16 | J) in dependency order
+    int ntasks;
+    int *ctrl;                 // [0] ticket counter, [1] error word (both zeroed before)
+    int *flags;                // completion flags (zeroed before, or 1 for blocks not recomputed)
+    int spin_limit;            // polls before a wait gives up and sets the error word
+};
+template <typename F, int KIND>
+hipError_t launch_flow(const FlowArgs<F> &a, int grid, hipStream_t st);
+hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
+hipError_t launch_tasks_tri(int nb, int mat, int2 *out, hipStream_t st);
+hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t st);
+hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const int64_t *flag0,
+                                   const int *nbc, int *flags, hipStream_t st);
+
+// Device workspace of the dataflow paths (sweep.hip): control words, flags,
+// task lists and, for the reduced-precision modes, FP32 copies (leading
+// dimension ld32) and per-block residual norms.
+struct FlowWs {
+    int *ctrl;
+    unsigned long long *maxes;  // max |t|, max |u|, max |correction|
+    int *flags;
+    int2 *tasks, *ftasks;
+    double *norms[2];
+    float *T32, *U32, *E32;
+    int64_t ld32;
+};
+FlowWs flow_ws_layout(char *base, int64_t n, bool mixed, size_t *total);
+// Algorithmic flops of the launches of one call (Section 3 counting), for the
+// opt-in kernel timers; all zero when the timers are off.
+struct SweepFlops {
+    double diag = 0, flow = 0, corr = 0, resid = 0, syl = 0;
+};
+size_t flow_host_bytes(int64_t n);
+hipError_t sweep_ph_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
+                         const int8_t *sgn, const double *dg, const FlowWs &w,
+                         const SweepFlops &fl, hipStream_t st);
+hipError_t sweep_ps_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
+                         int64_t p, int s, const double *dg, const FlowWs &w,
+                         const SweepFlops &fl, hipStream_t st);
+int sweep_mixed(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
+                const int8_t *sgn, const double *dg, int64_t p, int s, bool refine,
+                const signtri_options *opts, const FlowWs &w, void *host,
+                const SweepFlops &fl, hipStream_t st, signtri_info *info);
+
+// refine.hip
+hipError_t launch_to_f32(const double *T, int64_t ldt, float *T32, const double *U, int64_t ldu,
+                         float *U32, int64_t ld32, int64_t n, unsigned long long *tmax,
+                         hipStream_t st);
+hipError_t launch_widen(const float *U32, int64_t ld32, double *U, int64_t ldu, int64_t n,
+                        int64_t split, unsigned long long *umax, hipStream_t st);
+hipError_t launch_add_correction(const float *E, int64_t lde, double *U, int64_t ldu, int64_t n,
+                                 int64_t split, unsigned long long *emax, hipStream_t st);
+hipError_t launch_resid(const double *T, int64_t ldt, const double *U, int64_t ldu,
+                        const int8_t *sgn, int64_t n, const int2 *tasks, int ntasks, float *R,
+                        int64_t ldr, double *norm2, hipStream_t st);
+hipError_t launch_resid_syl(const double *T, int64_t ldt, const double *U, int64_t ldu, int64_t n,
+                            int64_t p, double two_s, const int2 *tasks, int ntasks, int nbr,
+                            int nbc, float *R, int64_t ldr, double *norm2, hipStream_t st);
+
+// Diagonal 32 x 32 blocks of a real U in FP64 (Algorithm 3 per block).
+hipError_t launch_diag_blocks(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
+                              const int8_t *sgn, hipStream_t st);
+// U = diag(s I_p, -s I_{n-p}), zeros elsewhere (real).
+hipError_t launch_fill_split_identity(double *U, int64_t ldu, int64_t n, int64_t p, double s,
+                                      hipStream_t st);
 
 // block size used for a request (0 = default), and bulk partial-sum slots
 int ph_tile_size(bool cplx, int requested);

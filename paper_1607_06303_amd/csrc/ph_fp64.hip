@@ -386,6 +386,16 @@ int64_t ph_zslots(int64_t n, int tb)
     return 2 * nb + kTargetWorkgroups + 128;
 }
 
+hipError_t launch_diag_blocks(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
+                              const int8_t *sgn, hipStream_t st)
+{
+    const int64_t nb = (n + 31) / 32;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_diag_tiles<double, 32>), dim3(nb), dim3(kThreads), 0, st, T, ldt, U, ldu,
+                       n, sgn);
+    return hipGetLastError();
+}
+
 hipError_t run_ph_fp64(const PhArgs &a, bool cplx, hipStream_t st)
 {
     const int tb = a.tile;

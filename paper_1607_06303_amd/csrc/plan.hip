@@ -8,9 +8,10 @@ namespace sgt {
 
 // One workgroup reads the diagonal, records sign(Re t_ii) as +1/-1 (Section 1),
 // the first index whose sign is undefined (zero or non-finite entry), and the
-// number of positive signs.
+// number of positive signs; optionally the real diagonal itself.
 __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int64_t ldt,
                                                int64_t n, int cplx, int8_t *__restrict__ sgn,
+                                               double *__restrict__ dg,
                                                ScanResult *__restrict__ res)
 {
     __shared__ unsigned long long bad;
@@ -33,6 +34,7 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
         int s = 0;
         if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
         sgn[i] = (int8_t)s;
+        if (dg) dg[i] = re;  // the divisors t_ii - t_jj of the real sweeps, in FP64
         if (s == 0) atomicMin(&bad, (unsigned long long)i);
         my_pos += (s > 0);
     }
@@ -44,11 +46,11 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
     }
 }
 
-hipError_t launch_scan(const void *T, int64_t ldt, int64_t n, bool cplx, int8_t *sgn,
+hipError_t launch_scan(const void *T, int64_t ldt, int64_t n, bool cplx, int8_t *sgn, double *dg,
                        ScanResult *res, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const double *)T, ldt, n,
-                       cplx ? 1 : 0, sgn, res);
+                       cplx ? 1 : 0, sgn, dg, res);
     return hipGetLastError();
 }
 

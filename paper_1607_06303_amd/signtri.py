@@ -24,8 +24,7 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
            "signtri_profile_read")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
-            "corr_gemm": 6, "corr_solve": 7, "syl_gemm": 8, "syl_solve": 9,
-            "batched": 10, "convert": 11}
+            "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10}
 
 
 class Info(ctypes.Structure):
@@ -49,7 +48,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("tile", ctypes.c_int32), ("max_refine_steps", ctypes.c_int32),
         ("stall_ratio", ctypes.c_double), ("no_fallback", ctypes.c_int32),
-        ("max_splits", ctypes.c_int32),
+        ("max_splits", ctypes.c_int32), ("force_stall", ctypes.c_int64),
     ]
 
 
@@ -77,7 +76,7 @@ def lib() -> ctypes.CDLL:
             L.signtri.argtypes = [p, i64, p, i64, i64, i32, i32, i32, i32, p, sz, p,
                                   ctypes.POINTER(Options), ctypes.POINTER(Info)]
             L.signtri.restype = i32
-            L.signtri_workspace_size.argtypes = [i64, i32, i32, i32]
+            L.signtri_workspace_size.argtypes = [i64, i32, i32, i32, i32]
             L.signtri_workspace_size.restype = sz
             L.signtri_batched.argtypes = [ctypes.POINTER(p), ctypes.POINTER(i64), ctypes.POINTER(p),
                                           ctypes.POINTER(i64), ctypes.POINTER(i64), i64, i32, i32,
@@ -107,8 +106,11 @@ def strerror(code: int) -> str:
     return lib().signtri_strerror(int(code)).decode()
 
 
-def workspace_size(n: int, complex_: bool = False, mode: str = "fp64", algo: str = "auto") -> int:
-    return int(lib().signtri_workspace_size(n, C128 if complex_ else R64, MODES[mode], ALGOS[algo]))
+def workspace_size(n: int, complex_: bool = False, mode: str = "fp64", algo: str = "auto",
+                   row_major: bool = False) -> int:
+    return int(lib().signtri_workspace_size(n, C128 if complex_ else R64,
+                                            ROW_MAJOR if row_major else COL_MAJOR, MODES[mode],
+                                            ALGOS[algo]))
 
 
 def plan_host(signs, complex_: bool = False) -> dict:

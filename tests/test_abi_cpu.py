@@ -40,8 +40,12 @@ def test_workspace_size():
     b = signtri.workspace_size(8192)
     c = signtri.workspace_size(4096, complex_=True)
     assert 0 < a < b and c > 0
-    assert signtri.lib().signtri_workspace_size(-1, 0, 0, 0) == 0
-    assert signtri.lib().signtri_workspace_size(10, 7, 0, 0) == 0
+    assert signtri.lib().signtri_workspace_size(-1, 0, 0, 0, 0) == 0
+    assert signtri.lib().signtri_workspace_size(10, 7, 0, 0, 0) == 0
+    assert signtri.lib().signtri_workspace_size(10, 0, 5, 0, 0) == 0
+    # mixed precision keeps FP32 copies; row-major keeps column-major copies
+    assert signtri.workspace_size(4096, mode="mixed") > signtri.workspace_size(4096)
+    assert signtri.workspace_size(4096, row_major=True) > signtri.workspace_size(4096)
 
 
 def _call(T, ldt, U, ldu, n, dtype=0, layout=0, mode=0, algo=0, ws=None, wsb=0):

@@ -1,0 +1,178 @@
+"""GPU parity of the dataflow paths against the CPU oracle: mixed precision with
+refinement (1e-11), unrefined FP32 (1e-4), the Parlett-Sylvester form on
+sign-grouped diagonals, row-major arguments, and the FP64 fallback of blocks
+whose refinement stalls (forced from the host through an option).
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06303_amd import workloads as wl
+from tests.conftest import rel_fro
+from tests.test_gpu_parity import TOL_FP64, check, dev, run_gpu, to_dev_colmajor  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-4
+
+
+@pytest.mark.parametrize("n", [2, 31, 33, 65, 200, 321])
+def test_mixed_refined_interleaved(dev, n):
+    rng = np.random.default_rng(6000 + n)
+    _, info, _ = check(wl.make_T(n, rng), dev, mode="mixed")
+    if n > 32:
+        assert info["refine_steps"] >= 1
+    assert info["fallback_tiles"] == 0
+
+
+@pytest.mark.parametrize("n", [130, 400])
+def test_mixed_refined_skewed(dev, n):
+    rng = np.random.default_rng(6100 + n)
+    s = wl.signs_with_negatives(n, 4, rng)
+    _, info, _ = check(wl.make_T(n, rng, signs=s), dev, mode="mixed")
+    assert info["path_name"] == "ph" and info["fallback_tiles"] == 0
+    assert 0.0 < info["correction_rel"] < 1e-4
+
+
+@pytest.mark.parametrize("n", [100, 300])
+def test_fp32_unrefined(dev, n):
+    rng = np.random.default_rng(6200 + n)
+    _, info, err = check(wl.make_T(n, rng), dev, tol=TOL_FP32, mode="fp32")
+    assert info["refine_steps"] == 0
+
+
+def test_fp32_is_less_accurate_than_refined(dev):
+    import oracle
+
+    rng = np.random.default_rng(6250)
+    T = wl.make_T(256, rng)
+    ref = oracle.sign_tri(T)
+    e32 = rel_fro(run_gpu(T, dev, mode="fp32")[0], ref)
+    emx = rel_fro(run_gpu(T, dev, mode="mixed")[0], ref)
+    assert emx <= TOL_FP64 < e32 <= TOL_FP32
+
+
+def grouped(n, n_first, first_sign, rng, cplx=False):
+    s = np.full(n, -first_sign, dtype=float)
+    s[:n_first] = first_sign
+    return wl.make_T(n, rng, complex_=cplx, signs=s)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,p,first", [(64, 32, 1.0), (200, 77, 1.0), (200, 77, -1.0),
+                                       (333, 1, 1.0), (333, 332, -1.0), (300, 150, 1.0)])
+def test_parlett_sylvester(dev, n, p, first, mode):
+    rng = np.random.default_rng(6300 + n + p)
+    T = grouped(n, p, first, rng)
+    U, info, _ = check(T, dev, mode=mode, algo="ps")
+    assert info["path_name"] == "ps"
+    # the diagonal blocks of a sign-grouped sign(T) are exactly +-I
+    assert np.array_equal(U[:p, :p], first * np.eye(p))
+    assert np.array_equal(U[p:, p:], -first * np.eye(n - p))
+
+
+def test_parlett_sylvester_fp32(dev):
+    rng = np.random.default_rng(6350)
+    T = grouped(250, 100, 1.0, rng)
+    _, info, _ = check(T, dev, tol=TOL_FP32, mode="fp32", algo="ps")
+    assert info["path_name"] == "ps"
+
+
+def test_auto_picks_ps_when_grouped_and_cheaper(dev):
+    rng = np.random.default_rng(6400)
+    T = grouped(300, 30, 1.0, rng)  # few negatives: the Sylvester form is far cheaper
+    _, info, _ = check(T, dev)
+    assert info["path_name"] == "ps" and info["model_pick_name"] == "ps"
+
+
+def test_ps_requires_grouped_diagonal(dev):
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(6450)
+    Tg = to_dev_colmajor(wl.make_T(100, rng), dev)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(Tg, algo="ps")
+    assert ei.value.code == 5
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_row_major(dev, cplx, mode):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+    import oracle
+
+    if cplx and mode != "fp64":
+        pytest.skip("complex runs in FP64 only")
+    rng = np.random.default_rng(6500)
+    n, ld = 150, 161
+    T = wl.make_T(n, rng, complex_=cplx)
+    buf = np.zeros((n, ld), dtype=T.dtype)
+    buf[:, :n] = T
+    Tg = torch.from_numpy(buf).to(dev)[:, :n]  # row-major with row stride ld
+    U, info = signtri.sign_tri(Tg, mode=mode)
+    torch.cuda.synchronize()
+    assert U.stride(1) == 1
+    assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_forced_stall_falls_back_everywhere(dev):
+    rng = np.random.default_rng(6600)
+    n = 200
+    nb = (n + 31) // 32
+    _, info, _ = check(wl.make_T(n, rng), dev, mode="mixed", options={"force_stall": -1})
+    assert info["fallback_tiles"] == nb * (nb - 1) // 2
+
+
+def test_forced_stall_one_block_recomputes_its_cone(dev):
+    rng = np.random.default_rng(6700)
+    n = 200
+    nb = (n + 31) // 32
+    I, J = 2, 4
+    _, info, _ = check(wl.make_T(n, rng), dev, mode="mixed",
+                       options={"force_stall": 1 + I * nb + J})
+    # blocks (I', J') with I' <= I and J' >= J read block (I, J)
+    assert info["fallback_tiles"] == (I + 1) * (nb - J)
+
+
+def test_forced_stall_ps_cone(dev):
+    rng = np.random.default_rng(6750)
+    n, p = 300, 130
+    T = grouped(n, p, 1.0, rng)
+    nbr, nbc = (p + 31) // 32, (n - p + 31) // 32
+    I, J = 1, 2
+    _, info, _ = check(T, dev, mode="mixed", algo="ps", options={"force_stall": 1 + I * nbc + J})
+    assert info["fallback_tiles"] == (I + 1) * (nbc - J)
+
+
+def test_no_fallback_reports_nonconvergence(dev):
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(6800)
+    Tg = to_dev_colmajor(wl.make_T(120, rng), dev)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(Tg, mode="mixed", options={"force_stall": -1, "no_fallback": 1})
+    assert ei.value.code == 4
+
+
+def test_complex_mixed_not_supported(dev):
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(6900)
+    Tg = to_dev_colmajor(wl.make_T(50, rng, complex_=True), dev)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(Tg, mode="mixed")
+    assert ei.value.code == 5
+
+
+def test_near_singular_divisors_mixed(dev):
+    # small |t_ii - t_jj| for opposite signs: refinement must still reach the bar
+    rng = np.random.default_rng(7000)
+    T = wl.make_T(256, rng, re_range=(1e-3, 1.0))
+    check(T, dev, mode="mixed")
+
+
+def test_repeated_diagonal_mixed(dev):
+    rng = np.random.default_rng(7100)
+    T = wl.schur_like(200, None, rng)
+    check(T, dev, tol=1e-10, mode="mixed")
