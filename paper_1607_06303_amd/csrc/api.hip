@@ -1,5 +1,6 @@
 // C-ABI entry points: argument checks, workspace, planning and dispatch.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -41,7 +42,7 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri
     L.flow_path = uses_flow(dtype, tb);
     if (L.flow_path) {
         size_t fb = 0;
-        (void)flow_ws_layout(nullptr, n, mode != SIGNTRI_FP64, &fb);
+        run_sizes(&n, 1, mode != SIGNTRI_FP64, &fb, nullptr);
         L.flow = off;
         off += align_up(fb);
     } else {
@@ -80,6 +81,13 @@ size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_
     return m;
 }
 
+// Bumped whenever the library-owned workspace moves; part of every graph key.
+std::atomic<uint64_t> &ws_generation()
+{
+    static std::atomic<uint64_t> g{0};
+    return g;
+}
+
 // Library-owned device workspace and pinned host staging, grown on demand.
 struct Owned {
     std::mutex mu;
@@ -110,6 +118,7 @@ int owned_workspace(size_t bytes, void **out)
         void *p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) return SIGNTRI_ENOMEM;
         slot = {p, bytes};
+        ws_generation().fetch_add(1);  // graphs captured on the old buffer are stale
     }
     *out = slot.first;
     return SIGNTRI_OK;
@@ -156,11 +165,12 @@ struct GraphKey {
     int64_t n;
     int dtype, tile, max_splits, device;
     void *ws;
+    uint64_t gen;
     bool operator==(const GraphKey &o) const
     {
         return T == o.T && ldt == o.ldt && U == o.U && ldu == o.ldu && n == o.n &&
                dtype == o.dtype && tile == o.tile && max_splits == o.max_splits &&
-               device == o.device && ws == o.ws;
+               device == o.device && ws == o.ws && gen == o.gen;
     }
 };
 struct GraphCache {
@@ -185,8 +195,9 @@ bool graphs_enabled()
 hipError_t launch_ph(const PhArgs &a, bool cplx, hipStream_t st, int device)
 {
     if (!graphs_enabled() || prof_on()) return run_ph_fp64(a, cplx, st);
-    GraphKey key{a.T, a.ldt, a.U, a.ldu, a.n, cplx ? 1 : 0, a.tile, a.max_splits, device,
-                 a.zbuf};
+    GraphKey key{a.T,    a.ldt,        a.U,    a.ldu,  a.n,
+                 cplx ? 1 : 0, a.tile, a.max_splits, device, a.zbuf,
+                 ws_generation().load()};
     GraphCache &g = graphs();
     std::lock_guard<std::mutex> lk(g.mu);
     for (size_t k = 0; k < g.entries.size(); ++k)
@@ -221,27 +232,126 @@ hipError_t launch_ph(const PhArgs &a, bool cplx, hipStream_t st, int device)
     return hipGraphLaunch(exec, st);
 }
 
-// Algorithmic flops of the dataflow launches (Section 3 counting, real).
-SweepFlops sweep_flops(const int8_t *s, int64_t n, const HostPlan &p)
+// Workspace of a batched call: scan table and results, per-matrix signs and
+// diagonals, then the run's own region.  The host staging mirrors the scan
+// part at the same offsets, then holds the run's host part.
+struct BatchLayout {
+    size_t scan_tab = 0, res = 0, sgn_end = 0, run = 0, dev = 0, run_host = 0, host = 0;
+    std::vector<size_t> sgn, dg;
+};
+
+BatchLayout batch_layout(const int64_t *n, int64_t batch, signtri_mode mode)
 {
-    SweepFlops f;
-    const FlopCounter fc{s, n, kFlowTile, 1.0};
-    f.diag = fc.diag();
-    f.flow = p.w_ph - f.diag;
-    const double dn = (double)n, np = (double)p.n_pos, nn = (double)p.n_neg;
-    // correction sweep: two products (4 flops) per k strictly between i and j,
-    // off the diagonal blocks
-    double cdiag = 0.0;
-    for (int64_t r0 = 0; r0 < n; r0 += kFlowTile) {
-        const double b = (double)std::min<int64_t>(kFlowTile, n - r0);
-        cdiag += b * (b - 1) * (b - 2) / 6.0;
+    BatchLayout B;
+    const int nm = (int)batch;
+    size_t o = 0;
+    B.scan_tab = o;
+    o += align_up(nm * sizeof(ScanMat));
+    B.res = o;
+    o += align_up(nm * sizeof(ScanResult));
+    B.sgn.resize(nm);
+    B.dg.resize(nm);
+    for (int m = 0; m < nm; ++m) {
+        B.sgn[m] = o;
+        o += (size_t)(n[m] + 7) / 8 * 8;
     }
-    f.corr = 4.0 * (dn * (dn - 1) * (dn - 2) / 6.0 - cdiag);
-    // residual: k = i .. j, i.e. two more terms per entry than the sweep
-    f.resid = f.flow + 2.0 * (2.0 * dn * (dn - 1) / 2.0 + 2.0 * np * nn);
-    // Sylvester: (p - 1 - i) + (j - p) multiply-adds per entry of X
-    f.syl = np * nn * (dn - 2.0);
-    return f;
+    B.sgn_end = o;
+    o = align_up(o);
+    for (int m = 0; m < nm; ++m) {
+        B.dg[m] = o;
+        o += (size_t)n[m] * sizeof(double);
+    }
+    o = align_up(o);
+    std::vector<int64_t> ns;
+    for (int m = 0; m < nm; ++m)
+        if (n[m] > 0) ns.push_back(n[m]);
+    size_t rd = 0, rh = 0;
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, &rd, &rh);
+    B.run = o;
+    B.dev = o + rd;
+    B.run_host = align_up(B.sgn_end);
+    B.host = B.run_host + rh;
+    return B;
+}
+
+// Captured launch sequences of batched runs (FP64 and unrefined FP32: no host
+// decision inside).  Each graph owns the pinned copy of the tables and task
+// lists its upload node reads, so later calls cannot change what it replays.
+struct BatchGraph {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+    void *host = nullptr;
+};
+std::mutex batch_graph_mu;
+std::vector<BatchGraph> batch_graphs;  // most recent last
+constexpr size_t kBatchGraphs = 4;
+std::vector<hipStream_t> batch_capture_streams;
+
+void drop_batch_graph(BatchGraph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.host) (void)hipHostFree(g.host);
+    g.exec = nullptr;
+    g.host = nullptr;
+}
+
+int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
+                       const signtri_options *opts, char *run_dev, hipStream_t st, int device)
+{
+    std::vector<int64_t> key{(int64_t)mode, (int64_t)device, (int64_t)(intptr_t)run_dev,
+                             (int64_t)ws_generation().load(), (int64_t)items.size()};
+    std::vector<int64_t> ns;
+    for (const RealItem &it : items) {
+        key.insert(key.end(), {(int64_t)(intptr_t)it.T, it.ldt, (int64_t)(intptr_t)it.U, it.ldu,
+                               it.n, it.path, it.p, it.s});
+        ns.push_back(it.n);
+    }
+    std::lock_guard<std::mutex> lk(batch_graph_mu);
+    for (size_t k = 0; k < batch_graphs.size(); ++k)
+        if (batch_graphs[k].key == key) {
+            BatchGraph hit = batch_graphs[k];
+            batch_graphs.erase(batch_graphs.begin() + k);
+            batch_graphs.push_back(hit);
+            return hipGraphLaunch(hit.exec, st) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
+        }
+    size_t host_bytes = 0;
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, nullptr, &host_bytes);
+    BatchGraph g;
+    g.key = key;
+    if (hipHostMalloc(&g.host, std::max<size_t>(host_bytes, 256), hipHostMallocDefault) !=
+        hipSuccess)
+        return SIGNTRI_ENOMEM;
+    if ((int)batch_capture_streams.size() <= device) batch_capture_streams.resize(device + 1, nullptr);
+    hipStream_t &cs = batch_capture_streams[device];
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        drop_batch_graph(g);
+        return SIGNTRI_EHIP;
+    }
+    // capture on a library stream (nothing runs there); the graph then runs on st
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        drop_batch_graph(g);
+        return SIGNTRI_EHIP;
+    }
+    const int rc = run_real(items, mode, opts, run_dev, g.host, false, nullptr, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != SIGNTRI_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        drop_batch_graph(g);
+        return rc != SIGNTRI_OK ? rc : SIGNTRI_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        drop_batch_graph(g);
+        return SIGNTRI_EHIP;
+    }
+    if (batch_graphs.size() >= kBatchGraphs) {
+        drop_batch_graph(batch_graphs.front());
+        batch_graphs.erase(batch_graphs.begin());
+    }
+    batch_graphs.push_back(g);
+    return hipGraphLaunch(g.exec, st) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 }
 
 void fill_info(signtri_info *info, const HostPlan &p)
@@ -334,8 +444,9 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         if (rc != SIGNTRI_OK) return rc;
     }
     void *hostbuf = nullptr;
-    const size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n) +
-                              (L.flow_path ? flow_host_bytes(n) : 0);
+    size_t run_host = 0;
+    if (L.flow_path) run_sizes(&n, 1, mode != SIGNTRI_FP64, nullptr, &run_host);
+    const size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n) + run_host;
     if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
     char *hb = (char *)hostbuf;
     void *hflow = hb + align_up(sizeof(ScanResult)) + align_up((size_t)n);
@@ -387,26 +498,24 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
 
     int rc = SIGNTRI_OK;
     hipError_t e = hipSuccess;
-    bool waited = false;
-    FlowWs fw{};
-    if (L.flow_path) fw = flow_ws_layout(ws + L.flow, n, mode != SIGNTRI_FP64, nullptr);
     if (path == SIGNTRI_PATH_TRIVIAL) {
         e = launch_fill_pm_identity(Uc, lduc, n, cplx, p.n_pos > 0 ? 1.0 : -1.0, st);
     } else if (L.flow_path) {
-        const double *Td = (const double *)Tc;
-        double *Ud = (double *)Uc;
-        const int64_t split = path == SIGNTRI_PATH_PS ? p.split : 0;
-        const SweepFlops fl = prof_on() ? sweep_flops(hs, n, p) : SweepFlops();
-        if (mode == SIGNTRI_FP64) {
-            if (path == SIGNTRI_PATH_PS)
-                e = sweep_ps_fp64(Td, ldtc, Ud, lduc, n, split, p.ps_sign, dg, fw, fl, st);
-            else
-                e = sweep_ph_fp64(Td, ldtc, Ud, lduc, n, sgn, dg, fw, fl, st);
-        } else {
-            rc = sweep_mixed(Td, ldtc, Ud, lduc, n, sgn, dg, split, p.ps_sign,
-                             mode == SIGNTRI_MIXED_REFINED, opts, fw, hflow, fl, st, info);
-            waited = mode == SIGNTRI_MIXED_REFINED;
-        }
+        std::vector<RealItem> items(1);
+        RealItem &it = items[0];
+        it.T = (const double *)Tc;
+        it.ldt = ldtc;
+        it.U = (double *)Uc;
+        it.ldu = lduc;
+        it.n = n;
+        it.path = path;
+        it.p = path == SIGNTRI_PATH_PS ? p.split : 0;
+        it.s = p.ps_sign;
+        it.sgn = sgn;
+        it.dg = dg;
+        it.info = info;
+        const int8_t *hsv[1] = {hs};
+        rc = run_real(items, mode, opts, ws + L.flow, hflow, prof_on(), hsv, st);
     } else {
         PhArgs a;
         a.T = Tc;
@@ -432,13 +541,10 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
         return SIGNTRI_EHIP;
     // with info requested, wait and report a dependency-wait timeout of the sweep
-    if (info && L.flow_path && path != SIGNTRI_PATH_TRIVIAL && !waited) {
-        int *herr = (int *)hflow;
-        if (hipMemcpyAsync(herr, fw.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return SIGNTRI_EHIP;
-        if (herr[1]) return SIGNTRI_EHIP;
+    if (info && L.flow_path && path != SIGNTRI_PATH_TRIVIAL && mode != SIGNTRI_MIXED_REFINED) {
+        int herr = 0;
+        if ((rc = sweep_error(ws + L.flow, &n, 1, mode != SIGNTRI_FP64, hflow, st, &herr)) != 0)
+            return rc;
     }
     if (info) {
         info->path = path;
@@ -459,12 +565,11 @@ size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch, signtri_d
                                       signtri_mode mode)
 {
     if (batch < 0 || (batch > 0 && !n)) return 0;
-    size_t m = 0;
-    for (int64_t b = 0; b < batch; ++b) {
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return 0;
+    if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
+    for (int64_t b = 0; b < batch; ++b)
         if (n[b] < 0) return 0;
-        m = std::max(m, signtri_workspace_size(n[b], dtype, SIGNTRI_COL_MAJOR, mode, SIGNTRI_AUTO));
-    }
-    return m;
+    return batch_layout(n, batch, mode).dev;
 }
 
 int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, const int64_t *ldu,
@@ -477,12 +582,102 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     if (batch > 0 && !U) return -3;
     if (batch > 0 && !ldu) return -4;
     if (batch > 0 && !n) return -5;
-    if (batch < 0) return -6;
+    if (batch < 0 || batch > (1 << 24)) return -6;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -7;
+    if (layout != SIGNTRI_COL_MAJOR && layout != SIGNTRI_ROW_MAJOR) return -8;
+    if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return -9;
+    if (workspace && ws_bytes == 0) return -11;
     for (int64_t b = 0; b < batch; ++b) {
-        int rc = signtri(T[b], ldt[b], U[b], ldu[b], n[b], dtype, layout, mode, SIGNTRI_AUTO,
-                         workspace, ws_bytes, stream, opts, infos ? infos + b : nullptr);
-        if (rc != SIGNTRI_OK) return rc;
+        if (infos) std::memset(&infos[b], 0, sizeof(signtri_info));
+        if (n[b] < 0 || n[b] > 65535 * (int64_t)kFlowTile) return -5;
+        if (n[b] > 0 && (!T[b] || !U[b])) return T[b] ? -3 : -1;
+        if (ldt[b] < std::max<int64_t>(1, n[b])) return -2;
+        if (ldu[b] < std::max<int64_t>(1, n[b])) return -4;
+        if (n[b] > 0 && ranges_overlap(T[b], extent_bytes(n[b], ldt[b], 8), U[b],
+                                       extent_bytes(n[b], ldu[b], 8)))
+            return -3;
     }
+    if (batch == 0) return SIGNTRI_OK;
+    if (dtype != SIGNTRI_R64 || layout != SIGNTRI_COL_MAJOR) return SIGNTRI_ENOTSUP;
+    if (opts && opts->tile != 0 && opts->tile != kFlowTile) return -13;
+
+    const BatchLayout BL = batch_layout(n, batch, mode);
+    if (workspace) {
+        if (ws_bytes < BL.dev) return SIGNTRI_EWORKSPACE;
+    } else if (int rc = owned_workspace(BL.dev, &workspace)) {
+        return rc;
+    }
+    void *hostbuf = nullptr;
+    if (int rc = owned_host(BL.host, &hostbuf)) return rc;
+    char *ws = (char *)workspace, *hb = (char *)hostbuf;
+    hipStream_t st = (hipStream_t)stream;
+    const int nm = (int)batch;
+
+    // diagonal scan of every matrix, one workgroup each
+    ScanMat *hsm = (ScanMat *)(hb + BL.scan_tab);
+    for (int m = 0; m < nm; ++m)
+        hsm[m] = ScanMat{(const double *)T[m], ldt[m], n[m], (int8_t *)(ws + BL.sgn[m]),
+                         (double *)(ws + BL.dg[m]), (ScanResult *)(ws + BL.res) + m};
+    if (hipMemcpyAsync(ws + BL.scan_tab, hsm, nm * sizeof(ScanMat), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return SIGNTRI_EHIP;
+    if (launch_scan_b((const ScanMat *)(ws + BL.scan_tab), nm, st) != hipSuccess) return SIGNTRI_EHIP;
+    // results and signs are adjacent: one copy back
+    if (hipMemcpyAsync(hb + BL.res, ws + BL.res, BL.sgn_end - BL.res, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    const ScanResult *hres = (const ScanResult *)(hb + BL.res);
+    for (int m = 0; m < nm; ++m)
+        if (n[m] > 0 && hres[m].bad_index < n[m]) {
+            if (infos) infos[m].bad_index = hres[m].bad_index + 1;
+            return SIGNTRI_EDOMAIN;
+        }
+
+    // plan every matrix (Section 3 choice, as signtri() with SIGNTRI_AUTO)
+    std::vector<RealItem> items;
+    std::vector<const int8_t *> hsigns;
+    items.reserve(nm);
+    for (int m = 0; m < nm; ++m) {
+        if (n[m] == 0) continue;
+        const int8_t *hs = (const int8_t *)(hb + BL.sgn[m]);
+        const HostPlan p = plan_from_signs(hs, n[m], false);
+        signtri_info *inf = infos ? &infos[m] : nullptr;
+        fill_info(inf, p);
+        RealItem it;
+        it.T = (const double *)T[m];
+        it.ldt = ldt[m];
+        it.U = (double *)U[m];
+        it.ldu = ldu[m];
+        it.n = n[m];
+        it.path = p.auto_path;
+        it.p = p.auto_path == SIGNTRI_PATH_PS ? p.split : 0;
+        it.s = it.path == SIGNTRI_PATH_TRIVIAL ? (p.n_pos > 0 ? 1 : -1) : p.ps_sign;
+        it.sgn = (const int8_t *)(ws + BL.sgn[m]);
+        it.dg = (const double *)(ws + BL.dg[m]);
+        it.info = inf;
+        if (inf) {
+            inf->path = it.path;
+            inf->tile = it.path == SIGNTRI_PATH_TRIVIAL ? 0 : kFlowTile;
+        }
+        items.push_back(it);
+        hsigns.push_back(hs);
+    }
+    std::vector<int64_t> ns(items.size());
+    for (size_t m = 0; m < items.size(); ++m) ns[m] = items[m].n;
+    char *run_dev = ws + BL.run, *run_host = hb + BL.run_host;
+    int rc;
+    if (mode != SIGNTRI_MIXED_REFINED && graphs_enabled() && !prof_on()) {
+        int device = 0;
+        if (hipGetDevice(&device) != hipSuccess) return SIGNTRI_EHIP;
+        rc = launch_batch_graph(items, mode, opts, run_dev, st, device);
+    } else {
+        rc = run_real(items, mode, opts, run_dev, run_host, prof_on(), hsigns.data(), st);
+    }
+    if (rc != SIGNTRI_OK) return rc;
+    if (infos && mode != SIGNTRI_MIXED_REFINED)
+        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, run_host, st,
+                           nullptr);
     return SIGNTRI_OK;
 }
 
@@ -508,6 +703,9 @@ void signtri_release(void)
     std::lock_guard<std::mutex> lk(gc.mu);
     for (auto &kv : gc.entries) (void)hipGraphExecDestroy(kv.second);
     gc.entries.clear();
+    std::lock_guard<std::mutex> lb(batch_graph_mu);
+    for (auto &g : batch_graphs) drop_batch_graph(g);
+    batch_graphs.clear();
 }
 
 }  // extern "C"

@@ -1,0 +1,141 @@
+// Table-driven kernels that let one launch serve a whole set of real matrices
+// (the batched entry point, and the single-matrix one as a set of one): the
+// diagonal scan, the output preparation, and the diagonal blocks.
+#include "common.h"
+
+namespace sgt {
+
+namespace {
+
+constexpr int TB = kFlowTile;
+
+// One workgroup per matrix: sign(Re t_ii) as +1/-1 (Section 1), the first
+// index whose sign is undefined (zero or non-finite), the number of positive
+// signs, and the real diagonal itself (the divisors t_ii - t_jj).
+__global__ __launch_bounds__(1024) void k_scan_b(const ScanMat *__restrict__ mats)
+{
+    const ScanMat d = mats[blockIdx.x];
+    __shared__ unsigned long long bad;
+    __shared__ unsigned long long npos;
+    if (threadIdx.x == 0) {
+        bad = (unsigned long long)d.n;
+        npos = 0;
+    }
+    __syncthreads();
+    unsigned long long my_pos = 0;
+    for (int64_t i = threadIdx.x; i < d.n; i += blockDim.x) {
+        const double re = d.T[i + i * d.ldt];
+        int s = 0;
+        if (isfinite(re)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
+        d.sgn[i] = (int8_t)s;
+        d.dg[i] = re;
+        if (s == 0) atomicMin(&bad, (unsigned long long)i);
+        my_pos += (s > 0);
+    }
+    atomicAdd(&npos, my_pos);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.res->bad_index = (int64_t)bad;
+        d.res->n_pos = (int64_t)npos;
+    }
+}
+
+// Output preparation of matrix blockIdx.z: kind 0 zeroes the strict lower
+// triangle (the sweep writes the rest), kind 1 writes diag(s I_p, -s I_{n-p})
+// (Parlett-Sylvester: the sweep writes X), kind 2 writes s I (one sign).
+__global__ __launch_bounds__(256) void k_prepare_b(const PrepMat *__restrict__ mats)
+{
+    const PrepMat d = mats[blockIdx.z];
+    for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y) {
+        const int64_t i0 = d.kind == 0 ? j + 1 : 0;
+        for (int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            double v = 0.0;
+            if (i == j && d.kind != 0) v = (d.kind == 2 || i < d.p) ? d.s : -d.s;
+            d.U[i + j * d.ldu] = v;
+        }
+    }
+}
+
+// Diagonal 32 x 32 blocks (Algorithm 3 per block, superdiagonal by
+// superdiagonal), one per workgroup: task (matrix, block row).  Eight lanes
+// share each entry's inner product.
+__global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats,
+                                                const int2 *__restrict__ tasks)
+{
+    constexpr int LD = TB + 1, LPE = 256 / TB;
+    __shared__ double sT[TB * LD], sU[TB * LD];
+    __shared__ int8_t ss[TB];
+    const int2 tk = tasks[blockIdx.x];
+    const PrepMat d = mats[uniform(tk.x)];
+    const int64_t r0 = (int64_t)uniform(tk.y) * TB;
+    const int bt = uniform((int)min((int64_t)TB, d.n - r0));
+    for (int e = threadIdx.x; e < TB * TB; e += 256) {
+        const int i = e % TB, j = e / TB;
+        const bool in = i < bt && j < bt;
+        sT[i + j * LD] = (in && i <= j) ? d.T[(r0 + i) + (r0 + j) * d.ldt] : 0.0;
+        sU[i + j * LD] = (in && i == j) ? (double)d.sgn[r0 + i] : 0.0;
+    }
+    if (threadIdx.x < TB) ss[threadIdx.x] = threadIdx.x < bt ? d.sgn[r0 + threadIdx.x] : 1;
+    __syncthreads();
+    const int i = threadIdx.x / LPE, q = threadIdx.x % LPE;
+    for (int dd = 1; dd < bt; ++dd) {
+        const int j = i + dd;
+        if (j < bt) {
+            const int si = ss[i], sj = ss[j];
+            double sum = 0.0;
+            if (si != sj) {
+                for (int k = i + 1 + q; k < j; k += LPE)
+                    sum += sU[i + k * LD] * sT[k + j * LD] - sT[i + k * LD] * sU[k + j * LD];
+            } else {
+                for (int k = i + 1 + q; k < j; k += LPE) sum += sU[i + k * LD] * sU[k + j * LD];
+            }
+            sum = group_sum<LPE>(sum);
+            if (q == 0) {
+                double u;
+                if (si != sj) {
+                    // Eq. (1): t_ij (u_ii - u_jj) = 2 s_i t_ij
+                    const double den = sT[i + i * LD] - sT[j + j * LD];
+                    u = (2.0 * si * sT[i + j * LD] + sum) / den;
+                } else {
+                    // Eq. (2): -sum / (u_ii + u_jj) = -(s_i / 2) sum, an exact scaling
+                    u = -0.5 * si * sum;
+                }
+                sU[i + j * LD] = u;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < TB * TB; e += 256) {
+        const int ii = e % TB, jj = e / TB;
+        if (ii < bt && jj < bt && ii <= jj) d.U[(r0 + ii) + (r0 + jj) * d.ldu] = sU[ii + jj * LD];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_scan_b(const ScanMat *mats, int nmat, hipStream_t st)
+{
+    if (nmat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_b, dim3(nmat), dim3(1024), 0, st, mats);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, hipStream_t st)
+{
+    if (nmat <= 0 || nmax <= 0) return hipSuccess;
+    const int64_t gx = std::min<int64_t>((nmax + 255) / 256, 8);
+    const int64_t gy = std::min<int64_t>(nmax, nmat > 1 ? 64 : 1024);
+    hipLaunchKernelGGL(k_prepare_b, dim3((unsigned)gx, (unsigned)gy, (unsigned)nmat), dim3(256), 0,
+                       st, mats);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, hipStream_t st)
+{
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag_b, dim3(ntasks), dim3(256), 0, st, mats, tasks);
+    return hipGetLastError();
+}
+
+}  // namespace sgt

@@ -118,6 +118,13 @@ template <int L, typename V> __device__ inline V group_sum(V v)
     return v;
 }
 
+// A value every lane of the wave holds, as a scalar (SGPR) value.  Every value
+// that decides whether or how often a barrier is reached must be provably
+// uniform: the compiler structures a loop whose trip count it sees as
+// divergent per lane, and the barriers inside it then no longer pair up
+// between waves.
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline dx4 mfma_f64(double a, double b, dx4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -342,53 +349,91 @@ hipError_t launch_flow(const FlowArgs<F> &a, int grid, hipStream_t st);
 hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
 hipError_t launch_tasks_tri(int nb, int mat, int2 *out, hipStream_t st);
 hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t st);
-hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const int64_t *flag0,
-                                   const int *nbc, int *flags, hipStream_t st);
+hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
+                                   int *flags, hipStream_t st);
 
-// Device workspace of the dataflow paths (sweep.hip): control words, flags,
-// task lists and, for the reduced-precision modes, FP32 copies (leading
-// dimension ld32) and per-block residual norms.
-struct FlowWs {
-    int *ctrl;
-    unsigned long long *maxes;  // max |t|, max |u|, max |correction|
-    int *flags;
-    int2 *tasks, *ftasks;
-    double *norms[2];
-    float *T32, *U32, *E32;
-    int64_t ld32;
-};
-FlowWs flow_ws_layout(char *base, int64_t n, bool mixed, size_t *total);
 // Algorithmic flops of the launches of one call (Section 3 counting), for the
 // opt-in kernel timers; all zero when the timers are off.
 struct SweepFlops {
     double diag = 0, flow = 0, corr = 0, resid = 0, syl = 0;
 };
-size_t flow_host_bytes(int64_t n);
-hipError_t sweep_ph_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                         const int8_t *sgn, const double *dg, const FlowWs &w,
-                         const SweepFlops &fl, hipStream_t st);
-hipError_t sweep_ps_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                         int64_t p, int s, const double *dg, const FlowWs &w,
-                         const SweepFlops &fl, hipStream_t st);
-int sweep_mixed(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                const int8_t *sgn, const double *dg, int64_t p, int s, bool refine,
-                const signtri_options *opts, const FlowWs &w, void *host,
-                const SweepFlops &fl, hipStream_t st, signtri_info *info);
 
-// refine.hip
-hipError_t launch_to_f32(const double *T, int64_t ldt, float *T32, const double *U, int64_t ldu,
-                         float *U32, int64_t ld32, int64_t n, unsigned long long *tmax,
-                         hipStream_t st);
-hipError_t launch_widen(const float *U32, int64_t ld32, double *U, int64_t ldu, int64_t n,
-                        int64_t split, unsigned long long *umax, hipStream_t st);
-hipError_t launch_add_correction(const float *E, int64_t lde, double *U, int64_t ldu, int64_t n,
-                                 int64_t split, unsigned long long *emax, hipStream_t st);
-hipError_t launch_resid(const double *T, int64_t ldt, const double *U, int64_t ldu,
-                        const int8_t *sgn, int64_t n, const int2 *tasks, int ntasks, float *R,
-                        int64_t ldr, double *norm2, hipStream_t st);
-hipError_t launch_resid_syl(const double *T, int64_t ldt, const double *U, int64_t ldu, int64_t n,
-                            int64_t p, double two_s, const int2 *tasks, int ntasks, int nbr,
-                            int nbc, float *R, int64_t ldr, double *norm2, hipStream_t st);
+// refine.hip: one real matrix of a reduced-precision computation.  The
+// kernels take a table of these (blockIdx.z or the task's matrix index), or
+// the single matrix m0 when the table pointer is null.
+struct RefMat {
+    const double *T;
+    int64_t ldt;
+    double *U;
+    int64_t ldu;
+    float *T32, *U32, *E32;    // FP32 copies of T and U0; residual / correction
+    int64_t ld32;
+    const int8_t *sgn;
+    int n, split;              // split > 0: Sylvester form, X = U(0:split, split:n)
+    int nbr, nbc;
+    double two_s;              // Sylvester: 2 s
+    int64_t f0;                // this matrix's first entry in the per-block arrays
+    unsigned long long *maxes; // max |t|, max |u0|, max |correction| (non-negative bits)
+};
+struct RefArgs {
+    RefMat m0;
+    const RefMat *mats;
+    int nmat;
+};
+hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, hipStream_t st);
+hipError_t launch_widen(const RefArgs &a, int64_t nmax, hipStream_t st);
+hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, hipStream_t st);
+hipError_t launch_resid(const RefArgs &a, bool syl, const int2 *tasks, int ntasks, double *norm2,
+                        hipStream_t st);
+
+// batch.hip: table-driven scan, output preparation and diagonal blocks.
+struct ScanMat {
+    const double *T;
+    int64_t ldt;
+    int64_t n;
+    int8_t *sgn;
+    double *dg;
+    ScanResult *res;
+};
+struct PrepMat {
+    const double *T;
+    int64_t ldt;
+    double *U;
+    int64_t ldu;
+    int64_t n;
+    const int8_t *sgn;
+    int kind;   // 0: zero the strict lower triangle; 1: diag(s I_p, -s I_{n-p}); 2: s I
+    int64_t p;
+    double s;
+};
+hipError_t launch_scan_b(const ScanMat *mats, int nmat, hipStream_t st);
+hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, hipStream_t st);
+hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, hipStream_t st);
+
+// sweep.hip: one real matrix of a run (a single call, or one matrix of a batch).
+struct RealItem {
+    const double *T;
+    int64_t ldt;
+    double *U;
+    int64_t ldu;
+    int64_t n;
+    int path;             // SIGNTRI_PATH_*
+    int64_t p;            // Parlett-Sylvester: order of the leading sign group
+    int s;                // its sign (trivial path: the one sign)
+    const int8_t *sgn;    // device signs and real diagonal
+    const double *dg;
+    signtri_info *info;   // optional host output
+};
+// Device and pinned-host bytes a run over these orders needs.
+void run_sizes(const int64_t *ns, int nmat, bool mixed, size_t *dev_bytes, size_t *host_bytes);
+// Run the sweeps of a set of real matrices: FP64, FP32, or FP32 with FP64
+// refinement (mode), every phase one launch over all matrices.
+int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
+             void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
+             hipStream_t st);
+// Wait for a run and report whether a dependency wait hit its safety bound.
+int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, void *host_ws,
+                hipStream_t st, int *err);
 
 // Diagonal 32 x 32 blocks of a real U in FP64 (Algorithm 3 per block).
 hipError_t launch_diag_blocks(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,

@@ -100,9 +100,6 @@ struct TileRef {
 // (s_waitcnt) before its flag store is issued, and the consumer issues its loads
 // only after it has read the flag.  Inputs and blocks written before the launch
 // use ordinary cached loads.
-// A value every lane of the wave holds, as a scalar (SGPR) value.
-__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
 __device__ inline int flag_load(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -609,14 +606,14 @@ __global__ void k_fill_int(int *p, int64_t n, int v)
 }
 
 // Mark the blocks of a task list as not finished (flag 0).
-__global__ void k_clear_task_flags(const int2 *tasks, int64_t ntasks, const int64_t *flag0,
-                                   const int *nbc, int *flags)
+__global__ void k_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
+                                   int *flags)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntasks) return;
     const int2 tk = tasks[t];
     const int I = tk.y >> 16, J = tk.y & 0xffff;
-    flags[flag0[tk.x] + (int64_t)I * nbc[tk.x] + J] = 0;
+    flags[mats[tk.x].flag0 + (int64_t)I * mats[tk.x].nbc + J] = 0;
 }
 
 }  // namespace
@@ -646,12 +643,12 @@ hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const int64_t *flag0,
-                                   const int *nbc, int *flags, hipStream_t st)
+hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
+                                   int *flags, hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear_task_flags, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0,
-                       st, tasks, ntasks, flag0, nbc, flags);
+                       st, tasks, ntasks, mats, flags);
     return hipGetLastError();
 }
 

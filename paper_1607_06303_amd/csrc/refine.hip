@@ -44,25 +44,26 @@ __device__ inline double block_max(double v, double *red)
     return r;
 }
 
+#define REF_MAT(a) (a.mats ? a.mats[blockIdx.z] : a.m0)
+
 // FP32 copies for the reduced-precision sweeps: the upper triangle of T, and
-// the (FP64-computed) diagonal blocks of U; max |t_ij| on the side.
-__global__ __launch_bounds__(NT) void k_to_f32(const double *__restrict__ T, int64_t ldt,
-                                               float *__restrict__ T32, const double *__restrict__ U,
-                                               int64_t ldu, float *__restrict__ U32, int64_t ld32,
-                                               int64_t n, unsigned long long *tmax)
+// the (FP64-computed) diagonal blocks of U; max |t_ij| on the side.  Matrix
+// blockIdx.z of the table; columns strided over blockIdx.y.
+__global__ __launch_bounds__(NT) void k_to_f32(RefArgs a)
 {
     __shared__ double red[NT / 64];
+    const RefMat d = REF_MAT(a);
     double m = 0.0;
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+    for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y)
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= j;
              i += (int64_t)gridDim.x * NT) {
-            const double t = T[i + j * ldt];
-            T32[i + j * ld32] = (float)t;
+            const double t = d.T[i + j * d.ldt];
+            d.T32[i + j * d.ld32] = (float)t;
             m = fmax(m, fabs(t));
-            if (i / TB == j / TB) U32[i + j * ld32] = (float)U[i + j * ldu];
+            if (d.split == 0 && i / TB == j / TB) d.U32[i + j * d.ld32] = (float)d.U[i + j * d.ldu];
         }
     m = block_max(m, red);
-    if (threadIdx.x == 0) atomic_max_nonneg(tmax, m);
+    if (threadIdx.x == 0) atomic_max_nonneg(&d.maxes[0], m);
 }
 
 // Rows of column j that the reduced-precision sweep computed: above the
@@ -74,55 +75,54 @@ __device__ inline int64_t region_rows(int64_t j, int64_t split)
 }
 
 // U(i, j) = U32(i, j) in FP64 for the entries of the computed region.
-__global__ __launch_bounds__(NT) void k_widen(const float *__restrict__ U32, int64_t ld32,
-                                              double *__restrict__ U, int64_t ldu, int64_t n,
-                                              int64_t split, unsigned long long *umax)
+__global__ __launch_bounds__(NT) void k_widen(RefArgs a)
 {
     __shared__ double red[NT / 64];
+    const RefMat d = REF_MAT(a);
     double m = 0.0;
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
-        const int64_t iend = region_rows(j, split);
+    for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y) {
+        const int64_t iend = region_rows(j, d.split);
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < iend;
              i += (int64_t)gridDim.x * NT) {
-            const double u = (double)U32[i + j * ld32];
-            U[i + j * ldu] = u;
+            const double u = (double)d.U32[i + j * d.ld32];
+            d.U[i + j * d.ldu] = u;
             m = fmax(m, fabs(u));
         }
     }
     m = block_max(m, red);
-    if (threadIdx.x == 0) atomic_max_nonneg(umax, m);
+    if (threadIdx.x == 0) atomic_max_nonneg(&d.maxes[1], m);
 }
 
 // U += E on the entries of the computed region; max |E| on the side.
-__global__ __launch_bounds__(NT) void k_add_correction(const float *__restrict__ E, int64_t lde,
-                                                       double *__restrict__ U, int64_t ldu,
-                                                       int64_t n, int64_t split,
-                                                       unsigned long long *emax)
+__global__ __launch_bounds__(NT) void k_add_correction(RefArgs a)
 {
     __shared__ double red[NT / 64];
+    const RefMat d = REF_MAT(a);
     double m = 0.0;
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
-        const int64_t iend = region_rows(j, split);
+    for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y) {
+        const int64_t iend = region_rows(j, d.split);
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < iend;
              i += (int64_t)gridDim.x * NT) {
-            const double e = (double)E[i + j * lde];
-            U[i + j * ldu] += e;
+            const double e = (double)d.E32[i + j * d.ld32];
+            d.U[i + j * d.ldu] += e;
             m = fmax(m, fabs(e));
         }
     }
     m = block_max(m, red);
-    if (threadIdx.x == 0) atomic_max_nonneg(emax, m);
+    if (threadIdx.x == 0) atomic_max_nonneg(&d.maxes[2], m);
+}
+
+__global__ void k_clear_correction_max(RefArgs a)
+{
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z < a.nmat) (a.mats ? a.mats[z] : a.m0).maxes[2] = 0;
 }
 
 // FP64 residual of one off-diagonal block per workgroup (tasks in reverse
 // order: the longest products first).  Output: R as FP32 (the right-hand side
-// of the correction sweep) and the block's squared Frobenius norm.
-__global__ __launch_bounds__(NT) void k_resid(const double *__restrict__ T, int64_t ldt,
-                                              const double *__restrict__ U, int64_t ldu,
-                                              const int8_t *__restrict__ sgn, int64_t n, int nb,
-                                              const int2 *__restrict__ tasks, int ntasks,
-                                              float *__restrict__ R, int64_t ldr,
-                                              double *__restrict__ norm2)
+// of the correction sweep, into E32) and the block's squared Frobenius norm.
+__global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict__ tasks,
+                                              int ntasks, double *__restrict__ norm2)
 {
     __shared__ double sAU[TB * APITCH], sAT[TB * APITCH];
     __shared__ double sBU[(TB / 4) * BSLAB], sBT[(TB / 4) * BSLAB];
@@ -133,12 +133,16 @@ __global__ __launch_bounds__(NT) void k_resid(const double *__restrict__ T, int6
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
     const int2 tk = tasks[ntasks - 1 - (int)blockIdx.x];
-    const int I = tk.y >> 16, J = tk.y & 0xffff;
+    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int I = uniform(tk.y >> 16), J = uniform(tk.y & 0xffff);
+    const int64_t n = uniform(d.n);
+    const double *T = d.T, *U = d.U;
+    const int64_t ldt = d.ldt, ldu = d.ldu;
     const int64_t r0 = (int64_t)I * TB, c0 = (int64_t)J * TB;
     const int bj = (int)min((int64_t)TB, n - c0);
     if (tid < TB) {
-        rs[tid] = sgn[r0 + tid];
-        cs[tid] = tid < bj ? sgn[c0 + tid] : 0;
+        rs[tid] = d.sgn[r0 + tid];
+        cs[tid] = tid < bj ? d.sgn[c0 + tid] : 0;
     }
     __syncthreads();
     bool needY = false, needX = false;
@@ -216,26 +220,22 @@ __global__ __launch_bounds__(NT) void k_resid(const double *__restrict__ T, int6
         const int j = 16 * pc + tl;
         const double v = rs[i] == cs[j] ? accY[r] : accX[r];
         if (j < bj) {
-            R[(r0 + i) + (c0 + j) * ldr] = (float)v;
+            d.E32[(r0 + i) + (c0 + j) * d.ld32] = (float)v;
             ss += v * v;
         }
     }
     for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) norm2[(int64_t)I * nb + J] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = red[0] + red[1] + red[2] + red[3];
 }
 
 // FP64 residual of the Sylvester equation T11 X - X T22 = 2 s T12 for one
 // block of X per workgroup: R = 2 s T12 - T11 X + X T22, with X = U(0:p, p:n).
 // K steps: blocks K >= I of T11's rows (K = I keeps its upper triangle), then
 // blocks K <= J of T22's columns (K = J likewise).
-__global__ __launch_bounds__(NT) void k_resid_syl(const double *__restrict__ T, int64_t ldt,
-                                                  const double *__restrict__ U, int64_t ldu,
-                                                  int64_t n, int64_t p, double two_s,
-                                                  const int2 *__restrict__ tasks, int ntasks,
-                                                  int nbr, int nbc, float *__restrict__ R,
-                                                  int64_t ldr, double *__restrict__ norm2)
+__global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restrict__ tasks,
+                                                  int ntasks, double *__restrict__ norm2)
 {
     __shared__ double sA[TB * APITCH];
     __shared__ double sB[(TB / 4) * BSLAB];
@@ -245,12 +245,16 @@ __global__ __launch_bounds__(NT) void k_resid_syl(const double *__restrict__ T, 
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
     const int2 tk = tasks[ntasks - 1 - (int)blockIdx.x];
-    const int I = tk.y >> 16, J = tk.y & 0xffff;
+    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int I = uniform(tk.y >> 16), J = uniform(tk.y & 0xffff);
+    const int64_t n = uniform(d.n), p = uniform(d.split);
+    const double *T = d.T, *U = d.U;
+    const int64_t ldt = d.ldt, ldu = d.ldu;
     const int64_t r0 = (int64_t)I * TB, c0 = p + (int64_t)J * TB;
 
     dx4 acc;
     for (int r = 0; r < 4; ++r) acc[r] = 0.0;
-    const int na = nbr - I, nsteps = na + J + 1;
+    const int na = uniform(d.nbr) - I, nsteps = uniform(na + J + 1);
     double ga[4], gb[4];
     auto load = [&](int s) {
         int64_t ar, ac, aend_r, aend_c, br, bc, bend_r, bend_c;
@@ -297,9 +301,9 @@ __global__ __launch_bounds__(NT) void k_resid_syl(const double *__restrict__ T, 
         if (more) load(s + 1);
 #pragma unroll
         for (int k4 = 0; k4 < TB / 4; ++k4) {
-            const double a = sA[(k4 * 4 + g) * APITCH + 16 * pr + tl];
-            const double b = sB[k4 * BSLAB + (16 * pc + tl) * 4 + g];
-            acc = mfma_f64(a, b, acc);
+            const double av = sA[(k4 * 4 + g) * APITCH + 16 * pr + tl];
+            const double bv = sB[k4 * BSLAB + (16 * pc + tl) * 4 + g];
+            acc = mfma_f64(av, bv, acc);
         }
         __syncthreads();
         if (more) {
@@ -313,73 +317,60 @@ __global__ __launch_bounds__(NT) void k_resid_syl(const double *__restrict__ T, 
         const int64_t i = r0 + 16 * pr + mfma64_row(lane, r);
         const int64_t j = c0 + 16 * pc + tl;
         if (i < p && j < n) {
-            const double v = two_s * T[i + j * ldt] + acc[r];
-            R[i + j * ldr] = (float)v;
+            const double v = d.two_s * T[i + j * ldt] + acc[r];
+            d.E32[i + j * d.ld32] = (float)v;
             ss += v * v;
         }
     }
     for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
-    if (tid == 0) norm2[(int64_t)I * nbc + J] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Grid of the column-wise elementwise kernels: a few thousand workgroups, each
-// over a strided set of columns, so that each publishes its maximum with one
-// atomic (one atomic per column made the maxima cost more than the copies).
-dim3 col_grid(int64_t n)
+// Grid of the column-wise elementwise kernels: a few thousand workgroups per
+// matrix, each over a strided set of columns, so that each publishes its
+// maximum with one atomic (one atomic per column made the maxima cost more
+// than the copies).  nmax: the largest order in the table.
+dim3 col_grid(int64_t nmax, int nmat)
 {
-    const int64_t bx = std::min<int64_t>((n + NT - 1) / NT, 8);
-    return dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)std::max<int64_t>(std::min<int64_t>(n, 512), 1));
+    const int64_t bx = std::min<int64_t>((nmax + NT - 1) / NT, 8);
+    const int64_t by = std::max<int64_t>(std::min<int64_t>(nmax, nmat > 1 ? 64 : 512), 1);
+    return dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)by, (unsigned)nmat);
 }
 
 }  // namespace
 
-hipError_t launch_to_f32(const double *T, int64_t ldt, float *T32, const double *U, int64_t ldu,
-                         float *U32, int64_t ld32, int64_t n, unsigned long long *tmax,
-                         hipStream_t st)
+hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_f32, col_grid(n), dim3(NT), 0, st, T, ldt, T32, U, ldu, U32, ld32, n,
-                       tmax);
+    if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_widen(const float *U32, int64_t ld32, double *U, int64_t ldu, int64_t n,
-                        int64_t split, unsigned long long *umax, hipStream_t st)
+hipError_t launch_widen(const RefArgs &a, int64_t nmax, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_widen, col_grid(n), dim3(NT), 0, st, U32, ld32, U, ldu, n, split, umax);
+    if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_widen, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_add_correction(const float *E, int64_t lde, double *U, int64_t ldu, int64_t n,
-                                 int64_t split, unsigned long long *emax, hipStream_t st)
+hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_add_correction, col_grid(n), dim3(NT), 0, st, E, lde, U, ldu, n, split,
-                       emax);
+    if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_correction_max, dim3((a.nmat + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_add_correction, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_resid(const double *T, int64_t ldt, const double *U, int64_t ldu,
-                        const int8_t *sgn, int64_t n, const int2 *tasks, int ntasks, float *R,
-                        int64_t ldr, double *norm2, hipStream_t st)
+hipError_t launch_resid(const RefArgs &a, bool syl, const int2 *tasks, int ntasks, double *norm2,
+                        hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
-    const int nb = (int)((n + TB - 1) / TB);
-    hipLaunchKernelGGL(k_resid, dim3(ntasks), dim3(NT), 0, st, T, ldt, U, ldu, sgn, n, nb, tasks,
-                       ntasks, R, ldr, norm2);
-    return hipGetLastError();
-}
-
-hipError_t launch_resid_syl(const double *T, int64_t ldt, const double *U, int64_t ldu, int64_t n,
-                            int64_t p, double two_s, const int2 *tasks, int ntasks, int nbr,
-                            int nbc, float *R, int64_t ldr, double *norm2, hipStream_t st)
-{
-    if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid_syl, dim3(ntasks), dim3(NT), 0, st, T, ldt, U, ldu, n, p, two_s,
-                       tasks, ntasks, nbr, nbc, R, ldr, norm2);
+    if (syl)
+        hipLaunchKernelGGL(k_resid_syl, dim3(ntasks), dim3(NT), 0, st, a, tasks, ntasks, norm2);
+    else
+        hipLaunchKernelGGL(k_resid, dim3(ntasks), dim3(NT), 0, st, a, tasks, ntasks, norm2);
     return hipGetLastError();
 }
 

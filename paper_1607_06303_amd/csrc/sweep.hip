@@ -1,9 +1,14 @@
-// Host orchestration of the real dataflow sweeps (flow.hip) for the three
-// precision modes, the Parlett-Higham and Parlett-Sylvester forms, and the
-// refinement loop with its FP64 fallback (refine.hip).
+// Host orchestration of the real sweeps (flow.hip) for a set of matrices --
+// one for signtri(), many for signtri_batched() -- in the three precision
+// modes, with the Parlett-Higham and Parlett-Sylvester forms side by side and
+// the refinement loop with its FP64 fallback (refine.hip).  Every phase is one
+// launch over all matrices: the dataflow kernel takes one task list spanning
+// them (dependency order within each matrix, interleaved across matrices), and
+// the other kernels take per-matrix tables.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "common.h"
@@ -16,32 +21,8 @@ constexpr int TB = kFlowTile;
 constexpr int kSpinLimit = 1 << 22;  // polls before a dependency wait gives up
 
 int64_t nblocks(int64_t m) { return (m + TB - 1) / TB; }
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Zero the flags of every block and the control words, then run one sweep.
-template <typename F, int KIND>
-hipError_t run_sweep(const FlowMat<F> &m, const FlowWs &w, int64_t ntasks, int64_t nflags,
-                     bool fresh_flags, int pk, double flops, hipStream_t st)
-{
-    hipError_t e;
-    prof_begin(st);
-    if (fresh_flags && (e = launch_fill_int(w.flags, nflags, 0, st)) != hipSuccess) return e;
-    if ((e = launch_fill_int(w.ctrl, 2, 0, st)) != hipSuccess) return e;
-    prof_end(st, PK_AUX, 0.0);
-    FlowArgs<F> a;
-    a.m0 = m;
-    a.mats = nullptr;
-    a.tasks = w.tasks;
-    a.ntasks = (int)ntasks;
-    a.ctrl = w.ctrl;
-    a.flags = w.flags;
-    a.spin_limit = kSpinLimit;
-    prof_begin(st);
-    e = launch_flow<F, KIND>(a, 0, st);
-    prof_end(st, pk, flops);
-    return e;
-}
-
-// Run a launch between the timer marks of its family.
 template <typename Fn> hipError_t timed(hipStream_t st, int pk, double flops, Fn fn)
 {
     prof_begin(st);
@@ -50,9 +31,31 @@ template <typename Fn> hipError_t timed(hipStream_t st, int pk, double flops, Fn
     return e;
 }
 
+// One dataflow sweep over a task list (after zeroing the control words).
+template <typename F, int KIND>
+hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *ctrl, int *flags,
+                    int pk, double flops, hipStream_t st)
+{
+    if (nt == 0) return hipSuccess;
+    hipError_t r = launch_fill_int(ctrl, 2, 0, st);
+    if (r != hipSuccess) return r;
+    FlowArgs<F> a;
+    std::memset(&a, 0, sizeof(a));
+    a.mats = mats;
+    a.tasks = tasks;
+    a.ntasks = (int)nt;
+    a.ctrl = ctrl;
+    a.flags = flags;
+    a.spin_limit = kSpinLimit;
+    prof_begin(st);
+    r = launch_flow<F, KIND>(a, 0, st);
+    prof_end(st, pk, flops);
+    return r;
+}
+
 template <typename F>
 FlowMat<F> ph_mat(const F *T, int64_t ldt, const F *C, int64_t ldc, F *V, int64_t ldv,
-                  const double *dg, const int8_t *sgn, int64_t n)
+                  const double *dg, const int8_t *sgn, int64_t n, int64_t flag0)
 {
     FlowMat<F> m;
     std::memset(&m, 0, sizeof(m));
@@ -66,12 +69,13 @@ FlowMat<F> ph_mat(const F *T, int64_t ldt, const F *C, int64_t ldc, F *V, int64_
     m.sgn = sgn;
     m.n = (int)n;
     m.nbr = m.nbc = (int)nblocks(n);
+    m.flag0 = flag0;
     return m;
 }
 
 template <typename F>
 FlowMat<F> syl_mat(const F *T, int64_t ldt, F *V, int64_t ldv, const F *Rh, int64_t ldrh,
-                   double scale, const double *dg, int64_t n, int64_t p)
+                   double scale, const double *dg, int64_t n, int64_t p, int64_t flag0)
 {
     FlowMat<F> m;
     std::memset(&m, 0, sizeof(m));
@@ -87,279 +91,398 @@ FlowMat<F> syl_mat(const F *T, int64_t ldt, F *V, int64_t ldv, const F *Rh, int6
     m.nbr = (int)nblocks(p);
     m.nbc = (int)nblocks(n - p);
     m.rhs_scale = scale;
+    m.flag0 = flag0;
     return m;
 }
 
-double ulp_floor(int D, double umax, double tmax)
+// Byte layout of a run.  The tables and task lists are built in pinned host
+// memory at the same offsets they take in device memory (one copy uploads
+// them); the rest of each buffer is its own.  Sizes are upper bounds valid for
+// any diagonal: a matrix has at most nb^2 blocks in either form.
+struct Lay {
+    size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, shared;   // shared part
+    size_t ctrl, flags, ftasks, norms0, norms1, maxes, f32, dev;
+    size_t h_norm0, h_norm1, h_maxes, h_err, h_ftasks, host;
+    int64_t nflags_max, ntasks_max, ndiag_max;
+    std::vector<int64_t> off32;  // per matrix, in floats, of its three FP32 n x n arrays
+};
+
+Lay make_lay(const int64_t *ns, int nm, bool mixed)
 {
-    // rounding level of an FP64 residual block: (D + 1) * TB products per entry
+    Lay L;
+    int64_t sq = 0, nbsum = 0, f32 = 0;
+    L.off32.resize(nm);
+    for (int m = 0; m < nm; ++m) {
+        const int64_t nb = nblocks(ns[m]);
+        sq += nb * nb;
+        nbsum += nb;
+        L.off32[m] = f32;
+        if (mixed) f32 += 3 * ns[m] * ns[m];
+    }
+    L.nflags_max = L.ntasks_max = std::max<int64_t>(sq, 1);
+    L.ndiag_max = std::max<int64_t>(nbsum, 1);
+    size_t o = 0;
+    L.fm64 = o; o += al(nm * sizeof(FlowMat<double>));
+    L.fm32 = o; o += al(mixed ? nm * sizeof(FlowMat<float>) : 0);
+    L.fmc = o; o += al(mixed ? nm * sizeof(FlowMat<float>) : 0);
+    L.rm = o; o += al(mixed ? nm * sizeof(RefMat) : 0);
+    L.pm = o; o += al(nm * sizeof(PrepMat));
+    L.dtasks = o; o += al(L.ndiag_max * sizeof(int2));
+    L.tasks = o; o += al(L.ntasks_max * sizeof(int2));
+    L.shared = o;
+    size_t d = o;
+    L.ctrl = d; d += al(64 * sizeof(int));
+    L.flags = d; d += al(L.nflags_max * sizeof(int));
+    L.ftasks = d; d += al(mixed ? L.ntasks_max * sizeof(int2) : 0);
+    L.norms0 = d; d += al(mixed ? L.nflags_max * sizeof(double) : 0);
+    L.norms1 = d; d += al(mixed ? L.nflags_max * sizeof(double) : 0);
+    L.maxes = d; d += al(mixed ? 3 * nm * sizeof(unsigned long long) : 0);
+    L.f32 = d; d += al((size_t)f32 * sizeof(float));
+    L.dev = d;
+    size_t h = o;
+    L.h_norm0 = h; h += al(mixed ? L.nflags_max * sizeof(double) : 0);
+    L.h_norm1 = h; h += al(mixed ? L.nflags_max * sizeof(double) : 0);
+    L.h_maxes = h; h += al(mixed ? 3 * nm * sizeof(unsigned long long) : 0);
+    L.h_err = h; h += al(64);
+    L.h_ftasks = h; h += al(mixed ? L.ntasks_max * sizeof(int2) : 0);
+    L.host = h;
+    return L;
+}
+
+double ulp_floor(int kblocks, double umax, double tmax)
+{
+    // rounding level of an FP64 residual block: kblocks * TB products per entry
     // of size up to umax * max(umax, tmax), TB x TB entries
     const double eps = std::ldexp(1.0, -52);
-    return eps * (double)(D + 1) * TB * TB * umax * std::max(umax, tmax);
+    return eps * (double)kblocks * TB * TB * umax * std::max(umax, tmax);
+}
+
+// Algorithmic flops (Section 3 counting, real) of one matrix's launches.
+SweepFlops item_flops(const int8_t *s, const RealItem &it)
+{
+    SweepFlops f;
+    const int64_t n = it.n;
+    if (it.path == SIGNTRI_PATH_TRIVIAL || !s) return f;
+    const HostPlan p = plan_from_signs(s, n, false);
+    const double dn = (double)n, np = (double)p.n_pos, nn = (double)p.n_neg;
+    if (it.path == SIGNTRI_PATH_PS) {
+        // (p - 1 - i) + (j - p) multiply-adds per entry of X
+        f.syl = np * nn * (dn - 2.0);
+        f.resid = f.syl + 4.0 * np * nn;
+        return f;
+    }
+    const FlopCounter fc{s, n, TB, 1.0};
+    f.diag = fc.diag();
+    f.flow = p.w_ph - f.diag;
+    double cdiag = 0.0;
+    for (int64_t r0 = 0; r0 < n; r0 += TB) {
+        const double b = (double)std::min<int64_t>(TB, n - r0);
+        cdiag += b * (b - 1) * (b - 2) / 6.0;
+    }
+    // correction: two products per k strictly between i and j, off the diagonal blocks
+    f.corr = 4.0 * (dn * (dn - 1) * (dn - 2) / 6.0 - cdiag);
+    // residual: k = i .. j, two more terms per entry than the sweep
+    f.resid = f.flow + 2.0 * (2.0 * dn * (dn - 1) / 2.0 + 2.0 * np * nn);
+    return f;
 }
 
 }  // namespace
 
-FlowWs flow_ws_layout(char *base, int64_t n, bool mixed, size_t *total)
+void run_sizes(const int64_t *ns, int nmat, bool mixed, size_t *dev_bytes, size_t *host_bytes)
 {
-    const int64_t nb = std::max<int64_t>(nblocks(n), 1);
-    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    size_t off = 0;
-    FlowWs w;
-    std::memset(&w, 0, sizeof(w));
-    auto take = [&](size_t bytes) -> char * {
-        char *p = base ? base + off : nullptr;
-        off += al(bytes);
-        return p;
-    };
-    w.ctrl = (int *)take(64 * sizeof(int));
-    // ctrl: [0] ticket, [1] error word, [8..13] three maxima, [16..18] flag-reset tables
-    w.maxes = (unsigned long long *)(w.ctrl + 8);
-    w.flags = (int *)take((size_t)nb * nb * sizeof(int));
-    w.tasks = (int2 *)take((size_t)nb * nb * sizeof(int2));
-    if (mixed) {
-        w.ftasks = (int2 *)take((size_t)nb * nb * sizeof(int2));
-        w.norms[0] = (double *)take((size_t)nb * nb * sizeof(double));
-        w.norms[1] = (double *)take((size_t)nb * nb * sizeof(double));
-        w.ld32 = std::max<int64_t>(n, 1);
-        const size_t mat = (size_t)w.ld32 * std::max<int64_t>(n, 1) * sizeof(float);
-        w.T32 = (float *)take(mat);
-        w.U32 = (float *)take(mat);
-        w.E32 = (float *)take(mat);
+    const Lay L = make_lay(ns, nmat, mixed);
+    if (dev_bytes) *dev_bytes = L.dev;
+    if (host_bytes) *host_bytes = L.host;
+}
+
+int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, void *host_ws,
+                hipStream_t st, int *err)
+{
+    const Lay L = make_lay(ns, nmat, mixed);
+    int *herr = (int *)((char *)host_ws + L.h_err);
+    if (hipMemcpyAsync(herr, (char *)dev_ws + L.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    if (err) *err = herr[1];
+    return herr[1] ? SIGNTRI_EHIP : SIGNTRI_OK;
+}
+
+int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
+             void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
+             hipStream_t st)
+{
+    const int nm = (int)items.size();
+    if (nm == 0) return SIGNTRI_OK;
+    const bool mixed = mode != SIGNTRI_FP64, refine = mode == SIGNTRI_MIXED_REFINED;
+    std::vector<int64_t> ns(nm);
+    int64_t nmax = 0;
+    for (int m = 0; m < nm; ++m) {
+        ns[m] = items[m].n;
+        nmax = std::max(nmax, ns[m]);
     }
-    if (total) *total = off;
-    return w;
-}
+    const Lay L = make_lay(ns.data(), nm, mixed);
+    char *D = (char *)dev_ws, *H = (char *)host_ws;
+    FlowMat<double> *hf64 = (FlowMat<double> *)(H + L.fm64);
+    FlowMat<float> *hf32 = (FlowMat<float> *)(H + L.fm32);
+    FlowMat<float> *hfc = (FlowMat<float> *)(H + L.fmc);
+    RefMat *hrm = (RefMat *)(H + L.rm);
+    PrepMat *hpm = (PrepMat *)(H + L.pm);
+    int2 *hdt = (int2 *)(H + L.dtasks);
+    int2 *htk = (int2 *)(H + L.tasks);
+    int *ctrl = (int *)(D + L.ctrl);
+    int *flags = (int *)(D + L.flags);
+    unsigned long long *maxes = (unsigned long long *)(D + L.maxes);
+    float *f32 = (float *)(D + L.f32);
 
-size_t flow_host_bytes(int64_t n)
-{
-    const int64_t nb = std::max<int64_t>(nblocks(n), 1);
-    return (size_t)nb * nb * (2 * sizeof(double) + sizeof(int2)) + 256;  // + small words
-}
+    // ---- per-matrix geometry and tables
+    std::vector<int64_t> f0(nm, 0);
+    std::vector<int> nbr(nm, 0), nbc(nm, 0);
+    int64_t nflags = 0, ndiag = 0;
+    SweepFlops fl;
+    for (int m = 0; m < nm; ++m) {
+        const RealItem &it = items[m];
+        const int64_t n = it.n;
+        const bool ps = it.path == SIGNTRI_PATH_PS, triv = it.path == SIGNTRI_PATH_TRIVIAL;
+        nbr[m] = triv ? 0 : (int)(ps ? nblocks(it.p) : nblocks(n));
+        nbc[m] = triv ? 0 : (int)(ps ? nblocks(n - it.p) : nblocks(n));
+        f0[m] = nflags;
+        nflags += (int64_t)nbr[m] * nbc[m];
+        hpm[m] = PrepMat{it.T, it.ldt, it.U, it.ldu, n, it.sgn, triv ? 2 : (ps ? 1 : 0), it.p,
+                         (double)it.s};
+        if (ps)
+            hf64[m] = syl_mat<double>(it.T, it.ldt, it.U, it.ldu, it.T, it.ldt, 2.0 * it.s, it.dg,
+                                      n, it.p, f0[m]);
+        else
+            hf64[m] = ph_mat<double>(it.T, it.ldt, nullptr, 0, it.U, it.ldu, it.dg, it.sgn, n,
+                                     f0[m]);
+        if (!triv && !ps)
+            for (int64_t I = 0; I < nblocks(n); ++I) hdt[ndiag++] = make_int2(m, (int)I);
+        if (mixed) {
+            float *T32 = f32 + L.off32[m], *U32 = T32 + n * n, *E32 = U32 + n * n;
+            const int64_t ld = std::max<int64_t>(n, 1);
+            if (ps) {
+                hf32[m] = syl_mat<float>(T32, ld, U32, ld, T32, ld, 2.0 * it.s, it.dg, n, it.p,
+                                         f0[m]);
+                hfc[m] = syl_mat<float>(T32, ld, E32, ld, E32, ld, 1.0, it.dg, n, it.p, f0[m]);
+            } else {
+                hf32[m] = ph_mat<float>(T32, ld, nullptr, 0, U32, ld, it.dg, it.sgn, n, f0[m]);
+                hfc[m] = ph_mat<float>(T32, ld, U32, ld, E32, ld, it.dg, it.sgn, n, f0[m]);
+            }
+            RefMat &r = hrm[m];
+            std::memset(&r, 0, sizeof(r));
+            r.T = it.T;
+            r.ldt = it.ldt;
+            r.U = it.U;
+            r.ldu = it.ldu;
+            r.T32 = T32;
+            r.U32 = U32;
+            r.E32 = E32;
+            r.ld32 = ld;
+            r.sgn = it.sgn;
+            r.n = triv ? 0 : (int)n;
+            r.split = ps ? (int)it.p : 0;
+            r.nbr = nbr[m];
+            r.nbc = nbc[m];
+            r.two_s = 2.0 * it.s;
+            r.f0 = f0[m];
+            r.maxes = maxes + 3 * m;
+        }
+        if (prof && host_signs) {
+            const SweepFlops g = item_flops(host_signs[m], it);
+            fl.diag += g.diag;
+            fl.flow += g.flow;
+            fl.corr += g.corr;
+            fl.resid += g.resid;
+            fl.syl += g.syl;
+        }
+    }
+    // ---- task lists: Parlett-Higham blocks by superdiagonal D across the
+    // matrices (largest first), then Sylvester blocks by anti-diagonal
+    std::vector<int> order(nm);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+    int64_t nph = 0, nps = 0;
+    const int nbmax = (int)nblocks(nmax);
+    for (int Dd = 1; Dd < nbmax; ++Dd)
+        for (int m : order)
+            if (items[m].path == SIGNTRI_PATH_PH)
+                for (int I = 0; I + Dd < nbr[m]; ++I)
+                    htk[nph++] = make_int2(m, (I << 16) | (I + Dd));
+    for (int d = 0; d < 2 * nbmax; ++d)
+        for (int m : order)
+            if (items[m].path == SIGNTRI_PATH_PS)
+                for (int I = nbr[m] - 1; I >= 0; --I) {
+                    const int J = d - (nbr[m] - 1 - I);
+                    if (J >= 0 && J < nbc[m]) htk[nph + nps++] = make_int2(m, (I << 16) | J);
+                }
+    const int2 *dtk = (const int2 *)(D + L.tasks);
+    const int2 *dtk_ps = dtk + nph;
+    const int2 *ddt = (const int2 *)(D + L.dtasks);
 
-// FP64 Parlett-Higham: diagonal blocks, then the dataflow sweep.
-hipError_t sweep_ph_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                         const int8_t *sgn, const double *dg, const FlowWs &w,
-                         const SweepFlops &fl, hipStream_t st)
-{
     hipError_t e;
-    const int64_t nb = nblocks(n), ntasks = nb * (nb - 1) / 2;
-    e = timed(st, PK_AUX, 0.0, [&] {
-        hipError_t r = launch_fill_int(w.ctrl, 16, 0, st);  // control words and maxima
-        if (r == hipSuccess) r = launch_zero_lower(U, ldu, n, false, st);
-        if (r == hipSuccess && ntasks > 0) r = launch_tasks_tri((int)nb, 0, w.tasks, st);
-        return r;
-    });
-    if (e != hipSuccess) return e;
-    e = timed(st, PK_DIAG, fl.diag, [&] { return launch_diag_blocks(T, ldt, U, ldu, n, sgn, st); });
-    if (e != hipSuccess || ntasks == 0) return e;
-    return run_sweep<double, FLOW_MAIN>(ph_mat<double>(T, ldt, nullptr, 0, U, ldu, dg, sgn, n), w,
-                                        ntasks, nb * nb, true, PK_FLOW, fl.flow, st);
-}
-
-// FP64 Parlett-Sylvester for a diagonal grouped by sign: the first p entries
-// have sign s, the rest -s; U = [[s I, X], [0, -s I]].
-hipError_t sweep_ps_fp64(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                         int64_t p, int s, const double *dg, const FlowWs &w,
-                         const SweepFlops &fl, hipStream_t st)
-{
-    const int64_t nbr = nblocks(p), nbc = nblocks(n - p), ntasks = nbr * nbc;
-    hipError_t e = timed(st, PK_AUX, 0.0, [&] {
-        hipError_t r = launch_fill_int(w.ctrl, 16, 0, st);  // control words and maxima
-        if (r == hipSuccess) r = launch_fill_split_identity(U, ldu, n, p, (double)s, st);
-        if (r == hipSuccess) r = launch_tasks_rect((int)nbr, (int)nbc, 0, w.tasks, st);
-        return r;
-    });
-    if (e != hipSuccess) return e;
-    return run_sweep<double, FLOW_SYL>(syl_mat<double>(T, ldt, U, ldu, T, ldt, 2.0 * s, dg, n, p),
-                                       w, ntasks, nbr * nbc, true, PK_SYL, fl.syl, st);
-}
-
-// Reduced-precision sweep, then (mode MIXED_REFINED) refinement steps with FP64
-// residuals, and FP64 recomputation of the blocks that do not converge.
-// p == 0: Parlett-Higham; p > 0: Parlett-Sylvester with leading sign s.
-int sweep_mixed(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n,
-                const int8_t *sgn, const double *dg, int64_t p, int s, bool refine,
-                const signtri_options *opts, const FlowWs &w, void *host,
-                const SweepFlops &fl, hipStream_t st, signtri_info *info)
-{
-    const bool syl = p > 0;
-    const int64_t ld = w.ld32;
-    hipError_t e;
-#define HIPCHK(x)                                \
-    do {                                         \
-        if ((e = (x)) != hipSuccess) return SIGNTRI_EHIP; \
+#define HIPCHK(x)                                          \
+    do {                                                   \
+        if ((e = (x)) != hipSuccess) return SIGNTRI_EHIP;  \
     } while (0)
-    const int64_t nbr = syl ? nblocks(p) : nblocks(n), nbc = syl ? nblocks(n - p) : nbr;
-    const int64_t ntasks = syl ? nbr * nbc : nbr * (nbr - 1) / 2, nflags = nbr * nbc;
+    HIPCHK(hipMemcpyAsync(D, H, L.shared, hipMemcpyHostToDevice, st));
+    const FlowMat<double> *df64 = (const FlowMat<double> *)(D + L.fm64);
+    const FlowMat<float> *df32 = (const FlowMat<float> *)(D + L.fm32);
+    const FlowMat<float> *dfc = (const FlowMat<float> *)(D + L.fmc);
+    const RefMat *drm = (const RefMat *)(D + L.rm);
+    const PrepMat *dpm = (const PrepMat *)(D + L.pm);
+    auto clear_flags = [&](int v) {
+        return timed(st, PK_AUX, 0.0, [&] { return launch_fill_int(flags, nflags, v, st); });
+    };
+
+    // ---- outputs, diagonal blocks (FP64 in every mode)
     HIPCHK(timed(st, PK_AUX, 0.0, [&] {
-        hipError_t r = launch_fill_int(w.ctrl, 16, 0, st);  // control words and maxima
-        if (r == hipSuccess)
-            r = syl ? launch_fill_split_identity(U, ldu, n, p, (double)s, st)
-                    : launch_zero_lower(U, ldu, n, false, st);
-        if (r == hipSuccess && ntasks > 0)
-            r = syl ? launch_tasks_rect((int)nbr, (int)nbc, 0, w.tasks, st)
-                    : launch_tasks_tri((int)nbr, 0, w.tasks, st);
+        hipError_t r = launch_fill_int(ctrl, 16, 0, st);
+        if (r == hipSuccess) r = launch_prepare_b(dpm, nm, nmax, st);
         return r;
     }));
-    if (!syl)
-        HIPCHK(timed(st, PK_DIAG, fl.diag,
-                     [&] { return launch_diag_blocks(T, ldt, U, ldu, n, sgn, st); }));
-    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] {
-        return launch_to_f32(T, ldt, w.T32, U, ldu, w.U32, ld, n, &w.maxes[0], st);
-    }));
-    if (ntasks == 0) return SIGNTRI_OK;
+    HIPCHK(timed(st, PK_DIAG, fl.diag, [&] { return launch_diag_b(dpm, ddt, (int)ndiag, st); }));
+    if (nph + nps == 0) return SIGNTRI_OK;
 
-    // U0 in FP32
-    if (syl)
-        HIPCHK((run_sweep<float, FLOW_SYL>(
-            syl_mat<float>(w.T32, ld, w.U32, ld, w.T32, ld, 2.0 * s, dg, n, p), w, ntasks, nflags,
-            true, PK_SYL, fl.syl, st)));
-    else
-        HIPCHK((run_sweep<float, FLOW_MAIN>(
-            ph_mat<float>(w.T32, ld, nullptr, 0, w.U32, ld, dg, sgn, n), w, ntasks, nflags, true,
-            PK_FLOW, fl.flow, st)));
-    HIPCHK(timed(st, PK_CONVERT, 0.0,
-                 [&] { return launch_widen(w.U32, ld, U, ldu, n, p, &w.maxes[1], st); }));
+    if (!mixed) {
+        HIPCHK(clear_flags(0));
+        HIPCHK((run_flow<double, FLOW_MAIN>(df64, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, st)));
+        HIPCHK((run_flow<double, FLOW_SYL>(df64, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, st)));
+        return SIGNTRI_OK;
+    }
+
+    // ---- reduced precision: FP32 copies, U0 by the FP32 sweeps, widened into U
+    RefArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.mats = drm;
+    ra.nmat = nm;
+    HIPCHK(timed(st, PK_AUX, 0.0, [&] { return launch_fill_int((int *)maxes, 6 * nm, 0, st); }));
+    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_to_f32(ra, nmax, st); }));
+    HIPCHK(clear_flags(0));
+    HIPCHK((run_flow<float, FLOW_MAIN>(df32, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, st)));
+    HIPCHK((run_flow<float, FLOW_SYL>(df32, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, st)));
+    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_widen(ra, nmax, st); }));
     if (!refine) return SIGNTRI_OK;
 
+    double *norms[2] = {(double *)(D + L.norms0), (double *)(D + L.norms1)};
     auto resid = [&](double *norm2) -> hipError_t {
         return timed(st, PK_RESID, fl.resid, [&] {
-            if (syl)
-                return launch_resid_syl(T, ldt, U, ldu, n, p, 2.0 * s, w.tasks, (int)ntasks,
-                                        (int)nbr, (int)nbc, w.E32, ld, norm2, st);
-            return launch_resid(T, ldt, U, ldu, sgn, n, w.tasks, (int)ntasks, w.E32, ld, norm2,
-                                st);
+            hipError_t r = launch_resid(ra, false, dtk, (int)nph, norm2, st);
+            if (r == hipSuccess) r = launch_resid(ra, true, dtk_ps, (int)nps, norm2, st);
+            return r;
         });
     };
-    HIPCHK(resid(w.norms[0]));
+    HIPCHK(resid(norms[0]));
 
     const int max_steps = (opts && opts->max_refine_steps > 0) ? opts->max_refine_steps : 2;
     const double stall = (opts && opts->stall_ratio > 0) ? opts->stall_ratio : 0.5;
     const double conv = 1e-5;  // residual reduction that counts as converged
     const int64_t force = opts ? opts->force_stall : 0;
+    double *h0 = (double *)(H + L.h_norm0), *h1 = (double *)(H + L.h_norm1);
+    unsigned long long *hm = (unsigned long long *)(H + L.h_maxes);
+    int *herr = (int *)(H + L.h_err);
+    int2 *hft = (int2 *)(H + L.h_ftasks);
 
-    char *hb = (char *)host;
-    double *h0 = (double *)hb, *h1 = h0 + nflags;
-    int2 *hf = (int2 *)(h1 + nflags);
-    unsigned long long *hm = (unsigned long long *)(hf + nflags);  // 3 maxima
-    int *herr = (int *)(hm + 3);                                   // 2 control words
-    int64_t *hflag0 = (int64_t *)(herr + 2);
-    int *hnbc = (int *)(hflag0 + 1);
     // per block: residual norm before the first step, converged, hopeless (stalled)
     std::vector<double> rinit((size_t)nflags, 0.0);
     std::vector<char> ok((size_t)nflags, 0), hopeless((size_t)nflags, 0);
-    int steps = 0;
-    int cur = 0;
-    double emax_all = 0.0;
+    std::vector<double> crel(nm, 0.0);
+    int steps = 0, cur = 0;
     for (int step = 1; step <= max_steps; ++step) {
-        // correction E (FP32): residual in E32 on entry, E on exit
-        if (syl)
-            HIPCHK((run_sweep<float, FLOW_SYL>(
-                syl_mat<float>(w.T32, ld, w.E32, ld, w.E32, ld, 1.0, dg, n, p), w, ntasks, nflags,
-                true, PK_CORR, fl.syl, st)));
-        else
-            HIPCHK((run_sweep<float, FLOW_CORR>(
-                ph_mat<float>(w.T32, ld, w.U32, ld, w.E32, ld, dg, sgn, n), w, ntasks, nflags,
-                true, PK_CORR, fl.corr, st)));
-        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] {
-            hipError_t r = launch_fill_int((int *)&w.maxes[2], 2, 0, st);
-            if (r == hipSuccess) r = launch_add_correction(w.E32, ld, U, ldu, n, p, &w.maxes[2], st);
-            return r;
-        }));
-        HIPCHK(resid(w.norms[cur ^ 1]));
+        // correction E (FP32): the residual in E32 on entry, E on exit
+        HIPCHK(clear_flags(0));
+        HIPCHK((run_flow<float, FLOW_CORR>(dfc, dtk, nph, ctrl, flags, PK_CORR, fl.corr, st)));
+        HIPCHK((run_flow<float, FLOW_SYL>(dfc, dtk_ps, nps, ctrl, flags, PK_CORR, fl.syl, st)));
+        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_add_correction(ra, nmax, st); }));
+        HIPCHK(resid(norms[cur ^ 1]));
         steps = step;
         // convergence decision on the host
-        HIPCHK(hipMemcpyAsync(h0, w.norms[cur], nflags * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h1, w.norms[cur ^ 1], nflags * sizeof(double), hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(h0, norms[cur], nflags * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h1, norms[cur ^ 1], nflags * sizeof(double), hipMemcpyDeviceToHost,
                               st));
-        HIPCHK(hipMemcpyAsync(hm, w.maxes, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                              st));
-        HIPCHK(hipMemcpyAsync(herr, w.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hm, maxes, 3 * nm * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(herr, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (herr[1]) return SIGNTRI_EHIP;
-        double tmax, umax, emax;
-        std::memcpy(&tmax, &hm[0], 8);
-        std::memcpy(&umax, &hm[1], 8);
-        std::memcpy(&emax, &hm[2], 8);
-        emax_all = umax > 0 ? emax / umax : emax;
         bool pending = false;
-        for (int64_t I = 0; I < nbr; ++I)
-            for (int64_t J = syl ? 0 : I + 1; J < nbc; ++J) {
-                const int64_t f = I * nbc + J;
-                const double aprev = std::sqrt(h0[f]), a = std::sqrt(h1[f]);
-                if (step == 1) rinit[f] = aprev;
-                // K blocks in each entry's residual products
-                const int kb = syl ? (int)((nbr - I) + (J + 1)) : (int)(J - I + 1);
-                const bool forced = force == -1 || (force > 0 && force - 1 == f);
-                const bool good = !forced && a <= std::max(ulp_floor(kb - 1, umax, tmax),
-                                                           conv * rinit[f]);
-                ok[f] = good;
-                if (!good && (forced || a > stall * aprev)) hopeless[f] = 1;
-                if (!good && !hopeless[f]) pending = true;
-            }
+        for (int m = 0; m < nm; ++m) {
+            if (nbr[m] == 0) continue;
+            double tmax, umax, emax;
+            std::memcpy(&tmax, &hm[3 * m], 8);
+            std::memcpy(&umax, &hm[3 * m + 1], 8);
+            std::memcpy(&emax, &hm[3 * m + 2], 8);
+            crel[m] = umax > 0 ? emax / umax : emax;
+            const bool syl = items[m].path == SIGNTRI_PATH_PS;
+            for (int64_t I = 0; I < nbr[m]; ++I)
+                for (int64_t J = syl ? 0 : I + 1; J < nbc[m]; ++J) {
+                    const int64_t lf = I * nbc[m] + J, f = f0[m] + lf;
+                    const double aprev = std::sqrt(h0[f]), a = std::sqrt(h1[f]);
+                    if (step == 1) rinit[f] = aprev;
+                    // K blocks in each entry's residual products
+                    const int kb = syl ? (int)((nbr[m] - I) + (J + 1)) : (int)(J - I + 1);
+                    const bool forced = force == -1 || (nm == 1 && force > 0 && force - 1 == lf);
+                    const bool good = !forced && a <= std::max(ulp_floor(kb, umax, tmax),
+                                                               conv * rinit[f]);
+                    ok[f] = good;
+                    if (!good && (forced || a > stall * aprev)) hopeless[f] = 1;
+                    if (!good && !hopeless[f]) pending = true;
+                }
+        }
         cur ^= 1;
         if (!pending) break;
     }
-    std::vector<char> bad((size_t)nflags, 0);
-    bool any_bad = false;
-    for (int64_t I = 0; I < nbr; ++I)
-        for (int64_t J = syl ? 0 : I + 1; J < nbc; ++J) {
-            bad[I * nbc + J] = !ok[I * nbc + J];
-            any_bad |= bad[I * nbc + J] != 0;
-        }
-    if (info) {
-        info->refine_steps = steps;
-        info->correction_rel = emax_all;
-    }
-    if (!any_bad) return SIGNTRI_OK;
-    if (opts && opts->no_fallback) return SIGNTRI_ENOCONV;
 
-    // FP64 recomputation of the blocks that did not converge and of every block
-    // whose products read them.  In both forms block (I, J) is read by the
-    // blocks (I', J') with I' <= I and J' >= J (MAIN: U_IK U_KJ with K = I or J;
-    // SYL: A_I'K X_KJ with K = I, X_IK B_KJ' with K = J), so the cone is grown
-    // from below and from the left.
-    std::vector<char> mk(bad);
-    for (int64_t I = nbr - 1; I >= 0; --I)
-        for (int64_t J = syl ? 0 : I + 1; J < nbc; ++J) {
-            char m = mk[I * nbc + J];
-            if (I + 1 < nbr && (syl || I + 1 < J)) m |= mk[(I + 1) * nbc + J];
-            if (J - 1 >= (syl ? 0 : I + 1)) m |= mk[I * nbc + J - 1];
-            mk[I * nbc + J] = m;
-        }
-    int64_t nfb = 0;
-    if (syl) {
-        for (int64_t d = 0; d < nbr + nbc - 1; ++d)
-            for (int64_t I = nbr - 1; I >= 0; --I) {
-                const int64_t J = d - (nbr - 1 - I);
-                if (J >= 0 && J < nbc && mk[I * nbc + J]) hf[nfb++] = make_int2(0, (int)((I << 16) | J));
+    // ---- FP64 recomputation of the blocks that did not converge and of every
+    // block whose products read them.  In both forms block (I, J) is read by the
+    // blocks (I', J') with I' <= I and J' >= J (Parlett-Higham: U_IK U_KJ with
+    // K = I or J; Sylvester: A_I'K X_KJ with K = I, X_IK B_KJ' with K = J), so
+    // the cone is grown from below and from the left.
+    std::vector<char> mk((size_t)nflags, 0);
+    std::vector<int64_t> nfb(nm, 0);
+    for (int m = 0; m < nm; ++m) {
+        const bool syl = items[m].path == SIGNTRI_PATH_PS;
+        for (int64_t I = nbr[m] - 1; I >= 0; --I)
+            for (int64_t J = syl ? 0 : I + 1; J < nbc[m]; ++J) {
+                const int64_t f = f0[m] + I * nbc[m] + J;
+                char v = !ok[f];
+                if (I + 1 < nbr[m] && (syl || I + 1 < J)) v |= mk[f + nbc[m]];
+                if (J - 1 >= (syl ? 0 : I + 1)) v |= mk[f - 1];
+                mk[f] = v;
+                nfb[m] += v;
             }
-    } else {
-        for (int64_t D = 1; D < nbr; ++D)
-            for (int64_t I = 0; I + D < nbr; ++I)
-                if (mk[I * nbc + I + D]) hf[nfb++] = make_int2(0, (int)((I << 16) | (I + D)));
     }
-    if (info) info->fallback_tiles = nfb;
-    if (nfb == 0) return SIGNTRI_OK;
-    HIPCHK(hipMemcpyAsync(w.ftasks, hf, nfb * sizeof(int2), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_fill_int(w.flags, nflags, 1, st));
-    int64_t *flag0 = (int64_t *)(w.ctrl + 16);  // one-matrix tables for the flag reset
-    int *nbcd = w.ctrl + 18;
-    *hflag0 = 0;
-    *hnbc = (int)nbc;
-    HIPCHK(hipMemcpyAsync(flag0, hflag0, sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(nbcd, hnbc, sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_clear_task_flags(w.ftasks, nfb, flag0, nbcd, w.flags, st));
-    FlowWs wf = w;
-    wf.tasks = w.ftasks;
-    if (syl)
-        HIPCHK((run_sweep<double, FLOW_SYL>(syl_mat<double>(T, ldt, U, ldu, T, ldt, 2.0 * s, dg, n, p),
-                                            wf, nfb, nflags, false, PK_SYL, 0.0, st)));
-    else
-        HIPCHK((run_sweep<double, FLOW_MAIN>(ph_mat<double>(T, ldt, nullptr, 0, U, ldu, dg, sgn, n),
-                                             wf, nfb, nflags, false, PK_FLOW, 0.0, st)));
-    HIPCHK(hipMemcpyAsync(herr, w.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    int64_t fph = 0, fps = 0;
+    for (int Dd = 1; Dd < nbmax; ++Dd)
+        for (int m : order)
+            if (items[m].path == SIGNTRI_PATH_PH)
+                for (int I = 0; I + Dd < nbr[m]; ++I)
+                    if (mk[f0[m] + (int64_t)I * nbc[m] + I + Dd])
+                        hft[fph++] = make_int2(m, (I << 16) | (I + Dd));
+    for (int d = 0; d < 2 * nbmax; ++d)
+        for (int m : order)
+            if (items[m].path == SIGNTRI_PATH_PS)
+                for (int I = nbr[m] - 1; I >= 0; --I) {
+                    const int J = d - (nbr[m] - 1 - I);
+                    if (J >= 0 && J < nbc[m] && mk[f0[m] + (int64_t)I * nbc[m] + J])
+                        hft[fph + fps++] = make_int2(m, (I << 16) | J);
+                }
+    for (int m = 0; m < nm; ++m)
+        if (items[m].info) {
+            items[m].info->refine_steps = nbr[m] ? steps : 0;
+            items[m].info->correction_rel = crel[m];
+            items[m].info->fallback_tiles = nfb[m];
+        }
+    if (fph + fps == 0) return SIGNTRI_OK;
+    if (opts && opts->no_fallback) return SIGNTRI_ENOCONV;
+    int2 *dft = (int2 *)(D + L.ftasks);
+    HIPCHK(hipMemcpyAsync(dft, hft, (fph + fps) * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIPCHK(clear_flags(1));
+    HIPCHK(timed(st, PK_AUX, 0.0,
+                 [&] { return launch_clear_task_flags(dft, fph + fps, df64, flags, st); }));
+    HIPCHK((run_flow<double, FLOW_MAIN>(df64, dft, fph, ctrl, flags, PK_FLOW, 0.0, st)));
+    HIPCHK((run_flow<double, FLOW_SYL>(df64, dft + fph, fps, ctrl, flags, PK_SYL, 0.0, st)));
+    HIPCHK(hipMemcpyAsync(herr, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (herr[1]) return SIGNTRI_EHIP;
 #undef HIPCHK

@@ -214,18 +214,19 @@ def sign_tri_batched(Ts, mode: str = "fp64", outs=None, workspace=None, stream=N
     if not Ts:
         return [], []
     dt = _dtype_code(Ts[0])
-    layouts = [_layout(t) for t in Ts]
+    layouts = [_layout(t) if t.shape[0] else (COL_MAJOR, 1) for t in Ts]
     if any(l is None for l in layouts):
         raise ValueError("every T must be column- or row-major strided")
-    layout = layouts[0][0]
+    nonempty = [l for t, l in zip(Ts, layouts) if t.shape[0] > 1]
+    layout = nonempty[0][0] if nonempty else COL_MAJOR
     Us = outs if outs is not None else [empty_like_layout(t) for t in Ts]
     B = len(Ts)
     P = ctypes.c_void_p * B
     I = ctypes.c_int64 * B
-    tp = P(*[t.data_ptr() for t in Ts])
-    up = P(*[u.data_ptr() for u in Us])
+    tp = P(*[t.data_ptr() if t.shape[0] else None for t in Ts])
+    up = P(*[u.data_ptr() if u.shape[0] else None for u in Us])
     ldt = I(*[l[1] for l in layouts])
-    ldu = I(*[_layout(u)[1] for u in Us])
+    ldu = I(*[_layout(u)[1] if u.shape[0] else 1 for u in Us])
     ns = I(*[t.shape[0] for t in Ts])
     infos = (Info * B)()
     ws_ptr, ws_bytes = None, 0

@@ -115,3 +115,40 @@ def test_planner_choice_rule():
 def test_planner_rejects_bad_signs():
     with pytest.raises(ValueError):
         signtri.plan_host(np.array([1, 0, -1], dtype=np.int8))
+
+
+def test_batched_argument_validation_without_device_work():
+    L = signtri.lib()
+    P = ctypes.c_void_p * 2
+    I = ctypes.c_int64 * 2
+    T = P(0x1000, 0x2000)
+    U = P(0x100000, 0x200000)
+    n = I(4, 4)
+    ld = I(4, 4)
+    bad_ld = I(4, 3)
+    neg = I(4, -1)
+    call = lambda t, lt, u, lu, nn, b, dt=0, lay=0, mode=0: L.signtri_batched(
+        t, lt, u, lu, nn, b, dt, lay, mode, None, 0, None, None, None)
+    assert call(None, ld, U, ld, n, 2) == -1
+    assert call(T, None, U, ld, n, 2) == -2
+    assert call(T, ld, None, ld, n, 2) == -3
+    assert call(T, bad_ld, U, ld, n, 2) == -2
+    assert call(T, ld, U, bad_ld, n, 2) == -4
+    assert call(T, ld, U, ld, neg, 2) == -5
+    assert call(T, ld, U, ld, n, -1) == -6
+    assert call(T, ld, U, ld, n, 2, dt=9) == -7
+    assert call(T, ld, U, ld, n, 2, lay=9) == -8
+    assert call(T, ld, U, ld, n, 2, mode=9) == -9
+    assert call(T, ld, U, ld, n, 0) == 0
+    # complex and row-major batches are not implemented (after validation)
+    assert call(T, ld, U, ld, n, 2, dt=1) == 5
+    assert call(T, ld, U, ld, n, 2, lay=1) == 5
+
+
+def test_batched_workspace_size():
+    I = ctypes.c_int64 * 3
+    L = signtri.lib()
+    a = L.signtri_batched_workspace_size(I(32, 100, 1000), 3, 0, 0)
+    b = L.signtri_batched_workspace_size(I(32, 100, 1000), 3, 0, 1)
+    assert 0 < a < b
+    assert L.signtri_batched_workspace_size(I(32, -1, 5), 3, 0, 0) == 0

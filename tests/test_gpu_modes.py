@@ -65,6 +65,7 @@ def test_parlett_sylvester(dev, n, p, first, mode):
     T = grouped(n, p, first, rng)
     U, info, _ = check(T, dev, mode=mode, algo="ps")
     assert info["path_name"] == "ps"
+    assert info["fallback_tiles"] == 0  # the refinement itself reaches the bar
     # the diagonal blocks of a sign-grouped sign(T) are exactly +-I
     assert np.array_equal(U[:p, :p], first * np.eye(p))
     assert np.array_equal(U[p:, p:], -first * np.eye(n - p))
