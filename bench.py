@@ -36,11 +36,65 @@ def parse():
     ap.add_argument("--negatives", type=int, default=64)
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="order of the leading principal block the CPU oracle is timed on "
+                         "(0: the whole matrix)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--check-block", type=int, default=1536)
     ap.add_argument("--tile", type=int, default=0, help="block size 32 or 64 (0: library default)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (default: tune each mode before its warm-up)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def kernel_name(family, mode, tile):
+    """The kernel behind one of the library's timer families, as rocprofv3 names it."""
+    fp = "double" if mode == "fp64" else "float"
+    return {"flow": "k_flow<%s, 0>" % fp, "corr": "k_flow<float, 1>", "syl": "k_flow<%s, 2>" % fp,
+            "resid": "k_resid", "gemm": "k_wave_gemm<double, %d>" % tile,
+            "solve": "k_solve_r<double, %d, 256>" % tile}.get(family)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the rocprofv3 --pmc summaries under
+    profiles/, if the kernel's sources are unchanged since they were taken, else None."""
+    import glob
+    import hashlib
+    import re
+
+    if not kernel:
+        return None
+    pat = re.compile(r"^traffic-bytes-per-dispatch `([^`]*)` (\S+) sources (\S+) sha256 (\w+)")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = pat.match(line)
+            if not m or m.group(1) != kernel:
+                continue
+            h = hashlib.sha256()
+            try:
+                for src in m.group(3).split("+"):
+                    h.update(open(os.path.join(ROOT, src), "rb").read())
+            except OSError:
+                continue
+            if h.hexdigest()[:len(m.group(4))] == m.group(4):
+                return float(m.group(2))
+    return None
+
+
+def calibrate_copy(torch, mib):
+    """A plain elementwise copy of known size: reads and writes mib MiB once.
+    Under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE give the scale from the
+    counters to bytes."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 launches, each %d MiB read + %d MiB written" % (mib, mib))
 
 
 def time_mode(signtri, torch, Tg, mode, steps, warmup, opts):
@@ -93,6 +147,9 @@ def main():
     import numpy as np
     import torch
 
+    if args.calibrate_copy:
+        calibrate_copy(torch, args.calibrate_copy)
+        return
     from paper_1607_06303_amd import signtri, workloads
 
     signtri.lib()  # fail loudly if the HIP library is missing
@@ -106,8 +163,15 @@ def main():
 
     opts = {"tile": args.tile} if args.tile else None
     results = {}
+    tuned = {}
     for mode in [m for m in args.modes.split(",") if m]:
         try:
+            if not args.no_tune and not opts:
+                # part of setup, outside the timed region: pick the sweep variant and grid
+                tuned[mode] = signtri.autotune(Tg, mode=mode, reps=2)
+                log("mode %s: tuned -> %s tile %d, %d workgroups/CU (%.3f ms)"
+                    % (mode, tuned[mode]["sweep_name"], tuned[mode]["tile"],
+                       tuned[mode]["wgs_per_cu"], tuned[mode]["ms"]))
             U, info, ms = time_mode(signtri, torch, Tg, mode, args.steps, args.warmup, opts)
         except signtri.SignTriError as e:
             log("mode %s unavailable: %s" % (mode, e))
@@ -147,24 +211,27 @@ def main():
     # the reduced-precision modes run their sweeps on FP32 matrix cores, the residual in FP64
     precision = "fp32" if headline in ("mixed", "fp32") and fam in ("flow", "corr", "syl") else "fp64"
     achieved = flops / (ms_k * 1e-3) / 1e12 if ms_k > 0 else 0.0
+    kname = kernel_name(fam, headline, H["info"]["tile"])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[precision],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[precision], "traffic": None,
-                "kernel_family": fam, "launches": launches,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[precision],
+                "traffic": measured_traffic(kname), "traffic_unit": "bytes per launch",
+                "kernel": kname, "kernel_family": fam, "launches": launches,
                 "avg_launch_ms": ms_k / max(launches, 1)}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        m = min(args.cpu_sample, n)
+        m = min(args.cpu_sample, n) if args.cpu_sample > 0 else n
         log("cpu baseline: oracle on the leading %d x %d block" % (m, m))
         t0 = time.perf_counter()
         oracle.sign_tri(T[:m, :m])
         dt = time.perf_counter() - t0
         cpu = {"value": m ** 3 / 3.0 / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "leading %dx%d principal block of the same T (its sign is the leading "
-                         "block of sign(T)); %.1f s" % (m, m, dt)}
+               "sample": ("the whole T (one FP64 oracle call, %.1f s)" % dt if m == n else
+                          "leading %dx%d principal block of the same T (its sign is the leading "
+                          "block of sign(T)); %.1f s" % (m, m, dt))}
 
     out = {
         "metric": "GFLOP/s (n^3/3) for sign(T) n=8192, mixed+refined vs FP64 at 1e-11 rel err",
@@ -186,6 +253,7 @@ def main():
                       "err_sampled": r.get("err_sampled"), "inv_u2": r.get("inv_u2"),
                       "inv_comm": r.get("inv_comm"), "path": r["info"]["path_name"],
                       "refine_steps": r["info"]["refine_steps"], "tile": r["info"]["tile"],
+                      "sweep": r["info"]["sweep_name"], "wgs_per_cu": r["info"]["wgs_per_cu"],
                       "fallback_tiles": r["info"]["fallback_tiles"],
                       "kernels": {k: {"ms": v[0], "launches": v[1],
                                       "tflops": (v[2] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}

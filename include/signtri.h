@@ -94,12 +94,27 @@ typedef struct {
     int64_t fallback_tiles;   /* blocks recomputed in FP64 after a stalled refinement     */
     double correction_rel;    /* max |correction| / max |U| of the last refinement step   */
     int64_t bad_index;        /* 1-based index of the offending diagonal (EDOMAIN), else 0 */
+    int32_t sweep;            /* SIGNTRI_SWEEP_* that ran (0 for the trivial path)        */
+    int32_t wgs_per_cu;       /* dataflow sweep: persistent workgroups per compute unit   */
 } signtri_info;
+
+/* How the off-diagonal blocks are scheduled.
+ * DATAFLOW: one persistent kernel per sweep; workgroups take 32 x 32 blocks in
+ *   dependency order and wait on per-block completion flags (real T, every
+ *   mode, both the substitution and the Sylvester form).
+ * SUPERDIAG: one product launch and one solve launch per block superdiagonal,
+ *   with a one-superdiagonal lookahead on a second stream, replayed from a
+ *   captured graph (FP64 only: real with 32 x 32 or 64 x 64 blocks, complex
+ *   with 32 x 32; the substitution only).
+ * AUTO: the choice recorded by signtri_autotune() for this dtype, mode, path
+ *   and size class, else DATAFLOW for real T and SUPERDIAG for complex T. */
+enum { SIGNTRI_SWEEP_AUTO = 0, SIGNTRI_SWEEP_DATAFLOW = 1, SIGNTRI_SWEEP_SUPERDIAG = 2 };
 
 /* Tunables; zero-initialise for defaults. */
 typedef struct {
-    int32_t tile;                /* block size: 0 = default (32); 64 selects, for real FP64
-                                    only, the two-stream superdiagonal sweep             */
+    int32_t tile;                /* block size: 0 = tuned choice or 32; 64 is available on
+                                    the superdiagonal sweep of real FP64 only (and selects
+                                    that sweep when `sweep` is AUTO)                      */
     int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2)   */
     double stall_ratio;          /* mixed mode: a block stalls when a step leaves its
                                     residual above this fraction of the previous one
@@ -112,6 +127,10 @@ typedef struct {
                                     stalled when this is 1 + I * nb + J (nb = block count
                                     of the row index space), every block when -1, none
                                     when 0                                               */
+    int32_t sweep;               /* SIGNTRI_SWEEP_*; 0 = tuned choice or default           */
+    int32_t wgs_per_cu;          /* dataflow sweep: persistent workgroups per compute unit,
+                                    0 = tuned choice, else as many as fit; values above
+                                    what fits are clamped to it                          */
 } signtri_options;
 
 /*
@@ -184,6 +203,50 @@ int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U)
  */
 int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype,
                       signtri_info *info);
+
+/*
+ * Autotuner.  The sweep variant and the dataflow grid that run fastest depend
+ * on the order, the inertia and the mode, so they are measured rather than
+ * modelled.  A table, keyed by (dtype, mode, path, size class ceil(log2 n)),
+ * holds the best choice measured so far; signtri() consults it for every
+ * option left at 0 (sweep, tile, wgs_per_cu).  The table lives in process
+ * memory; if the environment variable SIGNTRI_TUNE_FILE names a file, the
+ * table is read from it at the first lookup, and signtri_tune_save() writes
+ * it back.
+ */
+typedef struct {
+    int32_t dtype, mode, path;  /* key: signtri_dtype, signtri_mode, SIGNTRI_PATH_PH/_PS */
+    int32_t log2n;              /* key: ceil(log2 n)                                      */
+    int32_t sweep, tile, wgs_per_cu;  /* the choice                                       */
+    double ms;                  /* its measured time per call, milliseconds               */
+} signtri_tune_entry;
+
+/*
+ * Time every candidate (sweep variant, block size, dataflow workgroups per
+ * compute unit) on this column-major T (device; U is overwritten and holds
+ * sign(T) on return), `reps` timed calls each after one untimed call, on
+ * `stream`; record the fastest in the table and return it in *best (host).
+ * Every candidate computes the same sign(T) to the same accuracy.  Waits for
+ * the stream.  Returns 0, -p for argument p, or the first error of a call
+ * (SIGNTRI_EDOMAIN, ...).  For the trivial path (one sign) nothing is
+ * recorded and best->sweep is 0.
+ */
+int signtri_autotune(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n,
+                     signtri_dtype dtype, signtri_mode mode, signtri_algo algo,
+                     void *stream, int32_t reps, signtri_tune_entry *best);
+
+/* The recorded choice for this key, copied to *out: 1 if found, else 0. */
+int signtri_tune_lookup(signtri_dtype dtype, signtri_mode mode, int32_t path, int64_t n,
+                        signtri_tune_entry *out);
+
+/* Write the table as text (one entry per line) / merge a file written so.
+ * Return 0, or -1 if the file cannot be opened or holds a malformed line
+ * (nothing is merged then). */
+int signtri_tune_save(const char *path);
+int signtri_tune_load(const char *path);
+
+/* Forget every recorded choice. */
+void signtri_tune_clear(void);
 
 /* Release the library-owned workspace buffers (all devices). */
 void signtri_release(void);

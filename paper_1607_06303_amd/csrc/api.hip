@@ -18,17 +18,15 @@ struct Layout {
     size_t scan = 0, sgn = 0, dg = 0, flow = 0, tcopy = 0, ucopy = 0;
     size_t zbuf = 0, zbufs[2] = {0, 0}, ebuf = 0, total = 0;
     int64_t zslots = 0;
-    bool flow_path = false;  // real, 32 x 32 blocks: the dataflow sweeps
+    bool flow_path = false;  // the dataflow sweeps (32 x 32 blocks)
 };
 
-// Real matrices run the dataflow sweeps (32 x 32 blocks) unless the two-stream
-// 64 x 64 sweep is requested; complex matrices run the superdiagonal sweep.
-bool uses_flow(signtri_dtype dtype, int tb) { return dtype == SIGNTRI_R64 && tb == 32; }
-
+// Workspace layout of one call.  The prefix (scan result, signs, diagonal, the
+// column-major copies of row-major arguments) does not depend on the sweep, so
+// it can be used before the sweep is chosen.
 Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
-                  signtri_algo algo, int tb)
+                  int tb, bool flow)
 {
-    (void)algo;
     const bool cplx = dtype == SIGNTRI_C128;
     const size_t es = cplx ? 16 : 8;
     Layout L;
@@ -38,11 +36,19 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri
     L.sgn = off;
     off += align_up((size_t)std::max<int64_t>(n, 1));
     L.dg = off;
-    off += align_up((size_t)std::max<int64_t>(n, 1) * sizeof(double));
-    L.flow_path = uses_flow(dtype, tb);
-    if (L.flow_path) {
+    off += align_up((size_t)std::max<int64_t>(n, 1) * sizeof(double) * (cplx ? 2 : 1));
+    if (layout == SIGNTRI_ROW_MAJOR) {
+        // column-major copies of T and U (leading dimension n)
+        const size_t mat = (size_t)std::max<int64_t>(n, 1) * std::max<int64_t>(n, 1) * es;
+        L.tcopy = off;
+        off += align_up(mat);
+        L.ucopy = off;
+        off += align_up(mat);
+    }
+    L.flow_path = flow;
+    if (flow) {
         size_t fb = 0;
-        run_sizes(&n, 1, mode != SIGNTRI_FP64, &fb, nullptr);
+        run_sizes(&n, 1, mode != SIGNTRI_FP64, cplx, &fb, nullptr);
         L.flow = off;
         off += align_up(fb);
     } else {
@@ -59,26 +65,65 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri
             off += align_up((size_t)ph_real_edge_slots(n, tb) * tb * tb * es);
         }
     }
-    if (layout == SIGNTRI_ROW_MAJOR) {
-        // column-major copies of T and U (leading dimension n)
-        const size_t mat = (size_t)std::max<int64_t>(n, 1) * std::max<int64_t>(n, 1) * es;
-        L.tcopy = off;
-        off += align_up(mat);
-        L.ucopy = off;
-        off += align_up(mat);
-    }
     L.total = off;
     return L;
 }
 
-// Workspace valid for every block size the call may choose.
+// Workspace valid for every sweep and block size the call may choose.
 size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
                  signtri_algo algo)
 {
-    size_t m = layout_for(n, dtype, layout, mode, algo, 32).total;
-    if (dtype == SIGNTRI_R64 && mode == SIGNTRI_FP64)
-        m = std::max(m, layout_for(n, dtype, layout, mode, algo, 64).total);
+    (void)algo;
+    size_t m = layout_for(n, dtype, layout, mode, 32, true).total;
+    if (mode == SIGNTRI_FP64) {
+        m = std::max(m, layout_for(n, dtype, layout, mode, 32, false).total);
+        if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, layout, mode, 64, false).total);
+    }
     return m;
+}
+
+// Option checks that do not depend on T: -13 for values out of range,
+// SIGNTRI_ENOTSUP for combinations no sweep implements.
+int check_options(const signtri_options *o, signtri_dtype dtype, signtri_mode mode)
+{
+    if (!o) return SIGNTRI_OK;
+    if (o->tile != 0 && o->tile != 32 && o->tile != 64) return -13;
+    if (o->sweep < SIGNTRI_SWEEP_AUTO || o->sweep > SIGNTRI_SWEEP_SUPERDIAG) return -13;
+    if (o->wgs_per_cu < 0) return -13;
+    const bool cplx = dtype == SIGNTRI_C128;
+    if (cplx && o->tile == 64) return SIGNTRI_ENOTSUP;
+    if (mode != SIGNTRI_FP64 && (o->sweep == SIGNTRI_SWEEP_SUPERDIAG || o->tile == 64))
+        return SIGNTRI_ENOTSUP;
+    if (o->sweep == SIGNTRI_SWEEP_DATAFLOW && o->tile == 64) return SIGNTRI_ENOTSUP;
+    return SIGNTRI_OK;
+}
+
+// Fill the options left at 0 from the tuning table, then from the defaults.
+signtri_options resolve_options(const signtri_options *opts, signtri_dtype dtype,
+                                signtri_mode mode, int path, int64_t n)
+{
+    signtri_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    signtri_tune_entry te;
+    if ((o.sweep == 0 || o.wgs_per_cu == 0) && path != SIGNTRI_PATH_TRIVIAL &&
+        tune_find(dtype, mode, path, n, &te)) {
+        // a recorded block size belongs to its sweep: take both or neither
+        if (o.sweep == 0 && (o.tile == 0 || o.tile == te.tile)) {
+            o.sweep = te.sweep;
+            o.tile = te.tile;
+        }
+        if (o.wgs_per_cu == 0 && o.sweep == SIGNTRI_SWEEP_DATAFLOW) o.wgs_per_cu = te.wgs_per_cu;
+    }
+    if (o.sweep == 0) o.sweep = o.tile == 64 ? SIGNTRI_SWEEP_SUPERDIAG : SIGNTRI_SWEEP_DATAFLOW;
+    if (o.tile == 0) o.tile = 32;
+    if (o.sweep == SIGNTRI_SWEEP_DATAFLOW) {
+        const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, dtype == SIGNTRI_C128);
+        if (o.wgs_per_cu <= 0 || o.wgs_per_cu > mx) o.wgs_per_cu = mx;
+    } else {
+        o.wgs_per_cu = 0;
+    }
+    return o;
 }
 
 // Bumped whenever the library-owned workspace moves; part of every graph key.
@@ -266,7 +311,7 @@ BatchLayout batch_layout(const int64_t *n, int64_t batch, signtri_mode mode)
     for (int m = 0; m < nm; ++m)
         if (n[m] > 0) ns.push_back(n[m]);
     size_t rd = 0, rh = 0;
-    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, &rd, &rh);
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false, &rd, &rh);
     B.run = o;
     B.dev = o + rd;
     B.run_host = align_up(B.sgn_end);
@@ -299,7 +344,8 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
                        const signtri_options *opts, char *run_dev, hipStream_t st, int device)
 {
     std::vector<int64_t> key{(int64_t)mode, (int64_t)device, (int64_t)(intptr_t)run_dev,
-                             (int64_t)ws_generation().load(), (int64_t)items.size()};
+                             (int64_t)ws_generation().load(), (int64_t)items.size(),
+                             (int64_t)(opts ? opts->wgs_per_cu : 0)};
     std::vector<int64_t> ns;
     for (const RealItem &it : items) {
         key.insert(key.end(), {(int64_t)(intptr_t)it.T, it.ldt, (int64_t)(intptr_t)it.U, it.ldu,
@@ -315,7 +361,7 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
             return hipGraphLaunch(hit.exec, st) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
         }
     size_t host_bytes = 0;
-    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, nullptr, &host_bytes);
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false, nullptr, &host_bytes);
     BatchGraph g;
     g.key = key;
     if (hipHostMalloc(&g.host, std::max<size_t>(host_bytes, 256), hipHostMallocDefault) !=
@@ -429,13 +475,10 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     const bool cplx = dtype == SIGNTRI_C128;
     const size_t es = cplx ? 16 : 8;
     if (n > 0 && ranges_overlap(T, extent_bytes(n, ldt, es), U, extent_bytes(n, ldu, es))) return -3;
-    if (opts && opts->tile != 0 && opts->tile != 32 && opts->tile != 64) return -13;
+    if (int rc = check_options(opts, dtype, mode)) return rc;
     if (n == 0) return SIGNTRI_OK;
-    if (cplx && mode != SIGNTRI_FP64) return SIGNTRI_ENOTSUP;
 
-    int tb = ph_tile_size(cplx, opts ? opts->tile : 0);
-    if (mode != SIGNTRI_FP64) tb = 32;  // reduced precision runs on the dataflow sweeps
-    const Layout L = layout_for(n, dtype, layout, mode, algo, tb);
+    const Layout L0 = layout_for(n, dtype, layout, mode, 32, false);  // the common prefix
     const size_t need = max_total(n, dtype, layout, mode, algo);
     if (workspace) {
         if (ws_bytes < need) return SIGNTRI_EWORKSPACE;
@@ -445,7 +488,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     }
     void *hostbuf = nullptr;
     size_t run_host = 0;
-    if (L.flow_path) run_sizes(&n, 1, mode != SIGNTRI_FP64, nullptr, &run_host);
+    run_sizes(&n, 1, mode != SIGNTRI_FP64, cplx, nullptr, &run_host);
     const size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n) + run_host;
     if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
     char *hb = (char *)hostbuf;
@@ -453,31 +496,31 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
 
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    ScanResult *scan = (ScanResult *)(ws + L.scan);
-    int8_t *sgn = (int8_t *)(ws + L.sgn);
-    double *dg = (double *)(ws + L.dg);
+    ScanResult *scan = (ScanResult *)(ws + L0.scan);
+    int8_t *sgn = (int8_t *)(ws + L0.sgn);
+    double *dg = (double *)(ws + L0.dg);
 
     // row-major arguments run on column-major copies
     const void *Tc = T;
     void *Uc = U;
     int64_t ldtc = ldt, lduc = ldu;
     if (layout == SIGNTRI_ROW_MAJOR) {
-        Tc = ws + L.tcopy;
-        Uc = ws + L.ucopy;
+        Tc = ws + L0.tcopy;
+        Uc = ws + L0.ucopy;
         ldtc = lduc = n;
         if (launch_transpose(T, ldt, (void *)Tc, n, n, cplx, st) != hipSuccess) return SIGNTRI_EHIP;
     }
 
-    if (launch_scan(Tc, ldtc, n, cplx, sgn, cplx ? nullptr : dg, scan, st) != hipSuccess)
+    if (launch_scan(Tc, ldtc, n, cplx, sgn, dg, scan, st) != hipSuccess)
         return SIGNTRI_EHIP;
     // scan result and signs are adjacent in the workspace: one copy
-    if (hipMemcpyAsync(hb, ws + L.scan, L.sgn - L.scan + (size_t)n, hipMemcpyDeviceToHost, st) !=
+    if (hipMemcpyAsync(hb, ws + L0.scan, L0.sgn - L0.scan + (size_t)n, hipMemcpyDeviceToHost, st) !=
         hipSuccess)
         return SIGNTRI_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return SIGNTRI_EHIP;
     ScanResult sr;
     std::memcpy(&sr, hb, sizeof(sr));
-    const int8_t *hs = (const int8_t *)(hb + (L.sgn - L.scan));
+    const int8_t *hs = (const int8_t *)(hb + (L0.sgn - L0.scan));
     if (sr.bad_index < n) {
         if (info) info->bad_index = sr.bad_index + 1;
         return SIGNTRI_EDOMAIN;
@@ -491,16 +534,28 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         if (p.ps_sign == 0) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PS;
     }
-    if (path == SIGNTRI_PATH_PS && !L.flow_path) {
-        if (algo == SIGNTRI_PS) return SIGNTRI_ENOTSUP;
-        path = SIGNTRI_PATH_PH;  // the Sylvester form runs on the real dataflow sweeps
+    signtri_options eo = resolve_options(opts, dtype, mode, path, n);
+    if (path == SIGNTRI_PATH_PS && eo.sweep != SIGNTRI_SWEEP_DATAFLOW) {
+        // the Sylvester form runs on the dataflow sweeps only
+        const bool pinned = opts && (opts->sweep == SIGNTRI_SWEEP_SUPERDIAG || opts->tile == 64);
+        if (algo == SIGNTRI_PS && pinned) return SIGNTRI_ENOTSUP;
+        if (pinned) {
+            path = SIGNTRI_PATH_PH;
+        } else {
+            eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
+            eo.tile = 32;
+            eo.wgs_per_cu = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, cplx);
+        }
     }
+    const bool flow = eo.sweep == SIGNTRI_SWEEP_DATAFLOW;
+    const int tb = eo.tile;
+    const Layout L = layout_for(n, dtype, layout, mode, tb, flow);
 
     int rc = SIGNTRI_OK;
     hipError_t e = hipSuccess;
     if (path == SIGNTRI_PATH_TRIVIAL) {
         e = launch_fill_pm_identity(Uc, lduc, n, cplx, p.n_pos > 0 ? 1.0 : -1.0, st);
-    } else if (L.flow_path) {
+    } else if (flow) {
         std::vector<RealItem> items(1);
         RealItem &it = items[0];
         it.T = (const double *)Tc;
@@ -513,9 +568,10 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         it.s = p.ps_sign;
         it.sgn = sgn;
         it.dg = dg;
+        it.cplx = cplx;
         it.info = info;
         const int8_t *hsv[1] = {hs};
-        rc = run_real(items, mode, opts, ws + L.flow, hflow, prof_on(), hsv, st);
+        rc = run_real(items, mode, &eo, ws + L.flow, hflow, prof_on(), hsv, st);
     } else {
         PhArgs a;
         a.T = Tc;
@@ -530,7 +586,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         a.ebuf = ws + L.ebuf;
         a.zslots = L.zslots;
         a.hsgn = hs;
-        a.max_splits = opts ? opts->max_splits : 0;
+        a.max_splits = eo.max_splits;
         a.tile = tb;
         int device = 0;
         if (hipGetDevice(&device) != hipSuccess) return SIGNTRI_EHIP;
@@ -541,14 +597,18 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
         return SIGNTRI_EHIP;
     // with info requested, wait and report a dependency-wait timeout of the sweep
-    if (info && L.flow_path && path != SIGNTRI_PATH_TRIVIAL && mode != SIGNTRI_MIXED_REFINED) {
+    if (info && flow && path != SIGNTRI_PATH_TRIVIAL && mode != SIGNTRI_MIXED_REFINED) {
         int herr = 0;
-        if ((rc = sweep_error(ws + L.flow, &n, 1, mode != SIGNTRI_FP64, hflow, st, &herr)) != 0)
+        if ((rc = sweep_error(ws + L.flow, &n, 1, mode != SIGNTRI_FP64, cplx, hflow, st, &herr)) !=
+            0)
             return rc;
     }
     if (info) {
+        const bool triv = path == SIGNTRI_PATH_TRIVIAL;
         info->path = path;
-        info->tile = path == SIGNTRI_PATH_TRIVIAL ? 0 : tb;
+        info->tile = triv ? 0 : tb;
+        info->sweep = triv ? 0 : eo.sweep;
+        info->wgs_per_cu = triv ? 0 : eo.wgs_per_cu;
     }
     return SIGNTRI_OK;
 }
@@ -599,7 +659,18 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     }
     if (batch == 0) return SIGNTRI_OK;
     if (dtype != SIGNTRI_R64 || layout != SIGNTRI_COL_MAJOR) return SIGNTRI_ENOTSUP;
-    if (opts && opts->tile != 0 && opts->tile != kFlowTile) return -13;
+    if (int rc = check_options(opts, dtype, mode)) return rc;
+    if (opts && (opts->sweep == SIGNTRI_SWEEP_SUPERDIAG || opts->tile == 64)) return SIGNTRI_ENOTSUP;
+    // the batched form runs on the dataflow sweeps; only the grid is a choice
+    signtri_options eo;
+    std::memset(&eo, 0, sizeof(eo));
+    if (opts) eo = *opts;
+    eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
+    eo.tile = kFlowTile;
+    {
+        const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, false);
+        if (eo.wgs_per_cu <= 0 || eo.wgs_per_cu > mx) eo.wgs_per_cu = mx;
+    }
 
     const BatchLayout BL = batch_layout(n, batch, mode);
     if (workspace) {
@@ -655,10 +726,14 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
         it.s = it.path == SIGNTRI_PATH_TRIVIAL ? (p.n_pos > 0 ? 1 : -1) : p.ps_sign;
         it.sgn = (const int8_t *)(ws + BL.sgn[m]);
         it.dg = (const double *)(ws + BL.dg[m]);
+        it.cplx = false;
         it.info = inf;
         if (inf) {
+            const bool triv = it.path == SIGNTRI_PATH_TRIVIAL;
             inf->path = it.path;
-            inf->tile = it.path == SIGNTRI_PATH_TRIVIAL ? 0 : kFlowTile;
+            inf->tile = triv ? 0 : kFlowTile;
+            inf->sweep = triv ? 0 : SIGNTRI_SWEEP_DATAFLOW;
+            inf->wgs_per_cu = triv ? 0 : eo.wgs_per_cu;
         }
         items.push_back(it);
         hsigns.push_back(hs);
@@ -670,14 +745,14 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     if (mode != SIGNTRI_MIXED_REFINED && graphs_enabled() && !prof_on()) {
         int device = 0;
         if (hipGetDevice(&device) != hipSuccess) return SIGNTRI_EHIP;
-        rc = launch_batch_graph(items, mode, opts, run_dev, st, device);
+        rc = launch_batch_graph(items, mode, &eo, run_dev, st, device);
     } else {
-        rc = run_real(items, mode, opts, run_dev, run_host, prof_on(), hsigns.data(), st);
+        rc = run_real(items, mode, &eo, run_dev, run_host, prof_on(), hsigns.data(), st);
     }
     if (rc != SIGNTRI_OK) return rc;
     if (infos && mode != SIGNTRI_MIXED_REFINED)
-        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, run_host, st,
-                           nullptr);
+        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false,
+                           run_host, st, nullptr);
     return SIGNTRI_OK;
 }
 

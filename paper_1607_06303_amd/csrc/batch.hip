@@ -43,7 +43,8 @@ __global__ __launch_bounds__(1024) void k_scan_b(const ScanMat *__restrict__ mat
 // Output preparation of matrix blockIdx.z: kind 0 zeroes the strict lower
 // triangle (the sweep writes the rest), kind 1 writes diag(s I_p, -s I_{n-p})
 // (Parlett-Sylvester: the sweep writes X), kind 2 writes s I (one sign).
-__global__ __launch_bounds__(256) void k_prepare_b(const PrepMat *__restrict__ mats)
+// P = 2: complex entries (interleaved re, im).
+template <int P> __global__ __launch_bounds__(256) void k_prepare_b(const PrepMat *__restrict__ mats)
 {
     const PrepMat d = mats[blockIdx.z];
     for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y) {
@@ -52,19 +53,22 @@ __global__ __launch_bounds__(256) void k_prepare_b(const PrepMat *__restrict__ m
              i += (int64_t)gridDim.x * blockDim.x) {
             double v = 0.0;
             if (i == j && d.kind != 0) v = (d.kind == 2 || i < d.p) ? d.s : -d.s;
-            d.U[i + j * d.ldu] = v;
+            d.U[P * (i + j * d.ldu)] = v;
+            if (P == 2) d.U[P * (i + j * d.ldu) + 1] = 0.0;
         }
     }
 }
 
 // Diagonal 32 x 32 blocks (Algorithm 3 per block, superdiagonal by
 // superdiagonal), one per workgroup: task (matrix, block row).  Eight lanes
-// share each entry's inner product.
+// share each entry's inner product.  P = 2: complex entries, kept in LDS as
+// real and imaginary planes.
+template <int P>
 __global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats,
                                                 const int2 *__restrict__ tasks)
 {
-    constexpr int LD = TB + 1, LPE = 256 / TB;
-    __shared__ double sT[TB * LD], sU[TB * LD];
+    constexpr int LD = TB + 1, LPE = 256 / TB, PL = TB * LD;
+    __shared__ double sT[P * PL], sU[P * PL];
     __shared__ int8_t ss[TB];
     const int2 tk = tasks[blockIdx.x];
     const PrepMat d = mats[uniform(tk.x)];
@@ -73,8 +77,12 @@ __global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats
     for (int e = threadIdx.x; e < TB * TB; e += 256) {
         const int i = e % TB, j = e / TB;
         const bool in = i < bt && j < bt;
-        sT[i + j * LD] = (in && i <= j) ? d.T[(r0 + i) + (r0 + j) * d.ldt] : 0.0;
-        sU[i + j * LD] = (in && i == j) ? (double)d.sgn[r0 + i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            sT[q * PL + i + j * LD] =
+                (in && i <= j) ? d.T[P * ((r0 + i) + (r0 + j) * d.ldt) + q] : 0.0;
+            sU[q * PL + i + j * LD] = (q == 0 && in && i == j) ? (double)d.sgn[r0 + i] : 0.0;
+        }
     }
     if (threadIdx.x < TB) ss[threadIdx.x] = threadIdx.x < bt ? d.sgn[r0 + threadIdx.x] : 1;
     __syncthreads();
@@ -83,32 +91,64 @@ __global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats
         const int j = i + dd;
         if (j < bt) {
             const int si = ss[i], sj = ss[j];
-            double sum = 0.0;
+            double sr = 0.0, sim = 0.0;
             if (si != sj) {
-                for (int k = i + 1 + q; k < j; k += LPE)
-                    sum += sU[i + k * LD] * sT[k + j * LD] - sT[i + k * LD] * sU[k + j * LD];
+                for (int k = i + 1 + q; k < j; k += LPE) {
+                    const int ik = i + k * LD, kj = k + j * LD;
+                    sr += sU[ik] * sT[kj] - sT[ik] * sU[kj];
+                    if (P == 2) {
+                        sr += -sU[PL + ik] * sT[PL + kj] + sT[PL + ik] * sU[PL + kj];
+                        sim += sU[ik] * sT[PL + kj] + sU[PL + ik] * sT[kj] - sT[ik] * sU[PL + kj] -
+                               sT[PL + ik] * sU[kj];
+                    }
+                }
             } else {
-                for (int k = i + 1 + q; k < j; k += LPE) sum += sU[i + k * LD] * sU[k + j * LD];
+                for (int k = i + 1 + q; k < j; k += LPE) {
+                    const int ik = i + k * LD, kj = k + j * LD;
+                    sr += sU[ik] * sU[kj];
+                    if (P == 2) {
+                        sr -= sU[PL + ik] * sU[PL + kj];
+                        sim += sU[ik] * sU[PL + kj] + sU[PL + ik] * sU[kj];
+                    }
+                }
             }
-            sum = group_sum<LPE>(sum);
+            sr = group_sum<LPE>(sr);
+            if (P == 2) sim = group_sum<LPE>(sim);
             if (q == 0) {
-                double u;
+                double ur, ui = 0.0;
                 if (si != sj) {
                     // Eq. (1): t_ij (u_ii - u_jj) = 2 s_i t_ij
-                    const double den = sT[i + i * LD] - sT[j + j * LD];
-                    u = (2.0 * si * sT[i + j * LD] + sum) / den;
+                    const double nr = 2.0 * si * sT[i + j * LD] + sr;
+                    const double dr = sT[i + i * LD] - sT[j + j * LD];
+                    if (P == 2) {
+                        const double ni = 2.0 * si * sT[PL + i + j * LD] + sim;
+                        const double di = sT[PL + i + i * LD] - sT[PL + j + j * LD];
+                        // (nr + i ni) / (dr + i di), scaled against overflow
+                        const double s = fmax(fabs(dr), fabs(di));
+                        const double xr = dr / s, xi = di / s;
+                        const double den = s * (xr * xr + xi * xi);
+                        ur = (nr * xr + ni * xi) / den;
+                        ui = (ni * xr - nr * xi) / den;
+                    } else {
+                        ur = nr / dr;
+                    }
                 } else {
                     // Eq. (2): -sum / (u_ii + u_jj) = -(s_i / 2) sum, an exact scaling
-                    u = -0.5 * si * sum;
+                    ur = -0.5 * si * sr;
+                    ui = -0.5 * si * sim;
                 }
-                sU[i + j * LD] = u;
+                sU[i + j * LD] = ur;
+                if (P == 2) sU[PL + i + j * LD] = ui;
             }
         }
         __syncthreads();
     }
     for (int e = threadIdx.x; e < TB * TB; e += 256) {
         const int ii = e % TB, jj = e / TB;
-        if (ii < bt && jj < bt && ii <= jj) d.U[(r0 + ii) + (r0 + jj) * d.ldu] = sU[ii + jj * LD];
+        if (ii < bt && jj < bt && ii <= jj)
+#pragma unroll
+            for (int p2 = 0; p2 < P; ++p2)
+                d.U[P * ((r0 + ii) + (r0 + jj) * d.ldu) + p2] = sU[p2 * PL + ii + jj * LD];
     }
 }
 
@@ -121,20 +161,27 @@ hipError_t launch_scan_b(const ScanMat *mats, int nmat, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, hipStream_t st)
+hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, bool cplx, hipStream_t st)
 {
     if (nmat <= 0 || nmax <= 0) return hipSuccess;
     const int64_t gx = std::min<int64_t>((nmax + 255) / 256, 8);
     const int64_t gy = std::min<int64_t>(nmax, nmat > 1 ? 64 : 1024);
-    hipLaunchKernelGGL(k_prepare_b, dim3((unsigned)gx, (unsigned)gy, (unsigned)nmat), dim3(256), 0,
-                       st, mats);
+    const dim3 g((unsigned)gx, (unsigned)gy, (unsigned)nmat);
+    if (cplx)
+        hipLaunchKernelGGL(k_prepare_b<2>, g, dim3(256), 0, st, mats);
+    else
+        hipLaunchKernelGGL(k_prepare_b<1>, g, dim3(256), 0, st, mats);
     return hipGetLastError();
 }
 
-hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, hipStream_t st)
+hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, bool cplx,
+                         hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag_b, dim3(ntasks), dim3(256), 0, st, mats, tasks);
+    if (cplx)
+        hipLaunchKernelGGL(k_diag_b<2>, dim3(ntasks), dim3(256), 0, st, mats, tasks);
+    else
+        hipLaunchKernelGGL(k_diag_b<1>, dim3(ntasks), dim3(256), 0, st, mats, tasks);
     return hipGetLastError();
 }
 

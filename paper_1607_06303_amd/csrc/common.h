@@ -344,8 +344,12 @@ template <typename F> struct FlowArgs {
     int *flags;                // completion flags (zeroed before, or 1 for blocks not recomputed)
     int spin_limit;            // polls before a wait gives up and sets the error word
 };
-template <typename F, int KIND>
-hipError_t launch_flow(const FlowArgs<F> &a, int grid, hipStream_t st);
+// C: complex entries (interleaved re, im).
+template <typename F, int KIND, bool C>
+hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st);
+// Most workgroups per compute unit that fit, over the sweeps of one precision
+// (wgs_per_cu above a kernel's own limit is clamped at launch).
+int flow_max_wgs_per_cu(bool fp32, bool cplx);
 hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
 hipError_t launch_tasks_tri(int nb, int mat, int2 *out, hipStream_t st);
 hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t st);
@@ -380,11 +384,11 @@ struct RefArgs {
     const RefMat *mats;
     int nmat;
 };
-hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, hipStream_t st);
-hipError_t launch_widen(const RefArgs &a, int64_t nmax, hipStream_t st);
-hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, hipStream_t st);
-hipError_t launch_resid(const RefArgs &a, bool syl, const int2 *tasks, int ntasks, double *norm2,
-                        hipStream_t st);
+hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
+hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
+hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
+hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks, int ntasks,
+                        double *norm2, hipStream_t st);
 
 // batch.hip: table-driven scan, output preparation and diagonal blocks.
 struct ScanMat {
@@ -407,8 +411,9 @@ struct PrepMat {
     double s;
 };
 hipError_t launch_scan_b(const ScanMat *mats, int nmat, hipStream_t st);
-hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, hipStream_t st);
-hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, hipStream_t st);
+hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, bool cplx, hipStream_t st);
+hipError_t launch_diag_b(const PrepMat *mats, const int2 *tasks, int ntasks, bool cplx,
+                         hipStream_t st);
 
 // sweep.hip: one real matrix of a run (a single call, or one matrix of a batch).
 struct RealItem {
@@ -421,18 +426,20 @@ struct RealItem {
     int64_t p;            // Parlett-Sylvester: order of the leading sign group
     int s;                // its sign (trivial path: the one sign)
     const int8_t *sgn;    // device signs and real diagonal
-    const double *dg;
+    const double *dg;     // (complex: interleaved re, im pairs)
+    bool cplx;            // complex entries (interleaved re, im); the same for every item
     signtri_info *info;   // optional host output
 };
 // Device and pinned-host bytes a run over these orders needs.
-void run_sizes(const int64_t *ns, int nmat, bool mixed, size_t *dev_bytes, size_t *host_bytes);
+void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_bytes,
+               size_t *host_bytes);
 // Run the sweeps of a set of real matrices: FP64, FP32, or FP32 with FP64
 // refinement (mode), every phase one launch over all matrices.
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
              hipStream_t st);
 // Wait for a run and report whether a dependency wait hit its safety bound.
-int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, void *host_ws,
+int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, bool cplx, void *host_ws,
                 hipStream_t st, int *err);
 
 // Diagonal 32 x 32 blocks of a real U in FP64 (Algorithm 3 per block).
@@ -444,6 +451,10 @@ hipError_t launch_fill_split_identity(double *U, int64_t ldu, int64_t n, int64_t
 
 // block size used for a request (0 = default), and bulk partial-sum slots
 int ph_tile_size(bool cplx, int requested);
+
+// The autotuner's recorded choice for (dtype, mode, path, size class of n).
+bool tune_find(signtri_dtype dtype, signtri_mode mode, int path, int64_t n,
+               signtri_tune_entry *out);
 int64_t ph_zslots(int64_t n, int tb);
 hipError_t run_ph_fp64(const PhArgs &a, bool cplx, hipStream_t st);
 

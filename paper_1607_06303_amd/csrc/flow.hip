@@ -35,7 +35,10 @@
 // recently those blocks can have finished (lag >= 3, lag 2, lag 1, where the
 // lag of a product is how many block diagonals -- MAIN/CORR -- or
 // anti-diagonals -- SYL -- earlier its later operand lies).  The lag-1 group is
-// the critical path; everything else overlaps the solves of other blocks.
+// the critical path; everything else overlaps the solves of other blocks.  The
+// lag >= 3 steps are ordered by readiness and multiplied prefix by prefix as
+// their flags appear, so that a long block does most of its products while the
+// few blocks it still waits for are being solved.
 // Every task only waits for tasks with smaller tickets, which are held by
 // running workgroups, so the schedule cannot deadlock; every wait is also
 // bounded and, when the bound is hit, sets an error word and gives up, so the
@@ -115,34 +118,50 @@ template <typename F> __device__ inline void coherent_store(F *p, F v)
 
 // Global-to-LDS staging of one K step: each thread carries 4 consecutive rows
 // of one column of every operand tile the step needs (A side: unknown, -T, U0;
-// B side: unknown, T, U0), and a mask of the slots it loaded.
-template <typename F, int NS> struct Stage {
-    F ga[NS][4], gb[NS][4];
+// B side: unknown, T, U0), one plane per component (P = 2 for complex
+// entries: real and imaginary parts), and a mask of the slots it loaded.
+template <typename F, int NS, int P> struct Stage {
+    F ga[NS][P][4], gb[NS][P][4];
     unsigned live;
 };
 
-template <typename F, int KIND>
+// Complex multiply-accumulate of 16 x 16 MFMA pieces kept as real and
+// imaginary planes: (ar + i ai)(br + i bi) = (ar br - ai bi) + i (ar bi + ai br).
+template <typename F, typename A>
+__device__ inline void cmma(F ar, F ai, F br, F bi, A &cr, A &ci)
+{
+    cr = mm<F>::mma(ar, br, cr);
+    cr = mm<F>::mma(-ai, bi, cr);
+    ci = mm<F>::mma(ar, bi, ci);
+    ci = mm<F>::mma(ai, br, ci);
+}
+
+// C selects complex entries: every array then holds interleaved (re, im)
+// pairs and every leading dimension counts complex elements.
+template <typename F, int KIND, bool C>
 __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
 {
     typedef typename mm<F>::acc acc_t;
     constexpr bool CORR = KIND == FLOW_CORR;
     constexpr bool syl = KIND == FLOW_SYL;
     constexpr int NS = CORR ? 3 : 2;  // operand slots per side
+    constexpr int P = C ? 2 : 1;      // planes per entry
     constexpr int SV = 0, ST = 1, SC = 2;  // slot roles: unknown, T, U0
     // Operand staging of the products; during the solve the same memory holds
     // the block (column-major X and a row-major copy XT, pitch LDX) and the
-    // column coefficients of block J (RU, RT: column-major, zero for k >= j).
-    __shared__ __align__(16) F sA[NS][TB * APITCH];
-    __shared__ __align__(16) F sB[NS][(TB / 4) * BSLAB];
-    __shared__ double rcp[TB * TB];  // 1/(d_i - d_j) for opposite-sign entries, row-major
-    static_assert(2 * TB * LDX <= NS * TB * APITCH, "X and XT fit in the A staging");
-    static_assert(2 * TB * TB <= NS * (TB / 4) * BSLAB, "RU and RT fit in the B staging");
-    F *const X = &sA[0][0];
-    F *const XT = X + TB * LDX;
-    F *const RU = &sB[0][0];
-    F *const RT = RU + TB * TB;
+    // column coefficients of block J (RU, RT: column-major, zero for k >= j),
+    // each as P planes.
+    __shared__ __align__(16) F sA[NS][P][TB * APITCH];
+    __shared__ __align__(16) F sB[NS][P][(TB / 4) * BSLAB];
+    __shared__ double rcp[P][TB * TB];  // 1/(d_i - d_j) for opposite-sign entries, row-major
+    static_assert(2 * P * TB * LDX <= NS * P * TB * APITCH, "X and XT fit in the A staging");
+    static_assert(2 * P * TB * TB <= NS * P * (TB / 4) * BSLAB, "RU and RT fit in the B staging");
+    F *const X = &sA[0][0][0];     // plane q at X + q * TB * LDX
+    F *const XT = X + P * TB * LDX;
+    F *const RU = &sB[0][0][0];    // plane q at RU + q * TB * TB
+    F *const RT = RU + P * TB * TB;
     __shared__ int8_t rs[TB], cs[TB];
-    __shared__ int s_task;
+    __shared__ int s_task, s_first;
     typedef F f4 __attribute__((ext_vector_type(4)));
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,6 +191,10 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
         const int64_t gr0 = ro + (int64_t)I * TB, gc0 = co + (int64_t)J * TB;
         const int bi = uniform((int)min((int64_t)TB, rend - gr0));
         const int bj = uniform((int)min((int64_t)TB, cend - gc0));
+        // entry (r, c), plane q of a column-major array with leading dimension ld
+        auto at = [&](int64_t r, int64_t c, int64_t ld, int q) -> int64_t {
+            return P * (r + c * ld) + q;
+        };
 
         if (tid < TB) {
             if (syl) {
@@ -200,12 +223,14 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
         }
         const bool any_x = uniform(__syncthreads_or(pneedX));
 
-        acc_t accY, accX;
+        acc_t accY[P], accX[P];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            accY[r] = 0;
-            accX[r] = 0;
-        }
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                accY[q][r] = 0;
+                accX[q][r] = 0;
+            }
         const int D = J - I;
         const int na = syl ? uniform(M.nbr) - 1 - I : 0;  // SYL: K blocks of T11 below I
         const int nb_ = syl ? J : 0;             // SYL: K blocks of T22 left of J
@@ -232,19 +257,45 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             }
             if (!syl) {
                 kind = ST_MID;
-                if (g == 1) K = I + 3 + s;
-                else if (g == 2) K = s == 0 ? I + 2 : J - 2;
-                else K = s == 0 ? I + 1 : J - 1;
+                if (g == 1) {
+                    // middle out: K's operands (I, K) and (K, J) are both finished once
+                    // superdiagonal max(K - I, J - K) is, so the steps come in order of
+                    // readiness
+                    const int off = (s & 1) ? ((s + 1) >> 1) : -(s >> 1);
+                    K = I + (D >> 1) + off;
+                } else if (g == 2) {
+                    K = s == 0 ? I + 2 : J - 2;
+                } else {
+                    K = s == 0 ? I + 1 : J - 1;
+                }
                 return;
             }
-            const int lagA = g == 1 ? max(0, na - 2) : (g == 2 ? (na >= 2) : (na >= 1));
+            if (g == 1) {
+                // A steps (K, J) with lag K - I and B steps (I, K) with lag J - K,
+                // merged by decreasing lag (in order of readiness)
+                const int L1 = max(na, nb_), L2 = min(na, nb_);
+                const int f = max(0, L1 - max(L2, 2));
+                bool isA;
+                int lag;
+                if (s < f) {
+                    lag = L1 - s;
+                    isA = na >= nb_;
+                } else {
+                    const int q = s - f;
+                    lag = L2 - (q >> 1);
+                    isA = (q & 1) == 0;
+                }
+                kind = isA ? ST_SYLA : ST_SYLB;
+                K = isA ? I + lag : J - lag;
+                return;
+            }
+            const int lagA = g == 2 ? (na >= 2) : (na >= 1);
             if (s < lagA) {
                 kind = ST_SYLA;
-                K = g == 1 ? I + 3 + s : (g == 2 ? I + 2 : I + 1);
+                K = g == 2 ? I + 2 : I + 1;
             } else {
                 kind = ST_SYLB;
-                const int sb = s - lagA;
-                K = g == 1 ? sb : (g == 2 ? J - 2 : J - 1);
+                K = g == 2 ? J - 2 : J - 1;
             }
         };
         auto dep_flag = [&](int kind, int K, int d) -> const int * {
@@ -277,6 +328,26 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             }
             if (timed_out && tid == 0) atomicOr(a.ctrl + 1, 1);
             __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the poll
+        };
+
+        // First step in [from, cnt) of group g whose operand flags are not all set
+        // (cnt when every one is).
+        auto ready_prefix = [&](int g, int from, int cnt) -> int {
+            const int per = syl ? 1 : 2;
+            if (tid == 0) s_first = cnt;
+            __syncthreads();
+            const int total = per * (cnt - from);
+            for (int e = tid; e < total; e += NT) {
+                int kind, K;
+                const int st = from + e / per;
+                step_of(g, st, kind, K);
+                if (flag_load(dep_flag(kind, K, e % per)) == 0) atomicMin(&s_first, st);
+            }
+            __syncthreads();
+            const int pfx = uniform(s_first);
+            __syncthreads();  // s_first is reused
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no operand load moves above the poll
+            return pfx;
         };
 
         // operand tiles of a K step for a slot (false: the step does not use it)
@@ -337,16 +408,19 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 return false;
             }
         };
-        typedef Stage<F, NS> stage_t;
-        auto load_tile = [&](const F *p, int64_t ld, const TileRef &tr, bool coh, F (&dst)[4]) {
+        typedef Stage<F, NS, P> stage_t;
+        auto load_tile = [&](const F *p, int64_t ld, const TileRef &tr, bool coh, F (&dst)[P][4]) {
             const int64_t c = tr.c0 + lc;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t r = tr.r0 + lr + e;
                 const bool ok = r < tr.rend && c < tr.cend && !(tr.diag && r > c);
-                F v = 0;
-                if (ok) v = coh ? coherent_load(p + r + c * ld) : p[r + c * ld];
-                dst[e] = v;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    F v = 0;
+                    if (ok) v = coh ? coherent_load(p + at(r, c, ld, q)) : p[at(r, c, ld, q)];
+                    dst[q][e] = v;
+                }
             }
         };
         auto load_step = [&](int kind, int K, stage_t &g) {
@@ -372,12 +446,25 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const F sg = q == ST ? (F)-1 : (F)1;  // T is stored negated on the A side
-                if (g.live & (1u << q))
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) sA[q][lc * APITCH + lr + e] = sg * g.ga[q][e];
-                if (g.live & (1u << (8 + q)))
+                for (int pl = 0; pl < P; ++pl) {
+                    if (g.live & (1u << q))
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) sB[q][(lr >> 2) * BSLAB + lc * 4 + e] = g.gb[q][e];
+                        for (int e = 0; e < 4; ++e)
+                            sA[q][pl][lc * APITCH + lr + e] = sg * g.ga[q][pl][e];
+                    if (g.live & (1u << (8 + q)))
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            sB[q][pl][(lr >> 2) * BSLAB + lc * 4 + e] = g.gb[q][pl][e];
+                }
+            }
+        };
+        // acc += a * b for one slot pair at LDS offsets ao, bo
+        auto mac = [&](int qa, int qb, int ao, int bo, acc_t (&acc)[P]) {
+            if constexpr (C) {
+                cmma<F>(sA[qa][0][ao], sA[qa][1][ao], sB[qb][0][bo], sB[qb][1][bo], acc[0], acc[1]);
+            } else {
+                acc[0] = mm<F>::mma(sA[qa][0][ao], sB[qb][0][bo], acc[0]);
             }
         };
         auto compute_step = [&](int kind) {
@@ -389,31 +476,30 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             for (int k4 = 0; k4 < TB / 4; ++k4) {
                 const int ao = (k4 * 4 + mg) * APITCH + 16 * pr + mt;
                 const int bo = k4 * BSLAB + (16 * pc + mt) * 4 + mg;
-                const F aV = sA[SV][ao], aT = sA[ST][ao];
-                const F bV = sB[SV][bo], bT = sB[ST][bo];
                 if (yy) {
                     if constexpr (CORR) {
-                        const F aC = sA[SC][ao], bC = sB[SC][bo];
-                        accY = mm<F>::mma(aC, bV, accY);
-                        accY = mm<F>::mma(aV, bC, accY);
+                        mac(SC, SV, ao, bo, accY);
+                        mac(SV, SC, ao, bo, accY);
                     } else {
-                        accY = mm<F>::mma(aV, bV, accY);
+                        mac(SV, SV, ao, bo, accY);
                     }
                 }
-                if (xv_t) accX = mm<F>::mma(aV, bT, accX);
-                if (xt_v) accX = mm<F>::mma(aT, bV, accX);
+                if (xv_t) mac(SV, ST, ao, bo, accX);
+                if (xt_v) mac(ST, SV, ao, bo, accX);
             }
         };
-        // The K steps of a group: step s is multiplied from LDS while steps s+1
-        // and s+2 are in flight from global memory into two register stages.
-        auto run_group = [&](int g, int cnt) {
-            if (cnt == 0) return;
+        // Steps s0 .. s1-1 of a group: step s is multiplied from LDS while steps
+        // s+1 and s+2 are in flight from global memory into two register stages.
+        auto run_group = [&](int g, int s0, int s1) {
+            const int cnt = s1 - s0;
+            if (cnt <= 0) return;
+            auto step_at = [&](int s, int &kind, int &K) { step_of(g, s0 + s, kind, K); };
             stage_t r0, r1;
             int kd[3], kk[3];
-            step_of(g, 0, kd[0], kk[0]);
+            step_at(0, kd[0], kk[0]);
             load_step(kd[0], kk[0], r0);
             if (cnt > 1) {
-                step_of(g, 1, kd[1], kk[1]);
+                step_at(1, kd[1], kk[1]);
                 load_step(kd[1], kk[1], r1);
             }
             __syncthreads();  // earlier users of the staging memory are done
@@ -422,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             for (int s = 0; s < cnt; s += 2) {
                 // step s in LDS, s + 1 in r1
                 if (s + 2 < cnt) {
-                    step_of(g, s + 2, kd[2], kk[2]);
+                    step_at(s + 2, kd[2], kk[2]);
                     load_step(kd[2], kk[2], r0);
                 }
                 compute_step(kd[0]);
@@ -432,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 __syncthreads();
                 // step s + 1 in LDS, s + 2 in r0
                 if (s + 3 < cnt) {
-                    step_of(g, s + 3, kd[0], kk[0]);
+                    step_at(s + 3, kd[0], kk[0]);
                     load_step(kd[0], kk[0], r1);
                 }
                 compute_step(kd[1]);
@@ -449,11 +535,33 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             }
         };
 
-        run_group(0, group_count(0));
-        for (int g = 1; g <= 2; ++g) {
-            const int cnt = group_count(g);
-            wait_group(g, cnt);
-            run_group(g, cnt);
+        run_group(0, 0, group_count(0));
+        // lag >= 3: multiply each ready prefix of the steps as soon as it is
+        // ready, so a long block's products proceed while the blocks it still
+        // needs are being solved
+        {
+            const int cnt = group_count(1);
+            int s = 0, idle = 0;
+            while (s < cnt) {
+                const int pfx = ready_prefix(1, s, cnt);
+                if (pfx > s) {
+                    run_group(1, s, pfx);
+                    s = pfx;
+                    idle = 0;
+                    continue;
+                }
+                const bool err = uniform(__syncthreads_or(tid == 0 && flag_load(a.ctrl + 1) != 0));
+                if (err || ++idle >= a.spin_limit) {
+                    if (tid == 0) atomicOr(a.ctrl + 1, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        {
+            const int cnt = group_count(2);
+            wait_group(2, cnt);
+            run_group(2, 0, cnt);
         }
 
         // ---- solve prologue, loaded before the lag-1 wait: row li of the left
@@ -461,60 +569,89 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
         // diagonal block's columns and the initial right-hand side in registers
         // (the staging memory they go to is busy until the last product), the
         // reciprocals 1/(d_i - d_j) in their own LDS table.
-        F cu[CPL], ct[CPL];
+        F cu[P][CPL], ct[P][CPL];
 #pragma unroll
         for (int u = 0; u < CPL; ++u) {
             const int k = kq + u;
             const bool up = k > li && k < bi;
             const int64_t gi = gr0 + li, gk = gr0 + k;
-            cu[u] = (up && !syl) ? (CORR ? M.C[gi + gk * M.ldc] : M.V[gi + gk * M.ldv]) : (F)0;
-            ct[u] = up ? M.T[gi + gk * M.ldt] : (F)0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                cu[q][u] = (up && !syl) ? (CORR ? M.C[at(gi, gk, M.ldc, q)] : M.V[at(gi, gk, M.ldv, q)])
+                                        : (F)0;
+                ct[q][u] = up ? M.T[at(gi, gk, M.ldt, q)] : (F)0;
+            }
         }
         constexpr int RPT = TB * TB / NT;  // entries per thread of a 32 x 32 table
-        F ru[RPT], rt[RPT], r0v[RPT];
+        F ru[P][RPT], rt[P][RPT], r0v[P][RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int e = tid + NT * q, k = e % TB, c = e / TB;
+        for (int w = 0; w < RPT; ++w) {
+            const int e = tid + NT * w, k = e % TB, c = e / TB;
             const bool in = k < c && c < bj;
             const int64_t gi = gc0 + k, gk = gc0 + c;
-            rt[q] = in ? M.T[gi + gk * M.ldt] : (F)0;
-            ru[q] = (in && !syl) ? (CORR ? M.C[gi + gk * M.ldc] : M.V[gi + gk * M.ldv]) : (F)0;
-            F v = 0;
-            if (k < bi && c < bj) {
-                if (CORR) v = M.V[(gr0 + k) + (gc0 + c) * M.ldv];
-                if (syl) v = (F)M.rhs_scale * M.Rh[(gr0 + k) + (gc0 + c) * M.ldrh];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                rt[q][w] = in ? M.T[at(gi, gk, M.ldt, q)] : (F)0;
+                ru[q][w] = (in && !syl) ? (CORR ? M.C[at(gi, gk, M.ldc, q)] : M.V[at(gi, gk, M.ldv, q)])
+                                        : (F)0;
+                F v = 0;
+                if (k < bi && c < bj) {
+                    if (CORR) v = M.V[at(gr0 + k, gc0 + c, M.ldv, q)];
+                    if (syl) v = (F)M.rhs_scale * M.Rh[at(gr0 + k, gc0 + c, M.ldrh, q)];
+                }
+                r0v[q][w] = v;
             }
-            r0v[q] = v;
         }
         for (int e = tid; e < TB * TB; e += NT) {
             const int r = e / TB, c = e % TB;
-            rcp[e] = (r < bi && c < bj && rs[r] != cs[c]) ? 1.0 / (M.dg[gr0 + r] - M.dg[gc0 + c])
-                                                         : 0.0;
+            const bool opp = r < bi && c < bj && rs[r] != cs[c];
+            if constexpr (C) {
+                double zr = 0.0, zi = 0.0;
+                if (opp) {
+                    // 1 / (d_i - d_j) for a complex difference z: conj(z) / |z|^2
+                    const double dr = M.dg[2 * (gr0 + r)] - M.dg[2 * (gc0 + c)];
+                    const double di = M.dg[2 * (gr0 + r) + 1] - M.dg[2 * (gc0 + c) + 1];
+                    const double s = fmax(fabs(dr), fabs(di));
+                    const double xr = dr / s, xi = di / s;
+                    const double den = s * (xr * xr + xi * xi);
+                    zr = xr / den;
+                    zi = -xi / den;
+                }
+                rcp[0][e] = zr;
+                rcp[1][e] = zi;
+            } else {
+                rcp[0][e] = opp ? 1.0 / (M.dg[gr0 + r] - M.dg[gc0 + c]) : 0.0;
+            }
         }
 
         // ---- lag-1 products: the critical path
         {
             const int cnt = group_count(3);
             wait_group(3, cnt);
-            run_group(3, cnt);
+            run_group(3, 0, cnt);
         }
         __syncthreads();  // the staging memory becomes the solve's
 
         // ---- right-hand side: initial part + products (X or Y by the entry's signs)
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int e = tid + NT * q;
-            X[(e % TB) + (e / TB) * LDX] = r0v[q];
-            RU[e] = ru[q];
-            RT[e] = rt[q];
+        for (int w = 0; w < RPT; ++w) {
+            const int e = tid + NT * w;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                X[q * TB * LDX + (e % TB) + (e / TB) * LDX] = r0v[q][w];
+                RU[q * TB * TB + e] = ru[q][w];
+                RT[q * TB * TB + e] = rt[q][w];
+            }
         }
-        for (int e = tid; e < TB * LDX; e += NT) XT[e] = 0;
+        for (int e = tid; e < P * TB * LDX; e += NT) XT[e] = 0;
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * pr + mm<F>::row(lane, r);
             const int j = 16 * pc + mt;
-            X[i + j * LDX] += (rs[i] == cs[j]) ? accY[r] : accX[r];
+            const bool same = rs[i] == cs[j];
+#pragma unroll
+            for (int q = 0; q < P; ++q) X[q * TB * LDX + i + j * LDX] += same ? accY[q][r] : accX[q][r];
         }
         const int si = rs[li];
         unsigned long long cpos = 0;
@@ -529,20 +666,65 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             const int j = st - (bi - 1 - li);
             const int jj = min(max(j, 0), TB - 1);
             const bool same = !syl && ((((cpos >> jj) & 1ull) != 0) == (si > 0));
-            const f4 xc = *(const f4 *)&X[kq + jj * LDX];
-            const f4 xr = *(const f4 *)&XT[kq + li * LDX];
-            const f4 rr = *(const f4 *)&(same ? RU : RT)[kq + jj * TB];
-            const F rhs = X[li + jj * LDX];
-            const F colu = (cu[0] * xc[0] + cu[1] * xc[1]) + (cu[2] * xc[2] + cu[3] * xc[3]);
-            const F colt = (ct[0] * xc[0] + ct[1] * xc[1]) + (ct[2] * xc[2] + ct[3] * xc[3]);
-            const F row = (xr[0] * rr[0] + xr[1] * rr[1]) + (xr[2] * rr[2] + xr[3] * rr[3]);
-            F tot = same ? colu + row : row - colt;
-            tot = group_sum<LPR>(tot);
+            const F *rsrc = same ? RU : RT;
+            F tot[P], rhs[P];
+            if constexpr (C) {
+                const f4 xcr = *(const f4 *)&X[kq + jj * LDX];
+                const f4 xci = *(const f4 *)&X[TB * LDX + kq + jj * LDX];
+                const f4 xrr = *(const f4 *)&XT[kq + li * LDX];
+                const f4 xri = *(const f4 *)&XT[TB * LDX + kq + li * LDX];
+                const f4 rrr = *(const f4 *)&rsrc[kq + jj * TB];
+                const f4 rri = *(const f4 *)&rsrc[TB * TB + kq + jj * TB];
+                rhs[0] = X[li + jj * LDX];
+                rhs[1] = X[TB * LDX + li + jj * LDX];
+                F cur = 0, cui = 0, ctr = 0, cti = 0, rwr = 0, rwi = 0;
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    cur += cu[0][u] * xcr[u] - cu[1][u] * xci[u];
+                    cui += cu[0][u] * xci[u] + cu[1][u] * xcr[u];
+                    ctr += ct[0][u] * xcr[u] - ct[1][u] * xci[u];
+                    cti += ct[0][u] * xci[u] + ct[1][u] * xcr[u];
+                    rwr += xrr[u] * rrr[u] - xri[u] * rri[u];
+                    rwi += xrr[u] * rri[u] + xri[u] * rrr[u];
+                }
+                tot[0] = same ? cur + rwr : rwr - ctr;
+                tot[1] = same ? cui + rwi : rwi - cti;
+            } else {
+                const f4 xc = *(const f4 *)&X[kq + jj * LDX];
+                const f4 xr = *(const f4 *)&XT[kq + li * LDX];
+                const f4 rr = *(const f4 *)&rsrc[kq + jj * TB];
+                rhs[0] = X[li + jj * LDX];
+                const F colu = (cu[0][0] * xc[0] + cu[0][1] * xc[1]) + (cu[0][2] * xc[2] + cu[0][3] * xc[3]);
+                const F colt = (ct[0][0] * xc[0] + ct[0][1] * xc[1]) + (ct[0][2] * xc[2] + ct[0][3] * xc[3]);
+                const F row = (xr[0] * rr[0] + xr[1] * rr[1]) + (xr[2] * rr[2] + xr[3] * rr[3]);
+                tot[0] = same ? colu + row : row - colt;
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) tot[q] = group_sum<LPR>(tot[q]);
             if (li < bi && j >= 0 && j < bj && lq == 0) {
-                const double scale = same ? -0.5 * (double)si : rcp[li * TB + jj];
-                const F x = (F)(((double)rhs + (double)tot) * scale);
-                X[li + jj * LDX] = x;
-                XT[jj + li * LDX] = x;
+                if constexpr (C) {
+                    const double vr = (double)rhs[0] + (double)tot[0];
+                    const double vi = (double)rhs[1] + (double)tot[1];
+                    double xr, xi;
+                    if (same) {
+                        const double h = -0.5 * (double)si;
+                        xr = vr * h;
+                        xi = vi * h;
+                    } else {
+                        const double zr = rcp[0][li * TB + jj], zi = rcp[1][li * TB + jj];
+                        xr = vr * zr - vi * zi;
+                        xi = vr * zi + vi * zr;
+                    }
+                    X[li + jj * LDX] = (F)xr;
+                    X[TB * LDX + li + jj * LDX] = (F)xi;
+                    XT[jj + li * LDX] = (F)xr;
+                    XT[TB * LDX + jj + li * LDX] = (F)xi;
+                } else {
+                    const double scale = same ? -0.5 * (double)si : rcp[0][li * TB + jj];
+                    const F x = (F)(((double)rhs[0] + (double)tot[0]) * scale);
+                    X[li + jj * LDX] = x;
+                    XT[jj + li * LDX] = x;
+                }
             }
             __syncthreads();
         }
@@ -550,7 +732,10 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
         // ---- publish the block: coherent stores, all complete before the flag
         for (int e = tid; e < TB * TB; e += NT) {
             const int r = e % TB, c = e / TB;
-            if (r < bi && c < bj) coherent_store(M.V + (gr0 + r) + (gc0 + c) * M.ldv, X[r + c * LDX]);
+            if (r < bi && c < bj)
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    coherent_store(M.V + at(gr0 + r, gc0 + c, M.ldv, q), X[q * TB * LDX + r + c * LDX]);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -654,34 +839,76 @@ hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const Flow
 
 // Workgroups of a persistent sweep: as many as fit on the device at once
 // (more would only queue behind the first wave of them).
-template <typename F, int KIND> static int flow_grid()
+struct FlowFit {
+    int cus = 0, per = 0;
+};
+
+// Compute units of the current device and resident workgroups of this kernel per unit.
+template <typename F, int KIND, bool C> static FlowFit flow_fit()
 {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_flow<F, KIND>, NT, 0) != hipSuccess ||
-        per <= 0)
-        per = 1;
-    return cus * per;
+    FlowFit f;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&f.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        f.cus <= 0)
+        f.cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.per, k_flow<F, KIND, C>, NT, 0) !=
+            hipSuccess ||
+        f.per <= 0)
+        f.per = 1;
+    return f;
 }
 
-template <typename F, int KIND>
-hipError_t launch_flow(const FlowArgs<F> &a, int grid, hipStream_t st)
+template <typename F, int KIND, bool C> static const FlowFit &flow_fit_cached()
+{
+    static const FlowFit f = flow_fit<F, KIND, C>();
+    return f;
+}
+
+// The persistent grid: wgs_per_cu workgroups on every compute unit (0, or more
+// than fit: as many as fit), never more than there are tasks.  Tasks are taken
+// by ticket in dependency order, so any grid size is deadlock-free.
+template <typename F, int KIND, bool C>
+hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st)
 {
     if (a.ntasks <= 0) return hipSuccess;
-    static int full = 0;
-    if (!full) full = flow_grid<F, KIND>();
-    int g = grid > 0 ? grid : full;
-    g = std::min(g, a.ntasks);
-    hipLaunchKernelGGL((k_flow<F, KIND>), dim3(g), dim3(NT), 0, st, a);
+    const FlowFit &f = flow_fit_cached<F, KIND, C>();
+    const int per = (wgs_per_cu > 0 && wgs_per_cu < f.per) ? wgs_per_cu : f.per;
+    const int g = std::min(f.cus * per, a.ntasks);
+    hipLaunchKernelGGL((k_flow<F, KIND, C>), dim3(g), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-template hipError_t launch_flow<double, FLOW_MAIN>(const FlowArgs<double> &, int, hipStream_t);
-template hipError_t launch_flow<double, FLOW_SYL>(const FlowArgs<double> &, int, hipStream_t);
-template hipError_t launch_flow<float, FLOW_MAIN>(const FlowArgs<float> &, int, hipStream_t);
-template hipError_t launch_flow<float, FLOW_CORR>(const FlowArgs<float> &, int, hipStream_t);
-template hipError_t launch_flow<float, FLOW_SYL>(const FlowArgs<float> &, int, hipStream_t);
+int flow_max_wgs_per_cu(bool fp32, bool cplx)
+{
+    if (cplx) {
+        if (fp32)
+            return std::min({flow_fit_cached<float, FLOW_MAIN, true>().per,
+                             flow_fit_cached<float, FLOW_CORR, true>().per,
+                             flow_fit_cached<float, FLOW_SYL, true>().per});
+        return std::min(flow_fit_cached<double, FLOW_MAIN, true>().per,
+                        flow_fit_cached<double, FLOW_SYL, true>().per);
+    }
+    if (fp32)
+        return std::min({flow_fit_cached<float, FLOW_MAIN, false>().per,
+                         flow_fit_cached<float, FLOW_CORR, false>().per,
+                         flow_fit_cached<float, FLOW_SYL, false>().per});
+    return std::min(flow_fit_cached<double, FLOW_MAIN, false>().per,
+                    flow_fit_cached<double, FLOW_SYL, false>().per);
+}
+
+#define SGT_FLOW(F, K, C) \
+    template hipError_t launch_flow<F, K, C>(const FlowArgs<F> &, int, hipStream_t);
+SGT_FLOW(double, FLOW_MAIN, false)
+SGT_FLOW(double, FLOW_SYL, false)
+SGT_FLOW(float, FLOW_MAIN, false)
+SGT_FLOW(float, FLOW_CORR, false)
+SGT_FLOW(float, FLOW_SYL, false)
+SGT_FLOW(double, FLOW_MAIN, true)
+SGT_FLOW(double, FLOW_SYL, true)
+SGT_FLOW(float, FLOW_MAIN, true)
+SGT_FLOW(float, FLOW_CORR, true)
+SGT_FLOW(float, FLOW_SYL, true)
+#undef SGT_FLOW
 
 }  // namespace sgt

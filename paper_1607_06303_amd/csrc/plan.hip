@@ -8,7 +8,7 @@ namespace sgt {
 
 // One workgroup reads the diagonal, records sign(Re t_ii) as +1/-1 (Section 1),
 // the first index whose sign is undefined (zero or non-finite entry), and the
-// number of positive signs; optionally the real diagonal itself.
+// number of positive signs; optionally the diagonal itself.
 __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int64_t ldt,
                                                int64_t n, int cplx, int8_t *__restrict__ sgn,
                                                double *__restrict__ dg,
@@ -34,7 +34,13 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
         int s = 0;
         if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
         sgn[i] = (int8_t)s;
-        if (dg) dg[i] = re;  // the divisors t_ii - t_jj of the real sweeps, in FP64
+        // the divisors t_ii - t_jj of the sweeps, in FP64 (complex: re, im pairs)
+        if (dg && cplx) {
+            dg[2 * i] = re;
+            dg[2 * i + 1] = im;
+        } else if (dg) {
+            dg[i] = re;
+        }
         if (s == 0) atomicMin(&bad, (unsigned long long)i);
         my_pos += (s > 0);
     }

@@ -1,4 +1,5 @@
-// Kernels of the mixed-precision path with iterative refinement (real).
+// Kernels of the mixed-precision path with iterative refinement, for real
+// entries (P = 1) and complex entries (P = 2: interleaved re, im).
 //
 // A U0 computed with FP32 products is improved by Newton's method on the two
 // matrix equations that define U = sign(T) entry by entry in the substitution
@@ -44,12 +45,22 @@ __device__ inline double block_max(double v, double *red)
     return r;
 }
 
+// |z| of entry e (P planes at p[P * e + q]).
+template <int P, typename S> __device__ inline double mag(const S *p, int64_t e)
+{
+    if constexpr (P == 1) {
+        return fabs((double)p[e]);
+    } else {
+        return hypot((double)p[2 * e], (double)p[2 * e + 1]);
+    }
+}
+
 #define REF_MAT(a) (a.mats ? a.mats[blockIdx.z] : a.m0)
 
 // FP32 copies for the reduced-precision sweeps: the upper triangle of T, and
 // the (FP64-computed) diagonal blocks of U; max |t_ij| on the side.  Matrix
 // blockIdx.z of the table; columns strided over blockIdx.y.
-__global__ __launch_bounds__(NT) void k_to_f32(RefArgs a)
+template <int P> __global__ __launch_bounds__(NT) void k_to_f32(RefArgs a)
 {
     __shared__ double red[NT / 64];
     const RefMat d = REF_MAT(a);
@@ -57,10 +68,13 @@ __global__ __launch_bounds__(NT) void k_to_f32(RefArgs a)
     for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y)
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i <= j;
              i += (int64_t)gridDim.x * NT) {
-            const double t = d.T[i + j * d.ldt];
-            d.T32[i + j * d.ld32] = (float)t;
-            m = fmax(m, fabs(t));
-            if (d.split == 0 && i / TB == j / TB) d.U32[i + j * d.ld32] = (float)d.U[i + j * d.ldu];
+            const int64_t et = i + j * d.ldt, e32 = i + j * d.ld32, eu = i + j * d.ldu;
+#pragma unroll
+            for (int q = 0; q < P; ++q) d.T32[P * e32 + q] = (float)d.T[P * et + q];
+            m = fmax(m, mag<P>(d.T, et));
+            if (d.split == 0 && i / TB == j / TB)
+#pragma unroll
+                for (int q = 0; q < P; ++q) d.U32[P * e32 + q] = (float)d.U[P * eu + q];
         }
     m = block_max(m, red);
     if (threadIdx.x == 0) atomic_max_nonneg(&d.maxes[0], m);
@@ -75,7 +89,7 @@ __device__ inline int64_t region_rows(int64_t j, int64_t split)
 }
 
 // U(i, j) = U32(i, j) in FP64 for the entries of the computed region.
-__global__ __launch_bounds__(NT) void k_widen(RefArgs a)
+template <int P> __global__ __launch_bounds__(NT) void k_widen(RefArgs a)
 {
     __shared__ double red[NT / 64];
     const RefMat d = REF_MAT(a);
@@ -84,9 +98,10 @@ __global__ __launch_bounds__(NT) void k_widen(RefArgs a)
         const int64_t iend = region_rows(j, d.split);
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < iend;
              i += (int64_t)gridDim.x * NT) {
-            const double u = (double)d.U32[i + j * d.ld32];
-            d.U[i + j * d.ldu] = u;
-            m = fmax(m, fabs(u));
+            const int64_t e32 = i + j * d.ld32, eu = i + j * d.ldu;
+#pragma unroll
+            for (int q = 0; q < P; ++q) d.U[P * eu + q] = (double)d.U32[P * e32 + q];
+            m = fmax(m, mag<P>(d.U32, e32));
         }
     }
     m = block_max(m, red);
@@ -94,7 +109,7 @@ __global__ __launch_bounds__(NT) void k_widen(RefArgs a)
 }
 
 // U += E on the entries of the computed region; max |E| on the side.
-__global__ __launch_bounds__(NT) void k_add_correction(RefArgs a)
+template <int P> __global__ __launch_bounds__(NT) void k_add_correction(RefArgs a)
 {
     __shared__ double red[NT / 64];
     const RefMat d = REF_MAT(a);
@@ -103,9 +118,10 @@ __global__ __launch_bounds__(NT) void k_add_correction(RefArgs a)
         const int64_t iend = region_rows(j, d.split);
         for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < iend;
              i += (int64_t)gridDim.x * NT) {
-            const double e = (double)d.E32[i + j * d.ld32];
-            d.U[i + j * d.ldu] += e;
-            m = fmax(m, fabs(e));
+            const int64_t e32 = i + j * d.ld32, eu = i + j * d.ldu;
+#pragma unroll
+            for (int q = 0; q < P; ++q) d.U[P * eu + q] += (double)d.E32[P * e32 + q];
+            m = fmax(m, mag<P>(d.E32, e32));
         }
     }
     m = block_max(m, red);
@@ -118,14 +134,32 @@ __global__ void k_clear_correction_max(RefArgs a)
     if (z < a.nmat) (a.mats ? a.mats[z] : a.m0).maxes[2] = 0;
 }
 
+// acc (P planes) += a * b for one MFMA operand pair (complex: four products)
+template <int P>
+__device__ inline void mac64(const double *a, const double *b, int ao, int bo, int as, int bs,
+                             dx4 (&acc)[P])
+{
+    if constexpr (P == 1) {
+        acc[0] = mfma_f64(a[ao], b[bo], acc[0]);
+    } else {
+        const double ar = a[ao], ai = a[as + ao], br = b[bo], bi = b[bs + bo];
+        acc[0] = mfma_f64(ar, br, acc[0]);
+        acc[0] = mfma_f64(-ai, bi, acc[0]);
+        acc[1] = mfma_f64(ar, bi, acc[1]);
+        acc[1] = mfma_f64(ai, br, acc[1]);
+    }
+}
+
 // FP64 residual of one off-diagonal block per workgroup (tasks in reverse
 // order: the longest products first).  Output: R as FP32 (the right-hand side
 // of the correction sweep, into E32) and the block's squared Frobenius norm.
+template <int P>
 __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict__ tasks,
                                               int ntasks, double *__restrict__ norm2)
 {
-    __shared__ double sAU[TB * APITCH], sAT[TB * APITCH];
-    __shared__ double sBU[(TB / 4) * BSLAB], sBT[(TB / 4) * BSLAB];
+    constexpr int AS = TB * APITCH, BS = (TB / 4) * BSLAB;  // plane strides
+    __shared__ double sAU[P * AS], sAT[P * AS];
+    __shared__ double sBU[P * BS], sBT[P * BS];
     __shared__ int8_t rs[TB], cs[TB];
     __shared__ double red[NT / 64];
 
@@ -160,10 +194,12 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     }
     const bool any_x = __syncthreads_or(needX);
 
-    dx4 accY, accX;
-    for (int r = 0; r < 4; ++r) accY[r] = accX[r] = 0.0;
+    dx4 accY[P], accX[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        for (int r = 0; r < 4; ++r) accY[q][r] = accX[q][r] = 0.0;
 
-    double gaU[4], gaT[4], gbU[4], gbT[4];
+    double gaU[P][4], gaT[P][4], gbU[P][4], gbT[P][4];
     auto load = [&](int K) {
         const int64_t k0 = (int64_t)K * TB;
         const bool dA = K == I, dB = K == J;
@@ -174,20 +210,25 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
             const int64_t ra = r0 + lr + e, rb = k0 + lr + e;
             const bool okA = ca < n && !(dA && ra > ca);
             const bool okB = rb < n && cb < n && !(dB && rb > cb);
-            gaU[e] = okA ? U[ra + ca * ldu] : 0.0;
-            gaT[e] = (okA && any_x) ? T[ra + ca * ldt] : 0.0;
-            gbU[e] = okB ? U[rb + cb * ldu] : 0.0;
-            gbT[e] = (okB && any_x) ? T[rb + cb * ldt] : 0.0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                gaU[q][e] = okA ? U[P * (ra + ca * ldu) + q] : 0.0;
+                gaT[q][e] = (okA && any_x) ? T[P * (ra + ca * ldt) + q] : 0.0;
+                gbU[q][e] = okB ? U[P * (rb + cb * ldu) + q] : 0.0;
+                gbT[q][e] = (okB && any_x) ? T[P * (rb + cb * ldt) + q] : 0.0;
+            }
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sAU[lc * APITCH + lr + e] = gaU[e];
-            sAT[lc * APITCH + lr + e] = -gaT[e];
-            sBU[(lr >> 2) * BSLAB + lc * 4 + e] = gbU[e];
-            sBT[(lr >> 2) * BSLAB + lc * 4 + e] = gbT[e];
-        }
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sAU[q * AS + lc * APITCH + lr + e] = gaU[q][e];
+                sAT[q * AS + lc * APITCH + lr + e] = -gaT[q][e];
+                sBU[q * BS + (lr >> 2) * BSLAB + lc * 4 + e] = gbU[q][e];
+                sBT[q * BS + (lr >> 2) * BSLAB + lc * 4 + e] = gbT[q][e];
+            }
     };
     const int g = lane >> 4, tl = lane & 15;
     load(I);
@@ -200,11 +241,10 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
         for (int k4 = 0; k4 < TB / 4; ++k4) {
             const int ao = (k4 * 4 + g) * APITCH + 16 * pr + tl;
             const int bo = k4 * BSLAB + (16 * pc + tl) * 4 + g;
-            const double aU = sAU[ao], aT = sAT[ao], bU = sBU[bo], bT = sBT[bo];
-            if (needY) accY = mfma_f64(aU, bU, accY);
+            if (needY) mac64<P>(sAU, sBU, ao, bo, AS, BS, accY);
             if (needX) {
-                accX = mfma_f64(aU, bT, accX);
-                accX = mfma_f64(aT, bU, accX);
+                mac64<P>(sAU, sBT, ao, bo, AS, BS, accX);
+                mac64<P>(sAT, sBU, ao, bo, AS, BS, accX);
             }
         }
         __syncthreads();
@@ -218,10 +258,15 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     for (int r = 0; r < 4; ++r) {
         const int i = 16 * pr + mfma64_row(lane, r);
         const int j = 16 * pc + tl;
-        const double v = rs[i] == cs[j] ? accY[r] : accX[r];
+        const bool same = rs[i] == cs[j];
         if (j < bj) {
-            d.E32[(r0 + i) + (c0 + j) * d.ld32] = (float)v;
-            ss += v * v;
+            const int64_t e = (r0 + i) + (c0 + j) * d.ld32;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const double v = same ? accY[q][r] : accX[q][r];
+                d.E32[P * e + q] = (float)v;
+                ss += v * v;
+            }
         }
     }
     for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
@@ -234,11 +279,13 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
 // block of X per workgroup: R = 2 s T12 - T11 X + X T22, with X = U(0:p, p:n).
 // K steps: blocks K >= I of T11's rows (K = I keeps its upper triangle), then
 // blocks K <= J of T22's columns (K = J likewise).
+template <int P>
 __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restrict__ tasks,
                                                   int ntasks, double *__restrict__ norm2)
 {
-    __shared__ double sA[TB * APITCH];
-    __shared__ double sB[(TB / 4) * BSLAB];
+    constexpr int AS = TB * APITCH, BS = (TB / 4) * BSLAB;
+    __shared__ double sA[P * AS];
+    __shared__ double sB[P * BS];
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -252,10 +299,12 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
     const int64_t ldt = d.ldt, ldu = d.ldu;
     const int64_t r0 = (int64_t)I * TB, c0 = p + (int64_t)J * TB;
 
-    dx4 acc;
-    for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+    dx4 acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        for (int r = 0; r < 4; ++r) acc[q][r] = 0.0;
     const int na = uniform(d.nbr) - I, nsteps = uniform(na + J + 1);
-    double ga[4], gb[4];
+    double ga[P][4], gb[P][4];
     auto load = [&](int s) {
         int64_t ar, ac, aend_r, aend_c, br, bc, bend_r, bend_c;
         bool adiag, bdiag;
@@ -281,16 +330,21 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
             const int64_t rb = br + lr + e, cb = bc + lc;
             const bool okA = ra < aend_r && ca < aend_c && !(adiag && ra > ca);
             const bool okB = rb < bend_r && cb < bend_c && !(bdiag && rb > cb);
-            ga[e] = okA ? sa * pa[ra + ca * lda] : 0.0;
-            gb[e] = okB ? pb[rb + cb * ldb] : 0.0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                ga[q][e] = okA ? sa * pa[P * (ra + ca * lda) + q] : 0.0;
+                gb[q][e] = okB ? pb[P * (rb + cb * ldb) + q] : 0.0;
+            }
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sA[lc * APITCH + lr + e] = ga[e];
-            sB[(lr >> 2) * BSLAB + lc * 4 + e] = gb[e];
-        }
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sA[q * AS + lc * APITCH + lr + e] = ga[q][e];
+                sB[q * BS + (lr >> 2) * BSLAB + lc * 4 + e] = gb[q][e];
+            }
     };
     const int g = lane >> 4, tl = lane & 15;
     load(0);
@@ -301,9 +355,9 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
         if (more) load(s + 1);
 #pragma unroll
         for (int k4 = 0; k4 < TB / 4; ++k4) {
-            const double av = sA[(k4 * 4 + g) * APITCH + 16 * pr + tl];
-            const double bv = sB[k4 * BSLAB + (16 * pc + tl) * 4 + g];
-            acc = mfma_f64(av, bv, acc);
+            const int ao = (k4 * 4 + g) * APITCH + 16 * pr + tl;
+            const int bo = k4 * BSLAB + (16 * pc + tl) * 4 + g;
+            mac64<P>(sA, sB, ao, bo, AS, BS, acc);
         }
         __syncthreads();
         if (more) {
@@ -317,9 +371,12 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
         const int64_t i = r0 + 16 * pr + mfma64_row(lane, r);
         const int64_t j = c0 + 16 * pc + tl;
         if (i < p && j < n) {
-            const double v = d.two_s * T[i + j * ldt] + acc[r];
-            d.E32[i + j * d.ld32] = (float)v;
-            ss += v * v;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const double v = d.two_s * T[P * (i + j * ldt) + q] + acc[q][r];
+                d.E32[P * (i + j * d.ld32) + q] = (float)v;
+                ss += v * v;
+            }
         }
     }
     for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
@@ -341,36 +398,50 @@ dim3 col_grid(int64_t nmax, int nmat)
 
 }  // namespace
 
-hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, hipStream_t st)
+hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st)
 {
     if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_f32, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    if (cplx)
+        hipLaunchKernelGGL(k_to_f32<2>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_to_f32<1>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_widen(const RefArgs &a, int64_t nmax, hipStream_t st)
+hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st)
 {
     if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_widen, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    if (cplx)
+        hipLaunchKernelGGL(k_widen<2>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_widen<1>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, hipStream_t st)
+hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st)
 {
     if (nmax <= 0 || a.nmat <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear_correction_max, dim3((a.nmat + 255) / 256), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_add_correction, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    if (cplx)
+        hipLaunchKernelGGL(k_add_correction<2>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_add_correction<1>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_resid(const RefArgs &a, bool syl, const int2 *tasks, int ntasks, double *norm2,
-                        hipStream_t st)
+hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks, int ntasks,
+                        double *norm2, hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
-    if (syl)
-        hipLaunchKernelGGL(k_resid_syl, dim3(ntasks), dim3(NT), 0, st, a, tasks, ntasks, norm2);
+    const dim3 g(ntasks), b(NT);
+    if (syl && cplx)
+        hipLaunchKernelGGL(k_resid_syl<2>, g, b, 0, st, a, tasks, ntasks, norm2);
+    else if (syl)
+        hipLaunchKernelGGL(k_resid_syl<1>, g, b, 0, st, a, tasks, ntasks, norm2);
+    else if (cplx)
+        hipLaunchKernelGGL(k_resid<2>, g, b, 0, st, a, tasks, ntasks, norm2);
     else
-        hipLaunchKernelGGL(k_resid, dim3(ntasks), dim3(NT), 0, st, a, tasks, ntasks, norm2);
+        hipLaunchKernelGGL(k_resid<1>, g, b, 0, st, a, tasks, ntasks, norm2);
     return hipGetLastError();
 }
 

@@ -32,9 +32,9 @@ template <typename Fn> hipError_t timed(hipStream_t st, int pk, double flops, Fn
 }
 
 // One dataflow sweep over a task list (after zeroing the control words).
-template <typename F, int KIND>
+template <typename F, int KIND, bool C>
 hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *ctrl, int *flags,
-                    int pk, double flops, hipStream_t st)
+                    int pk, double flops, int wgs, hipStream_t st)
 {
     if (nt == 0) return hipSuccess;
     hipError_t r = launch_fill_int(ctrl, 2, 0, st);
@@ -48,9 +48,17 @@ hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *
     a.flags = flags;
     a.spin_limit = kSpinLimit;
     prof_begin(st);
-    r = launch_flow<F, KIND>(a, 0, st);
+    r = launch_flow<F, KIND, C>(a, wgs, st);
     prof_end(st, pk, flops);
     return r;
+}
+
+template <typename F, int KIND>
+hipError_t run_flow_any(bool cplx, const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *ctrl,
+                        int *flags, int pk, double flops, int wgs, hipStream_t st)
+{
+    return cplx ? run_flow<F, KIND, true>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st)
+                : run_flow<F, KIND, false>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st);
 }
 
 template <typename F>
@@ -105,9 +113,10 @@ struct Lay {
     size_t h_norm0, h_norm1, h_maxes, h_err, h_ftasks, host;
     int64_t nflags_max, ntasks_max, ndiag_max;
     std::vector<int64_t> off32;  // per matrix, in floats, of its three FP32 n x n arrays
+                                 // (complex: interleaved pairs, twice the floats)
 };
 
-Lay make_lay(const int64_t *ns, int nm, bool mixed)
+Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
 {
     Lay L;
     int64_t sq = 0, nbsum = 0, f32 = 0;
@@ -117,7 +126,7 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed)
         sq += nb * nb;
         nbsum += nb;
         L.off32[m] = f32;
-        if (mixed) f32 += 3 * ns[m] * ns[m];
+        if (mixed) f32 += (cplx ? 6 : 3) * ns[m] * ns[m];
     }
     L.nflags_max = L.ntasks_max = std::max<int64_t>(sq, 1);
     L.ndiag_max = std::max<int64_t>(nbsum, 1);
@@ -188,17 +197,18 @@ SweepFlops item_flops(const int8_t *s, const RealItem &it)
 
 }  // namespace
 
-void run_sizes(const int64_t *ns, int nmat, bool mixed, size_t *dev_bytes, size_t *host_bytes)
+void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_bytes,
+               size_t *host_bytes)
 {
-    const Lay L = make_lay(ns, nmat, mixed);
+    const Lay L = make_lay(ns, nmat, mixed, cplx);
     if (dev_bytes) *dev_bytes = L.dev;
     if (host_bytes) *host_bytes = L.host;
 }
 
-int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, void *host_ws,
+int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, bool cplx, void *host_ws,
                 hipStream_t st, int *err)
 {
-    const Lay L = make_lay(ns, nmat, mixed);
+    const Lay L = make_lay(ns, nmat, mixed, cplx);
     int *herr = (int *)((char *)host_ws + L.h_err);
     if (hipMemcpyAsync(herr, (char *)dev_ws + L.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
@@ -215,13 +225,16 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     const int nm = (int)items.size();
     if (nm == 0) return SIGNTRI_OK;
     const bool mixed = mode != SIGNTRI_FP64, refine = mode == SIGNTRI_MIXED_REFINED;
+    const bool cplx = items[0].cplx;  // every item of a run has the same entry type
+    const int P = cplx ? 2 : 1;
+    const int wgs = opts ? opts->wgs_per_cu : 0;
     std::vector<int64_t> ns(nm);
     int64_t nmax = 0;
     for (int m = 0; m < nm; ++m) {
         ns[m] = items[m].n;
         nmax = std::max(nmax, ns[m]);
     }
-    const Lay L = make_lay(ns.data(), nm, mixed);
+    const Lay L = make_lay(ns.data(), nm, mixed, cplx);
     char *D = (char *)dev_ws, *H = (char *)host_ws;
     FlowMat<double> *hf64 = (FlowMat<double> *)(H + L.fm64);
     FlowMat<float> *hf32 = (FlowMat<float> *)(H + L.fm32);
@@ -259,7 +272,7 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
         if (!triv && !ps)
             for (int64_t I = 0; I < nblocks(n); ++I) hdt[ndiag++] = make_int2(m, (int)I);
         if (mixed) {
-            float *T32 = f32 + L.off32[m], *U32 = T32 + n * n, *E32 = U32 + n * n;
+            float *T32 = f32 + L.off32[m], *U32 = T32 + P * n * n, *E32 = U32 + P * n * n;
             const int64_t ld = std::max<int64_t>(n, 1);
             if (ps) {
                 hf32[m] = syl_mat<float>(T32, ld, U32, ld, T32, ld, 2.0 * it.s, it.dg, n, it.p,
@@ -338,16 +351,16 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     // ---- outputs, diagonal blocks (FP64 in every mode)
     HIPCHK(timed(st, PK_AUX, 0.0, [&] {
         hipError_t r = launch_fill_int(ctrl, 16, 0, st);
-        if (r == hipSuccess) r = launch_prepare_b(dpm, nm, nmax, st);
+        if (r == hipSuccess) r = launch_prepare_b(dpm, nm, nmax, cplx, st);
         return r;
     }));
-    HIPCHK(timed(st, PK_DIAG, fl.diag, [&] { return launch_diag_b(dpm, ddt, (int)ndiag, st); }));
+    HIPCHK(timed(st, PK_DIAG, fl.diag, [&] { return launch_diag_b(dpm, ddt, (int)ndiag, cplx, st); }));
     if (nph + nps == 0) return SIGNTRI_OK;
 
     if (!mixed) {
         HIPCHK(clear_flags(0));
-        HIPCHK((run_flow<double, FLOW_MAIN>(df64, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, st)));
-        HIPCHK((run_flow<double, FLOW_SYL>(df64, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, st)));
+        HIPCHK((run_flow_any<double, FLOW_MAIN>(cplx, df64, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, wgs, st)));
+        HIPCHK((run_flow_any<double, FLOW_SYL>(cplx, df64, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, wgs, st)));
         return SIGNTRI_OK;
     }
 
@@ -357,18 +370,18 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     ra.mats = drm;
     ra.nmat = nm;
     HIPCHK(timed(st, PK_AUX, 0.0, [&] { return launch_fill_int((int *)maxes, 6 * nm, 0, st); }));
-    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_to_f32(ra, nmax, st); }));
+    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_to_f32(ra, nmax, cplx, st); }));
     HIPCHK(clear_flags(0));
-    HIPCHK((run_flow<float, FLOW_MAIN>(df32, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, st)));
-    HIPCHK((run_flow<float, FLOW_SYL>(df32, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, st)));
-    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_widen(ra, nmax, st); }));
+    HIPCHK((run_flow_any<float, FLOW_MAIN>(cplx, df32, dtk, nph, ctrl, flags, PK_FLOW, fl.flow, wgs, st)));
+    HIPCHK((run_flow_any<float, FLOW_SYL>(cplx, df32, dtk_ps, nps, ctrl, flags, PK_SYL, fl.syl, wgs, st)));
+    HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_widen(ra, nmax, cplx, st); }));
     if (!refine) return SIGNTRI_OK;
 
     double *norms[2] = {(double *)(D + L.norms0), (double *)(D + L.norms1)};
     auto resid = [&](double *norm2) -> hipError_t {
         return timed(st, PK_RESID, fl.resid, [&] {
-            hipError_t r = launch_resid(ra, false, dtk, (int)nph, norm2, st);
-            if (r == hipSuccess) r = launch_resid(ra, true, dtk_ps, (int)nps, norm2, st);
+            hipError_t r = launch_resid(ra, false, cplx, dtk, (int)nph, norm2, st);
+            if (r == hipSuccess) r = launch_resid(ra, true, cplx, dtk_ps, (int)nps, norm2, st);
             return r;
         });
     };
@@ -391,9 +404,9 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     for (int step = 1; step <= max_steps; ++step) {
         // correction E (FP32): the residual in E32 on entry, E on exit
         HIPCHK(clear_flags(0));
-        HIPCHK((run_flow<float, FLOW_CORR>(dfc, dtk, nph, ctrl, flags, PK_CORR, fl.corr, st)));
-        HIPCHK((run_flow<float, FLOW_SYL>(dfc, dtk_ps, nps, ctrl, flags, PK_CORR, fl.syl, st)));
-        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_add_correction(ra, nmax, st); }));
+        HIPCHK((run_flow_any<float, FLOW_CORR>(cplx, dfc, dtk, nph, ctrl, flags, PK_CORR, fl.corr, wgs, st)));
+        HIPCHK((run_flow_any<float, FLOW_SYL>(cplx, dfc, dtk_ps, nps, ctrl, flags, PK_CORR, fl.syl, wgs, st)));
+        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_add_correction(ra, nmax, cplx, st); }));
         HIPCHK(resid(norms[cur ^ 1]));
         steps = step;
         // convergence decision on the host
@@ -480,8 +493,8 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     HIPCHK(clear_flags(1));
     HIPCHK(timed(st, PK_AUX, 0.0,
                  [&] { return launch_clear_task_flags(dft, fph + fps, df64, flags, st); }));
-    HIPCHK((run_flow<double, FLOW_MAIN>(df64, dft, fph, ctrl, flags, PK_FLOW, 0.0, st)));
-    HIPCHK((run_flow<double, FLOW_SYL>(df64, dft + fph, fps, ctrl, flags, PK_SYL, 0.0, st)));
+    HIPCHK((run_flow_any<double, FLOW_MAIN>(cplx, df64, dft, fph, ctrl, flags, PK_FLOW, 0.0, wgs, st)));
+    HIPCHK((run_flow_any<double, FLOW_SYL>(cplx, df64, dft + fph, fps, ctrl, flags, PK_SYL, 0.0, wgs, st)));
     HIPCHK(hipMemcpyAsync(herr, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (herr[1]) return SIGNTRI_EHIP;

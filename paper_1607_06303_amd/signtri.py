@@ -18,11 +18,14 @@ COL_MAJOR, ROW_MAJOR = 0, 1
 MODES = {"fp64": 0, "mixed": 1, "fp32": 2}
 ALGOS = {"auto": 0, "ph": 1, "ps": 2}
 PATH_NAMES = {0: "trivial", 1: "ph", 2: "ps"}
+SWEEPS = {"auto": 0, "dataflow": 1, "superdiag": 2}
+SWEEP_NAMES = {0: "-", 1: "dataflow", 2: "superdiag"}
 
 EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_batched_workspace_size", "signtri_strerror", "sign_tri",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
-           "signtri_profile_read")
+           "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
+           "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
             "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10}
 
@@ -34,12 +37,14 @@ class Info(ctypes.Structure):
         ("w_ph", ctypes.c_double), ("w_ps", ctypes.c_double),
         ("refine_steps", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("fallback_tiles", ctypes.c_int64), ("correction_rel", ctypes.c_double),
-        ("bad_index", ctypes.c_int64),
+        ("bad_index", ctypes.c_int64), ("sweep", ctypes.c_int32),
+        ("wgs_per_cu", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
         d["path_name"] = PATH_NAMES.get(self.path, "?")
+        d["sweep_name"] = SWEEP_NAMES.get(self.sweep, "?")
         d["model_pick_name"] = PATH_NAMES.get(self.model_pick, "?")
         return d
 
@@ -49,7 +54,21 @@ class Options(ctypes.Structure):
         ("tile", ctypes.c_int32), ("max_refine_steps", ctypes.c_int32),
         ("stall_ratio", ctypes.c_double), ("no_fallback", ctypes.c_int32),
         ("max_splits", ctypes.c_int32), ("force_stall", ctypes.c_int64),
+        ("sweep", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
     ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("mode", ctypes.c_int32), ("path", ctypes.c_int32),
+        ("log2n", ctypes.c_int32), ("sweep", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["sweep_name"] = SWEEP_NAMES.get(self.sweep, "?")
+        return d
 
 
 class SignTriError(RuntimeError):
@@ -98,6 +117,17 @@ def lib() -> ctypes.CDLL:
             L.signtri_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
             L.signtri_profile_read.restype = i32
+            L.signtri_autotune.argtypes = [p, i64, p, i64, i64, i32, i32, i32, p, i32,
+                                           ctypes.POINTER(TuneEntry)]
+            L.signtri_autotune.restype = i32
+            L.signtri_tune_lookup.argtypes = [i32, i32, i32, i64, ctypes.POINTER(TuneEntry)]
+            L.signtri_tune_lookup.restype = i32
+            L.signtri_tune_save.argtypes = [ctypes.c_char_p]
+            L.signtri_tune_save.restype = i32
+            L.signtri_tune_load.argtypes = [ctypes.c_char_p]
+            L.signtri_tune_load.restype = i32
+            L.signtri_tune_clear.argtypes = []
+            L.signtri_tune_clear.restype = None
             _lib = L
     return _lib
 
@@ -170,6 +200,8 @@ def _opts(options: dict | None):
         return None
     o = Options()
     for k, v in options.items():
+        if k == "sweep" and isinstance(v, str):
+            v = SWEEPS[v]
         setattr(o, k, v)
     return ctypes.byref(o)
 
@@ -259,3 +291,45 @@ def profile_read() -> dict:
         if cnt.value:
             out[name] = (ms.value, cnt.value, fl.value)
     return out
+
+
+def autotune(T, mode: str = "fp64", algo: str = "auto", reps: int = 3, out=None, stream=None) -> dict:
+    """Time every sweep variant on the column-major T and record the fastest in the
+    library's tuning table (used by later calls that leave those options at 0)."""
+    if T.dim() != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    n = T.shape[0]
+    lay = _layout(T)
+    if lay is None or (n > 1 and lay[0] != COL_MAJOR):
+        raise ValueError("autotune takes a column-major T")
+    U = out if out is not None else empty_like_layout(T)
+    best = TuneEntry()
+    rc = lib().signtri_autotune(T.data_ptr() if n else None, lay[1], U.data_ptr() if n else None,
+                                _layout(U)[1], n, _dtype_code(T), MODES[mode], ALGOS[algo],
+                                _stream_handle(T, stream), int(reps), ctypes.byref(best))
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc))
+    return best.as_dict()
+
+
+def tune_lookup(complex_: bool, mode: str, path: str, n: int) -> dict | None:
+    e = TuneEntry()
+    code = {"ph": 1, "ps": 2}[path]
+    if lib().signtri_tune_lookup(C128 if complex_ else R64, MODES[mode], code, int(n),
+                                 ctypes.byref(e)):
+        return e.as_dict()
+    return None
+
+
+def tune_save(path: str) -> None:
+    if lib().signtri_tune_save(os.fsencode(path)) != 0:
+        raise OSError("cannot write tuning table to %s" % path)
+
+
+def tune_load(path: str) -> None:
+    if lib().signtri_tune_load(os.fsencode(path)) != 0:
+        raise OSError("cannot read tuning table from %s" % path)
+
+
+def tune_clear() -> None:
+    lib().signtri_tune_clear()

@@ -73,6 +73,43 @@ def test_argument_validation_without_device_work():
     assert _call(None, 1, None, 1, 0) == 0
 
 
+def _call_opts(n, dtype=0, mode=0, **opts):
+    o = signtri.Options()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    info = signtri.Info()
+    t, u = (ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000000)) if n else (None, None)
+    return signtri.lib().signtri(t, max(n, 1), u, max(n, 1), n, dtype, 0, mode, 0, None, 0, None,
+                                 ctypes.byref(o), ctypes.byref(info))
+
+
+@pytest.mark.parametrize("n", [0, 8])
+def test_option_validation_without_device_work(n):
+    # values out of range: argument 13
+    assert _call_opts(n, tile=48) == -13
+    assert _call_opts(n, sweep=3) == -13
+    assert _call_opts(n, sweep=-1) == -13
+    assert _call_opts(n, wgs_per_cu=-2) == -13
+    # combinations no sweep implements
+    assert _call_opts(n, dtype=1, tile=64) == 5          # complex with 64 x 64 blocks
+    assert _call_opts(n, mode=1, sweep=2) == 5           # refinement on the superdiagonal sweep
+    assert _call_opts(n, mode=2, tile=64) == 5
+    assert _call_opts(n, sweep=1, tile=64) == 5          # 64 x 64 blocks on the dataflow sweep
+
+
+def test_batched_option_validation_without_device_work():
+    L = signtri.lib()
+    P, I = ctypes.c_void_p * 1, ctypes.c_int64 * 1
+    for opts, want in (({"sweep": 2}, 5), ({"tile": 64}, 5), ({"tile": 48}, -13),
+                       ({"wgs_per_cu": -1}, -13)):
+        o = signtri.Options()
+        for k, v in opts.items():
+            setattr(o, k, v)
+        rc = L.signtri_batched(P(0x1000), I(8), P(0x1000000), I(8), I(8), 1, 0, 0, 0, None, 0,
+                               None, ctypes.byref(o), None)
+        assert rc == want, (opts, rc)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 5, 33, 120])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_planner_matches_bruteforce(n, cplx):

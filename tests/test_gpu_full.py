@@ -1,0 +1,134 @@
+"""GPU parity at the full sizes of the benchmark workloads, through the same
+entry points bench.py times.
+
+The oracle cannot run sign(T) of the whole matrix in seconds at these sizes, so
+each result is checked on samples it can compute: for an upper-triangular T,
+the principal block U[a:a+m, a:a+m] of U = sign(T) is sign(T[a:a+m, a:a+m])
+(a function of a triangular matrix restricted to a contiguous diagonal range),
+so leading, trailing and random interior windows are compared entry by entry
+with the oracle at the 1e-11 bar.  At full size the invariants U^2 = I and
+TU = UT are checked as well (computed on the GPU in FP64), which covers the
+entries outside the windows.  The 2000-matrix batched workload is checked
+matrix by matrix in full.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06303_amd import workloads as wl
+from tests.conftest import rel_fro
+from tests.test_gpu_parity import TOL_FP64, dev, to_dev_colmajor  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def windows(n, m, rng, count=2):
+    starts = {0, n - m}
+    starts.update(int(a) for a in rng.integers(1, n - m, size=count))
+    return sorted(starts)
+
+
+def check_windows(T, U, m, seed):
+    import oracle
+
+    n = T.shape[0]
+    worst = 0.0
+    for a in windows(n, m, np.random.default_rng(seed)):
+        ref = oracle.sign_tri(T[a:a + m, a:a + m])
+        err = rel_fro(U[a:a + m, a:a + m], ref)
+        assert err <= TOL_FP64, (a, m, err)
+        worst = max(worst, err)
+    return worst
+
+
+def invariants(Tg, Ug):
+    import torch
+
+    n = Tg.shape[0]
+    U = Ug.contiguous()
+    T = torch.triu(Tg.contiguous())
+    nu = torch.linalg.norm(U).item()
+    eye = torch.eye(n, dtype=U.dtype, device=U.device)
+    inv = torch.linalg.norm(U @ U - eye).item() / (nu * nu)
+    com = torch.linalg.norm(T @ U - U @ T).item() / (torch.linalg.norm(T).item() * nu)
+    lower = torch.count_nonzero(torch.tril(U, -1)).item()
+    return inv, com, lower
+
+
+def run_full(T, dev, mode):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    Tg = to_dev_colmajor(T, dev)
+    U, info = signtri.sign_tri(Tg, mode=mode)
+    torch.cuda.synchronize()
+    return Tg, U, info
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_workload3_full(dev, mode):
+    """Real n = 8192 with 64 negative diagonal entries (the benchmark)."""
+    T = wl.workload3()
+    Tg, U, info = run_full(T, dev, mode)
+    print("workload3 %s: path %s sweep %s refine %d fallback %d"
+          % (mode, info["path_name"], info["sweep_name"], info["refine_steps"],
+             info["fallback_tiles"]))
+    assert info["fallback_tiles"] == 0
+    inv, com, lower = invariants(Tg, U)
+    assert lower == 0 and inv <= 1e-13 and com <= 1e-13, (inv, com)
+    check_windows(T, U.cpu().numpy(), 1024, 31)
+
+
+@pytest.mark.parametrize("sorted_", [False, True])
+def test_workload2_full(dev, sorted_):
+    """Complex n = 4096, balanced inertia, interleaved or grouped by sign."""
+    T = wl.workload2(sorted_=sorted_)
+    Tg, U, info = run_full(T, dev, "fp64")
+    # grouped by sign, the Section 3 model takes the Sylvester form
+    assert info["path_name"] == ("ps" if sorted_ else "ph")
+    inv, com, lower = invariants(Tg, U)
+    assert lower == 0 and inv <= 1e-12 and com <= 1e-12, (inv, com)
+    check_windows(T, U.cpu().numpy(), 768, 32)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_workload5_full(dev, mode):
+    """Complex n = 16384 with diagonal real parts down to 1e-3 (near the imaginary axis);
+    mixed precision refines, and recomputes in FP64 any block whose refinement stalls."""
+    import torch
+
+    T = wl.workload5()
+    Tg, U, info = run_full(T, dev, mode)
+    print("workload5 %s: path %s sweep %s refine %d fallback %d"
+          % (mode, info["path_name"], info["sweep_name"], info["refine_steps"],
+             info["fallback_tiles"]))
+    Uh = U.cpu().numpy()
+    assert np.all(np.isfinite(Uh))
+    check_windows(T, Uh, 768, 35)
+    del Uh
+    inv, com, lower = invariants(Tg, U)
+    print("workload5: |U^2-I|/|U|^2 %.2e  |TU-UT|/(|T||U|) %.2e" % (inv, com))
+    assert lower == 0 and inv <= 1e-10 and com <= 1e-10, (inv, com)
+    del Tg, U
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_workload4_full_batched(dev, mode):
+    """All 2000 matrices (orders 32..1024), one batched call, every entry checked."""
+    import torch
+
+    import oracle
+    from paper_1607_06303_amd import signtri
+
+    Ts = wl.workload4()
+    Tg = [to_dev_colmajor(T, dev) for T in Ts]
+    Us, infos = signtri.sign_tri_batched(Tg, mode=mode)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for T, U, inf in zip(Ts, Us, infos):
+        err = rel_fro(U.cpu().numpy(), oracle.sign_tri(T))
+        assert err <= TOL_FP64, (T.shape, err, inf)
+        worst = max(worst, err)
+    assert all(i["fallback_tiles"] == 0 for i in infos)
+    print("workload4 %s: worst rel err %.2e" % (mode, worst))

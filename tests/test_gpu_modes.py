@@ -103,8 +103,6 @@ def test_row_major(dev, cplx, mode):
     from paper_1607_06303_amd import signtri
     import oracle
 
-    if cplx and mode != "fp64":
-        pytest.skip("complex runs in FP64 only")
     rng = np.random.default_rng(6500)
     n, ld = 150, 161
     T = wl.make_T(n, rng, complex_=cplx)
@@ -156,14 +154,59 @@ def test_no_fallback_reports_nonconvergence(dev):
     assert ei.value.code == 4
 
 
-def test_complex_mixed_not_supported(dev):
+@pytest.mark.parametrize("n", [2, 33, 100, 257])
+@pytest.mark.parametrize("mode,tol", [("fp64", TOL_FP64), ("mixed", TOL_FP64), ("fp32", TOL_FP32)])
+def test_complex_dataflow(dev, n, mode, tol):
+    rng = np.random.default_rng(6900 + n)
+    _, info, _ = check(wl.make_T(n, rng, complex_=True), dev, tol=tol, mode=mode,
+                       options={"sweep": "dataflow"})
+    assert info["sweep_name"] == ("dataflow" if n > 1 else "-")
+    if mode == "mixed":
+        assert info["fallback_tiles"] == 0
+        if n > 32:
+            assert info["refine_steps"] >= 1
+
+
+def test_complex_near_imaginary_mixed(dev):
+    rng = np.random.default_rng(6950)
+    T = wl.make_T(300, rng, complex_=True, re_range=(1e-3, 1.0), im_range=(-2.0, 2.0))
+    _, info, _ = check(T, dev, mode="mixed")
+    assert info["path_name"] == "ph"
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,p,first", [(200, 77, 1.0), (300, 150, -1.0), (97, 1, 1.0)])
+def test_complex_parlett_sylvester(dev, n, p, first, mode):
+    rng = np.random.default_rng(6970 + n + p)
+    T = grouped(n, p, first, rng, cplx=True)
+    U, info, _ = check(T, dev, mode=mode, algo="ps")
+    assert info["path_name"] == "ps" and info["fallback_tiles"] == 0
+    assert np.array_equal(U[:p, :p], first * np.eye(p))
+    assert np.array_equal(U[p:, p:], -first * np.eye(n - p))
+
+
+def test_complex_forced_stall_cone(dev):
+    rng = np.random.default_rng(6990)
+    n = 200
+    nb = (n + 31) // 32
+    I, J = 1, 3
+    _, info, _ = check(wl.make_T(n, rng, complex_=True), dev, mode="mixed",
+                       options={"force_stall": 1 + I * nb + J})
+    assert info["fallback_tiles"] == (I + 1) * (nb - J)
+
+
+def test_complex_sweeps_agree(dev):
+    import torch
+
     from paper_1607_06303_amd import signtri
 
-    rng = np.random.default_rng(6900)
-    Tg = to_dev_colmajor(wl.make_T(50, rng, complex_=True), dev)
-    with pytest.raises(signtri.SignTriError) as ei:
-        signtri.sign_tri(Tg, mode="mixed")
-    assert ei.value.code == 5
+    rng = np.random.default_rng(6995)
+    Tg = to_dev_colmajor(wl.make_T(230, rng, complex_=True), dev)
+    Ua, ia = signtri.sign_tri(Tg, options={"sweep": "dataflow"})
+    Ub, ib = signtri.sign_tri(Tg, options={"sweep": "superdiag"})
+    torch.cuda.synchronize()
+    assert ia["sweep_name"] == "dataflow" and ib["sweep_name"] == "superdiag"
+    assert rel_fro(Ua.cpu().numpy(), Ub.cpu().numpy()) <= 1e-13
 
 
 def test_near_singular_divisors_mixed(dev):
