@@ -52,8 +52,9 @@ def parse():
 def kernel_name(family, mode, tile):
     """The kernel behind one of the library's timer families, as rocprofv3 names it."""
     fp = "double" if mode == "fp64" else "float"
-    return {"flow": "k_flow<%s, 0>" % fp, "corr": "k_flow<float, 1>", "syl": "k_flow<%s, 2>" % fp,
-            "resid": "k_resid", "gemm": "k_wave_gemm<double, %d>" % tile,
+    return {"flow": "k_flow<%s, 0, false>" % fp, "corr": "k_flow<float, 1, false>",
+            "syl": "k_flow<%s, 2, false>" % fp,
+            "resid": "k_resid<1>", "gemm": "k_wave_gemm<double, %d>" % tile,
             "solve": "k_solve_r<double, %d, 256>" % tile}.get(family)
 
 
