@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--check-block", type=int, default=1536)
     ap.add_argument("--tile", type=int, default=0, help="block size 32 or 64 (0: library default)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the side measurement of the 2000-matrix batched workload")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default: tune each mode before its warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -82,6 +84,37 @@ def measured_traffic(kernel):
             if h.hexdigest()[:len(m.group(4))] == m.group(4):
                 return float(m.group(2))
     return None
+
+
+def bench_batched(signtri, torch, workloads, oracle_mod, steps):
+    """Side measurement (not the headline): the 2000-matrix batch of orders
+    32..1024 in one batched call per mode, with every 100th matrix checked
+    against the oracle."""
+    import numpy as np
+
+    Ts = workloads.workload4()
+    Tg = [torch.from_numpy(np.asfortranarray(T).T.copy()).cuda().t() for T in Ts]
+    Us = [signtri.empty_like_layout(t) for t in Tg]
+    n3 = sum(T.shape[0] ** 3 / 3.0 for T in Ts)
+    out = {"workload": "2000 real matrices, orders log-uniform in [32, 1024], per-matrix "
+                       "positive fraction U[0, 1]", "sum_n3_over_3": n3}
+    for mode in ("fp64", "mixed"):
+        signtri.sign_tri_batched(Tg, mode=mode, outs=Us)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            signtri.sign_tri_batched(Tg, mode=mode, outs=Us)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = 0.0
+        if oracle_mod is not None:
+            for k in range(0, len(Ts), 100):
+                ref = oracle_mod.sign_tri(Ts[k])
+                err = max(err, float(np.linalg.norm(Us[k].cpu().numpy() - ref) / np.linalg.norm(ref)))
+        out[mode] = {"ms": ms, "gflops": n3 / ms / 1e6, "err_sampled": err}
+        log("batched %s: %.3f ms, %.1f GFLOP/s (sum n^3/3), sampled rel err %.2e"
+            % (mode, ms, n3 / ms / 1e6, err))
+    return out
 
 
 def calibrate_copy(torch, mib):
@@ -219,6 +252,13 @@ def main():
                 "kernel": kname, "kernel_family": fam, "launches": launches,
                 "avg_launch_ms": ms_k / max(launches, 1)}
 
+    batched = None
+    if not args.no_batched:
+        import oracle as oracle_mod
+
+        batched = bench_batched(signtri, torch, workloads, None if args.no_check else oracle_mod,
+                                max(1, min(args.steps, 5)))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -262,6 +302,7 @@ def main():
                   for m, r in results.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 
