@@ -168,7 +168,8 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout lay
  * order, in one graph-captured persistent launch.
  *   T, U        HOST arrays of `batch` DEVICE pointers
  *   ldt, ldu, n HOST arrays of `batch` leading dimensions and orders
- *   dtype       SIGNTRI_R64 only in this build (else SIGNTRI_ENOTSUP)
+ *   dtype       SIGNTRI_R64 or SIGNTRI_C128
+ *   layout      SIGNTRI_COL_MAJOR only in this build (else SIGNTRI_ENOTSUP)
  *   mode        as for signtri(); MIXED_REFINED refines each matrix
  *   workspace   device scratch of ws_bytes, or NULL for a library buffer
  *   infos       optional HOST array of `batch` results

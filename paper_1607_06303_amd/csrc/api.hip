@@ -285,7 +285,7 @@ struct BatchLayout {
     std::vector<size_t> sgn, dg;
 };
 
-BatchLayout batch_layout(const int64_t *n, int64_t batch, signtri_mode mode)
+BatchLayout batch_layout(const int64_t *n, int64_t batch, signtri_mode mode, bool cplx)
 {
     BatchLayout B;
     const int nm = (int)batch;
@@ -304,14 +304,14 @@ BatchLayout batch_layout(const int64_t *n, int64_t batch, signtri_mode mode)
     o = align_up(o);
     for (int m = 0; m < nm; ++m) {
         B.dg[m] = o;
-        o += (size_t)n[m] * sizeof(double);
+        o += (size_t)n[m] * sizeof(double) * (cplx ? 2 : 1);
     }
     o = align_up(o);
     std::vector<int64_t> ns;
     for (int m = 0; m < nm; ++m)
         if (n[m] > 0) ns.push_back(n[m]);
     size_t rd = 0, rh = 0;
-    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false, &rd, &rh);
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx, &rd, &rh);
     B.run = o;
     B.dev = o + rd;
     B.run_host = align_up(B.sgn_end);
@@ -343,9 +343,10 @@ void drop_batch_graph(BatchGraph &g)
 int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
                        const signtri_options *opts, char *run_dev, hipStream_t st, int device)
 {
+    const bool cplx = !items.empty() && items[0].cplx;
     std::vector<int64_t> key{(int64_t)mode, (int64_t)device, (int64_t)(intptr_t)run_dev,
                              (int64_t)ws_generation().load(), (int64_t)items.size(),
-                             (int64_t)(opts ? opts->wgs_per_cu : 0)};
+                             (int64_t)(opts ? opts->wgs_per_cu : 0), (int64_t)cplx};
     std::vector<int64_t> ns;
     for (const RealItem &it : items) {
         key.insert(key.end(), {(int64_t)(intptr_t)it.T, it.ldt, (int64_t)(intptr_t)it.U, it.ldu,
@@ -361,7 +362,7 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
             return hipGraphLaunch(hit.exec, st) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
         }
     size_t host_bytes = 0;
-    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false, nullptr, &host_bytes);
+    run_sizes(ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx, nullptr, &host_bytes);
     BatchGraph g;
     g.key = key;
     if (hipHostMalloc(&g.host, std::max<size_t>(host_bytes, 256), hipHostMallocDefault) !=
@@ -629,7 +630,7 @@ size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch, signtri_d
     if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
     for (int64_t b = 0; b < batch; ++b)
         if (n[b] < 0) return 0;
-    return batch_layout(n, batch, mode).dev;
+    return batch_layout(n, batch, mode, dtype == SIGNTRI_C128).dev;
 }
 
 int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, const int64_t *ldu,
@@ -653,12 +654,14 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
         if (n[b] > 0 && (!T[b] || !U[b])) return T[b] ? -3 : -1;
         if (ldt[b] < std::max<int64_t>(1, n[b])) return -2;
         if (ldu[b] < std::max<int64_t>(1, n[b])) return -4;
-        if (n[b] > 0 && ranges_overlap(T[b], extent_bytes(n[b], ldt[b], 8), U[b],
-                                       extent_bytes(n[b], ldu[b], 8)))
+        const size_t es = dtype == SIGNTRI_C128 ? 16 : 8;
+        if (n[b] > 0 && ranges_overlap(T[b], extent_bytes(n[b], ldt[b], es), U[b],
+                                       extent_bytes(n[b], ldu[b], es)))
             return -3;
     }
     if (batch == 0) return SIGNTRI_OK;
-    if (dtype != SIGNTRI_R64 || layout != SIGNTRI_COL_MAJOR) return SIGNTRI_ENOTSUP;
+    if (layout != SIGNTRI_COL_MAJOR) return SIGNTRI_ENOTSUP;
+    const bool cplx = dtype == SIGNTRI_C128;
     if (int rc = check_options(opts, dtype, mode)) return rc;
     if (opts && (opts->sweep == SIGNTRI_SWEEP_SUPERDIAG || opts->tile == 64)) return SIGNTRI_ENOTSUP;
     // the batched form runs on the dataflow sweeps; only the grid is a choice
@@ -668,11 +671,11 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
     eo.tile = kFlowTile;
     {
-        const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, false);
+        const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, cplx);
         if (eo.wgs_per_cu <= 0 || eo.wgs_per_cu > mx) eo.wgs_per_cu = mx;
     }
 
-    const BatchLayout BL = batch_layout(n, batch, mode);
+    const BatchLayout BL = batch_layout(n, batch, mode, cplx);
     if (workspace) {
         if (ws_bytes < BL.dev) return SIGNTRI_EWORKSPACE;
     } else if (int rc = owned_workspace(BL.dev, &workspace)) {
@@ -688,7 +691,7 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     ScanMat *hsm = (ScanMat *)(hb + BL.scan_tab);
     for (int m = 0; m < nm; ++m)
         hsm[m] = ScanMat{(const double *)T[m], ldt[m], n[m], (int8_t *)(ws + BL.sgn[m]),
-                         (double *)(ws + BL.dg[m]), (ScanResult *)(ws + BL.res) + m};
+                         (double *)(ws + BL.dg[m]), (ScanResult *)(ws + BL.res) + m, cplx ? 1 : 0};
     if (hipMemcpyAsync(ws + BL.scan_tab, hsm, nm * sizeof(ScanMat), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return SIGNTRI_EHIP;
@@ -712,7 +715,7 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     for (int m = 0; m < nm; ++m) {
         if (n[m] == 0) continue;
         const int8_t *hs = (const int8_t *)(hb + BL.sgn[m]);
-        const HostPlan p = plan_from_signs(hs, n[m], false);
+        const HostPlan p = plan_from_signs(hs, n[m], cplx);
         signtri_info *inf = infos ? &infos[m] : nullptr;
         fill_info(inf, p);
         RealItem it;
@@ -726,7 +729,7 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
         it.s = it.path == SIGNTRI_PATH_TRIVIAL ? (p.n_pos > 0 ? 1 : -1) : p.ps_sign;
         it.sgn = (const int8_t *)(ws + BL.sgn[m]);
         it.dg = (const double *)(ws + BL.dg[m]);
-        it.cplx = false;
+        it.cplx = cplx;
         it.info = inf;
         if (inf) {
             const bool triv = it.path == SIGNTRI_PATH_TRIVIAL;
@@ -751,7 +754,7 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     }
     if (rc != SIGNTRI_OK) return rc;
     if (infos && mode != SIGNTRI_MIXED_REFINED)
-        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, false,
+        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx,
                            run_host, st, nullptr);
     return SIGNTRI_OK;
 }

@@ -11,7 +11,7 @@ constexpr int TB = kFlowTile;
 
 // One workgroup per matrix: sign(Re t_ii) as +1/-1 (Section 1), the first
 // index whose sign is undefined (zero or non-finite), the number of positive
-// signs, and the real diagonal itself (the divisors t_ii - t_jj).
+// signs, and the diagonal itself (the divisors t_ii - t_jj).
 __global__ __launch_bounds__(1024) void k_scan_b(const ScanMat *__restrict__ mats)
 {
     const ScanMat d = mats[blockIdx.x];
@@ -24,11 +24,19 @@ __global__ __launch_bounds__(1024) void k_scan_b(const ScanMat *__restrict__ mat
     __syncthreads();
     unsigned long long my_pos = 0;
     for (int64_t i = threadIdx.x; i < d.n; i += blockDim.x) {
-        const double re = d.T[i + i * d.ldt];
+        double re, im = 0.0;
+        if (d.cplx) {
+            re = d.T[2 * (i + i * d.ldt)];
+            im = d.T[2 * (i + i * d.ldt) + 1];
+            d.dg[2 * i] = re;
+            d.dg[2 * i + 1] = im;
+        } else {
+            re = d.T[i + i * d.ldt];
+            d.dg[i] = re;
+        }
         int s = 0;
-        if (isfinite(re)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
+        if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
         d.sgn[i] = (int8_t)s;
-        d.dg[i] = re;
         if (s == 0) atomicMin(&bad, (unsigned long long)i);
         my_pos += (s > 0);
     }

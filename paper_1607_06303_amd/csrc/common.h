@@ -389,6 +389,9 @@ hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t s
 hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
 hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks, int ntasks,
                         double *norm2, hipStream_t st);
+// Real substitution form on 64 x 64 tiles (matrix, a << 16 | b), a <= b.
+hipError_t launch_resid64(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
+                          hipStream_t st);
 
 // batch.hip: table-driven scan, output preparation and diagonal blocks.
 struct ScanMat {
@@ -396,8 +399,9 @@ struct ScanMat {
     int64_t ldt;
     int64_t n;
     int8_t *sgn;
-    double *dg;
+    double *dg;          // the diagonal (complex: re, im pairs)
     ScanResult *res;
+    int cplx;            // complex entries (interleaved re, im)
 };
 struct PrepMat {
     const double *T;

@@ -275,6 +275,160 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     if (tid == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = red[0] + red[1] + red[2] + red[3];
 }
 
+// FP64 residual of the real substitution form on 64 x 64 tiles: tile (a, b)
+// covers blocks 2a, 2a+1 x 2b, 2b+1 and each wave owns one of them (2 x 2 MFMA
+// pieces); a tile reads half the operand bytes per flop of four 32 x 32
+// blocks.  K runs over the blocks 2a .. 2b+1 with every operand masked to its
+// upper triangle (row <= column), which zeroes the terms outside a block's own
+// range I .. J and T's strict lower triangle.  Blocks outside the strict upper
+// block triangle are skipped.  Output as k_resid: R in FP32 into E32, squared
+// Frobenius norm per block.  Tiles in reverse task order (longest first).
+constexpr int RAP = 2 * TB + 16;    // LDS: A as [k][m], 64 rows + pad
+constexpr int RBS = 8 * TB + 4;     // LDS: B as [k/4][n][k%4], 64 columns
+
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_resid64(RefArgs a, const int2 *__restrict__ tiles, int ntiles, double *__restrict__ norm2)
+{
+    __shared__ double sAU[TB * RAP], sAT[TB * RAP];
+    __shared__ double sBU[(TB / 4) * RBS], sBT[(TB / 4) * RBS];
+    __shared__ int8_t rs[2 * TB], cs[2 * TB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int pr = wave >> 1, pc = wave & 1;
+    const int mg = lane >> 4, mt = lane & 15;
+    const int2 tk = tiles[ntiles - 1 - (int)blockIdx.x];
+    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int ta = uniform(tk.y >> 16), tb = uniform(tk.y & 0xffff);
+    const int64_t n = uniform(d.n);
+    const int nb = uniform(d.nbc);
+    const double *T = d.T, *U = d.U;
+    const int64_t ldt = d.ldt, ldu = d.ldu;
+    const int64_t r0 = (int64_t)ta * 2 * TB, c0 = (int64_t)tb * 2 * TB;
+    const int I = 2 * ta + pr, J = 2 * tb + pc;
+    const bool mine = I < J && J < nb;  // this wave's block is an off-diagonal block
+    if (tid < 2 * TB) {
+        rs[tid] = r0 + tid < n ? d.sgn[r0 + tid] : 0;
+        cs[tid] = c0 + tid < n ? d.sgn[c0 + tid] : 0;
+    }
+    __syncthreads();
+    bool nY[2][2], nX[2][2];
+    bool wx = false;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            bool rp = false, rn = false, cp = false, cn = false;
+            for (int u = 0; u < 16; ++u) {
+                const int vr = rs[32 * pr + 16 * ra + u], vc = cs[32 * pc + 16 * cb + u];
+                rp |= vr > 0;
+                rn |= vr < 0;
+                cp |= vc > 0;
+                cn |= vc < 0;
+            }
+            nY[ra][cb] = mine && ((rp && cp) || (rn && cn));
+            nX[ra][cb] = mine && ((rp && cn) || (rn && cp));
+            wx |= nX[ra][cb];
+        }
+    const bool any_x = __syncthreads_or(wx);
+
+    dx4 accY[2][2], accX[2][2];
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+            for (int r = 0; r < 4; ++r) accY[ra][cb][r] = accX[ra][cb][r] = 0.0;
+
+    // staging of one 32-deep K step: A 64 x 32 (U, T), B 32 x 64 (U, T);
+    // every thread 4 consecutive rows of 2 columns of each
+    double gaU[2][4], gaT[2][4], gbU[2][4], gbT[2][4];
+    const int alc = tid >> 4, alr = (tid & 15) * 4;  // A: columns alc, alc + 16; rows alr ..
+    const int blc = tid >> 3, blr = (tid & 7) * 4;   // B: columns blc, blc + 32; rows blr ..
+    auto load = [&](int K) {
+        const int64_t k0 = (int64_t)K * TB;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t ra = r0 + alr + e, ca = k0 + alc + 16 * h;
+                const int64_t rb = k0 + blr + e, cb = c0 + blc + 32 * h;
+                const bool okA = ra < n && ca < n && ra <= ca;
+                const bool okB = rb < n && cb < n && rb <= cb;
+                gaU[h][e] = okA ? U[ra + ca * ldu] : 0.0;
+                gaT[h][e] = (okA && any_x) ? T[ra + ca * ldt] : 0.0;
+                gbU[h][e] = okB ? U[rb + cb * ldu] : 0.0;
+                gbT[h][e] = (okB && any_x) ? T[rb + cb * ldt] : 0.0;
+            }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ka = alc + 16 * h;
+                sAU[ka * RAP + alr + e] = gaU[h][e];
+                sAT[ka * RAP + alr + e] = -gaT[h][e];
+                const int nbb = blc + 32 * h;
+                sBU[(blr >> 2) * RBS + nbb * 4 + e] = gbU[h][e];
+                sBT[(blr >> 2) * RBS + nbb * 4 + e] = gbT[h][e];
+            }
+    };
+    const int K0 = 2 * ta, K1 = uniform(min(2 * tb + 1, nb - 1));
+    load(K0);
+    store();
+    __syncthreads();
+    for (int K = K0; K <= K1; ++K) {
+        const bool more = K < K1;
+        if (more) load(K + 1);
+#pragma unroll
+        for (int k4 = 0; k4 < TB / 4; ++k4) {
+            double aU[2], aT[2], bU[2], bT[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ao = (k4 * 4 + mg) * RAP + 32 * pr + 16 * h + mt;
+                const int bo = k4 * RBS + (32 * pc + 16 * h + mt) * 4 + mg;
+                aU[h] = sAU[ao];
+                aT[h] = sAT[ao];
+                bU[h] = sBU[bo];
+                bT[h] = sBT[bo];
+            }
+#pragma unroll
+            for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    if (nY[ra][cb]) accY[ra][cb] = mfma_f64(aU[ra], bU[cb], accY[ra][cb]);
+                    if (nX[ra][cb]) {
+                        accX[ra][cb] = mfma_f64(aU[ra], bT[cb], accX[ra][cb]);
+                        accX[ra][cb] = mfma_f64(aT[ra], bU[cb], accX[ra][cb]);
+                    }
+                }
+        }
+        __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
+    }
+    if (mine) {
+        double ss = 0.0;
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 32 * pr + 16 * ra + mfma64_row(lane, r);
+                    const int j = 32 * pc + 16 * cb + mt;
+                    if (c0 + j < n) {
+                        const double v = rs[i] == cs[j] ? accY[ra][cb][r] : accX[ra][cb][r];
+                        d.E32[(r0 + i) + (c0 + j) * d.ld32] = (float)v;
+                        ss += v * v;
+                    }
+                }
+        for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
+        if (lane == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = ss;
+    }
+}
+
 // FP64 residual of the Sylvester equation T11 X - X T22 = 2 s T12 for one
 // block of X per workgroup: R = 2 s T12 - T11 X + X T22, with X = U(0:p, p:n).
 // K steps: blocks K >= I of T11's rows (K = I keeps its upper triangle), then
@@ -426,6 +580,14 @@ hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipS
         hipLaunchKernelGGL(k_add_correction<2>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
     else
         hipLaunchKernelGGL(k_add_correction<1>, col_grid(nmax, a.nmat), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid64(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
+                          hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid64, dim3(ntiles), dim3(NT), 0, st, a, tiles, ntiles, norm2);
     return hipGetLastError();
 }
 

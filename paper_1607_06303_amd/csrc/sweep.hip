@@ -108,7 +108,7 @@ FlowMat<F> syl_mat(const F *T, int64_t ldt, F *V, int64_t ldv, const F *Rh, int6
 // them); the rest of each buffer is its own.  Sizes are upper bounds valid for
 // any diagonal: a matrix has at most nb^2 blocks in either form.
 struct Lay {
-    size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, shared;   // shared part
+    size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, rtiles, shared;   // shared part
     size_t ctrl, flags, ftasks, norms0, norms1, maxes, f32, dev;
     size_t h_norm0, h_norm1, h_maxes, h_err, h_ftasks, host;
     int64_t nflags_max, ntasks_max, ndiag_max;
@@ -119,11 +119,12 @@ struct Lay {
 Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
 {
     Lay L;
-    int64_t sq = 0, nbsum = 0, f32 = 0;
+    int64_t sq = 0, sq2 = 0, nbsum = 0, f32 = 0;
     L.off32.resize(nm);
     for (int m = 0; m < nm; ++m) {
-        const int64_t nb = nblocks(ns[m]);
+        const int64_t nb = nblocks(ns[m]), nb2 = (nb + 1) / 2;
         sq += nb * nb;
+        sq2 += nb2 * nb2;
         nbsum += nb;
         L.off32[m] = f32;
         if (mixed) f32 += (cplx ? 6 : 3) * ns[m] * ns[m];
@@ -138,6 +139,7 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     L.pm = o; o += al(nm * sizeof(PrepMat));
     L.dtasks = o; o += al(L.ndiag_max * sizeof(int2));
     L.tasks = o; o += al(L.ntasks_max * sizeof(int2));
+    L.rtiles = o; o += al((mixed ? std::max<int64_t>(sq2, 1) : 0) * sizeof(int2));
     L.shared = o;
     size_t d = o;
     L.ctrl = d; d += al(64 * sizeof(int));
@@ -329,6 +331,22 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
                     const int J = d - (nbr[m] - 1 - I);
                     if (J >= 0 && J < nbc[m]) htk[nph + nps++] = make_int2(m, (I << 16) | J);
                 }
+    // 64 x 64 tiles of the real substitution form's residual, shortest first
+    // (the kernel takes them in reverse)
+    int64_t nrt = 0;
+    if (mixed && !cplx) {
+        int2 *hrt = (int2 *)(H + L.rtiles);
+        const int nb2max = (int)((nblocks(nmax) + 1) / 2);
+        for (int dd = 0; dd < nb2max; ++dd)
+            for (auto it = order.rbegin(); it != order.rend(); ++it) {
+                const int m = *it;
+                if (items[m].path != SIGNTRI_PATH_PH) continue;
+                const int nb2 = (nbc[m] + 1) / 2;
+                for (int ta = 0; ta + dd < nb2; ++ta)
+                    if (dd > 0 || 2 * ta + 1 < nbc[m]) hrt[nrt++] = make_int2(m, (ta << 16) | (ta + dd));
+            }
+    }
+    const int2 *drt = (const int2 *)(D + L.rtiles);
     const int2 *dtk = (const int2 *)(D + L.tasks);
     const int2 *dtk_ps = dtk + nph;
     const int2 *ddt = (const int2 *)(D + L.dtasks);
@@ -380,7 +398,8 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     double *norms[2] = {(double *)(D + L.norms0), (double *)(D + L.norms1)};
     auto resid = [&](double *norm2) -> hipError_t {
         return timed(st, PK_RESID, fl.resid, [&] {
-            hipError_t r = launch_resid(ra, false, cplx, dtk, (int)nph, norm2, st);
+            hipError_t r = cplx ? launch_resid(ra, false, cplx, dtk, (int)nph, norm2, st)
+                                : launch_resid64(ra, drt, (int)nrt, norm2, st);
             if (r == hipSuccess) r = launch_resid(ra, true, cplx, dtk_ps, (int)nps, norm2, st);
             return r;
         });

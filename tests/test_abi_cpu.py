@@ -177,8 +177,7 @@ def test_batched_argument_validation_without_device_work():
     assert call(T, ld, U, ld, n, 2, lay=9) == -8
     assert call(T, ld, U, ld, n, 2, mode=9) == -9
     assert call(T, ld, U, ld, n, 0) == 0
-    # complex and row-major batches are not implemented (after validation)
-    assert call(T, ld, U, ld, n, 2, dt=1) == 5
+    # row-major batches are not implemented (after validation)
     assert call(T, ld, U, ld, n, 2, lay=1) == 5
 
 
@@ -189,3 +188,6 @@ def test_batched_workspace_size():
     b = L.signtri_batched_workspace_size(I(32, 100, 1000), 3, 0, 1)
     assert 0 < a < b
     assert L.signtri_batched_workspace_size(I(32, -1, 5), 3, 0, 0) == 0
+    # complex: twice the diagonal and FP32 copies
+    c = L.signtri_batched_workspace_size(I(32, 100, 1000), 3, 1, 1)
+    assert c > b

@@ -138,3 +138,27 @@ def test_batched_workload4_sample(dev):
     Ts = wl.workload4(count=60)
     Us, infos, _, _ = run_batch(Ts, dev, mode="mixed")
     check_all(Ts, Us, TOL_FP64)
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64", TOL_FP64), ("mixed", TOL_FP64), ("fp32", TOL_FP32)])
+def test_batched_complex(dev, mode, tol):
+    """Complex matrices in one batched call: interleaved, grouped by sign
+    (Parlett-Sylvester), one sign, near the imaginary axis, and empty."""
+    rng = np.random.default_rng(8700)
+    Ts = []
+    for k, n in enumerate([1, 40, 97, 130, 0, 64, 200]):
+        if n == 0:
+            Ts.append(np.zeros((0, 0), dtype=complex))
+        elif k % 3 == 1:
+            p = n // 3
+            s = np.concatenate([np.ones(p), -np.ones(n - p)])
+            Ts.append(wl.make_T(n, rng, complex_=True, signs=s))
+        elif k == 5:
+            Ts.append(wl.make_T(n, rng, complex_=True, signs=np.ones(n)))
+        else:
+            Ts.append(wl.make_T(n, rng, complex_=True, re_range=(1e-2, 1.0)))
+    Us, infos, _, _ = run_batch(Ts, dev, mode=mode)
+    check_all(Ts, Us, tol)
+    assert {i["path_name"] for i in infos} == {"trivial", "ph", "ps"}
+    if mode == "mixed":
+        assert all(i["fallback_tiles"] == 0 for i in infos)
