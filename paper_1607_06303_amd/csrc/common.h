@@ -72,16 +72,18 @@ __device__ inline int mfma32_row(int lane, int r) { return 4 * (lane >> 4) + r; 
 
 // Sum over aligned groups of 8 consecutive lanes with DPP moves (no LDS):
 // quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror.
+// Every lane reads a valid source lane in these patterns (all rows and banks
+// enabled), so the move needs no prior value in its destination.
 template <int CTRL> __device__ inline float dppf(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 template <int CTRL> __device__ inline double dppd(double v)
 {
     long long b = __double_as_longlong(v);
     int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ inline double group8_sum(double v)

@@ -668,6 +668,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             const bool same = !syl && ((((cpos >> jj) & 1ull) != 0) == (si > 0));
             const F *rsrc = same ? RU : RT;
             F tot[P], rhs[P];
+            double rsc = 0.0;  // real entries: the entry's scale, read before the reduction
             if constexpr (C) {
                 const f4 xcr = *(const f4 *)&X[kq + jj * LDX];
                 const f4 xci = *(const f4 *)&X[TB * LDX + kq + jj * LDX];
@@ -690,14 +691,19 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 tot[0] = same ? cur + rwr : rwr - ctr;
                 tot[1] = same ? cui + rwi : rwi - cti;
             } else {
+                // one column coefficient set per entry, selected without a branch:
+                // U's row where the signs agree, -T's row where they differ
                 const f4 xc = *(const f4 *)&X[kq + jj * LDX];
                 const f4 xr = *(const f4 *)&XT[kq + li * LDX];
                 const f4 rr = *(const f4 *)&rsrc[kq + jj * TB];
                 rhs[0] = X[li + jj * LDX];
-                const F colu = (cu[0][0] * xc[0] + cu[0][1] * xc[1]) + (cu[0][2] * xc[2] + cu[0][3] * xc[3]);
-                const F colt = (ct[0][0] * xc[0] + ct[0][1] * xc[1]) + (ct[0][2] * xc[2] + ct[0][3] * xc[3]);
+                F cc[CPL];
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) cc[u] = same ? cu[0][u] : -ct[0][u];
+                const F col = (cc[0] * xc[0] + cc[1] * xc[1]) + (cc[2] * xc[2] + cc[3] * xc[3]);
                 const F row = (xr[0] * rr[0] + xr[1] * rr[1]) + (xr[2] * rr[2] + xr[3] * rr[3]);
-                tot[0] = same ? colu + row : row - colt;
+                tot[0] = col + row;
+                rsc = same ? -0.5 * (double)si : rcp[0][li * TB + jj];
             }
 #pragma unroll
             for (int q = 0; q < P; ++q) tot[q] = group_sum<LPR>(tot[q]);
@@ -720,8 +726,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                     XT[jj + li * LDX] = (F)xr;
                     XT[TB * LDX + jj + li * LDX] = (F)xi;
                 } else {
-                    const double scale = same ? -0.5 * (double)si : rcp[0][li * TB + jj];
-                    const F x = (F)(((double)rhs[0] + (double)tot[0]) * scale);
+                    const F x = (F)(((double)rhs[0] + (double)tot[0]) * rsc);
                     X[li + jj * LDX] = x;
                     XT[jj + li * LDX] = x;
                 }
