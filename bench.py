@@ -56,7 +56,7 @@ def kernel_name(family, mode, tile):
     fp = "double" if mode == "fp64" else "float"
     return {"flow": "k_flow<%s, 0, false>" % fp, "corr": "k_flow<float, 1, false>",
             "syl": "k_flow<%s, 2, false>" % fp,
-            "resid": "k_resid<1>", "gemm": "k_wave_gemm<double, %d>" % tile,
+            "resid": "k_resid64", "gemm": "k_wave_gemm<double, %d>" % tile,
             "solve": "k_solve_r<double, %d, 256>" % tile}.get(family)
 
 

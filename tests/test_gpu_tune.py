@@ -124,3 +124,23 @@ def test_batched_grid_option(dev, clean_table):
         for T, U, inf in zip(Ts, Us, infos):
             assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
             assert inf["wgs_per_cu"] == wgs and inf["sweep_name"] == "dataflow"
+
+
+def test_tuning_table_file_round_trip(dev, clean_table, tmp_path):
+    """A measured choice survives save / clear / load and steers a later call."""
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(9600)
+    T = wl.make_T(300, rng)
+    Tg = to_dev_colmajor(T, dev)
+    best = signtri.autotune(Tg, reps=1)
+    path = str(tmp_path / "tune.txt")
+    signtri.tune_save(path)
+    signtri.tune_clear()
+    assert signtri.tune_lookup(False, "fp64", "ph", 300) is None
+    signtri.tune_load(path)
+    got = signtri.tune_lookup(False, "fp64", "ph", 300)
+    assert (got["sweep"], got["tile"], got["wgs_per_cu"]) == (best["sweep"], best["tile"],
+                                                             best["wgs_per_cu"])
+    _, info, _ = check(T, dev)
+    assert (info["sweep"], info["tile"]) == (best["sweep"], best["tile"])
