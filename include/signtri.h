@@ -62,14 +62,25 @@ typedef enum { SIGNTRI_R64 = 0, SIGNTRI_C128 = 1 } signtri_dtype;
  * FP32: the mixed path without refinement (about 1e-6 relative accuracy). */
 typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } signtri_mode;
 
-/* AUTO picks by the Section 3 work estimates (PS only when the diagonal is
- * already grouped by sign, since this library does not reorder the Schur form). */
-typedef enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2 } signtri_algo;
+/* PH: the Parlett-Higham substitution (Algorithm 3 in block form).
+ * PS: the Parlett-Sylvester form (Algorithm 2 with diagonal blocks +-I) on a
+ *   diagonal already grouped by sign.
+ * PROJ: the Parlett-Sylvester result for a diagonal whose signs are not grouped
+ *   (Section 3 reaches it by Schur reordering, the sign-split Sylvester equation
+ *   and a transformation back).  Computed here without reordering: the right
+ *   and left invariant subspaces of the minority sign class, each from a
+ *   triangular substitution, give the spectral projector P of that class, and
+ *   U = s (I - 2 P) with s the majority sign.  Real T in FP64 (every mode runs
+ *   it in FP64), at most 64 entries in the minority class.
+ * AUTO picks by work estimates: PS when the diagonal is grouped and the
+ *   Section 3 model favours it, PROJ when the minority class is small (real T,
+ *   1..64 entries) and its estimate 3 n^2 m is below the PH estimate, else PH. */
+typedef enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2, SIGNTRI_PROJ = 3 } signtri_algo;
 
 typedef enum { SIGNTRI_COL_MAJOR = 0, SIGNTRI_ROW_MAJOR = 1 } signtri_layout;
 
 /* Path actually run. */
-enum { SIGNTRI_PATH_TRIVIAL = 0, SIGNTRI_PATH_PH = 1, SIGNTRI_PATH_PS = 2 };
+enum { SIGNTRI_PATH_TRIVIAL = 0, SIGNTRI_PATH_PH = 1, SIGNTRI_PATH_PS = 2, SIGNTRI_PATH_PROJ = 3 };
 
 enum {
     SIGNTRI_OK = 0,
@@ -141,8 +152,9 @@ typedef struct {
  *   dtype       SIGNTRI_R64 or SIGNTRI_C128
  *   layout      storage order of both T and U
  *   mode        SIGNTRI_FP64, SIGNTRI_MIXED_REFINED or SIGNTRI_FP32
- *   algo        SIGNTRI_AUTO, SIGNTRI_PH or SIGNTRI_PS (PS requires a real T
- *               whose diagonal is already grouped by sign, else SIGNTRI_ENOTSUP)
+ *   algo        SIGNTRI_AUTO, SIGNTRI_PH, SIGNTRI_PS or SIGNTRI_PROJ (PS requires a
+ *               real T whose diagonal is already grouped by sign; PROJ a real T with
+ *               1..64 entries in its minority sign class; else SIGNTRI_ENOTSUP)
  *   Complex T supports mode SIGNTRI_FP64 only in this build (else SIGNTRI_ENOTSUP).
  *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
  *               use a buffer it allocates and keeps for later calls

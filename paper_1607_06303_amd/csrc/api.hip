@@ -15,7 +15,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t scan = 0, sgn = 0, dg = 0, flow = 0, tcopy = 0, ucopy = 0;
+    size_t scan = 0, sgn = 0, dg = 0, flow = 0, tcopy = 0, ucopy = 0, prefix = 0;
     size_t zbuf = 0, zbufs[2] = {0, 0}, ebuf = 0, total = 0;
     int64_t zslots = 0;
     bool flow_path = false;  // the dataflow sweeps (32 x 32 blocks)
@@ -45,6 +45,7 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri
         L.ucopy = off;
         off += align_up(mat);
     }
+    L.prefix = off;
     L.flow_path = flow;
     if (flow) {
         size_t fb = 0;
@@ -73,12 +74,14 @@ Layout layout_for(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri
 size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_mode mode,
                  signtri_algo algo)
 {
-    (void)algo;
     size_t m = layout_for(n, dtype, layout, mode, 32, true).total;
     if (mode == SIGNTRI_FP64) {
         m = std::max(m, layout_for(n, dtype, layout, mode, 32, false).total);
         if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, layout, mode, 64, false).total);
     }
+    if (dtype == SIGNTRI_R64 && (algo == SIGNTRI_AUTO || algo == SIGNTRI_PROJ))
+        m = std::max(m, layout_for(n, dtype, layout, mode, 32, true).prefix +
+                            align_up(proj_workspace_bytes(n)));
     return m;
 }
 
@@ -440,7 +443,7 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout lay
     if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return 0;
     if (layout != SIGNTRI_COL_MAJOR && layout != SIGNTRI_ROW_MAJOR) return 0;
     if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return 0;
-    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return 0;
+    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PROJ) return 0;
     return max_total(n, dtype, layout, mode, algo);
 }
 
@@ -453,7 +456,7 @@ int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype, signtri_i
     std::memset(info, 0, sizeof(*info));
     HostPlan p = plan_from_signs(s, n, dtype == SIGNTRI_C128);
     fill_info(info, p);
-    info->path = n == 0 ? SIGNTRI_PATH_TRIVIAL : p.auto_path;
+    info->path = n == 0 ? SIGNTRI_PATH_TRIVIAL : (p.proj_pick ? SIGNTRI_PATH_PROJ : p.auto_path);
     return 0;
 }
 
@@ -471,7 +474,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -6;
     if (layout != SIGNTRI_COL_MAJOR && layout != SIGNTRI_ROW_MAJOR) return -7;
     if (mode < SIGNTRI_FP64 || mode > SIGNTRI_FP32) return -8;
-    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PS) return -9;
+    if (algo < SIGNTRI_AUTO || algo > SIGNTRI_PROJ) return -9;
     if (workspace && ws_bytes == 0) return -11;
     const bool cplx = dtype == SIGNTRI_C128;
     const size_t es = cplx ? 16 : 8;
@@ -530,10 +533,30 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     fill_info(info, p);
 
     int path = p.auto_path;
+    if (algo == SIGNTRI_AUTO && p.proj_pick) path = SIGNTRI_PATH_PROJ;
     if (algo == SIGNTRI_PH && path != SIGNTRI_PATH_TRIVIAL) path = SIGNTRI_PATH_PH;
     if (algo == SIGNTRI_PS && path != SIGNTRI_PATH_TRIVIAL) {
         if (p.ps_sign == 0) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PS;
+    }
+    if (algo == SIGNTRI_PROJ && path != SIGNTRI_PATH_TRIVIAL) {
+        if (cplx || p.n_min < 1 || p.n_min > kProjMaxMinority) return SIGNTRI_ENOTSUP;
+        path = SIGNTRI_PATH_PROJ;
+    }
+    if (path == SIGNTRI_PATH_PROJ) {
+        // every mode: FP64 substitutions and products, no sweep options apply
+        if (run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, p.min_sign,
+                     (int)p.n_min, ws + L0.prefix, st) != SIGNTRI_OK)
+            return SIGNTRI_EHIP;
+        if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
+            return SIGNTRI_EHIP;
+        if (info) {
+            info->path = path;
+            info->tile = 0;
+            info->sweep = 0;
+            info->wgs_per_cu = 0;
+        }
+        return SIGNTRI_OK;
     }
     signtri_options eo = resolve_options(opts, dtype, mode, path, n);
     if (path == SIGNTRI_PATH_PS && eo.sweep != SIGNTRI_SWEEP_DATAFLOW) {

@@ -153,6 +153,9 @@ struct HostPlan {
     int auto_path = SIGNTRI_PATH_PH;
     int ps_sign = 0;  // +1: positives first, -1: negatives first, 0: not grouped
     int64_t split = 0;  // size of the leading sign group when grouped
+    int64_t n_min = 0;  // entries in the minority sign class (ties: the negatives)
+    int min_sign = 0;   // sign of the minority class
+    bool proj_pick = false;  // AUTO runs the projector form instead of auto_path
 };
 HostPlan plan_from_signs(const int8_t *s, int64_t n, bool is_complex);
 
@@ -312,6 +315,17 @@ int wave_gemm_edge_slices(int D, int L);
 // task, completion flags between tasks.
 // ---------------------------------------------------------------------------
 constexpr int kFlowTile = 32;
+
+// ---------------------------------------------------------------------------
+// Projector form (proj.hip): the Parlett-Sylvester result for an ungrouped
+// diagonal with at most kProjMaxMinority entries in its minority sign class.
+// ---------------------------------------------------------------------------
+constexpr int kProjMaxMinority = 64;
+size_t proj_workspace_bytes(int64_t n);
+// T, U column-major real; sgn the device sign vector; minority = its sign (+1/-1),
+// m = its count.  Queues every launch on st.
+int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
+             int minority, int m, void *ws, hipStream_t st);
 enum FlowKind { FLOW_MAIN = 0, FLOW_CORR = 1, FLOW_SYL = 2 };
 
 // One real triangular system of a sweep; column-major device arrays.

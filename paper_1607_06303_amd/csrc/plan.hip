@@ -105,9 +105,17 @@ HostPlan plan_from_signs(const int8_t *s, int64_t n, bool is_complex)
         p.ps_sign = -1;
         p.split = p.n_neg;
     }
-    // No Schur reordering here: PS runs only on an already grouped diagonal.
+    // PS runs as such only on an already grouped diagonal.
     double w_ps_grouped = c * nng * npn * nd;
     p.auto_path = (p.ps_sign != 0 && w_ps_grouped < p.w_ph) ? SIGNTRI_PATH_PS : SIGNTRI_PATH_PH;
+    // Otherwise the same result through the minority class's spectral projector:
+    // two substitutions of about n^2 m / 2 multiply-adds each and the n^2 m / 2
+    // multiply-adds of the rank-m product, 3 n^2 m flops in all (real T).
+    p.n_min = std::min(p.n_pos, p.n_neg);
+    p.min_sign = p.n_neg <= p.n_pos ? -1 : 1;
+    const double w_proj = 3.0 * nd * nd * (double)p.n_min;
+    p.proj_pick = !is_complex && p.auto_path == SIGNTRI_PATH_PH && p.n_min >= 1 &&
+                  p.n_min <= kProjMaxMinority && w_proj < p.w_ph;
     return p;
 }
 

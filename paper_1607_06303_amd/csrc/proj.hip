@@ -1,0 +1,527 @@
+// The Sylvester form for a diagonal whose signs are not grouped, without a
+// Schur reordering.
+//
+// Section 3 makes the Parlett-Sylvester form apply to any inertia by reordering
+// T (adjacent swaps by plane rotations) until the signs are grouped, solving the
+// Sylvester equation T11 X - X T22 = 2 s T12 of the sign-split case (Algorithm 2
+// with diagonal blocks +-I) and transforming back.  The swaps form a long serial
+// chain of small rotations, so the same result is reached here through the
+// invariant subspaces that the reordering exposes.  With m entries in the
+// minority sign class, at rows b_0 < ... < b_{m-1}:
+//
+//   right basis Z (n x m):  T Z = Z L,   Z[b_l, :] = e_l,  Z[i, l] = 0 for i > b_l
+//   left basis  W (n x m):  W^T T = L' W^T,  W[b_l, :] = e_l,  W[i, l] = 0 for i < b_l
+//
+// L and L' are upper triangular with the minority eigenvalues on the diagonal.
+// The spectral projector of the minority eigenvalues is P = Z (W^T Z)^-1 W^T,
+// W^T Z is unit upper triangular, and sign(T) = s (I - 2 P) with s the majority
+// sign.  When the signs are already grouped, Z = [X; I] with X the solution of
+// the sign-split Sylvester equation above, W = [0; I], and this is the
+// Parlett-Sylvester form itself.
+//
+// Z is found by substitution from the bottom row up.  Row i of T Z = Z L reads
+//   t_ii z_il + sum_{j>i} t_ij z_jl = sum_{l'} z_il' L[l', l],
+// so at a minority row i = b_l0 it defines row l0 of L (z_i = e_l0), and at any
+// other row it gives z_il from the columns l' < l of the same row (the L
+// coupling) and the rows below:
+//   z_il = (sum_{l'<l} z_il' L[l', l] - sum_{j>i} t_ij z_jl) / (t_ii - L[l, l]).
+// The divisions are by differences of eigenvalues of opposite sign, the same
+// divisions as Eq. (1).  W is Z of the flipped matrix J T^T J (J the reversal),
+// which is upper triangular with the same diagonal in reverse order.
+//
+// Kernels:
+//   k_proj_flip    J T^T J, the upper triangle, as a column-major copy;
+//   k_proj_prep    minority rows and row types of both bases, from the signs;
+//   k_proj_front   one workgroup per basis and block of 64 rows: the
+//                  substitution above as a wavefront, column l at row
+//                  r1 - 1 - s + l at step s; block operands in LDS;
+//   k_proj_update  acc[rows above the block] += T[rows above, block] Z[block]
+//                  (FP64 MFMA), the rows-below sums the front starts from;
+//   k_proj_gram    partial sums of W^T Z over 64-row chunks (MFMA);
+//   k_proj_gsum    W^T Z, the partials summed;
+//   k_proj_minv    its inverse (unit upper triangular, m x m);
+//   k_proj_a       A = Z (W^T Z)^-1;
+//   k_proj_u       U = s (I - 2 A W^T) on the upper triangle, zeros below
+//                  (FP64 MFMA, 64 x 64 output tiles).
+#include <algorithm>
+
+#include "common.h"
+
+namespace sgt {
+
+namespace {
+
+constexpr int PM = kProjMaxMinority;  // minority columns: one lane each
+constexpr int PB = 64;                // rows per front block
+constexpr int AP = PM + 1;            // LDS pitch of the accumulated sums
+
+struct ProjBasis {
+    const double *T;      // upper-triangular matrix of this basis (column-major)
+    int64_t ldt;
+    double *Z;            // n x PM, leading dimension n
+    double *acc;          // n x PM: sum over the rows below the current block
+    double *lam;          // PM x PM, lam[lp * PM + l] = L[lp][l]
+    const int *rowtype;   // n: minority column of row i, or -1
+    const int *pos;       // PM: row of minority column l, or -1 (l >= m)
+};
+
+struct ProjArgs {
+    ProjBasis b[2];
+    int64_t n;
+    int m;
+};
+
+// ---------------------------------------------------------------------------
+// Flipped copy F = J T^T J: F[i, j] = T[n-1-j, n-1-i], upper triangle only.
+// 32 x 32 tiles through LDS so that both the reads and the writes are
+// coalesced down columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_proj_flip(const double *__restrict__ T, int64_t ldt,
+                                                   double *__restrict__ F, int64_t n)
+{
+    __shared__ double tile[32][33];
+    const int64_t ti = blockIdx.x, tj = blockIdx.y;  // tile of F
+    if (ti > tj) return;
+    const int64_t i0 = ti * 32, j0 = tj * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    // F[i0 + a, j0 + b] = T[n-1-j0-b, n-1-i0-a]; read T down its columns
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t b = 31 - tx, a = y;      // T row n-1-j0-b, T column n-1-i0-a
+        const int64_t tr = n - 1 - j0 - b, tc = n - 1 - i0 - a;
+        double v = 0.0;
+        if (tr >= 0 && tc >= 0 && tr < n && tc < n) v = T[tr + tc * ldt];
+        tile[a][b] = v;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t i = i0 + tx, j = j0 + y;
+        if (i < n && j < n && i <= j) F[i + j * n] = tile[tx][y];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Minority rows of both bases from the signs (one workgroup).
+// Basis 0 (T):      pos[l] = b_l,              rowtype[b_l] = l
+// Basis 1 (J T^T J): pos[l] = n-1-b_{m-1-l},   rowtype[n-1-b_l] = m-1-l
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_proj_prep(const int8_t *__restrict__ sgn, int64_t n,
+                                                    int minority, int m, int *__restrict__ rt0,
+                                                    int *__restrict__ pos0, int *__restrict__ rt1,
+                                                    int *__restrict__ pos1)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = std::min<int64_t>(n, t * per), hi = std::min<int64_t>(n, lo + per);
+    int c = 0;
+    for (int64_t i = lo; i < hi; ++i) c += sgn[i] == minority;
+    part[t] = c;
+    __syncthreads();
+    // exclusive scan (Hillis-Steele over 1024 entries)
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int l = part[t] - c;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t f = n - 1 - i;
+        if (sgn[i] == minority) {
+            rt0[i] = l;
+            pos0[l] = (int)i;
+            rt1[f] = m - 1 - l;
+            pos1[m - 1 - l] = (int)f;
+            ++l;
+        } else {
+            rt0[i] = -1;
+            rt1[f] = -1;
+        }
+    }
+    for (int q = m + t; q < PM; q += 1024) {
+        pos0[q] = -1;
+        pos1[q] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Front: rows [r0, r1) of Z for both bases (blockIdx.x = basis).  Four waves;
+// column l is served by the four lanes 4 (l % 16) + q of wave l / 16, lane q
+// taking the terms 4 u + q (u = 0..15) of the two 64-term sums of every entry
+// (reduced over the four lanes by DPP), so that the LDS reads of one 16-lane
+// pass fall in distinct banks (pitches = 4 mod 16 doubles).  Column l's
+// coefficients L[4 u + q][l] stay in registers.
+// ---------------------------------------------------------------------------
+constexpr int FP = PB + 4;  // LDS pitch of the staged T block and of the Z block
+
+__global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int64_t r1)
+{
+    __shared__ double Tt[PB * FP];   // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
+    __shared__ double Zr[PB * FP];   // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
+    __shared__ double Ab[PB * AP];   // Ab[r * AP + l] = acc[r0 + r, l]
+    __shared__ int rt[PB];
+
+    const ProjBasis B = a.b[blockIdx.x];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int t = threadIdx.x;
+    const int nr = (int)(r1 - r0);
+
+    // ---- stage the block's operands (64 consecutive rows per wave, coalesced)
+    {
+        const int row = t & 63;
+        for (int c = t >> 6; c < PB; c += 4) {
+            double v = 0.0;
+            if (row < nr && c < nr && row <= c) v = B.T[(r0 + row) + (r0 + c) * B.ldt];
+            Tt[row * FP + c] = v;
+            double w = 0.0;
+            if (row < nr && c < m) w = B.acc[(r0 + row) + (int64_t)c * n];
+            Ab[row * AP + c] = w;
+            Zr[row * FP + c] = 0.0;
+        }
+        if (t < PB) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
+    }
+    const int col = (t >> 6) * 16 + ((t & 63) >> 2);
+    const int q = t & 3;
+    double lreg[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lreg[u] = B.lam[(4 * u + q) * PM + col];
+    double lamll = B.lam[col * PM + col];
+    const int pl = col < m ? B.pos[col] : -1;
+    __syncthreads();
+
+    // ---- wavefront: column l handles block row nr - 1 - s + l at step s
+    const int steps = uniform(nr + m - 1);
+    for (int s = 0; s < steps; ++s) {
+        const int r = nr - 1 - s + col;
+        const int64_t i = r0 + r;
+        if (col < m && r >= 0 && r < nr && i <= pl) {
+            const double *trow = Tt + r * FP;
+            const double *zrow = Zr + r * FP;
+            const double tii = trow[r];
+            const double rcp = 1.0 / (tii - lamll);  // used only where lamll is set
+            // Full sums: every term outside the ranges that count is zero (the
+            // lower triangle of the staged block, entries of Z not computed yet).
+            double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; u += 2) {
+                const int k0 = 4 * u + q, k1 = 4 * (u + 1) + q;
+                v0 += trow[k0] * Zr[k0 * FP + col];
+                v1 += trow[k1] * Zr[k1 * FP + col];
+                c0 += zrow[k0] * lreg[u];
+                c1 += zrow[k1] * lreg[u + 1];
+            }
+            const double v = group_sum<4>(v0 + v1);
+            const double cpl = group_sum<4>(c0 + c1);
+            const int typ = rt[r];
+            double z;
+            if (i == pl) {
+                z = 1.0;
+                lamll = tii;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (4 * u + q == col) lreg[u] = tii;
+            } else if (typ >= 0) {
+                // minority row b_typ (typ < l): row typ of L
+                z = 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (4 * u + q == typ) lreg[u] = v;
+            } else {
+                z = (cpl - v) * rcp;
+            }
+            if (q == 0) Zr[r * FP + col] = z;
+        }
+        __syncthreads();
+    }
+
+    // ---- publish the rows and L
+    {
+        const int row = t & 63;
+        for (int c = t >> 6; c < m; c += 4)
+            if (row < nr) B.Z[(r0 + row) + (int64_t)c * n] = Zr[row * FP + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) B.lam[(4 * u + q) * PM + col] = lreg[u];
+}
+
+// ---------------------------------------------------------------------------
+// 64 x 64 x 64 FP64 MFMA product of two LDS operands, 4 waves in a 2 x 2
+// arrangement of 32 x 32 quarters: D[i][j] = sum_k A[k][i] B[k][j] with
+// A and B stored k-major (pitch 65).
+// ---------------------------------------------------------------------------
+constexpr int OP = 65;
+
+__device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    const int kr = lane >> 4, cc = lane & 15;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) d[x][y] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < 64; k += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = As[(k + kr) * OP + rb + 16 * x + cc];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = Bs[(k + kr) * OP + cb + 16 * y + cc];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) d[x][y] = mfma_f64(av[x], bv[y], d[x][y]);
+    }
+}
+
+// acc[0:r0, :] += T[0:r0, r0:r1] Z[r0:r1, :]; blockIdx.x = 64-row tile, y = basis.
+__global__ __launch_bounds__(256) void k_proj_update(ProjArgs a, int64_t r0, int64_t r1)
+{
+    __shared__ double As[64 * OP];  // As[k * OP + row] = T[row0 + row, r0 + k]
+    __shared__ double Bs[64 * OP];  // Bs[k * OP + col] = Z[r0 + k, col]
+    const ProjBasis B = a.b[blockIdx.y];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int nk = (int)(r1 - r0);
+    const int t = threadIdx.x, lr = t & 63, q = t >> 6;
+    for (int k = q; k < 64; k += 4) {
+        const int64_t row = row0 + lr;
+        As[k * OP + lr] = (k < nk && row < r0) ? B.T[row + (r0 + k) * B.ldt] : 0.0;
+        Bs[k * OP + lr] = (k < nk && lr < m) ? B.Z[(r0 + k) + (int64_t)lr * n] : 0.0;
+    }
+    __syncthreads();
+    dx4 d[2][2];
+    mm64(As, Bs, d);
+    const int lane = t & 63, w = t >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row0 + rb + 16 * x + mfma64_row(lane, e);
+                const int col = cb + 16 * y + (lane & 15);
+                if (row < r0 && col < m) B.acc[row + (int64_t)col * n] += d[x][y][e];
+            }
+}
+
+// Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'] (row-major l).
+// W[j, l] = Zf[n-1-j, m-1-l] with Zf the basis of the flipped matrix.
+__global__ __launch_bounds__(256) void k_proj_gram(const double *__restrict__ Z,
+                                                   const double *__restrict__ Zf, int64_t n, int m,
+                                                   double *__restrict__ part)
+{
+    __shared__ double As[64 * OP];  // As[k * OP + l]  = W[j0 + k, l]
+    __shared__ double Bs[64 * OP];  // Bs[k * OP + l'] = Z[j0 + k, l']
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x, lr = t & 63, q = t >> 6;
+    for (int k = q; k < 64; k += 4) {
+        const int64_t j = j0 + k;
+        const bool ok = j < n && lr < m;
+        As[k * OP + lr] = ok ? Zf[(n - 1 - j) + (int64_t)(m - 1 - lr) * n] : 0.0;
+        Bs[k * OP + lr] = ok ? Z[j + (int64_t)lr * n] : 0.0;
+    }
+    __syncthreads();
+    dx4 d[2][2];
+    mm64(As, Bs, d);
+    const int lane = t & 63, w = t >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    double *out = part + (int64_t)blockIdx.x * PM * PM;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = rb + 16 * x + mfma64_row(lane, e);
+                const int c = cb + 16 * y + (lane & 15);
+                out[r * PM + c] = d[x][y][e];
+            }
+}
+
+// M = sum of the partials (one entry per thread, coalesced over the partials).
+__global__ __launch_bounds__(64) void k_proj_gsum(const double *__restrict__ part, int nparts,
+                                                  int m, double *__restrict__ M)
+{
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    const int r = e / PM, c = e % PM;
+    double s = 0.0;
+    if (r < m && c < m)
+        for (int g = 0; g < nparts; ++g) s += part[(int64_t)g * PM * PM + e];
+    else
+        s = r == c ? 1.0 : 0.0;
+    M[e] = s;
+}
+
+// Minv = M^-1 for the upper triangular M (unit diagonal on the leading m x m
+// block, identity beyond), by back substitution over the rows k = 63 .. 0; the
+// 64 columns in parallel, each row's inner products split over four threads.
+__global__ __launch_bounds__(256) void k_proj_minv(const double *Mg,
+                                                   double *minv)
+{
+    __shared__ double M[PM * PM];
+    __shared__ double X[PM * (PM + 1)];
+    __shared__ double red[4][PM];
+    const int t = threadIdx.x, l = t & 63, q = t >> 6;
+    for (int e = t; e < PM * PM; e += 256) M[e] = Mg[e];
+    for (int e = t; e < PM * (PM + 1); e += 256) X[e] = 0.0;
+    __syncthreads();
+    for (int k = PM - 1; k >= 0; --k) {
+        double s = 0.0;
+        for (int kk = k + 1 + q; kk < PM; kk += 4) s += M[k * PM + kk] * X[kk * (PM + 1) + l];
+        red[q][l] = s;
+        __syncthreads();
+        if (q == 0 && k <= l) {
+            const double v = (k == l ? 1.0 : 0.0) - (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
+            X[k * (PM + 1) + l] = v / M[k * PM + k];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < PM * PM; e += 256) minv[e] = X[(e / PM) * (PM + 1) + e % PM];
+}
+
+// A = Z Minv: A[i, l] = sum_{l' <= l} Z[i, l'] Minv[l'][l]; 4 rows per workgroup.
+__global__ __launch_bounds__(256) void k_proj_a(const double *__restrict__ Z,
+                                                const double *__restrict__ minv, int64_t n, int m,
+                                                double *__restrict__ A)
+{
+    __shared__ double X[PM * PM];
+    const int t = threadIdx.x;
+    for (int e = t; e < PM * PM; e += 256) X[e] = minv[e];
+    __syncthreads();
+    const int l = t & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (t >> 6);
+    if (i >= n) return;
+    double s = 0.0;
+    if (l < m)
+        for (int lp = 0; lp <= l; ++lp) s += Z[i + (int64_t)lp * n] * X[lp * PM + l];
+    A[i + (int64_t)l * n] = s;
+}
+
+// U[i, j] = s (delta_ij - 2 sum_l A[i, l] W[j, l]) for i <= j, 0 for i > j.
+// Computed as the transpose product C[j][i] = sum_l W[j, l] A[i, l], so that
+// the accumulator's lane index runs down a column of U.
+__global__ __launch_bounds__(256) void k_proj_u(const double *__restrict__ A,
+                                                const double *__restrict__ Zf, int64_t n, int m,
+                                                double smaj, double *__restrict__ U, int64_t ldu)
+{
+    __shared__ double Ws[64 * OP];  // Ws[l * OP + jj] = W[j0 + jj, l]
+    __shared__ double As[64 * OP];  // As[l * OP + ii] = A[i0 + ii, l]
+    const int64_t ti = blockIdx.x, tj = blockIdx.y;
+    const int64_t i0 = ti * 64, j0 = tj * 64;
+    const int t = threadIdx.x, lr = t & 63, q = t >> 6;
+    if (ti > tj) {
+        for (int c = q; c < 64; c += 4) {
+            const int64_t i = i0 + lr, j = j0 + c;
+            if (i < n && j < n) U[i + j * ldu] = 0.0;
+        }
+        return;
+    }
+    for (int l = q; l < 64; l += 4) {
+        const int64_t j = j0 + lr, i = i0 + lr;
+        Ws[l * OP + lr] = (j < n && l < m) ? Zf[(n - 1 - j) + (int64_t)(m - 1 - l) * n] : 0.0;
+        As[l * OP + lr] = (i < n && l < m) ? A[i + (int64_t)l * n] : 0.0;
+    }
+    __syncthreads();
+    dx4 d[2][2];
+    mm64(Ws, As, d);  // d[jj][ii]
+    const int lane = t & 63, w = t >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t j = j0 + rb + 16 * x + mfma64_row(lane, e);
+                const int64_t i = i0 + cb + 16 * y + (lane & 15);
+                if (i < n && j < n) {
+                    double v = 0.0;
+                    if (i <= j) v = smaj * ((i == j ? 1.0 : 0.0) - 2.0 * d[x][y][e]);
+                    U[i + j * ldu] = v;
+                }
+            }
+}
+
+inline size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t proj_workspace_bytes(int64_t n)
+{
+    const size_t nn = (size_t)n;
+    const size_t nparts = (nn + 63) / 64;
+    return al(nn * nn * 8)                  // flipped T
+           + 4 * al(nn * PM * 8)            // Z and acc, two bases
+           + 2 * al(PM * PM * 8)            // L, two bases
+           + 2 * al(nn * 4) + 2 * al(PM * 4)  // row types and minority rows
+           + al(nparts * PM * PM * 8)       // partial Gram matrices
+           + al(PM * PM * 8)                // Minv
+           + al(nn * PM * 8);               // A
+}
+
+int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
+             int minority, int m, void *ws, hipStream_t st)
+{
+    if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
+    const size_t nn = (size_t)n;
+    const int64_t nparts = (n + 63) / 64;
+    char *p = (char *)ws;
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += al(bytes);
+        return (void *)q;
+    };
+    double *F = (double *)take(nn * nn * 8);
+    double *Z0 = (double *)take(nn * PM * 8), *Z1 = (double *)take(nn * PM * 8);
+    double *C0 = (double *)take(nn * PM * 8), *C1 = (double *)take(nn * PM * 8);
+    double *L0 = (double *)take(PM * PM * 8), *L1 = (double *)take(PM * PM * 8);
+    int *rt0 = (int *)take(nn * 4), *rt1 = (int *)take(nn * 4);
+    int *ps0 = (int *)take(PM * 4), *ps1 = (int *)take(PM * 4);
+    double *part = (double *)take((size_t)nparts * PM * PM * 8);
+    double *minv = (double *)take(PM * PM * 8);
+    double *A = (double *)take(nn * PM * 8);
+
+    // Z, acc and L of both bases are contiguous: one clear
+    if (hipMemsetAsync(Z0, 0, (char *)rt0 - (char *)Z0, st) != hipSuccess) return SIGNTRI_EHIP;
+    prof_begin(st);
+    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
+                       ps1);
+    const int64_t nt = (n + 31) / 32;
+    hipLaunchKernelGGL(k_proj_flip, dim3(nt, nt), dim3(256), 0, st, T, ldt, F, n);
+    prof_end(st, PK_AUX, 0.0);
+
+    ProjArgs a;
+    a.n = n;
+    a.m = m;
+    a.b[0] = ProjBasis{T, ldt, Z0, C0, L0, rt0, ps0};
+    a.b[1] = ProjBasis{F, n, Z1, C1, L1, rt1, ps1};
+    // blocks of PB rows from the bottom up; the top block may be short
+    const double nd = (double)n, md = (double)m;
+    prof_begin(st);
+    for (int64_t r1 = n; r1 > 0;) {
+        const int64_t r0 = std::max<int64_t>(0, r1 - PB);
+        hipLaunchKernelGGL(k_proj_front, dim3(2), dim3(256), 0, st, a, r0, r1);
+        if (r0 > 0)
+            hipLaunchKernelGGL(k_proj_update, dim3((r0 + 63) / 64, 2), dim3(256), 0, st, a, r0,
+                               r1);
+        r1 = r0;
+    }
+    // two bases, about n^2 m / 2 multiply-adds each
+    prof_end(st, PK_SYL, 2.0 * nd * nd * md);
+    prof_begin(st);
+    hipLaunchKernelGGL(k_proj_gram, dim3(nparts), dim3(256), 0, st, Z0, Z1, n, m, part);
+    hipLaunchKernelGGL(k_proj_gsum, dim3(PM * PM / 64), dim3(64), 0, st, part, (int)nparts, m,
+                       minv);
+    hipLaunchKernelGGL(k_proj_minv, dim3(1), dim3(256), 0, st, minv, minv);
+    hipLaunchKernelGGL(k_proj_a, dim3((n + 3) / 4), dim3(256), 0, st, Z0, minv, n, m, A);
+    const int64_t nu = (n + 63) / 64;
+    hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, n, m,
+                       minority > 0 ? -1.0 : 1.0, U, ldu);
+    prof_end(st, PK_GEMM, nd * nd * md);
+    return hipGetLastError() == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
+}
+
+}  // namespace sgt

@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(HERE, "libsigntri.so")
 R64, C128 = 0, 1
 COL_MAJOR, ROW_MAJOR = 0, 1
 MODES = {"fp64": 0, "mixed": 1, "fp32": 2}
-ALGOS = {"auto": 0, "ph": 1, "ps": 2}
-PATH_NAMES = {0: "trivial", 1: "ph", 2: "ps"}
+ALGOS = {"auto": 0, "ph": 1, "ps": 2, "proj": 3}
+PATH_NAMES = {0: "trivial", 1: "ph", 2: "ps", 3: "proj"}
 SWEEPS = {"auto": 0, "dataflow": 1, "superdiag": 2}
 SWEEP_NAMES = {0: "-", 1: "dataflow", 2: "superdiag"}
 

@@ -141,12 +141,26 @@ def test_planner_choice_rule():
     inter = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
     info = signtri.plan_host(inter)
     assert info["path_name"] == "ph" and info["model_pick_name"] == "ph"
-    # few negatives at random positions: the model (with reordering) prefers PS,
-    # but without a reordering step PH runs (the paper's Fig. 3 regime)
+    # few negatives at random positions: the model (with reordering) prefers PS
+    # (the paper's Fig. 3 regime); the library reaches that result through the
+    # minority class's projector (real T, at most 64 minority entries), and runs
+    # PH for complex T
     few = np.ones(n, dtype=np.int8)
     few[rng.choice(n, 3, replace=False)] = -1
     info = signtri.plan_host(few)
-    assert info["model_pick_name"] == "ps" and info["path_name"] == "ph"
+    assert info["model_pick_name"] == "ps" and info["path_name"] == "proj"
+    assert signtri.plan_host(-few)["path_name"] == "proj"       # positive minority
+    assert signtri.plan_host(few, complex_=True)["path_name"] == "ph"
+    # projector estimate 3 n^2 m against the PH estimate; at most 64 minority entries
+    big = np.ones(4096, dtype=np.int8)
+    big[rng.choice(4096, 64, replace=False)] = -1
+    assert signtri.plan_host(big)["path_name"] == "proj"
+    big[rng.choice(np.flatnonzero(big > 0), 1, replace=False)] = -1
+    assert signtri.plan_host(big)["path_name"] == "ph"          # 65 minority entries
+    mid = np.ones(n, dtype=np.int8)
+    mid[rng.choice(n, 40, replace=False)] = -1                  # 3 n^2 m above W_PH
+    info = signtri.plan_host(mid)
+    assert 3.0 * n * n * 40 >= info["w_ph"] and info["path_name"] == "ph"
 
 
 def test_planner_rejects_bad_signs():

@@ -1,0 +1,134 @@
+"""GPU parity of the projector form (the Parlett-Sylvester result for an
+ungrouped diagonal) against the oracle, through the C ABI.
+
+The oracle sides: the element-by-element Parlett-Higham substitution (C), and
+on some cases also the Section 3 route itself (Schur reordering by adjacent
+swaps, the sign-split Sylvester equation, the transformation back).  Bar:
+1e-11 relative Frobenius error.  Sizes span one to several 64-row blocks with
+ragged tops; minority counts span 1..64 including 32/33 and 63/64; the
+minority class is negative or positive; its rows sit at the ends, in runs and
+adjacent pairs.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06303_amd import workloads as wl
+from tests.conftest import rel_fro
+from tests.test_gpu_parity import TOL_FP64, dev, run_gpu, to_dev_colmajor  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def skewed(n, m, seed, minority=-1, where=None):
+    rng = wl.rng_for(3, salt=seed)
+    s = -minority * np.ones(n)
+    if where is None:
+        where = rng.choice(n, size=m, replace=False)
+    s[np.asarray(where)] = minority
+    return wl.make_T(n, rng, signs=s)
+
+
+CASES = [
+    (2, 1, None),
+    (3, 1, [1]),
+    (64, 1, [63]),
+    (64, 3, [0, 1, 63]),
+    (65, 7, None),
+    (127, 32, None),
+    (128, 33, None),
+    (200, 5, [0, 1, 2, 198, 199]),
+    (333, 31, None),
+    (333, 63, None),
+    (700, 64, None),
+    (700, 16, list(range(300, 316))),   # one contiguous run
+]
+
+
+@pytest.mark.parametrize("n,m,where", CASES)
+@pytest.mark.parametrize("minority", [-1, 1])
+def test_proj_matches_oracle(dev, n, m, where, minority):
+    import oracle
+
+    T = skewed(n, m, n * 7 + m, minority, where)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj", info
+    err = rel_fro(U, oracle.sign_tri(T))
+    assert err <= TOL_FP64, (n, m, err)
+    assert not np.any(np.tril(U, -1))
+
+
+@pytest.mark.parametrize("n,m", [(150, 4), (260, 20)])
+def test_proj_matches_reordering_route(dev, n, m):
+    from oracle import reorder
+
+    T = skewed(n, m, 91 + n)
+    U, info = run_gpu(T, dev, algo="proj")
+    ref, rinfo = reorder.sign_tri_reordered(T)
+    assert rinfo["k"] > 0
+    assert rel_fro(U, ref) <= TOL_FP64
+
+
+def test_proj_schur_recipe_and_grouped(dev):
+    """Repeated diagonal values (the paper's Schur-form recipe), and a grouped diagonal
+    where the projector form is the Sylvester form itself."""
+    import oracle
+
+    T = wl.schur_like(300, 6, wl.rng_for(9, salt=3))
+    U, _ = run_gpu(T, dev, algo="proj")
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+    G = wl.sorted_positive_first(skewed(250, 12, 5))
+    U, _ = run_gpu(G, dev, algo="proj")
+    assert rel_fro(U, oracle.sign_tri(G)) <= TOL_FP64
+
+
+def test_proj_garbage_below_and_row_major(dev):
+    import torch
+
+    import oracle
+    from paper_1607_06303_amd import signtri
+
+    T = skewed(190, 9, 17)
+    Tg = T + np.tril(np.full_like(T, np.nan), -1)
+    U, _ = run_gpu(Tg, dev, algo="proj")
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+    Tr = torch.from_numpy(np.ascontiguousarray(T)).to(dev)   # row-major
+    Ur, info = signtri.sign_tri(Tr, algo="proj")
+    torch.cuda.synchronize()
+    assert info["path_name"] == "proj"
+    assert rel_fro(Ur.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_proj_repeated_calls_and_modes(dev):
+    """Back-to-back calls reuse the workspace; every mode runs the FP64 form."""
+    import oracle
+
+    T1 = skewed(300, 40, 1)
+    T2 = skewed(129, 3, 2, minority=1)
+    for T in (T1, T2, T1):
+        for mode in ("fp64", "mixed", "fp32"):
+            U, info = run_gpu(T, dev, algo="proj", mode=mode)
+            assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64, mode
+
+
+def test_auto_choice(dev):
+    """AUTO: the projector form for a small minority class, the substitution for
+    balanced inertia, the Sylvester form for a grouped diagonal."""
+    _, info = run_gpu(skewed(512, 8, 3), dev)
+    assert info["path_name"] == "proj"
+    _, info = run_gpu(wl.workload1(256), dev)
+    assert info["path_name"] == "ph"
+    _, info = run_gpu(wl.sorted_positive_first(wl.workload1(256)), dev)
+    assert info["path_name"] == "ps"
+
+
+def test_proj_unsupported(dev):
+    from paper_1607_06303_amd import signtri
+
+    T = wl.make_T(64, wl.rng_for(2, salt=4), complex_=True)
+    with pytest.raises(signtri.SignTriError):
+        run_gpu(T, dev, algo="proj")
+    with pytest.raises(signtri.SignTriError):
+        run_gpu(skewed(300, 65, 8), dev, algo="proj")
+    # all one sign: the trivial path, whatever the algorithm asked for
+    U, info = run_gpu(wl.make_T(40, wl.rng_for(1, salt=4), signs=np.ones(40)), dev, algo="proj")
+    assert info["path_name"] == "trivial" and np.array_equal(U, np.eye(40))
