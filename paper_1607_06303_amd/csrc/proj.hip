@@ -32,11 +32,11 @@
 // Kernels:
 //   k_proj_flip    J T^T J, the upper triangle, as a column-major copy;
 //   k_proj_prep    minority rows and row types of both bases, from the signs;
-//   k_proj_front   one workgroup per basis and block of 64 rows: the
-//                  substitution above as a wavefront, column l at row
-//                  r1 - 1 - s + l at step s; block operands in LDS;
-//   k_proj_update  acc[rows above the block] += T[rows above, block] Z[block]
-//                  (FP64 MFMA), the rows-below sums the front starts from;
+//   k_proj_step    one launch per block of 64 rows, bottom up: a workgroup
+//                  per basis runs the substitution above as a wavefront
+//                  (column l at row r1 - 1 - s + l at step s, block operands in
+//                  LDS), and FP64 MFMA products keep acc, the sums over the
+//                  rows below each block, up to date for the next blocks;
 //   k_proj_gram    partial sums of W^T Z over 64-row chunks (MFMA);
 //   k_proj_gsum    W^T Z, the partials summed;
 //   k_proj_minv    its inverse (unit upper triangular, m x m);
@@ -145,6 +145,79 @@ __global__ __launch_bounds__(1024) void k_proj_prep(const int8_t *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
+// 64 x 64 x 64 FP64 MFMA product of two LDS operands, 4 waves in a 2 x 2
+// arrangement of 32 x 32 quarters: d[i][j] += sum_k A[k][i] B[k][j] with A
+// and B stored k-major (pitches PA and PBB).
+// ---------------------------------------------------------------------------
+constexpr int OP = 65;
+
+template <int PA, int PBB>
+__device__ inline void mm64_acc(const double *As, const double *Bs, dx4 (&d)[2][2])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    const int kr = lane >> 4, cc = lane & 15;
+    for (int k = 0; k < 64; k += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = As[(k + kr) * PA + rb + 16 * x + cc];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = Bs[(k + kr) * PBB + cb + 16 * y + cc];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) d[x][y] = mfma_f64(av[x], bv[y], d[x][y]);
+    }
+}
+
+__device__ inline void mm64_acc_zero(dx4 (&d)[2][2])
+{
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) d[x][y] = dx4{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
+{
+    mm64_acc_zero(d);
+    mm64_acc<OP, OP>(As, Bs, d);
+}
+
+// Stage As[k * OP + r] = T[row0 + r, k0 + k] (rows < rlim, k < k1 - k0) and, when
+// Bs is given, Bs[k * OP + c] = Z[k0 + k, c] (c < m); zeros elsewhere.
+__device__ inline void stage_tz(const ProjBasis &B, int64_t n, int m, int64_t row0, int64_t rlim,
+                                int64_t k0, int64_t k1, double *As, double *Bs)
+{
+    const int t = threadIdx.x, lr = t & 63;
+    const int nk = (int)(k1 - k0);
+    // As down T's columns, Bs down Z's columns (lr = k), both coalesced
+    for (int k = t >> 6; k < 64; k += 4) {
+        const int64_t row = row0 + lr;
+        As[k * OP + lr] = (k < nk && row < rlim) ? B.T[row + (k0 + k) * B.ldt] : 0.0;
+        if (Bs) Bs[lr * OP + k] = (lr < nk && k < m) ? B.Z[(k0 + lr) + (int64_t)k * n] : 0.0;
+    }
+}
+
+// acc[row0 + i, j] += d (rows < rlim, columns < m)
+__device__ inline void add_acc(const ProjBasis &B, int64_t n, int m, int64_t row0, int64_t rlim,
+                               const dx4 (&d)[2][2])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row0 + rb + 16 * x + mfma64_row(lane, e);
+                const int c = cb + 16 * y + (lane & 15);
+                if (row < rlim && c < m) B.acc[row + (int64_t)c * n] += d[x][y][e];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Front: rows [r0, r1) of Z for both bases (blockIdx.x = basis).  Four waves;
 // column l is served by the four lanes 4 (l % 16) + q of wave l / 16, lane q
 // taking the terms 4 u + q (u = 0..15) of the two 64-term sums of every entry
@@ -154,30 +227,64 @@ __global__ __launch_bounds__(1024) void k_proj_prep(const int8_t *__restrict__ s
 // ---------------------------------------------------------------------------
 constexpr int FP = PB + 4;  // LDS pitch of the staged T block and of the Z block
 
-__global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int64_t r1)
+//
+// One launch per block [r0, r1), with the block below it, [r1, p1), already
+// solved (p1 == r1 for the bottom block).  Workgroups 0 and 1 run the front of
+// the two bases; each first adds the block below's contribution to its own
+// rows' sums, in LDS, with operands fetched together with the block's.
+// Workgroups 2.. add the block below's contribution to every row above the
+// block, concurrently (the fronts read only the sums of rows [r0, r1)).  So
+// the sums of a block's rows hold every block below it when its front starts.
+__global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1)
 {
     __shared__ double Tt[PB * FP];   // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
     __shared__ double Zr[PB * FP];   // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
+    __shared__ double Zc[PM * FP];   // Zc[l * FP + r] = Z[r0 + r, l], the same values by column
     __shared__ double Ab[PB * AP];   // Ab[r * AP + l] = acc[r0 + r, l]
     __shared__ int rt[PB];
 
-    const ProjBasis B = a.b[blockIdx.x];
     const int64_t n = a.n;
     const int m = a.m;
     const int t = threadIdx.x;
     const int nr = (int)(r1 - r0);
+    const bool below = p1 > r1;
 
-    // ---- stage the block's operands (64 consecutive rows per wave, coalesced)
+    if (blockIdx.x >= 2) {
+        // rows [64 x, 64 x + 64) above the block, of one basis, times the block below
+        const int bid = (int)blockIdx.x - 2;
+        const ProjBasis B = a.b[bid & 1];
+        const int64_t row0 = (int64_t)(bid >> 1) * 64;
+        stage_tz(B, n, m, row0, r0, r1, p1, Tt, Ab);
+        __syncthreads();
+        dx4 d[2][2];
+        mm64(Tt, Ab, d);
+        add_acc(B, n, m, row0, r0, d);
+        return;
+    }
+
+    const ProjBasis B = a.b[blockIdx.x];
+
+    // ---- stage the block's operands and the block below's (64 consecutive rows
+    // per wave, coalesced; every load issued before the first store)
     {
-        const int row = t & 63;
-        for (int c = t >> 6; c < PB; c += 4) {
-            double v = 0.0;
-            if (row < nr && c < nr && row <= c) v = B.T[(r0 + row) + (r0 + c) * B.ldt];
-            Tt[row * FP + c] = v;
-            double w = 0.0;
-            if (row < nr && c < m) w = B.acc[(r0 + row) + (int64_t)c * n];
-            Ab[row * AP + c] = w;
-            Zr[row * FP + c] = 0.0;
+        const int row = t & 63, c0 = t >> 6;
+        const int nk = (int)(p1 - r1);
+        double tv[16], av[16], pv[16], zv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = c0 + 4 * k;
+            tv[k] = (row < nr && c < nr && row <= c) ? B.T[(r0 + row) + (r0 + c) * B.ldt] : 0.0;
+            av[k] = (row < nr && c < m) ? B.acc[(r0 + row) + (int64_t)c * n] : 0.0;
+            pv[k] = (row < nr && c < nk) ? B.T[(r0 + row) + (r1 + c) * B.ldt] : 0.0;
+            zv[k] = (row < nk && c < m) ? B.Z[(r1 + row) + (int64_t)c * n] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = c0 + 4 * k;
+            Tt[row * FP + c] = tv[k];
+            Ab[row * AP + c] = av[k];
+            Zr[c * FP + row] = pv[k];  // k-major: Zr[k * FP + r] = T[r0 + r, r1 + k]
+            Zc[row * FP + c] = zv[k];  // k-major: Zc[k * FP + l] = Z[r1 + k, l]
         }
         if (t < PB) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
     }
@@ -188,6 +295,29 @@ __global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int6
     for (int u = 0; u < 16; ++u) lreg[u] = B.lam[(4 * u + q) * PM + col];
     double lamll = B.lam[col * PM + col];
     const int pl = col < m ? B.pos[col] : -1;
+    __syncthreads();
+    if (below) {
+        dx4 d[2][2];
+        mm64_acc_zero(d);
+        mm64_acc<FP, FP>(Zr, Zc, d);
+        const int lane = t & 63, w = t >> 6;
+        const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = rb + 16 * x + mfma64_row(lane, e);
+                    const int c = cb + 16 * y + (lane & 15);
+                    Ab[r * AP + c] += d[x][y][e];
+                }
+        __syncthreads();
+    }
+    for (int e = t; e < PB * FP; e += 256) {
+        Zr[e] = 0.0;
+        Zc[e] = 0.0;
+    }
     __syncthreads();
 
     // ---- wavefront: column l handles block row nr - 1 - s + l at step s
@@ -202,14 +332,22 @@ __global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int6
             const double rcp = 1.0 / (tii - lamll);  // used only where lamll is set
             // Full sums: every term outside the ranges that count is zero (the
             // lower triangle of the staged block, entries of Z not computed yet).
+            // all operands first (paired LDS reads), then the multiply-adds
+            const double *zcol = Zc + col * FP;
+            double tv[16], zv[16], rv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                tv[u] = trow[4 * u + q];
+                zv[u] = zcol[4 * u + q];
+                rv[u] = zrow[4 * u + q];
+            }
             double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
 #pragma unroll
             for (int u = 0; u < 16; u += 2) {
-                const int k0 = 4 * u + q, k1 = 4 * (u + 1) + q;
-                v0 += trow[k0] * Zr[k0 * FP + col];
-                v1 += trow[k1] * Zr[k1 * FP + col];
-                c0 += zrow[k0] * lreg[u];
-                c1 += zrow[k1] * lreg[u + 1];
+                v0 += tv[u] * zv[u];
+                v1 += tv[u + 1] * zv[u + 1];
+                c0 += rv[u] * lreg[u];
+                c1 += rv[u + 1] * lreg[u + 1];
             }
             const double v = group_sum<4>(v0 + v1);
             const double cpl = group_sum<4>(c0 + c1);
@@ -230,7 +368,10 @@ __global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int6
             } else {
                 z = (cpl - v) * rcp;
             }
-            if (q == 0) Zr[r * FP + col] = z;
+            if (q == 0) {
+                Zr[r * FP + col] = z;
+                Zc[col * FP + r] = z;
+            }
         }
         __syncthreads();
     }
@@ -243,68 +384,7 @@ __global__ __launch_bounds__(256) void k_proj_front(ProjArgs a, int64_t r0, int6
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) B.lam[(4 * u + q) * PM + col] = lreg[u];
-}
 
-// ---------------------------------------------------------------------------
-// 64 x 64 x 64 FP64 MFMA product of two LDS operands, 4 waves in a 2 x 2
-// arrangement of 32 x 32 quarters: D[i][j] = sum_k A[k][i] B[k][j] with
-// A and B stored k-major (pitch 65).
-// ---------------------------------------------------------------------------
-constexpr int OP = 65;
-
-__device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    const int kr = lane >> 4, cc = lane & 15;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) d[x][y] = dx4{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < 64; k += 4) {
-        double av[2], bv[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = As[(k + kr) * OP + rb + 16 * x + cc];
-#pragma unroll
-        for (int y = 0; y < 2; ++y) bv[y] = Bs[(k + kr) * OP + cb + 16 * y + cc];
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) d[x][y] = mfma_f64(av[x], bv[y], d[x][y]);
-    }
-}
-
-// acc[0:r0, :] += T[0:r0, r0:r1] Z[r0:r1, :]; blockIdx.x = 64-row tile, y = basis.
-__global__ __launch_bounds__(256) void k_proj_update(ProjArgs a, int64_t r0, int64_t r1)
-{
-    __shared__ double As[64 * OP];  // As[k * OP + row] = T[row0 + row, r0 + k]
-    __shared__ double Bs[64 * OP];  // Bs[k * OP + col] = Z[r0 + k, col]
-    const ProjBasis B = a.b[blockIdx.y];
-    const int64_t n = a.n;
-    const int m = a.m;
-    const int64_t row0 = (int64_t)blockIdx.x * 64;
-    const int nk = (int)(r1 - r0);
-    const int t = threadIdx.x, lr = t & 63, q = t >> 6;
-    for (int k = q; k < 64; k += 4) {
-        const int64_t row = row0 + lr;
-        As[k * OP + lr] = (k < nk && row < r0) ? B.T[row + (r0 + k) * B.ldt] : 0.0;
-        Bs[k * OP + lr] = (k < nk && lr < m) ? B.Z[(r0 + k) + (int64_t)lr * n] : 0.0;
-    }
-    __syncthreads();
-    dx4 d[2][2];
-    mm64(As, Bs, d);
-    const int lane = t & 63, w = t >> 6;
-    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = row0 + rb + 16 * x + mfma64_row(lane, e);
-                const int col = cb + 16 * y + (lane & 15);
-                if (row < r0 && col < m) B.acc[row + (int64_t)col * n] += d[x][y][e];
-            }
 }
 
 // Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'] (row-major l).
@@ -501,12 +581,11 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     // blocks of PB rows from the bottom up; the top block may be short
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
-    for (int64_t r1 = n; r1 > 0;) {
+    for (int64_t r1 = n, p1 = n; r1 > 0;) {
         const int64_t r0 = std::max<int64_t>(0, r1 - PB);
-        hipLaunchKernelGGL(k_proj_front, dim3(2), dim3(256), 0, st, a, r0, r1);
-        if (r0 > 0)
-            hipLaunchKernelGGL(k_proj_update, dim3((r0 + 63) / 64, 2), dim3(256), 0, st, a, r0,
-                               r1);
+        const int64_t nbulk = p1 > r1 ? 2 * ((r0 + 63) / 64) : 0;
+        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(256), 0, st, a, r0, r1, p1);
+        p1 = r1;
         r1 = r0;
     }
     // two bases, about n^2 m / 2 multiply-adds each
