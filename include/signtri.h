@@ -73,8 +73,10 @@ typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } s
  *   U = s (I - 2 P) with s the majority sign.  Real T in FP64 (every mode runs
  *   it in FP64), at most 64 entries in the minority class.
  * AUTO picks by work estimates: PS when the diagonal is grouped and the
- *   Section 3 model favours it, PROJ when the minority class is small (real T,
- *   1..64 entries) and its estimate 3 n^2 m is below the PH estimate, else PH. */
+ *   Section 3 model favours it; in FP64 mode with no sweep or block size pinned
+ *   in the options, PROJ when the minority class is small (real T, 1..64
+ *   entries) and its estimate 3 n^2 m is below the PH estimate; else PH.
+ *   signtri_plan_host() reports the FP64-mode choice. */
 typedef enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2, SIGNTRI_PROJ = 3 } signtri_algo;
 
 typedef enum { SIGNTRI_COL_MAJOR = 0, SIGNTRI_ROW_MAJOR = 1 } signtri_layout;
@@ -285,7 +287,9 @@ enum {
     SIGNTRI_K_SYL = 7,         /* Sylvester dataflow sweep (products + solves)        */
     SIGNTRI_K_FLOW = 8,        /* Parlett-Higham dataflow sweep (products + solves)   */
     SIGNTRI_K_BATCHED = 9,     /* batched persistent sweep                            */
-    SIGNTRI_K_CONVERT = 10     /* precision and layout conversions                    */
+    SIGNTRI_K_CONVERT = 10,    /* precision and layout conversions                    */
+    SIGNTRI_K_PROJ = 11,       /* projector form: the two invariant-subspace substitutions */
+    SIGNTRI_K_PROJ_OUT = 12    /* projector form: W^T Z, its inverse, U = s (I - 2 P)  */
 };
 void signtri_profile_enable(int on);
 int signtri_profile_read(int family, double *ms, int64_t *launches, double *flops);

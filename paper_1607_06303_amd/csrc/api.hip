@@ -533,7 +533,10 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     fill_info(info, p);
 
     int path = p.auto_path;
-    if (algo == SIGNTRI_AUTO && p.proj_pick) path = SIGNTRI_PATH_PROJ;
+    // AUTO takes the projector form in FP64 mode when no sweep or block size is pinned
+    const bool pinned_sweep = opts && (opts->sweep != 0 || opts->tile != 0);
+    if (algo == SIGNTRI_AUTO && p.proj_pick && mode == SIGNTRI_FP64 && !pinned_sweep)
+        path = SIGNTRI_PATH_PROJ;
     if (algo == SIGNTRI_PH && path != SIGNTRI_PATH_TRIVIAL) path = SIGNTRI_PATH_PH;
     if (algo == SIGNTRI_PS && path != SIGNTRI_PATH_TRIVIAL) {
         if (p.ps_sign == 0) return SIGNTRI_ENOTSUP;
@@ -545,8 +548,17 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     }
     if (path == SIGNTRI_PATH_PROJ) {
         // every mode: FP64 substitutions and products, no sweep options apply
+        // algorithmic flops of the substitutions: column l of Z takes the rows above
+        // its minority row b_l, about b_l^2 / 2 multiply-adds, and of W the rows below;
+        // the L coupling adds about m^2 n / 2 per basis
+        double flops = 2.0 * (double)p.n_min * (double)p.n_min * (double)n;
+        for (int64_t i = 0; i < n; ++i)
+            if (hs[i] == p.min_sign) {
+                const double b = (double)i, f = (double)(n - 1 - i);
+                flops += b * b + f * f;
+            }
         if (run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, p.min_sign,
-                     (int)p.n_min, ws + L0.prefix, st) != SIGNTRI_OK)
+                     (int)p.n_min, flops, ws + L0.prefix, st) != SIGNTRI_OK)
             return SIGNTRI_EHIP;
         if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
             return SIGNTRI_EHIP;

@@ -176,11 +176,14 @@ enum ProfKind {
     PK_FLOW = SIGNTRI_K_FLOW,
     PK_BATCHED = SIGNTRI_K_BATCHED,
     PK_CONVERT = SIGNTRI_K_CONVERT,
+    PK_PROJ = SIGNTRI_K_PROJ,
+    PK_PROJ_OUT = SIGNTRI_K_PROJ_OUT,
     PK_COUNT = 16
 };
 bool prof_on();
 void prof_begin(hipStream_t st);
-void prof_end(hipStream_t st, int kind, double flops);
+// launches: kernel launches between the two events (one timed record)
+void prof_end(hipStream_t st, int kind, double flops, int launches = 1);
 
 // ---------------------------------------------------------------------------
 // Launchers (each in its own translation unit).
@@ -324,8 +327,9 @@ constexpr int kProjMaxMinority = 64;
 size_t proj_workspace_bytes(int64_t n);
 // T, U column-major real; sgn the device sign vector; minority = its sign (+1/-1),
 // m = its count.  Queues every launch on st.
+// flops: algorithmic flops of the two substitutions, for the kernel timers.
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
-             int minority, int m, void *ws, hipStream_t st);
+             int minority, int m, double flops, void *ws, hipStream_t st);
 enum FlowKind { FLOW_MAIN = 0, FLOW_CORR = 1, FLOW_SYL = 2 };
 
 // One real triangular system of a sweep; column-major device arrays.

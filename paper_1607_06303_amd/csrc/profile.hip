@@ -12,6 +12,7 @@ struct Rec {
     hipEvent_t a, b;
     int kind;
     double flops;
+    int launches;
 };
 
 struct Prof {
@@ -53,7 +54,7 @@ void prof_begin(hipStream_t st)
     if (p.pending) (void)hipEventRecord(p.pending, st);
 }
 
-void prof_end(hipStream_t st, int kind, double flops)
+void prof_end(hipStream_t st, int kind, double flops, int launches)
 {
     Prof &p = prof();
     if (!p.on) return;
@@ -62,7 +63,7 @@ void prof_end(hipStream_t st, int kind, double flops)
     hipEvent_t e = take_event(p);
     if (!e) return;
     (void)hipEventRecord(e, st);
-    p.recs.push_back({p.pending, e, kind, flops});
+    p.recs.push_back({p.pending, e, kind, flops, launches});
     p.pending = nullptr;
 }
 
@@ -98,7 +99,7 @@ int signtri_profile_read(int kind, double *ms, int64_t *launches, double *flops)
         if (hipEventElapsedTime(&x, r.a, r.b) != hipSuccess) return SIGNTRI_EHIP;
         t += x;
         f += r.flops;
-        ++c;
+        c += r.launches;
     }
     if (ms) *ms = t;
     if (launches) *launches = c;

@@ -543,7 +543,7 @@ size_t proj_workspace_bytes(int64_t n)
 }
 
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
-             int minority, int m, void *ws, hipStream_t st)
+             int minority, int m, double flops, void *ws, hipStream_t st)
 {
     if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
     const size_t nn = (size_t)n;
@@ -571,7 +571,7 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
                        ps1);
     const int64_t nt = (n + 31) / 32;
     hipLaunchKernelGGL(k_proj_flip, dim3(nt, nt), dim3(256), 0, st, T, ldt, F, n);
-    prof_end(st, PK_AUX, 0.0);
+    prof_end(st, PK_AUX, 0.0, 2);
 
     ProjArgs a;
     a.n = n;
@@ -581,16 +581,17 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     // blocks of PB rows from the bottom up; the top block may be short
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
-    for (int64_t r1 = n, p1 = n; r1 > 0;) {
+    int launches = 0;
+    for (int64_t r1 = n, p1 = n; r1 > 0; ++launches) {
         const int64_t r0 = std::max<int64_t>(0, r1 - PB);
         const int64_t nbulk = p1 > r1 ? 2 * ((r0 + 63) / 64) : 0;
         hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(256), 0, st, a, r0, r1, p1);
         p1 = r1;
         r1 = r0;
     }
-    // two bases, about n^2 m / 2 multiply-adds each
-    prof_end(st, PK_SYL, 2.0 * nd * nd * md);
+    prof_end(st, PK_PROJ, flops, launches);
     prof_begin(st);
+    // four launches: W^T Z partials, their sum, its inverse, A; then the product
     hipLaunchKernelGGL(k_proj_gram, dim3(nparts), dim3(256), 0, st, Z0, Z1, n, m, part);
     hipLaunchKernelGGL(k_proj_gsum, dim3(PM * PM / 64), dim3(64), 0, st, part, (int)nparts, m,
                        minv);
@@ -599,7 +600,8 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     const int64_t nu = (n + 63) / 64;
     hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, n, m,
                        minority > 0 ? -1.0 : 1.0, U, ldu);
-    prof_end(st, PK_GEMM, nd * nd * md);
+    // W^T Z and A = Z Minv (3 n m^2), the rank-m product on the upper triangle (n^2 m)
+    prof_end(st, PK_PROJ_OUT, nd * nd * md + 3.0 * nd * md * md, 5);
     return hipGetLastError() == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 }
 

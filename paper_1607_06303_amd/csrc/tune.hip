@@ -196,9 +196,9 @@ int signtri_autotune(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n
     best->mode = mode;
     best->path = info.path;
     best->log2n = size_class(n);
-    if (info.path == SIGNTRI_PATH_TRIVIAL) return hipStreamSynchronize(st) == hipSuccess
-                                                      ? SIGNTRI_OK
-                                                      : SIGNTRI_EHIP;
+    // nothing to choose on the trivial path and the projector form
+    if (info.path == SIGNTRI_PATH_TRIVIAL || info.path == SIGNTRI_PATH_PROJ)
+        return hipStreamSynchronize(st) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 
     std::vector<Candidate> cands;
     const bool cplx = dtype == SIGNTRI_C128;

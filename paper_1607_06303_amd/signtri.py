@@ -27,7 +27,8 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
            "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
-            "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10}
+            "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10, "proj": 11,
+            "proj_out": 12}
 
 
 class Info(ctypes.Structure):

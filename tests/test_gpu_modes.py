@@ -28,7 +28,7 @@ def test_mixed_refined_interleaved(dev, n):
 def test_mixed_refined_skewed(dev, n):
     rng = np.random.default_rng(6100 + n)
     s = wl.signs_with_negatives(n, 4, rng)
-    _, info, _ = check(wl.make_T(n, rng, signs=s), dev, mode="mixed")
+    _, info, _ = check(wl.make_T(n, rng, signs=s), dev, mode="mixed", algo="ph")
     assert info["path_name"] == "ph" and info["fallback_tiles"] == 0
     assert 0.0 < info["correction_rel"] < 1e-4
 

@@ -82,8 +82,12 @@ def test_complex_interleaved(dev, n):
 def test_skewed_few_negatives(dev, n, cplx):
     rng = np.random.default_rng(3000 + n)
     s = wl.signs_with_negatives(n, 5, rng)
-    _, info, _ = check(wl.make_T(n, rng, complex_=cplx, signs=s), dev)
+    T = wl.make_T(n, rng, complex_=cplx, signs=s)
+    _, info, _ = check(T, dev, algo="ph")
     assert info["path_name"] == "ph"
+    # AUTO: the projector form for real T (a small minority class), PH for complex
+    _, info, _ = check(T, dev)
+    assert info["path_name"] == ("ph" if cplx else "proj")
 
 
 @pytest.mark.parametrize("cplx", [False, True])
