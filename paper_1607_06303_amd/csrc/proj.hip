@@ -218,14 +218,19 @@ __device__ inline void add_acc(const ProjBasis &B, int64_t n, int m, int64_t row
 }
 
 // ---------------------------------------------------------------------------
-// Front: rows [r0, r1) of Z for both bases (blockIdx.x = basis).  Four waves;
-// column l is served by the four lanes 4 (l % 16) + q of wave l / 16, lane q
-// taking the terms 4 u + q (u = 0..15) of the two 64-term sums of every entry
-// (reduced over the four lanes by DPP), so that the LDS reads of one 16-lane
-// pass fall in distinct banks (pitches = 4 mod 16 doubles).  Column l's
-// coefficients L[4 u + q][l] stay in registers.
+// Front: rows [r0, r1) of Z for both bases (blockIdx.x = basis).  NQ lanes
+// per column: column l is served by lanes NQ (l % (64 / NQ)) + q of wave
+// l / (64 / NQ), lane q taking the terms NQ u + q of the two 64-term sums of
+// every entry (reduced over the NQ lanes by DPP), so that the LDS reads of one
+// 16-lane pass fall in distinct banks (pitch = NQ mod 16 doubles).  Column l's
+// coefficients L[NQ u + q][l] stay in registers.
 // ---------------------------------------------------------------------------
-constexpr int FP = PB + 4;  // LDS pitch of the staged T block and of the Z block
+constexpr int NQ = 8;          // lanes per column, each taking every NQ-th term
+constexpr int NU = PB / NQ;    // terms per lane
+constexpr int NTS = 64 * NQ;   // threads of a front workgroup (one column per NQ lanes)
+constexpr int NWS = NTS / 64;  // its waves
+constexpr int FP = PB + NQ;    // LDS pitch of the staged T block and of the Z block: one
+                               // 16-lane pass of a read falls in distinct banks
 
 //
 // One launch per block [r0, r1), with the block below it, [r1, p1), already
@@ -235,7 +240,7 @@ constexpr int FP = PB + 4;  // LDS pitch of the staged T block and of the Z bloc
 // Workgroups 2.. add the block below's contribution to every row above the
 // block, concurrently (the fronts read only the sums of rows [r0, r1)).  So
 // the sums of a block's rows hold every block below it when its front starts.
-__global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1)
+__global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1)
 {
     __shared__ double Tt[PB * FP];   // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
     __shared__ double Zr[PB * FP];   // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
@@ -251,14 +256,17 @@ __global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64
 
     if (blockIdx.x >= 2) {
         // rows [64 x, 64 x + 64) above the block, of one basis, times the block below
+        // (on the first four waves; the others only meet the barrier)
         const int bid = (int)blockIdx.x - 2;
         const ProjBasis B = a.b[bid & 1];
         const int64_t row0 = (int64_t)(bid >> 1) * 64;
-        stage_tz(B, n, m, row0, r0, r1, p1, Tt, Ab);
+        if (t < 256) stage_tz(B, n, m, row0, r0, r1, p1, Tt, Ab);
         __syncthreads();
-        dx4 d[2][2];
-        mm64(Tt, Ab, d);
-        add_acc(B, n, m, row0, r0, d);
+        if (t < 256) {
+            dx4 d[2][2];
+            mm64(Tt, Ab, d);
+            add_acc(B, n, m, row0, r0, d);
+        }
         return;
     }
 
@@ -269,18 +277,19 @@ __global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64
     {
         const int row = t & 63, c0 = t >> 6;
         const int nk = (int)(p1 - r1);
-        double tv[16], av[16], pv[16], zv[16];
+        constexpr int NK = 64 / NWS;
+        double tv[NK], av[NK], pv[NK], zv[NK];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int c = c0 + 4 * k;
+        for (int k = 0; k < NK; ++k) {
+            const int c = c0 + NWS * k;
             tv[k] = (row < nr && c < nr && row <= c) ? B.T[(r0 + row) + (r0 + c) * B.ldt] : 0.0;
             av[k] = (row < nr && c < m) ? B.acc[(r0 + row) + (int64_t)c * n] : 0.0;
             pv[k] = (row < nr && c < nk) ? B.T[(r0 + row) + (r1 + c) * B.ldt] : 0.0;
             zv[k] = (row < nk && c < m) ? B.Z[(r1 + row) + (int64_t)c * n] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int c = c0 + 4 * k;
+        for (int k = 0; k < NK; ++k) {
+            const int c = c0 + NWS * k;
             Tt[row * FP + c] = tv[k];
             Ab[row * AP + c] = av[k];
             Zr[c * FP + row] = pv[k];  // k-major: Zr[k * FP + r] = T[r0 + r, r1 + k]
@@ -288,33 +297,35 @@ __global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64
         }
         if (t < PB) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
     }
-    const int col = (t >> 6) * 16 + ((t & 63) >> 2);
-    const int q = t & 3;
-    double lreg[16];
+    const int col = (t >> 6) * (64 / NQ) + ((t & 63) / NQ);
+    const int q = t % NQ;
+    double lreg[NU];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) lreg[u] = B.lam[(4 * u + q) * PM + col];
+    for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
     double lamll = B.lam[col * PM + col];
     const int pl = col < m ? B.pos[col] : -1;
     __syncthreads();
     if (below) {
-        dx4 d[2][2];
-        mm64_acc_zero(d);
-        mm64_acc<FP, FP>(Zr, Zc, d);
-        const int lane = t & 63, w = t >> 6;
-        const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+        if (t < 256) {  // the product runs on four waves
+            dx4 d[2][2];
+            mm64_acc_zero(d);
+            mm64_acc<FP, FP>(Zr, Zc, d);
+            const int lane = t & 63, w = t >> 6;
+            const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < 2; ++y)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = rb + 16 * x + mfma64_row(lane, e);
-                    const int c = cb + 16 * y + (lane & 15);
-                    Ab[r * AP + c] += d[x][y][e];
-                }
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = rb + 16 * x + mfma64_row(lane, e);
+                        const int c = cb + 16 * y + (lane & 15);
+                        Ab[r * AP + c] += d[x][y][e];
+                    }
+        }
         __syncthreads();
     }
-    for (int e = t; e < PB * FP; e += 256) {
+    for (int e = t; e < PB * FP; e += NTS) {
         Zr[e] = 0.0;
         Zc[e] = 0.0;
     }
@@ -334,37 +345,37 @@ __global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64
             // lower triangle of the staged block, entries of Z not computed yet).
             // all operands first (paired LDS reads), then the multiply-adds
             const double *zcol = Zc + col * FP;
-            double tv[16], zv[16], rv[16];
+            double tv[NU], zv[NU], rv[NU];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                tv[u] = trow[4 * u + q];
-                zv[u] = zcol[4 * u + q];
-                rv[u] = zrow[4 * u + q];
+            for (int u = 0; u < NU; ++u) {
+                tv[u] = trow[NQ * u + q];
+                zv[u] = zcol[NQ * u + q];
+                rv[u] = zrow[NQ * u + q];
             }
             double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
 #pragma unroll
-            for (int u = 0; u < 16; u += 2) {
+            for (int u = 0; u < NU; u += 2) {
                 v0 += tv[u] * zv[u];
                 v1 += tv[u + 1] * zv[u + 1];
                 c0 += rv[u] * lreg[u];
                 c1 += rv[u + 1] * lreg[u + 1];
             }
-            const double v = group_sum<4>(v0 + v1);
-            const double cpl = group_sum<4>(c0 + c1);
+            const double v = group_sum<NQ>(v0 + v1);
+            const double cpl = group_sum<NQ>(c0 + c1);
             const int typ = rt[r];
             double z;
             if (i == pl) {
                 z = 1.0;
                 lamll = tii;
 #pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (4 * u + q == col) lreg[u] = tii;
+                for (int u = 0; u < NU; ++u)
+                    if (NQ * u + q == col) lreg[u] = tii;
             } else if (typ >= 0) {
                 // minority row b_typ (typ < l): row typ of L
                 z = 0.0;
 #pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (4 * u + q == typ) lreg[u] = v;
+                for (int u = 0; u < NU; ++u)
+                    if (NQ * u + q == typ) lreg[u] = v;
             } else {
                 z = (cpl - v) * rcp;
             }
@@ -379,11 +390,11 @@ __global__ __launch_bounds__(256) void k_proj_step(ProjArgs a, int64_t r0, int64
     // ---- publish the rows and L
     {
         const int row = t & 63;
-        for (int c = t >> 6; c < m; c += 4)
+        for (int c = t >> 6; c < m; c += NWS)
             if (row < nr) B.Z[(r0 + row) + (int64_t)c * n] = Zr[row * FP + c];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) B.lam[(4 * u + q) * PM + col] = lreg[u];
+    for (int u = 0; u < NU; ++u) B.lam[(NQ * u + q) * PM + col] = lreg[u];
 
 }
 
@@ -585,7 +596,7 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     for (int64_t r1 = n, p1 = n; r1 > 0; ++launches) {
         const int64_t r0 = std::max<int64_t>(0, r1 - PB);
         const int64_t nbulk = p1 > r1 ? 2 * ((r0 + 63) / 64) : 0;
-        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(256), 0, st, a, r0, r1, p1);
+        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(NTS), 0, st, a, r0, r1, p1);
         p1 = r1;
         r1 = r0;
     }
