@@ -360,8 +360,10 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 c0 += rv[u] * lreg[u];
                 c1 += rv[u + 1] * lreg[u + 1];
             }
-            const double v = group_sum<NQ>(v0 + v1);
-            const double cpl = group_sum<NQ>(c0 + c1);
+            // one reduction: d = coupling - sum.  At a minority row the coupling is
+            // zero (L's row typ is not set yet and the row of Z is e_typ), so
+            // there d = -sum.
+            const double d = group_sum<NQ>((c0 + c1) - (v0 + v1));
             const int typ = rt[r];
             double z;
             if (i == pl) {
@@ -375,9 +377,9 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 z = 0.0;
 #pragma unroll
                 for (int u = 0; u < NU; ++u)
-                    if (NQ * u + q == typ) lreg[u] = v;
+                    if (NQ * u + q == typ) lreg[u] = -d;
             } else {
-                z = (cpl - v) * rcp;
+                z = d * rcp;
             }
             if (q == 0) {
                 Zr[r * FP + col] = z;
