@@ -495,13 +495,19 @@ __global__ __launch_bounds__(256) void k_proj_a(const double *__restrict__ Z,
 
 // U[i, j] = s (delta_ij - 2 sum_l A[i, l] W[j, l]) for i <= j, 0 for i > j.
 // Computed as the transpose product C[j][i] = sum_l W[j, l] A[i, l], so that
-// the accumulator's lane index runs down a column of U.
+// the accumulator's lane index runs down a column of U.  A[i, l] is zero for
+// i > b_l and W[j, l] for j < b_l, and the columns are ordered by b_l: a tile
+// with rows [i0, i0 + 64) and columns [j0, j0 + 64) takes only the columns l
+// with i0 <= b_l < j0 + 64, in chunks of 16.
+constexpr int UK = 16;
+
 __global__ __launch_bounds__(256) void k_proj_u(const double *__restrict__ A,
-                                                const double *__restrict__ Zf, int64_t n, int m,
+                                                const double *__restrict__ Zf,
+                                                const int *__restrict__ pos, int64_t n, int m,
                                                 double smaj, double *__restrict__ U, int64_t ldu)
 {
-    __shared__ double Ws[64 * OP];  // Ws[l * OP + jj] = W[j0 + jj, l]
-    __shared__ double As[64 * OP];  // As[l * OP + ii] = A[i0 + ii, l]
+    __shared__ double Ws[UK * OP];  // Ws[k * OP + jj] = W[j0 + jj, l0 + k]
+    __shared__ double As[UK * OP];  // As[k * OP + ii] = A[i0 + ii, l0 + k]
     const int64_t ti = blockIdx.x, tj = blockIdx.y;
     const int64_t i0 = ti * 64, j0 = tj * 64;
     const int t = threadIdx.x, lr = t & 63, q = t >> 6;
@@ -512,16 +518,42 @@ __global__ __launch_bounds__(256) void k_proj_u(const double *__restrict__ A,
         }
         return;
     }
-    for (int l = q; l < 64; l += 4) {
-        const int64_t j = j0 + lr, i = i0 + lr;
-        Ws[l * OP + lr] = (j < n && l < m) ? Zf[(n - 1 - j) + (int64_t)(m - 1 - l) * n] : 0.0;
-        As[l * OP + lr] = (i < n && l < m) ? A[i + (int64_t)l * n] : 0.0;
+    // the contributing columns [lo, hi)
+    int lo = 0, hi = 0;
+    for (int l = 0; l < m; ++l) {
+        const int64_t b = pos[l];
+        lo += b < i0;
+        hi += b < j0 + 64;
     }
-    __syncthreads();
+    lo = uniform(lo);
+    hi = uniform(hi);
     dx4 d[2][2];
-    mm64(Ws, As, d);  // d[jj][ii]
+    mm64_acc_zero(d);
     const int lane = t & 63, w = t >> 6;
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    const int kr = lane >> 4, cc = lane & 15;
+    for (int l0 = lo; l0 < hi; l0 += UK) {
+        for (int k = q; k < UK; k += 4) {
+            const int l = l0 + k;
+            const int64_t j = j0 + lr, i = i0 + lr;
+            Ws[k * OP + lr] = (j < n && l < hi) ? Zf[(n - 1 - j) + (int64_t)(m - 1 - l) * n] : 0.0;
+            As[k * OP + lr] = (i < n && l < hi) ? A[i + (int64_t)l * n] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < UK; k += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) av[x] = Ws[(k + kr) * OP + rb + 16 * x + cc];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) bv[y] = As[(k + kr) * OP + cb + 16 * y + cc];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) d[x][y] = mfma_f64(av[x], bv[y], d[x][y]);
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -611,7 +643,7 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     hipLaunchKernelGGL(k_proj_minv, dim3(1), dim3(256), 0, st, minv, minv);
     hipLaunchKernelGGL(k_proj_a, dim3((n + 3) / 4), dim3(256), 0, st, Z0, minv, n, m, A);
     const int64_t nu = (n + 63) / 64;
-    hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, n, m,
+    hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, ps0, n, m,
                        minority > 0 ? -1.0 : 1.0, U, ldu);
     // W^T Z and A = Z Minv (3 n m^2), the rank-m product on the upper triangle (n^2 m)
     prof_end(st, PK_PROJ_OUT, nd * nd * md + 3.0 * nd * md * md, 5);
