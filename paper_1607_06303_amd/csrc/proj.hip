@@ -27,10 +27,10 @@
 //   z_il = (sum_{l'<l} z_il' L[l', l] - sum_{j>i} t_ij z_jl) / (t_ii - L[l, l]).
 // The divisions are by differences of eigenvalues of opposite sign, the same
 // divisions as Eq. (1).  W is Z of the flipped matrix J T^T J (J the reversal),
-// which is upper triangular with the same diagonal in reverse order.
+// which is upper triangular with the same diagonal in reverse order; it is
+// read from T through the reversal, not copied.
 //
 // Kernels:
-//   k_proj_flip    J T^T J, the upper triangle, as a column-major copy;
 //   k_proj_prep    minority rows and row types of both bases, from the signs;
 //   k_proj_step    one launch per block of 64 rows, bottom up: a workgroup
 //                  per basis runs the substitution above as a wavefront
@@ -56,8 +56,9 @@ constexpr int PB = 64;                // rows per front block
 constexpr int AP = PM + 1;            // LDS pitch of the accumulated sums
 
 struct ProjBasis {
-    const double *T;      // upper-triangular matrix of this basis (column-major)
+    const double *T;      // T (column-major); the left basis reads it as J T^T J
     int64_t ldt;
+    int flip;             // 1: entry (i, j) of this basis's matrix is T[n-1-j, n-1-i]
     double *Z;            // n x PM, leading dimension n
     double *acc;          // n x PM: sum over the rows below the current block
     double *lam;          // PM x PM, lam[lp * PM + l] = L[lp][l]
@@ -71,32 +72,10 @@ struct ProjArgs {
     int m;
 };
 
-// ---------------------------------------------------------------------------
-// Flipped copy F = J T^T J: F[i, j] = T[n-1-j, n-1-i], upper triangle only.
-// 32 x 32 tiles through LDS so that both the reads and the writes are
-// coalesced down columns.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_proj_flip(const double *__restrict__ T, int64_t ldt,
-                                                   double *__restrict__ F, int64_t n)
+// Offset of entry (i, j) of a basis's matrix in T: T itself, or J T^T J.
+__device__ inline int64_t toff(const ProjBasis &B, int64_t n, int64_t i, int64_t j)
 {
-    __shared__ double tile[32][33];
-    const int64_t ti = blockIdx.x, tj = blockIdx.y;  // tile of F
-    if (ti > tj) return;
-    const int64_t i0 = ti * 32, j0 = tj * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    // F[i0 + a, j0 + b] = T[n-1-j0-b, n-1-i0-a]; read T down its columns
-    for (int y = ty; y < 32; y += 8) {
-        const int64_t b = 31 - tx, a = y;      // T row n-1-j0-b, T column n-1-i0-a
-        const int64_t tr = n - 1 - j0 - b, tc = n - 1 - i0 - a;
-        double v = 0.0;
-        if (tr >= 0 && tc >= 0 && tr < n && tc < n) v = T[tr + tc * ldt];
-        tile[a][b] = v;
-    }
-    __syncthreads();
-    for (int y = ty; y < 32; y += 8) {
-        const int64_t i = i0 + tx, j = j0 + y;
-        if (i < n && j < n && i <= j) F[i + j * n] = tile[tx][y];
-    }
+    return B.flip ? (n - 1 - j) + (n - 1 - i) * B.ldt : i + j * B.ldt;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,10 +170,16 @@ __device__ inline void stage_tz(const ProjBasis &B, int64_t n, int m, int64_t ro
 {
     const int t = threadIdx.x, lr = t & 63;
     const int nk = (int)(k1 - k0);
-    // As down T's columns, Bs down Z's columns (lr = k), both coalesced
+    // As down the matrix's columns (in J T^T J: along T's columns, lane = k),
+    // Bs down Z's columns (lane = k): all coalesced
     for (int k = t >> 6; k < 64; k += 4) {
-        const int64_t row = row0 + lr;
-        As[k * OP + lr] = (k < nk && row < rlim) ? B.T[row + (k0 + k) * B.ldt] : 0.0;
+        if (B.flip) {
+            const int64_t row = row0 + k;
+            As[lr * OP + k] = (lr < nk && row < rlim) ? B.T[toff(B, n, row, k0 + lr)] : 0.0;
+        } else {
+            const int64_t row = row0 + lr;
+            As[k * OP + lr] = (k < nk && row < rlim) ? B.T[toff(B, n, row, k0 + k)] : 0.0;
+        }
         if (Bs) Bs[lr * OP + k] = (lr < nk && k < m) ? B.Z[(k0 + lr) + (int64_t)k * n] : 0.0;
     }
 }
@@ -278,21 +263,25 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
         const int row = t & 63, c0 = t >> 6;
         const int nk = (int)(p1 - r1);
         constexpr int NK = 64 / NWS;
+        // (in J T^T J the lane runs along the block's columns, which are T's rows)
+        const bool fl = B.flip != 0;
         double tv[NK], av[NK], pv[NK], zv[NK];
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int c = c0 + NWS * k;
-            tv[k] = (row < nr && c < nr && row <= c) ? B.T[(r0 + row) + (r0 + c) * B.ldt] : 0.0;
+            const int tr = fl ? c : row, tc = fl ? row : c;  // block row and column
+            tv[k] = (tr < nr && tc < nr && tr <= tc) ? B.T[toff(B, n, r0 + tr, r0 + tc)] : 0.0;
+            pv[k] = (tr < nr && tc < nk) ? B.T[toff(B, n, r0 + tr, r1 + tc)] : 0.0;
             av[k] = (row < nr && c < m) ? B.acc[(r0 + row) + (int64_t)c * n] : 0.0;
-            pv[k] = (row < nr && c < nk) ? B.T[(r0 + row) + (r1 + c) * B.ldt] : 0.0;
             zv[k] = (row < nk && c < m) ? B.Z[(r1 + row) + (int64_t)c * n] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int c = c0 + NWS * k;
-            Tt[row * FP + c] = tv[k];
+            const int tr = fl ? c : row, tc = fl ? row : c;
+            Tt[tr * FP + tc] = tv[k];
+            Zr[tc * FP + tr] = pv[k];  // k-major: Zr[k * FP + r] = T[r0 + r, r1 + k]
             Ab[row * AP + c] = av[k];
-            Zr[c * FP + row] = pv[k];  // k-major: Zr[k * FP + r] = T[r0 + r, r1 + k]
             Zc[row * FP + c] = zv[k];  // k-major: Zc[k * FP + l] = Z[r1 + k, l]
         }
         if (t < PB) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
@@ -578,8 +567,7 @@ size_t proj_workspace_bytes(int64_t n)
 {
     const size_t nn = (size_t)n;
     const size_t nparts = (nn + 63) / 64;
-    return al(nn * nn * 8)                  // flipped T
-           + 4 * al(nn * PM * 8)            // Z and acc, two bases
+    return 4 * al(nn * PM * 8)              // Z and acc, two bases
            + 2 * al(PM * PM * 8)            // L, two bases
            + 2 * al(nn * 4) + 2 * al(PM * 4)  // row types and minority rows
            + al(nparts * PM * PM * 8)       // partial Gram matrices
@@ -599,7 +587,6 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
         p += al(bytes);
         return (void *)q;
     };
-    double *F = (double *)take(nn * nn * 8);
     double *Z0 = (double *)take(nn * PM * 8), *Z1 = (double *)take(nn * PM * 8);
     double *C0 = (double *)take(nn * PM * 8), *C1 = (double *)take(nn * PM * 8);
     double *L0 = (double *)take(PM * PM * 8), *L1 = (double *)take(PM * PM * 8);
@@ -614,15 +601,13 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     prof_begin(st);
     hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
                        ps1);
-    const int64_t nt = (n + 31) / 32;
-    hipLaunchKernelGGL(k_proj_flip, dim3(nt, nt), dim3(256), 0, st, T, ldt, F, n);
-    prof_end(st, PK_AUX, 0.0, 2);
+    prof_end(st, PK_AUX, 0.0, 1);
 
     ProjArgs a;
     a.n = n;
     a.m = m;
-    a.b[0] = ProjBasis{T, ldt, Z0, C0, L0, rt0, ps0};
-    a.b[1] = ProjBasis{F, n, Z1, C1, L1, rt1, ps1};
+    a.b[0] = ProjBasis{T, ldt, 0, Z0, C0, L0, rt0, ps0};
+    a.b[1] = ProjBasis{T, ldt, 1, Z1, C1, L1, rt1, ps1};
     // blocks of PB rows from the bottom up; the top block may be short
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
