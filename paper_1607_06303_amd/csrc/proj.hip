@@ -256,6 +256,16 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     }
 
     const ProjBasis B = a.b[blockIdx.x];
+    const int col = (t >> 6) * (64 / NQ) + ((t & 63) / NQ);
+    const int q = t % NQ;
+    // column l's coefficients, its minority row and the block's row types: loaded
+    // first, so that their latency overlaps the staging below
+    double lreg[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
+    double lamll = B.lam[col * PM + col];
+    const int pl = col < m ? B.pos[col] : -1;
+    const int rtv = t < nr ? B.rowtype[r0 + t] : -1;
 
     // ---- stage the block's operands and the block below's (64 consecutive rows
     // per wave, coalesced; every load issued before the first store)
@@ -284,15 +294,8 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             Ab[row * AP + c] = av[k];
             Zc[row * FP + c] = zv[k];  // k-major: Zc[k * FP + l] = Z[r1 + k, l]
         }
-        if (t < PB) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
+        if (t < PB) rt[t] = rtv;
     }
-    const int col = (t >> 6) * (64 / NQ) + ((t & 63) / NQ);
-    const int q = t % NQ;
-    double lreg[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
-    double lamll = B.lam[col * PM + col];
-    const int pl = col < m ? B.pos[col] : -1;
     __syncthreads();
     if (below) {
         if (t < 256) {  // the product runs on four waves
