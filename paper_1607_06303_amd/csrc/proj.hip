@@ -433,10 +433,18 @@ __global__ __launch_bounds__(64) void k_proj_gsum(const double *__restrict__ par
     const int e = blockIdx.x * 64 + threadIdx.x;
     const int r = e / PM, c = e % PM;
     double s = 0.0;
-    if (r < m && c < m)
-        for (int g = 0; g < nparts; ++g) s += part[(int64_t)g * PM * PM + e];
-    else
+    if (r < m && c < m) {
+        // eight independent partial sums, so that the loads are issued ahead
+        double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int g = 0;
+        for (; g + 8 <= nparts; g += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) p[k] += part[(int64_t)(g + k) * PM * PM + e];
+        for (; g < nparts; ++g) p[0] += part[(int64_t)g * PM * PM + e];
+        s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    } else {
         s = r == c ? 1.0 : 0.0;
+    }
     M[e] = s;
 }
 

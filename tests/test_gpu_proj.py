@@ -132,3 +132,44 @@ def test_proj_unsupported(dev):
     # all one sign: the trivial path, whatever the algorithm asked for
     U, info = run_gpu(wl.make_T(40, wl.rng_for(1, salt=4), signs=np.ones(40)), dev, algo="proj")
     assert info["path_name"] == "trivial" and np.array_equal(U, np.eye(40))
+
+
+def test_proj_padded_and_workspace(dev):
+    """Padded leading dimensions of T and U (the padding rows of U untouched), and a
+    caller workspace of exactly the size the library asks for (smaller: an error)."""
+    import torch
+
+    import oracle
+    from paper_1607_06303_amd import signtri
+
+    n, ld = 230, 257
+    T = skewed(n, 11, 41)
+    G = T + np.tril(np.full_like(T, 1e300), -1)
+    Tg = to_dev_colmajor(G, dev, ld=ld)
+    Ubuf = torch.full((n, ld), 7.0, dtype=torch.float64, device=dev)  # column-major ld x n
+    U = Ubuf.t()[:n, :]
+    _, info = signtri.sign_tri(Tg, out=U, algo="proj")
+    torch.cuda.synchronize()
+    assert info["path_name"] == "proj"
+    full = Ubuf.cpu().numpy().T
+    assert np.all(full[n:, :] == 7.0), "padding rows must be untouched"
+    assert rel_fro(full[:n, :], oracle.sign_tri(T)) <= TOL_FP64
+    need = signtri.workspace_size(n, algo="proj")
+    small = torch.empty(need - 256, dtype=torch.uint8, device=dev)
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri(to_dev_colmajor(T, dev), workspace=small, algo="proj")
+    assert ei.value.code == 3
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    U2, _ = signtri.sign_tri(to_dev_colmajor(T, dev), workspace=ws, algo="proj")
+    torch.cuda.synchronize()
+    assert rel_fro(U2.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+@pytest.mark.parametrize("where", [[0], [99], [1, 98]])
+def test_proj_minority_at_the_ends(dev, where):
+    import oracle
+
+    T = skewed(100, len(where), 50 + where[0], where=where)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj"
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
