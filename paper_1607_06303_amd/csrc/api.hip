@@ -557,7 +557,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
                 const double b = (double)i, f = (double)(n - 1 - i);
                 flops += b * b + f * f;
             }
-        if (run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, p.min_sign,
+        if (run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, hs, p.min_sign,
                      (int)p.n_min, flops, ws + L0.prefix, st) != SIGNTRI_OK)
             return SIGNTRI_EHIP;
         if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)

@@ -225,7 +225,11 @@ constexpr int FP = PB + NQ;    // LDS pitch of the staged T block and of the Z b
 // Workgroups 2.. add the block below's contribution to every row above the
 // block, concurrently (the fronts read only the sums of rows [r0, r1)).  So
 // the sums of a block's rows hold every block below it when its front starts.
-__global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1)
+// lmin0, lmin1: per basis, the minority columns whose row lies above the block
+// (b_l < r0): they stay zero throughout it, and the wavefront starts at the
+// first column after them.
+__global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1,
+                                                   int lmin0, int lmin1)
 {
     __shared__ double Tt[PB * FP];   // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
     __shared__ double Zr[PB * FP];   // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
@@ -324,9 +328,10 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     __syncthreads();
 
     // ---- wavefront: column l handles block row nr - 1 - s + l at step s
-    const int steps = uniform(nr + m - 1);
+    const int lmin = uniform(blockIdx.x == 0 ? lmin0 : lmin1);
+    const int steps = uniform(m > lmin ? nr + (m - lmin) - 1 : 0);
     for (int s = 0; s < steps; ++s) {
-        const int r = nr - 1 - s + col;
+        const int r = nr - 1 - s + (col - lmin);
         const int64_t i = r0 + r;
         if (col < m && r >= 0 && r < nr && i <= pl) {
             const double *trow = Tt + r * FP;
@@ -587,9 +592,15 @@ size_t proj_workspace_bytes(int64_t n)
 }
 
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
-             int minority, int m, double flops, void *ws, hipStream_t st)
+             const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st)
 {
     if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
+    // the minority rows on the host (ascending), for the first active column of each block
+    std::vector<int64_t> mrow;
+    mrow.reserve(m);
+    for (int64_t i = 0; i < n; ++i)
+        if (hsgn[i] == minority) mrow.push_back(i);
+    if ((int)mrow.size() != m) return SIGNTRI_ENOTSUP;
     const size_t nn = (size_t)n;
     const int64_t nparts = (n + 63) / 64;
     char *p = (char *)ws;
@@ -626,7 +637,12 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     for (int64_t r1 = n, p1 = n; r1 > 0; ++launches) {
         const int64_t r0 = std::max<int64_t>(0, r1 - PB);
         const int64_t nbulk = p1 > r1 ? 2 * ((r0 + 63) / 64) : 0;
-        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(NTS), 0, st, a, r0, r1, p1);
+        // basis 0: columns with b_l < r0; basis 1 (rows n-1-b_l): those with b_l > n-1-r0
+        const int lmin0 = (int)(std::lower_bound(mrow.begin(), mrow.end(), r0) - mrow.begin());
+        const int lmin1 =
+            (int)(mrow.end() - std::upper_bound(mrow.begin(), mrow.end(), n - 1 - r0));
+        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(NTS), 0, st, a, r0, r1, p1, lmin0,
+                           lmin1);
         p1 = r1;
         r1 = r0;
     }
