@@ -173,3 +173,44 @@ def test_proj_minority_at_the_ends(dev, where):
     U, info = run_gpu(T, dev, algo="proj")
     assert info["path_name"] == "proj"
     assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_proj_near_zero_diagonal(dev):
+    """Real diagonal magnitudes down to 1e-3 on both sides of the imaginary axis: the
+    substitutions divide by differences as small as 2e-3 (as Eq. (1) does)."""
+    import oracle
+
+    rng = wl.rng_for(5, salt=21)
+    s = np.ones(400)
+    s[rng.choice(400, 10, replace=False)] = -1
+    T = wl.make_T(400, rng, signs=s, re_range=(1e-3, 1.0))
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj"
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_proj_full_size_positive_minority(dev):
+    """n = 4096 with 40 positive entries (majority sign -1), through AUTO: invariants at
+    full size, leading, trailing and interior principal blocks against the oracle."""
+    import torch
+
+    import oracle
+
+    T = skewed(4096, 40, 77, minority=1)
+    Tg = to_dev_colmajor(T, dev)
+    from paper_1607_06303_amd import signtri
+
+    U, info = signtri.sign_tri(Tg)
+    torch.cuda.synchronize()
+    assert info["path_name"] == "proj"
+    Ut = U.contiguous()
+    Tt = torch.triu(Tg.contiguous())
+    nu = torch.linalg.norm(Ut).item()
+    eye = torch.eye(4096, dtype=Ut.dtype, device=Ut.device)
+    assert torch.linalg.norm(Ut @ Ut - eye).item() / (nu * nu) <= 1e-13
+    com = torch.linalg.norm(Tt @ Ut - Ut @ Tt).item() / (torch.linalg.norm(Tt).item() * nu)
+    assert com <= 1e-13
+    Uh = U.cpu().numpy()
+    for a in (0, 1500, 4096 - 600):
+        ref = oracle.sign_tri(T[a:a + 600, a:a + 600])
+        assert rel_fro(Uh[a:a + 600, a:a + 600], ref) <= TOL_FP64, a
