@@ -337,7 +337,12 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             const double *trow = Tt + r * FP;
             const double *zrow = Zr + r * FP;
             const double tii = trow[r];
-            const double rcp = 1.0 / (tii - lamll);  // used only where lamll is set
+            // 1 / (t_ii - L[l, l]): the hardware estimate and two Newton steps
+            // (used only where lamll is set)
+            const double dx = tii - lamll;
+            double rcp = __builtin_amdgcn_rcp(dx);
+            rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
+            rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
             // Full sums: every term outside the ranges that count is zero (the
             // lower triangle of the staged block, entries of Z not computed yet).
             // all operands first (paired LDS reads), then the multiply-adds
