@@ -70,8 +70,8 @@ typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } s
  *   and a transformation back).  Computed here without reordering: the right
  *   and left invariant subspaces of the minority sign class, each from a
  *   triangular substitution, give the spectral projector P of that class, and
- *   U = s (I - 2 P) with s the majority sign.  Real T in FP64 (every mode runs
- *   it in FP64), at most 64 entries in the minority class.
+ *   U = s (I - 2 P) with s the majority sign.  Real or complex T, in FP64 (every
+ *   mode runs it in FP64), at most 64 entries in the minority class.
  * AUTO picks by work estimates: PS when the diagonal is grouped and the
  *   Section 3 model favours it; in FP64 mode with no sweep or block size pinned
  *   in the options, PROJ when the minority class is small (real T, 1..64
@@ -155,8 +155,8 @@ typedef struct {
  *   layout      storage order of both T and U
  *   mode        SIGNTRI_FP64, SIGNTRI_MIXED_REFINED or SIGNTRI_FP32
  *   algo        SIGNTRI_AUTO, SIGNTRI_PH, SIGNTRI_PS or SIGNTRI_PROJ (PS requires a
- *               real T whose diagonal is already grouped by sign; PROJ a real T with
- *               1..64 entries in its minority sign class; else SIGNTRI_ENOTSUP)
+ *               diagonal already grouped by sign; PROJ 1..64 entries in the minority
+ *               sign class; else SIGNTRI_ENOTSUP)
  *   Complex T supports mode SIGNTRI_FP64 only in this build (else SIGNTRI_ENOTSUP).
  *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
  *               use a buffer it allocates and keeps for later calls

@@ -79,9 +79,9 @@ size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_
         m = std::max(m, layout_for(n, dtype, layout, mode, 32, false).total);
         if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, layout, mode, 64, false).total);
     }
-    if (dtype == SIGNTRI_R64 && (algo == SIGNTRI_AUTO || algo == SIGNTRI_PROJ))
+    if (algo == SIGNTRI_AUTO || algo == SIGNTRI_PROJ)
         m = std::max(m, layout_for(n, dtype, layout, mode, 32, true).prefix +
-                            align_up(proj_workspace_bytes(n)));
+                            align_up(proj_workspace_bytes(n, dtype == SIGNTRI_C128)));
     return m;
 }
 
@@ -543,7 +543,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         path = SIGNTRI_PATH_PS;
     }
     if (algo == SIGNTRI_PROJ && path != SIGNTRI_PATH_TRIVIAL) {
-        if (cplx || p.n_min < 1 || p.n_min > kProjMaxMinority) return SIGNTRI_ENOTSUP;
+        if (p.n_min < 1 || p.n_min > kProjMaxMinority) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PROJ;
     }
     if (path == SIGNTRI_PATH_PROJ) {
@@ -557,9 +557,11 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
                 const double b = (double)i, f = (double)(n - 1 - i);
                 flops += b * b + f * f;
             }
-        if (run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, hs, p.min_sign,
-                     (int)p.n_min, flops, ws + L0.prefix, st) != SIGNTRI_OK)
-            return SIGNTRI_EHIP;
+        const int prc = cplx ? run_proj_c(Tc, ldtc, Uc, lduc, n, sgn, hs, p.min_sign,
+                                          (int)p.n_min, 4.0 * flops, ws + L0.prefix, st)
+                             : run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, hs,
+                                        p.min_sign, (int)p.n_min, flops, ws + L0.prefix, st);
+        if (prc != SIGNTRI_OK) return SIGNTRI_EHIP;
         if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
             return SIGNTRI_EHIP;
         if (info) {

@@ -324,13 +324,16 @@ constexpr int kFlowTile = 32;
 // diagonal with at most kProjMaxMinority entries in its minority sign class.
 // ---------------------------------------------------------------------------
 constexpr int kProjMaxMinority = 64;
-size_t proj_workspace_bytes(int64_t n);
+size_t proj_workspace_bytes(int64_t n, bool cplx);
 // T, U column-major real; sgn the device sign vector; minority = its sign (+1/-1),
 // m = its count.  Queues every launch on st.
 // flops: algorithmic flops of the two substitutions, for the kernel timers.
 // hsgn: the same signs on the host.
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
              const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st);
+// The same for complex T (interleaved complex128).
+int run_proj_c(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, const int8_t *sgn,
+               const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st);
 enum FlowKind { FLOW_MAIN = 0, FLOW_CORR = 1, FLOW_SYL = 2 };
 
 // One real triangular system of a sweep; column-major device arrays.

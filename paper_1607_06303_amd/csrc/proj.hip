@@ -44,6 +44,7 @@
 //   k_proj_u       U = s (I - 2 A W^T) on the upper triangle, zeros below
 //                  (FP64 MFMA, 64 x 64 output tiles).
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -582,18 +583,381 @@ __global__ __launch_bounds__(256) void k_proj_u(const double *__restrict__ A,
 
 inline size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+
+// ===========================================================================
+// Complex T.  The same form with transposes (not conjugate transposes): the
+// left basis solves W^T T = L' W^T, i.e. it is the right basis of J T^T J, and
+// P = Z (W^T Z)^-1 W^T.  Simpler kernels than the real ones: 32-row blocks (the
+// complex operands of a block fit in LDS), four lanes per column, a separate
+// update launch per block, and plain FMA products.
+// ===========================================================================
+constexpr int PBC = 32;          // rows per block
+constexpr int TPC = PBC + 1;     // LDS pitch of the staged block and the column copy
+constexpr int ZPC = PM + 1;      // LDS pitch of the Z rows and the running sums
+
+struct CBasis {
+    const cd *T;
+    int64_t ldt;
+    int flip;             // 1: entry (i, j) of this basis's matrix is T[n-1-j, n-1-i]
+    cd *Z;                // n x PM, leading dimension n
+    cd *acc;              // n x PM: sum over the rows below the current block
+    cd *lam;              // PM x PM, lam[lp * PM + l] = L[lp][l]
+    const int *rowtype;
+    const int *pos;
+};
+
+struct CArgs {
+    CBasis b[2];
+    int64_t n;
+    int m;
+};
+
+__device__ inline int64_t ctoff(const CBasis &B, int64_t n, int64_t i, int64_t j)
+{
+    return B.flip ? (n - 1 - j) + (n - 1 - i) * B.ldt : i + j * B.ldt;
+}
+
+__device__ inline cd cfma(cd a, cd b, cd c)
+{
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+
+// Front of one 32-row block [r0, r1) for both bases (blockIdx.x = basis): column
+// l handles block row r1 - 1 - s + (l - lmin) at step s, four lanes per column
+// each taking every fourth term of the block-row sum (32 terms) and of the L
+// coupling (64 terms).
+__global__ __launch_bounds__(256) void k_projc_front(CArgs a, int64_t r0, int64_t r1, int lmin0,
+                                                     int lmin1)
+{
+    __shared__ cd Tt[PBC * TPC];  // Tt[r * TPC + c] = T[r0 + r, r0 + c], zero below the diagonal
+    __shared__ cd Zr[PBC * ZPC];  // Zr[r * ZPC + l] = Z[r0 + r, l] (zero until computed)
+    __shared__ cd Zc[PM * TPC];   // Zc[l * TPC + r]: the same values by column
+    __shared__ cd Ab[PBC * ZPC];  // Ab[r * ZPC + l] = acc[r0 + r, l]
+    __shared__ int rt[PBC];
+    const CBasis B = a.b[blockIdx.x];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int t = threadIdx.x;
+    const int nr = (int)(r1 - r0);
+    const cd zero = {0.0, 0.0};
+    for (int e = t; e < PBC * PBC; e += 256) {
+        const int r = e % PBC, c = e / PBC;
+        Tt[r * TPC + c] = (r < nr && c < nr && r <= c) ? B.T[ctoff(B, n, r0 + r, r0 + c)] : zero;
+    }
+    for (int e = t; e < PBC * PM; e += 256) {
+        const int r = e % PBC, c = e / PBC;
+        Ab[r * ZPC + c] = (r < nr && c < m) ? B.acc[(r0 + r) + (int64_t)c * n] : zero;
+        Zr[r * ZPC + c] = zero;
+    }
+    for (int e = t; e < PM * TPC; e += 256) Zc[e] = zero;
+    if (t < PBC) rt[t] = t < nr ? B.rowtype[r0 + t] : -1;
+    const int col = t >> 2, q = t & 3;
+    cd lreg[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lreg[u] = B.lam[(4 * u + q) * PM + col];
+    cd lamll = B.lam[col * PM + col];
+    const int pl = col < m ? B.pos[col] : -1;
+    __syncthreads();
+
+    const int lmin = uniform(blockIdx.x == 0 ? lmin0 : lmin1);
+    const int steps = uniform(m > lmin ? nr + (m - lmin) - 1 : 0);
+    for (int s = 0; s < steps; ++s) {
+        const int r = nr - 1 - s + (col - lmin);
+        const int64_t i = r0 + r;
+        if (col < m && r >= 0 && r < nr && i <= pl) {
+            cd v = q == 0 ? Ab[r * ZPC + col] : zero, cp = zero;
+#pragma unroll
+            for (int u = 0; u < PBC / 4; ++u) {
+                const int c = 4 * u + q;
+                v = cfma(Tt[r * TPC + c], Zc[col * TPC + c], v);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cp = cfma(Zr[r * ZPC + 4 * u + q], lreg[u], cp);
+            // coupling minus sum; at a minority row the coupling is zero (see the real kernel)
+            cd d = {cp.re - v.re, cp.im - v.im};
+            d.re = group_sum<4>(d.re);
+            d.im = group_sum<4>(d.im);
+            const cd tii = Tt[r * TPC + r];
+            const int typ = rt[r];
+            cd z;
+            if (i == pl) {
+                z = {1.0, 0.0};
+                lamll = tii;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (4 * u + q == col) lreg[u] = tii;
+            } else if (typ >= 0) {
+                z = zero;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (4 * u + q == typ) lreg[u] = {-d.re, -d.im};
+            } else {
+                z = d / (tii - lamll);
+            }
+            if (q == 0) {
+                Zr[r * ZPC + col] = z;
+                Zc[col * TPC + r] = z;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < PBC * m; e += 256) {
+        const int r = e % PBC, c = e / PBC;
+        if (r < nr) B.Z[(r0 + r) + (int64_t)c * n] = Zr[r * ZPC + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) B.lam[(4 * u + q) * PM + col] = lreg[u];
+}
+
+// acc[0:r0, :] += T[0:r0, r0:r1] Z[r0:r1, :] (64-row tiles, blockIdx.y = basis)
+__global__ __launch_bounds__(256) void k_projc_update(CArgs a, int64_t r0, int64_t r1)
+{
+    __shared__ cd As[64 * (PBC + 1)];  // As[r * (PBC + 1) + k] = T[row0 + r, r0 + k]
+    __shared__ cd Bs[PBC * ZPC];       // Bs[k * ZPC + l] = Z[r0 + k, l]
+    const CBasis B = a.b[blockIdx.y];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int nk = (int)(r1 - r0);
+    const int t = threadIdx.x;
+    const cd zero = {0.0, 0.0};
+    for (int e = t; e < 64 * PBC; e += 256) {
+        const int r = e % 64, k = e / 64;
+        As[r * (PBC + 1) + k] = (row0 + r < r0 && k < nk) ? B.T[ctoff(B, n, row0 + r, r0 + k)] : zero;
+    }
+    for (int e = t; e < PBC * PM; e += 256) {
+        const int k = e % PBC, l = e / PBC;
+        Bs[k * ZPC + l] = (k < nk && l < m) ? B.Z[(r0 + k) + (int64_t)l * n] : zero;
+    }
+    __syncthreads();
+    const int l = t & 63, rg = t >> 6;
+    if (l >= m) return;
+    for (int rr = 0; rr < 16; ++rr) {
+        const int r = rg * 16 + rr;
+        const int64_t row = row0 + r;
+        if (row >= r0) break;
+        cd sum = zero;
+        for (int k = 0; k < PBC; ++k) sum = cfma(As[r * (PBC + 1) + k], Bs[k * ZPC + l], sum);
+        cd &o = B.acc[row + (int64_t)l * n];
+        o = {o.re + sum.re, o.im + sum.im};
+    }
+}
+
+// Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'].
+__global__ __launch_bounds__(256) void k_projc_gram(const cd *__restrict__ Z,
+                                                    const cd *__restrict__ Zf, int64_t n, int m,
+                                                    cd *__restrict__ part)
+{
+    __shared__ cd Ws[64 * ZPC];  // Ws[k * ZPC + l] = W[j0 + k, l]
+    __shared__ cd Zs[64 * ZPC];  // Zs[k * ZPC + l] = Z[j0 + k, l]
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x;
+    const cd zero = {0.0, 0.0};
+    for (int e = t; e < 64 * PM; e += 256) {
+        const int k = e % 64, l = e / 64;
+        const int64_t j = j0 + k;
+        const bool ok = j < n && l < m;
+        Ws[k * ZPC + l] = ok ? Zf[(n - 1 - j) + (int64_t)(m - 1 - l) * n] : zero;
+        Zs[k * ZPC + l] = ok ? Z[j + (int64_t)l * n] : zero;
+    }
+    __syncthreads();
+    const int l = t & 63, g = t >> 6;
+    cd *out = part + (int64_t)blockIdx.x * PM * PM;
+    for (int c = 0; c < 16; ++c) {
+        const int lp = g * 16 + c;
+        cd sum = zero;
+        for (int k = 0; k < 64; ++k) sum = cfma(Ws[k * ZPC + l], Zs[k * ZPC + lp], sum);
+        out[l * PM + lp] = sum;
+    }
+}
+
+// M = sum of the partials (identity beyond the leading m x m block), then
+// Minv = M^-1 by back substitution, one column per thread.
+__global__ __launch_bounds__(64) void k_projc_minv(const cd *__restrict__ part, int nparts, int m,
+                                                   cd *__restrict__ minv)
+{
+    __shared__ cd M[PM * PM];
+    __shared__ cd X[PM * ZPC];
+    const int l = threadIdx.x;
+    for (int e = l; e < PM * PM; e += 64) {
+        const int r = e / PM, c = e % PM;
+        cd s = {0.0, 0.0};
+        if (r < m && c < m)
+            for (int g = 0; g < nparts; ++g) {
+                const cd v = part[(int64_t)g * PM * PM + e];
+                s = {s.re + v.re, s.im + v.im};
+            }
+        else
+            s = {r == c ? 1.0 : 0.0, 0.0};
+        M[e] = s;
+    }
+    __syncthreads();
+    for (int k = PM - 1; k >= 0; --k) {
+        cd v = {k == l ? 1.0 : 0.0, 0.0};
+        if (k < l)
+            for (int kk = k + 1; kk <= l; ++kk) {
+                const cd p = M[k * PM + kk] * X[kk * ZPC + l];
+                v = {v.re - p.re, v.im - p.im};
+            }
+        X[k * ZPC + l] = k <= l ? v / M[k * PM + k] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int e = l; e < PM * PM; e += 64) minv[e] = X[(e / PM) * ZPC + e % PM];
+}
+
+// A = Z Minv, 4 rows per workgroup.
+__global__ __launch_bounds__(256) void k_projc_a(const cd *__restrict__ Z,
+                                                 const cd *__restrict__ minv, int64_t n, int m,
+                                                 cd *__restrict__ A)
+{
+    __shared__ cd X[PM * PM];
+    const int t = threadIdx.x;
+    for (int e = t; e < PM * PM; e += 256) X[e] = minv[e];
+    __syncthreads();
+    const int l = t & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (t >> 6);
+    if (i >= n) return;
+    cd s = {0.0, 0.0};
+    if (l < m)
+        for (int lp = 0; lp <= l; ++lp) s = cfma(Z[i + (int64_t)lp * n], X[lp * PM + l], s);
+    A[i + (int64_t)l * n] = s;
+}
+
+// U[i, j] = s (delta_ij - 2 sum_l A[i, l] W[j, l]) on the upper triangle, zeros
+// below; a tile takes the columns l with i0 <= b_l < j0 + 64, 16 at a time.
+__global__ __launch_bounds__(256) void k_projc_u(const cd *__restrict__ A,
+                                                 const cd *__restrict__ Zf,
+                                                 const int *__restrict__ pos, int64_t n, int m,
+                                                 double smaj, cd *__restrict__ U, int64_t ldu)
+{
+    __shared__ cd As[64 * 17];  // As[ii * 17 + k] = A[i0 + ii, l0 + k]
+    __shared__ cd Ws[64 * 17];  // Ws[jj * 17 + k] = W[j0 + jj, l0 + k]
+    const int64_t ti = blockIdx.x, tj = blockIdx.y;
+    const int64_t i0 = ti * 64, j0 = tj * 64;
+    const int t = threadIdx.x, ii = t & 63, jg = t >> 6;
+    const cd zero = {0.0, 0.0};
+    if (ti > tj) {
+        for (int c = jg; c < 64; c += 4) {
+            const int64_t i = i0 + ii, j = j0 + c;
+            if (i < n && j < n) U[i + j * ldu] = zero;
+        }
+        return;
+    }
+    int lo = 0, hi = 0;
+    for (int l = 0; l < m; ++l) {
+        const int64_t b = pos[l];
+        lo += b < i0;
+        hi += b < j0 + 64;
+    }
+    lo = uniform(lo);
+    hi = uniform(hi);
+    cd acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = zero;
+    for (int l0 = lo; l0 < hi; l0 += 16) {
+        for (int e = t; e < 64 * 16; e += 256) {
+            const int r = e % 64, k = e / 64, l = l0 + k;
+            const int64_t i = i0 + r, j = j0 + r;
+            As[r * 17 + k] = (i < n && l < hi) ? A[i + (int64_t)l * n] : zero;
+            Ws[r * 17 + k] = (j < n && l < hi) ? Zf[(n - 1 - j) + (int64_t)(m - 1 - l) * n] : zero;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int jj = jg * 16 + c;
+            for (int k = 0; k < 16; ++k) acc[c] = cfma(As[ii * 17 + k], Ws[jj * 17 + k], acc[c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int64_t i = i0 + ii, j = j0 + jg * 16 + c;
+        if (i < n && j < n) {
+            cd v = zero;
+            if (i <= j) v = {smaj * ((i == j ? 1.0 : 0.0) - 2.0 * acc[c].re), -2.0 * smaj * acc[c].im};
+            U[i + j * ldu] = v;
+        }
+    }
+}
+
 }  // namespace
 
-size_t proj_workspace_bytes(int64_t n)
+size_t proj_workspace_bytes(int64_t n, bool cplx)
 {
-    const size_t nn = (size_t)n;
+    const size_t nn = (size_t)n, es = cplx ? 16 : 8;
     const size_t nparts = (nn + 63) / 64;
-    return 4 * al(nn * PM * 8)              // Z and acc, two bases
-           + 2 * al(PM * PM * 8)            // L, two bases
+    return 4 * al(nn * PM * es)             // Z and acc, two bases
+           + 2 * al(PM * PM * es)           // L, two bases
            + 2 * al(nn * 4) + 2 * al(PM * 4)  // row types and minority rows
-           + al(nparts * PM * PM * 8)       // partial Gram matrices
-           + al(PM * PM * 8)                // Minv
-           + al(nn * PM * 8);               // A
+           + al(nparts * PM * PM * es)      // partial Gram matrices
+           + al(PM * PM * es)               // Minv
+           + al(nn * PM * es);              // A
+}
+
+int run_proj_c(const void *Tv, int64_t ldt, void *Uv, int64_t ldu, int64_t n, const int8_t *sgn,
+               const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st)
+{
+    if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
+    const cd *T = (const cd *)Tv;
+    cd *U = (cd *)Uv;
+    std::vector<int64_t> mrow;
+    mrow.reserve(m);
+    for (int64_t i = 0; i < n; ++i)
+        if (hsgn[i] == minority) mrow.push_back(i);
+    if ((int)mrow.size() != m) return SIGNTRI_ENOTSUP;
+    const size_t nn = (size_t)n;
+    const int64_t nparts = (n + 63) / 64;
+    char *p = (char *)ws;
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += al(bytes);
+        return (void *)q;
+    };
+    cd *Z0 = (cd *)take(nn * PM * 16), *Z1 = (cd *)take(nn * PM * 16);
+    cd *C0 = (cd *)take(nn * PM * 16), *C1 = (cd *)take(nn * PM * 16);
+    cd *L0 = (cd *)take(PM * PM * 16), *L1 = (cd *)take(PM * PM * 16);
+    int *rt0 = (int *)take(nn * 4), *rt1 = (int *)take(nn * 4);
+    int *ps0 = (int *)take(PM * 4), *ps1 = (int *)take(PM * 4);
+    cd *part = (cd *)take((size_t)nparts * PM * PM * 16);
+    cd *minv = (cd *)take(PM * PM * 16);
+    cd *A = (cd *)take(nn * PM * 16);
+    if (hipMemsetAsync(Z0, 0, (char *)rt0 - (char *)Z0, st) != hipSuccess) return SIGNTRI_EHIP;
+    prof_begin(st);
+    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
+                       ps1);
+    prof_end(st, PK_AUX, 0.0, 1);
+    CArgs a;
+    a.n = n;
+    a.m = m;
+    a.b[0] = CBasis{T, ldt, 0, Z0, C0, L0, rt0, ps0};
+    a.b[1] = CBasis{T, ldt, 1, Z1, C1, L1, rt1, ps1};
+    const double nd = (double)n, md = (double)m;
+    prof_begin(st);
+    int launches = 0;
+    for (int64_t r1 = n; r1 > 0;) {
+        const int64_t r0 = std::max<int64_t>(0, r1 - PBC);
+        const int lmin0 = (int)(std::lower_bound(mrow.begin(), mrow.end(), r0) - mrow.begin());
+        const int lmin1 =
+            (int)(mrow.end() - std::upper_bound(mrow.begin(), mrow.end(), n - 1 - r0));
+        hipLaunchKernelGGL(k_projc_front, dim3(2), dim3(256), 0, st, a, r0, r1, lmin0, lmin1);
+        ++launches;
+        if (r0 > 0) {
+            hipLaunchKernelGGL(k_projc_update, dim3((r0 + 63) / 64, 2), dim3(256), 0, st, a, r0, r1);
+            ++launches;
+        }
+        r1 = r0;
+    }
+    prof_end(st, PK_PROJ, flops, launches);
+    prof_begin(st);
+    hipLaunchKernelGGL(k_projc_gram, dim3(nparts), dim3(256), 0, st, Z0, Z1, n, m, part);
+    hipLaunchKernelGGL(k_projc_minv, dim3(1), dim3(64), 0, st, part, (int)nparts, m, minv);
+    hipLaunchKernelGGL(k_projc_a, dim3((n + 3) / 4), dim3(256), 0, st, Z0, minv, n, m, A);
+    const int64_t nu = (n + 63) / 64;
+    hipLaunchKernelGGL(k_projc_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, ps0, n, m,
+                       minority > 0 ? -1.0 : 1.0, U, ldu);
+    // complex multiply-adds count 8 flops
+    prof_end(st, PK_PROJ_OUT, 4.0 * (nd * nd * md + 3.0 * nd * md * md), 4);
+    return hipGetLastError() == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 }
 
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,

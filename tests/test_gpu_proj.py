@@ -124,9 +124,6 @@ def test_auto_choice(dev):
 def test_proj_unsupported(dev):
     from paper_1607_06303_amd import signtri
 
-    T = wl.make_T(64, wl.rng_for(2, salt=4), complex_=True)
-    with pytest.raises(signtri.SignTriError):
-        run_gpu(T, dev, algo="proj")
     with pytest.raises(signtri.SignTriError):
         run_gpu(skewed(300, 65, 8), dev, algo="proj")
     # all one sign: the trivial path, whatever the algorithm asked for
@@ -214,3 +211,39 @@ def test_proj_full_size_positive_minority(dev):
     for a in (0, 1500, 4096 - 600):
         ref = oracle.sign_tri(T[a:a + 600, a:a + 600])
         assert rel_fro(Uh[a:a + 600, a:a + 600], ref) <= TOL_FP64, a
+
+
+def cskewed(n, m, seed, minority=-1, re_range=(0.5, 2.0), where=None):
+    rng = wl.rng_for(2, salt=seed)
+    s = -minority * np.ones(n)
+    if where is None:
+        where = rng.choice(n, size=m, replace=False)
+    s[np.asarray(where)] = minority
+    return wl.make_T(n, rng, complex_=True, signs=s, re_range=re_range, im_range=(-1.0, 1.0))
+
+
+@pytest.mark.parametrize("n,m,where", [(2, 1, None), (33, 3, [0, 1, 32]), (100, 5, None),
+                                       (257, 31, None), (300, 64, None)])
+@pytest.mark.parametrize("minority", [-1, 1])
+def test_proj_complex_matches_oracle(dev, n, m, where, minority):
+    """Complex T: the same form with transposes (left basis of J T^T J), 32-row blocks."""
+    import oracle
+
+    T = cskewed(n, m, n + 3 * m, minority, where=where)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj"
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+    assert not np.any(np.tril(U, -1))
+
+
+def test_proj_complex_reordering_route_and_near_imaginary(dev):
+    import oracle
+    from oracle import reorder
+
+    T = cskewed(180, 7, 5)
+    U, _ = run_gpu(T, dev, algo="proj")
+    ref, rinfo = reorder.sign_tri_reordered(T)
+    assert rinfo["k"] > 0 and rel_fro(U, ref) <= TOL_FP64
+    T = cskewed(240, 12, 6, re_range=(1e-3, 1.0))
+    U, _ = run_gpu(T, dev, algo="proj")
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
