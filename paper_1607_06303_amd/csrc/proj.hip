@@ -30,19 +30,21 @@
 // which is upper triangular with the same diagonal in reverse order; it is
 // read from T through the reversal, not copied.
 //
-// Kernels:
+// Kernels (real T):
 //   k_proj_prep    minority rows and row types of both bases, from the signs;
 //   k_proj_step    one launch per block of 64 rows, bottom up: a workgroup
 //                  per basis runs the substitution above as a wavefront
-//                  (column l at row r1 - 1 - s + l at step s, block operands in
-//                  LDS), and FP64 MFMA products keep acc, the sums over the
-//                  rows below each block, up to date for the next blocks;
+//                  (column l at row r1 - 1 - s + (l - lmin) at step s, lmin the
+//                  columns still zero in the block; block operands in LDS), and
+//                  FP64 MFMA products keep acc, the sums over the rows below
+//                  each block, up to date for the next blocks;
 //   k_proj_gram    partial sums of W^T Z over 64-row chunks (MFMA);
 //   k_proj_gsum    W^T Z, the partials summed;
 //   k_proj_minv    its inverse (unit upper triangular, m x m);
 //   k_proj_a       A = Z (W^T Z)^-1;
 //   k_proj_u       U = s (I - 2 A W^T) on the upper triangle, zeros below
 //                  (FP64 MFMA, 64 x 64 output tiles).
+// Complex T runs simpler kernels of the same structure (k_projc_*, below).
 #include <algorithm>
 #include <vector>
 
