@@ -33,9 +33,11 @@
 // Kernels (real T):
 //   k_proj_prep    minority rows and row types of both bases, from the signs;
 //   k_proj_step    one launch per block of 64 rows, bottom up: a workgroup
-//                  per basis runs the substitution above as a wavefront
-//                  (column l at row r1 - 1 - s + (l - lmin) at step s, lmin the
-//                  columns still zero in the block; block operands in LDS), and
+//                  per basis runs the substitution above as a wavefront over
+//                  waves of eight columns (wave w at row r1 - 1 - s + (w - wmin)
+//                  at step s, wmin the wave of the first column not still zero
+//                  in the block; the coupling among a wave's own columns solved
+//                  in order within the wave; block operands in LDS), and
 //                  FP64 MFMA products keep acc, the sums over the rows below
 //                  each block, up to date for the next blocks;
 //   k_proj_gram    partial sums of W^T Z over 64-row chunks (MFMA);
@@ -74,6 +76,15 @@ struct ProjArgs {
     int64_t n;
     int m;
 };
+
+// Lane src's double, as a value every lane holds.
+__device__ inline double readlane_f64(double v, int src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // Offset of entry (i, j) of a basis's matrix in T: T itself, or J T^T J.
 __device__ inline int64_t toff(const ProjBasis &B, int64_t n, int64_t i, int64_t j)
@@ -234,11 +245,13 @@ constexpr int FP = PB + NQ;    // LDS pitch of the staged T block and of the Z b
 __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1,
                                                    int lmin0, int lmin1)
 {
-    __shared__ double Tt[PB * FP];   // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
-    __shared__ double Zr[PB * FP];   // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
-    __shared__ double Zc[PM * FP];   // Zc[l * FP + r] = Z[r0 + r, l], the same values by column
-    __shared__ double Ab[PB * AP];   // Ab[r * AP + l] = acc[r0 + r, l]
-    __shared__ int rt[PB];
+    // one arena, so that a step's row of T and row of Z sit within the reach of
+    // one base address and the loads' immediate offsets
+    __shared__ double arena[PB * FP + PB * FP + PM * FP + PB * AP];
+    double *const Tt = arena;         // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
+    double *const Zr = Tt + PB * FP;  // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
+    double *const Zc = Zr + PB * FP;  // Zc[l * FP + r] = Z[r0 + r, l], the same values by column
+    double *const Ab = Zc + PM * FP;  // Ab[r * AP + l] = acc[r0 + r, l]
 
     const int64_t n = a.n;
     const int m = a.m;
@@ -267,12 +280,20 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     const int q = t % NQ;
     // column l's coefficients, its minority row and the block's row types: loaded
     // first, so that their latency overlaps the staging below
-    double lreg[NU];
+    constexpr int CW = 64 / NQ;  // columns per wave
+    const int wv = uniform(t >> 6), k = (t & 63) / NQ;  // col = CW wv + k
+    double lreg[NU], lw[CW];
 #pragma unroll
     for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
-    double lamll = B.lam[col * PM + col];
+    // the same column of L for the rows of this wave's columns, in every lane of
+    // the column: lw[k'] = L[CW wv + k', l] for k' < k, zero from the diagonal on
+#pragma unroll
+    for (int kp = 0; kp < CW; ++kp) lw[kp] = kp < k ? B.lam[(CW * wv + kp) * PM + col] : 0.0;
     const int pl = col < m ? B.pos[col] : -1;
-    const int rtv = t < nr ? B.rowtype[r0 + t] : -1;
+    // L[l, l] = t at row b_l: it divides every row above b_l, in any block
+    const double lamll = col < m ? B.T[toff(B, n, pl, pl)] : 0.0;
+    // the block's row types, lane i holding row i's (every wave)
+    const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
 
     // ---- stage the block's operands and the block below's (64 consecutive rows
     // per wave, coalesced; every load issued before the first store)
@@ -301,7 +322,6 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             Ab[row * AP + c] = av[k];
             Zc[row * FP + c] = zv[k];  // k-major: Zc[k * FP + l] = Z[r1 + k, l]
         }
-        if (t < PB) rt[t] = rtv;
     }
     __syncthreads();
     if (below) {
@@ -330,18 +350,38 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     }
     __syncthreads();
 
-    // ---- wavefront: column l handles block row nr - 1 - s + l at step s
+    // ---- wavefront by waves: at step s the columns of wave w all handle block
+    // row r = nr - 1 - s + (w - wmin), wmin the wave of the first active column.
+    // A column's sums read its own column (earlier steps) and row r of the
+    // columns of the waves before it (written at step s - 1 and earlier); the
+    // coupling among the wave's own columns, whose entries of row r are still
+    // zero in those sums, is solved after the reduction, column by column within
+    // the wave.  At a minority row that coupling is zero (the row of Z is e_typ
+    // and L's row typ is not set yet), so only majority rows take that chain.
     const int lmin = uniform(blockIdx.x == 0 ? lmin0 : lmin1);
-    const int steps = uniform(m > lmin ? nr + (m - lmin) - 1 : 0);
+    const int wmin = lmin / CW, wlast = (m - 1) / CW;
+    const int steps = uniform(m > lmin ? nr + (wlast - wmin) : 0);
+    // the column's minority row within the block (-1: above it, PB: below it)
+    const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
+    const int rhi = col < m ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
+    const double *const zcol = Zc + col * FP + q;
     for (int s = 0; s < steps; ++s) {
-        const int r = nr - 1 - s + (col - lmin);
-        const int64_t i = r0 + r;
-        if (col < m && r >= 0 && r < nr && i <= pl) {
-            const double *trow = Tt + r * FP;
-            const double *zrow = Zr + r * FP;
-            const double tii = trow[r];
+        const int r = nr - 1 - s + (wv - wmin);  // the wave's row (uniform)
+        const bool act = r >= 0 && r <= rhi;
+        // the wave's active columns: a contiguous range (b_l grows with l)
+        const uint64_t am = __builtin_amdgcn_ballot_w64(act);
+        if (am != 0) {  // then 0 <= r < nr
+            // chain steps: the active columns but the last, as a bit mask
+            const int klo = __builtin_ctzll(am) / NQ, khi = (64 - __builtin_clzll(am)) / NQ;
+            const int chain = uniform(((1 << (khi - 1)) - 1) & ~((1 << klo) - 1));
+            int ro = r * FP;
+            // opaque to loop strength reduction: one base address for the step's
+            // reads of both rows, with immediate offsets
+            asm volatile("" : "+v"(ro));
+            const double *trow = Tt + ro;
+            const double *zrow = Zr + ro;
+            const double tii = Tt[r * FP + r];
             // 1 / (t_ii - L[l, l]): the hardware estimate and two Newton steps
-            // (used only where lamll is set)
             const double dx = tii - lamll;
             double rcp = __builtin_amdgcn_rcp(dx);
             rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
@@ -349,12 +389,11 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             // Full sums: every term outside the ranges that count is zero (the
             // lower triangle of the staged block, entries of Z not computed yet).
             // all operands first (paired LDS reads), then the multiply-adds
-            const double *zcol = Zc + col * FP;
             double tv[NU], zv[NU], rv[NU];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 tv[u] = trow[NQ * u + q];
-                zv[u] = zcol[NQ * u + q];
+                zv[u] = zcol[NQ * u];
                 rv[u] = zrow[NQ * u + q];
             }
             double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
@@ -365,28 +404,40 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 c0 += rv[u] * lreg[u];
                 c1 += rv[u + 1] * lreg[u + 1];
             }
-            // one reduction: d = coupling - sum.  At a minority row the coupling is
-            // zero (L's row typ is not set yet and the row of Z is e_typ), so
-            // there d = -sum.
+            // d = coupling (waves before this one) - sum
             const double d = group_sum<NQ>((c0 + c1) - (v0 + v1));
-            const int typ = rt[r];
-            double z;
-            if (i == pl) {
-                z = 1.0;
-                lamll = tii;
+            const int typ = __builtin_amdgcn_readlane(rtl, r);
+            double z = 0.0;
+            if (typ >= 0) {
+                // (the active columns only: an inactive one's column of L stays as is)
+                if (act && r == plr) {
+                    z = 1.0;
 #pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    if (NQ * u + q == col) lreg[u] = tii;
-            } else if (typ >= 0) {
-                // minority row b_typ (typ < l): row typ of L
-                z = 0.0;
+                    for (int u = 0; u < NU; ++u)
+                        if (NQ * u + q == col) lreg[u] = tii;
+                } else if (act) {
+                    // minority row b_typ (typ < l): row typ of L
 #pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    if (NQ * u + q == typ) lreg[u] = -d;
+                    for (int u = 0; u < NU; ++u)
+                        if (NQ * u + q == typ) lreg[u] = -d;
+#pragma unroll
+                    for (int kp = 0; kp < CW; ++kp)
+                        if (CW * wv + kp == typ) lw[kp] = -d;
+                }
             } else {
-                z = d * rcp;
+                // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
+                // wave's active columns in order; lw is zero from the diagonal on,
+                // so the later terms add nothing to a column already solved
+                double acc = 0.0;
+#pragma unroll
+                for (int kp = 0; kp < CW - 1; ++kp)
+                    if (chain & (1 << kp)) {
+                        const double zk = readlane_f64((d + acc) * rcp, kp * NQ);
+                        acc = fma(zk, lw[kp], acc);
+                    }
+                z = (d + acc) * rcp;
             }
-            if (q == 0) {
+            if (q == 0 && act) {
                 Zr[r * FP + col] = z;
                 Zc[col * FP + r] = z;
             }
