@@ -426,16 +426,16 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 }
             } else {
                 // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
-                // wave's active columns in order; lw is zero from the diagonal on,
-                // so the later terms add nothing to a column already solved
-                double acc = 0.0;
+                // wave's active columns in order, with the reciprocal folded into
+                // the coefficients (one multiply-add per link); lw is zero from the
+                // diagonal on, so the later terms add nothing to a column solved
+                double lwr[CW - 1];
+#pragma unroll
+                for (int kp = 0; kp < CW - 1; ++kp) lwr[kp] = lw[kp] * rcp;
+                z = d * rcp;
 #pragma unroll
                 for (int kp = 0; kp < CW - 1; ++kp)
-                    if (chain & (1 << kp)) {
-                        const double zk = readlane_f64((d + acc) * rcp, kp * NQ);
-                        acc = fma(zk, lw[kp], acc);
-                    }
-                z = (d + acc) * rcp;
+                    if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
             }
             if (q == 0 && act) {
                 Zr[r * FP + col] = z;
