@@ -289,9 +289,9 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     // the column: lw[k'] = L[CW wv + k', l] for k' < k, zero from the diagonal on
 #pragma unroll
     for (int kp = 0; kp < CW; ++kp) lw[kp] = kp < k ? B.lam[(CW * wv + kp) * PM + col] : 0.0;
-    const int pl = col < m ? B.pos[col] : -1;
-    // L[l, l] = t at row b_l: it divides every row above b_l, in any block
-    const double lamll = col < m ? B.T[toff(B, n, pl, pl)] : 0.0;
+    // L[l, l] (t at row b_l; set at that row when it lies in this block)
+    double lamll = B.lam[col * PM + col];
+    const int pl = B.pos[col];  // (PM entries, -1 from m on)
     // the block's row types, lane i holding row i's (every wave)
     const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
 
@@ -412,6 +412,7 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 // (the active columns only: an inactive one's column of L stays as is)
                 if (act && r == plr) {
                     z = 1.0;
+                    lamll = tii;
 #pragma unroll
                     for (int u = 0; u < NU; ++u)
                         if (NQ * u + q == col) lreg[u] = tii;
