@@ -48,6 +48,7 @@
 //                  (FP64 MFMA, 64 x 64 output tiles).
 // Complex T runs simpler kernels of the same structure (k_projc_*, below).
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -365,6 +366,11 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
     const int rhi = col < m ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
     const double *const zcol = Zc + col * FP + q;
+    // The coupling terms of wave w come from the columns of the waves before it
+    // (chunks u < w); the others are still zero when read.  The step loop is
+    // instantiated per wave with that chunk count, so no step tests it.
+    auto front = [&](auto wtag) {
+    constexpr int NCU = decltype(wtag)::value;  // coupling chunks of this wave
     for (int s = 0; s < steps; ++s) {
         const int r = nr - 1 - s + (wv - wmin);  // the wave's row (uniform)
         const bool act = r >= 0 && r <= rhi;
@@ -389,20 +395,23 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             // Full sums: every term outside the ranges that count is zero (the
             // lower triangle of the staged block, entries of Z not computed yet).
             // all operands first (paired LDS reads), then the multiply-adds
-            double tv[NU], zv[NU], rv[NU];
+            double tv[NU], zv[NU], rv[NCU > 0 ? NCU : 1];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 tv[u] = trow[NQ * u + q];
                 zv[u] = zcol[NQ * u];
-                rv[u] = zrow[NQ * u + q];
+                if (u < NCU) rv[u] = zrow[NQ * u + q];
             }
             double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
 #pragma unroll
             for (int u = 0; u < NU; u += 2) {
                 v0 += tv[u] * zv[u];
                 v1 += tv[u + 1] * zv[u + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < NCU; u += 2) {
                 c0 += rv[u] * lreg[u];
-                c1 += rv[u + 1] * lreg[u + 1];
+                if (u + 1 < NCU) c1 += rv[u + 1] * lreg[u + 1];
             }
             // d = coupling (waves before this one) - sum
             const double d = group_sum<NQ>((c0 + c1) - (v0 + v1));
@@ -444,6 +453,18 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             }
         }
         __syncthreads();
+    }
+    };
+    static_assert(NWS == 8, "one instance per wave");
+    switch (wv) {
+        case 0: front(std::integral_constant<int, 0>{}); break;
+        case 1: front(std::integral_constant<int, 1>{}); break;
+        case 2: front(std::integral_constant<int, 2>{}); break;
+        case 3: front(std::integral_constant<int, 3>{}); break;
+        case 4: front(std::integral_constant<int, 4>{}); break;
+        case 5: front(std::integral_constant<int, 5>{}); break;
+        case 6: front(std::integral_constant<int, 6>{}); break;
+        default: front(std::integral_constant<int, 7>{}); break;
     }
 
     // ---- publish the rows and L
