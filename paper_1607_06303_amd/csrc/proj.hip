@@ -282,14 +282,14 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
     // column l's coefficients, its minority row and the block's row types: loaded
     // first, so that their latency overlaps the staging below
     constexpr int CW = 64 / NQ;  // columns per wave
-    const int wv = uniform(t >> 6), k = (t & 63) / NQ;  // col = CW wv + k
+    const int wv = uniform(t >> 6), kw = (t & 63) / NQ;  // col = CW wv + kw
     double lreg[NU], lw[CW];
 #pragma unroll
     for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
     // the same column of L for the rows of this wave's columns, in every lane of
-    // the column: lw[k'] = L[CW wv + k', l] for k' < k, zero from the diagonal on
+    // the column: lw[k'] = L[CW wv + k', l] for k' < kw, zero from the diagonal on
 #pragma unroll
-    for (int kp = 0; kp < CW; ++kp) lw[kp] = kp < k ? B.lam[(CW * wv + kp) * PM + col] : 0.0;
+    for (int kp = 0; kp < CW; ++kp) lw[kp] = kp < kw ? B.lam[(CW * wv + kp) * PM + col] : 0.0;
     // L[l, l] (t at row b_l; set at that row when it lies in this block)
     double lamll = B.lam[col * PM + col];
     const int pl = B.pos[col];  // (PM entries, -1 from m on)
