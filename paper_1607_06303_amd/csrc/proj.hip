@@ -535,48 +535,79 @@ __global__ __launch_bounds__(64) void k_proj_gsum(const double *__restrict__ par
 }
 
 // Minv = M^-1 for the upper triangular M (unit diagonal on the leading m x m
-// block, identity beyond), by back substitution over the rows k = 63 .. 0; the
-// 64 columns in parallel, each row's inner products split over four threads.
-__global__ __launch_bounds__(256) void k_proj_minv(const double *Mg,
-                                                   double *minv)
+// block, identity beyond; zero below the diagonal), by elimination from the last
+// row up: row k of the inverse is row k of the running right-hand side R
+// (initially I) divided by M[k][k], and then every row i of R loses M[i][k]
+// times it (no change for i > k, where M[i][k] = 0; row k itself is not read
+// again).  Thread (l, q) keeps R[4 j + q][l] for j < 16 in registers; a
+// finished row goes through LDS (two buffers, so one barrier per row).
+__global__ __launch_bounds__(256) void k_proj_minv(const double *__restrict__ Mg,
+                                                   double *__restrict__ minv)
 {
     __shared__ double M[PM * PM];
-    __shared__ double X[PM * (PM + 1)];
-    __shared__ double red[4][PM];
-    const int t = threadIdx.x, l = t & 63, q = t >> 6;
+    __shared__ double dinv[PM];
+    __shared__ double xr[2][PM];
+    const int t = threadIdx.x, l = t & 63, q = uniform(t >> 6);
     for (int e = t; e < PM * PM; e += 256) M[e] = Mg[e];
-    for (int e = t; e < PM * (PM + 1); e += 256) X[e] = 0.0;
+    if (t < PM) dinv[t] = 1.0 / Mg[t * PM + t];
+    double R[PM / 4];
+#pragma unroll
+    for (int j = 0; j < PM / 4; ++j) R[j] = 4 * j + q == l ? 1.0 : 0.0;
     __syncthreads();
+#pragma unroll
     for (int k = PM - 1; k >= 0; --k) {
-        double s = 0.0;
-        for (int kk = k + 1 + q; kk < PM; kk += 4) s += M[k * PM + kk] * X[kk * (PM + 1) + l];
-        red[q][l] = s;
-        __syncthreads();
-        if (q == 0 && k <= l) {
-            const double v = (k == l ? 1.0 : 0.0) - (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
-            X[k * (PM + 1) + l] = v / M[k * PM + k];
+        // column k of M for this thread's rows, read ahead of the barrier
+        double mv[PM / 4];
+#pragma unroll
+        for (int j = 0; j < PM / 4; ++j) mv[j] = M[(4 * j + q) * PM + k];
+        if (q == (k & 3)) {
+            const double x = R[k >> 2] * dinv[k];
+            xr[k & 1][l] = x;
+            minv[k * PM + l] = x;
         }
         __syncthreads();
+        const double x = xr[k & 1][l];
+#pragma unroll
+        for (int j = 0; j < PM / 4; ++j) R[j] -= mv[j] * x;
+        // applied now: otherwise the compiler defers each row's updates to the
+        // row's last step and keeps every earlier row of the inverse live
+#pragma unroll
+        for (int j = 0; j < PM / 4; ++j) asm volatile("" : "+v"(R[j]));
     }
-    for (int e = t; e < PM * PM; e += 256) minv[e] = X[(e / PM) * (PM + 1) + e % PM];
 }
 
-// A = Z Minv: A[i, l] = sum_{l' <= l} Z[i, l'] Minv[l'][l]; 4 rows per workgroup.
+// A = Z Minv over the rows [64 g, 64 g + 64): A[i, l] = sum_k Z[i, k] Minv[k][l]
+// (Minv is the identity beyond m, where Z's columns are zero).  Computed as the
+// transposed product C[l][i] = sum_k Minv[k][l] Z[i, k] (FP64 MFMA), so that the
+// accumulator's lanes run down A's columns.
 __global__ __launch_bounds__(256) void k_proj_a(const double *__restrict__ Z,
-                                                const double *__restrict__ minv, int64_t n, int m,
+                                                const double *__restrict__ minv, int64_t n,
                                                 double *__restrict__ A)
 {
-    __shared__ double X[PM * PM];
-    const int t = threadIdx.x;
-    for (int e = t; e < PM * PM; e += 256) X[e] = minv[e];
+    __shared__ double Ms[PM * OP];  // Ms[k * OP + l]  = Minv[k][l]
+    __shared__ double Zs[PM * OP];  // Zs[k * OP + ii] = Z[i0 + ii, k]
+    const int t = threadIdx.x, lr = t & 63, q = t >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    for (int k = q; k < PM; k += 4) {
+        const int64_t i = i0 + lr;
+        Ms[k * OP + lr] = minv[k * PM + lr];
+        Zs[k * OP + lr] = i < n ? Z[i + (int64_t)k * n] : 0.0;
+    }
     __syncthreads();
-    const int l = t & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (t >> 6);
-    if (i >= n) return;
-    double s = 0.0;
-    if (l < m)
-        for (int lp = 0; lp <= l; ++lp) s += Z[i + (int64_t)lp * n] * X[lp * PM + l];
-    A[i + (int64_t)l * n] = s;
+    dx4 d[2][2];
+    mm64(Ms, Zs, d);
+    const int lane = t & 63, w = t >> 6;
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int l = rb + 16 * x + mfma64_row(lane, e);
+                const int64_t i = i0 + cb + 16 * y + (lane & 15);
+                if (i < n) A[i + (int64_t)l * n] = d[x][y][e];
+            }
 }
 
 // U[i, j] = s (delta_ij - 2 sum_l A[i, l] W[j, l]) for i <= j, 0 for i > j.
@@ -1097,7 +1128,7 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     hipLaunchKernelGGL(k_proj_gsum, dim3(PM * PM / 64), dim3(64), 0, st, part, (int)nparts, m,
                        minv);
     hipLaunchKernelGGL(k_proj_minv, dim3(1), dim3(256), 0, st, minv, minv);
-    hipLaunchKernelGGL(k_proj_a, dim3((n + 3) / 4), dim3(256), 0, st, Z0, minv, n, m, A);
+    hipLaunchKernelGGL(k_proj_a, dim3((n + 63) / 64), dim3(256), 0, st, Z0, minv, n, A);
     const int64_t nu = (n + 63) / 64;
     hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, ps0, n, m,
                        minority > 0 ? -1.0 : 1.0, U, ldu);
