@@ -540,9 +540,9 @@ __global__ __launch_bounds__(64) void k_proj_gsum(const double *__restrict__ par
 // (initially I) divided by M[k][k], and then every row i of R loses M[i][k]
 // times it (no change for i > k, where M[i][k] = 0; row k itself is not read
 // again).  Thread (l, q) keeps R[4 j + q][l] for j < 16 in registers; a
-// finished row goes through LDS (two buffers, so one barrier per row).
-__global__ __launch_bounds__(256) void k_proj_minv(const double *__restrict__ Mg,
-                                                   double *__restrict__ minv)
+// finished row goes through LDS (two buffers, so one barrier per row).  Mg and
+// minv may be the same array: M is read whole before the first row is written.
+__global__ __launch_bounds__(256) void k_proj_minv(const double *Mg, double *minv)
 {
     __shared__ double M[PM * PM];
     __shared__ double dinv[PM];
