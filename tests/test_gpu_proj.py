@@ -247,3 +247,30 @@ def test_proj_complex_reordering_route_and_near_imaginary(dev):
     T = cskewed(240, 12, 6, re_range=(1e-3, 1.0))
     U, _ = run_gpu(T, dev, algo="proj")
     assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+
+
+CLUSTERS = [
+    # ten minority rows inside one 64-row block, two waves' worth of columns, with
+    # majority rows between them (the in-wave chain and the L rows set within a wave)
+    (256, [70, 72, 75, 77, 80, 90, 95, 100, 101, 102]),
+    # 64 consecutive minority rows across block boundaries (every wave's columns set
+    # their L rows within a block while later waves of the same block still solve)
+    (200, list(range(100, 164))),
+    # clusters at wave boundaries of the column order: columns 6..9 and 14..17
+    (330, [5, 9, 20, 40, 60, 64, 65, 66, 67, 130, 131, 132, 140, 150, 151, 152, 153, 154, 300]),
+    # one minority row per block, and one at each end
+    (520, [0] + [64 * k + 17 for k in range(1, 8)] + [519]),
+]
+
+
+@pytest.mark.parametrize("n,where", CLUSTERS, ids=["one-block", "run64", "wave-edges", "spread"])
+@pytest.mark.parametrize("minority", [-1, 1])
+def test_proj_clustered_minority(dev, n, where, minority):
+    """Minority rows clustered within blocks and across wave boundaries of the column order."""
+    import oracle
+
+    T = skewed(n, len(where), n + len(where), minority, where)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj"
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
+    assert not np.any(np.tril(U, -1))
