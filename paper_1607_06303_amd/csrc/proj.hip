@@ -402,7 +402,10 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
                 zv[u] = zcol[NQ * u];
                 if (u < NCU) rv[u] = zrow[NQ * u + q];
             }
-            double v0 = q == 0 ? Ab[r * AP + col] : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
+            // (the block's sum read by all the column's lanes, one address: a broadcast,
+            // no branch)
+            const double ab = Ab[r * AP + col];
+            double v0 = q == 0 ? ab : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
 #pragma unroll
             for (int u = 0; u < NU; u += 2) {
                 v0 += tv[u] * zv[u];
