@@ -260,10 +260,15 @@ CLUSTERS = [
     (330, [5, 9, 20, 40, 60, 64, 65, 66, 67, 130, 131, 132, 140, 150, 151, 152, 153, 154, 300]),
     # one minority row per block, and one at each end
     (520, [0] + [64 * k + 17 for k in range(1, 8)] + [519]),
+    # a block made only of minority rows, at the top and at the bottom (n = 1000: the
+    # blocks are cut from the bottom, so the top block is short)
+    (1000, list(range(0, 64))),
+    (1000, list(range(936, 1000))),
 ]
 
 
-@pytest.mark.parametrize("n,where", CLUSTERS, ids=["one-block", "run64", "wave-edges", "spread"])
+@pytest.mark.parametrize("n,where", CLUSTERS,
+                         ids=["one-block", "run64", "wave-edges", "spread", "top64", "bottom64"])
 @pytest.mark.parametrize("minority", [-1, 1])
 def test_proj_clustered_minority(dev, n, where, minority):
     """Minority rows clustered within blocks and across wave boundaries of the column order."""
