@@ -35,9 +35,16 @@
  *     device scan of the diagonal, to plan the work; the result in U is ready
  *     when the stream has been synchronised again.  Calls that also wait for
  *     their result before returning: MIXED_REFINED (its convergence test runs
- *     on the host), and any real call with a non-NULL `info` (it then also
- *     reports SIGNTRI_EHIP if a dependency wait of the dataflow sweep hit its
- *     safety bound, which does not happen in a correct run).
+ *     on the host), sign_tri(), signtri_batched(), and signtri() with a
+ *     non-NULL `info`.  Those calls also return SIGNTRI_EHIP if a dependency
+ *     wait of a dataflow sweep hit its safety bound (which does not happen in
+ *     a correct run; U then holds unusable values).  signtri() with a NULL
+ *     `info` and no refinement returns without waiting and cannot report it.
+ *   - Testing hooks, read from the environment at each call:
+ *     SIGNTRI_DEBUG_SPIN_LIMIT=<int> sets the polls a dependency wait makes
+ *     before it gives up (-1: the first wait of each sweep gives up at once);
+ *     SIGNTRI_DEBUG_FAIL_ALLOC=1 makes every allocation of the library-owned
+ *     workspace fail with SIGNTRI_ENOMEM.
  *   - Return codes: 0 on success; -p if argument p (1-based) is invalid;
  *     positive SIGNTRI_E* codes below.  On any nonzero return, U is untouched
  *     except after SIGNTRI_EHIP (a device error mid-computation).
@@ -113,7 +120,7 @@ typedef struct {
 
 /* How the off-diagonal blocks are scheduled.
  * DATAFLOW: one persistent kernel per sweep; workgroups take 32 x 32 blocks in
- *   dependency order and wait on per-block completion flags (real T, every
+ *   dependency order and wait on per-block completion flags (real or complex T, every
  *   mode, both the substitution and the Sylvester form).
  * SUPERDIAG: one product launch and one solve launch per block superdiagonal,
  *   with a one-superdiagonal lookahead on a second stream, replayed from a
@@ -128,7 +135,9 @@ typedef struct {
     int32_t tile;                /* block size: 0 = tuned choice or 32; 64 is available on
                                     the superdiagonal sweep of real FP64 only (and selects
                                     that sweep when `sweep` is AUTO)                      */
-    int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2)   */
+    int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2);
+                                    negative: none, so every block counts as not converged
+                                    (recomputed in FP64, or SIGNTRI_ENOCONV)             */
     double stall_ratio;          /* mixed mode: a block stalls when a step leaves its
                                     residual above this fraction of the previous one
                                     (0 = default 0.5)                                    */
@@ -157,7 +166,8 @@ typedef struct {
  *   algo        SIGNTRI_AUTO, SIGNTRI_PH, SIGNTRI_PS or SIGNTRI_PROJ (PS requires a
  *               diagonal already grouped by sign; PROJ 1..64 entries in the minority
  *               sign class; else SIGNTRI_ENOTSUP)
- *   Complex T supports mode SIGNTRI_FP64 only in this build (else SIGNTRI_ENOTSUP).
+ *   Real and complex T take every mode; the projector form (PROJ) computes in
+ *   FP64 whatever the mode.
  *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
  *               use a buffer it allocates and keeps for later calls
  *   stream      hipStream_t to queue work on (NULL = default stream)
@@ -180,7 +190,10 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout lay
 /*
  * Batched form: U_b = sign(T_b) for b = 0 .. batch-1, matrices of uneven
  * order, in one graph-captured persistent launch.
- *   T, U        HOST arrays of `batch` DEVICE pointers
+ *   T, U        HOST arrays of `batch` DEVICE pointers (host arrays, so that
+ *               the call can plan on the host without reading them back; the
+ *               captured graph of a batch is keyed by these pointers, so a new
+ *               set of buffers captures a new graph, and the same set replays it)
  *   ldt, ldu, n HOST arrays of `batch` leading dimensions and orders
  *   dtype       SIGNTRI_R64 or SIGNTRI_C128
  *   layout      SIGNTRI_COL_MAJOR only in this build (else SIGNTRI_ENOTSUP)
@@ -188,8 +201,9 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout lay
  *   workspace   device scratch of ws_bytes, or NULL for a library buffer
  *   infos       optional HOST array of `batch` results
  * The call plans on the host (one stream synchronisation for the diagonal
- * signs), then launches; a domain error in any matrix returns SIGNTRI_EDOMAIN
- * before anything is written and marks that matrix's info.
+ * signs), then launches, and waits for the result before returning; a domain
+ * error in any matrix returns SIGNTRI_EDOMAIN before anything is written and
+ * marks that matrix's info.
  */
 int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U,
                     const int64_t *ldu, const int64_t *n, int64_t batch,

@@ -158,6 +158,10 @@ int owned_workspace(size_t bytes, void **out)
     if ((int)o.dev.size() <= dev) o.dev.resize(dev + 1, {nullptr, 0});
     auto &slot = o.dev[dev];
     if (slot.second < bytes) {
+        // testing hook: SIGNTRI_DEBUG_FAIL_ALLOC=1 makes every allocation of the
+        // library-owned workspace fail, as hipMalloc does when memory runs out
+        const char *fail = getenv("SIGNTRI_DEBUG_FAIL_ALLOC");
+        if (fail && *fail && *fail != '0') return SIGNTRI_ENOMEM;
         if (slot.first) {
             if (hipDeviceSynchronize() != hipSuccess) return SIGNTRI_EHIP;
             (void)hipFree(slot.first);
@@ -349,7 +353,8 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
     const bool cplx = !items.empty() && items[0].cplx;
     std::vector<int64_t> key{(int64_t)mode, (int64_t)device, (int64_t)(intptr_t)run_dev,
                              (int64_t)ws_generation().load(), (int64_t)items.size(),
-                             (int64_t)(opts ? opts->wgs_per_cu : 0), (int64_t)cplx};
+                             (int64_t)(opts ? opts->wgs_per_cu : 0), (int64_t)cplx,
+                             (int64_t)flow_spin_limit()};
     std::vector<int64_t> ns;
     for (const RealItem &it : items) {
         key.insert(key.end(), {(int64_t)(intptr_t)it.T, it.ldt, (int64_t)(intptr_t)it.U, it.ldu,
@@ -653,8 +658,11 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
 
 int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U)
 {
+    // with an info, signtri() waits for the sweep and reports a dependency wait
+    // that gave up; this form waits anyway
+    signtri_info info;
     int rc = signtri(T, ld, U, ld, n, dtype, SIGNTRI_COL_MAJOR, SIGNTRI_FP64, SIGNTRI_AUTO, nullptr,
-                     0, nullptr, nullptr, nullptr);
+                     0, nullptr, nullptr, &info);
     if (rc != SIGNTRI_OK) return rc;
     return hipStreamSynchronize(nullptr) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 }
@@ -790,7 +798,9 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
         rc = run_real(items, mode, &eo, run_dev, run_host, prof_on(), hsigns.data(), st);
     }
     if (rc != SIGNTRI_OK) return rc;
-    if (infos && mode != SIGNTRI_MIXED_REFINED)
+    // wait, and report a dependency wait of the sweep that gave up (the mixed mode
+    // has read the error word already, at each of its convergence tests)
+    if (mode != SIGNTRI_MIXED_REFINED)
         return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx,
                            run_host, st, nullptr);
     return SIGNTRI_OK;

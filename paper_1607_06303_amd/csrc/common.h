@@ -30,8 +30,13 @@ __host__ __device__ inline cd operator*(cd a, cd b)
 __host__ __device__ inline cd operator*(cd a, double x) { return {a.re * x, a.im * x}; }
 __host__ __device__ inline cd operator/(cd a, cd b)
 {
-    double den = b.re * b.re + b.im * b.im;
-    return {(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+    // a conj(b) / |b|^2 with b scaled by max(|Re b|, |Im b|), so that |b|^2 neither
+    // overflows nor underflows (and a power-of-two scaling of a and b passes through
+    // exactly)
+    const double s = fmax(fabs(b.re), fabs(b.im));
+    const double xr = b.re / s, xi = b.im / s;
+    const double den = s * (xr * xr + xi * xi);
+    return {(a.re * xr + a.im * xi) / den, (a.im * xr - a.re * xi) / den};
 }
 __host__ __device__ inline cd operator/(cd a, double x) { return {a.re / x, a.im / x}; }
 
@@ -364,9 +369,11 @@ template <typename F> struct FlowArgs {
     const FlowMat<F> *mats;    // per-matrix table (batched), or null
     const int2 *tasks;         // (matrix, I << 16 | J) in dependency order
     int ntasks;
-    int *ctrl;                 // [0] ticket counter, [1] error word (both zeroed before)
+    int *ctrl;                 // [0] ticket counter (zeroed before each sweep), [1] error
+                               // word (zeroed once per run, so it keeps an earlier sweep's)
     int *flags;                // completion flags (zeroed before, or 1 for blocks not recomputed)
     int spin_limit;            // polls before a wait gives up and sets the error word
+                               // (negative: the first wait gives up at once; testing)
 };
 // C: complex entries (interleaved re, im).
 template <typename F, int KIND, bool C>
@@ -466,6 +473,12 @@ void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_b
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
              hipStream_t st);
+// Polls a dependency wait of the dataflow sweeps makes before it gives up and
+// sets the error word.  Testing hook: SIGNTRI_DEBUG_SPIN_LIMIT=-1 makes the first
+// wait of every sweep give up at once (the kernels still run to their end, on
+// whatever the operands hold), so that the host's check of the error word can be
+// exercised.
+int flow_spin_limit();
 // Wait for a run and report whether a dependency wait hit its safety bound.
 int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, bool cplx, void *host_ws,
                 hipStream_t st, int *err);

@@ -310,8 +310,9 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             if (g == 0 || cnt == 0) return;
             const int per = syl ? 1 : 2;  // flags per K step
             const int total = per * cnt;
-            bool timed_out = false;
-            for (int it = 0;; ++it) {
+            // (a negative limit, a testing hook, gives up at once)
+            bool timed_out = a.spin_limit < 0;
+            for (int it = 0; !timed_out; ++it) {
                 bool ok = true;
                 for (int e = tid; e < total; e += NT) {
                     int kind, K;

@@ -388,10 +388,14 @@ __global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64
             const double *zrow = Zr + ro;
             const double tii = Tt[r * FP + r];
             // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
-            // and one Newton step, which squares it (below 2.3e-15)
+            // and one Newton step, which squares it (below 2.3e-15); outside
+            // 2^-1020 <= |dx| <= 2^1020, where the estimate or its reciprocal would
+            // leave the normal range, the IEEE division instead
             const double dx = tii - lamll;
             double rcp = __builtin_amdgcn_rcp(dx);
             rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
+            const double adx = fabs(dx);
+            if (__builtin_expect(adx > 0x1p1020 || adx < 0x1p-1020, 0)) rcp = 1.0 / dx;
             // Full sums: every term outside the ranges that count is zero (the
             // lower triangle of the staged block, entries of Z not computed yet).
             // all operands first (paired LDS reads), then the multiply-adds

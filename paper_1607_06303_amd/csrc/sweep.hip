@@ -7,6 +7,7 @@
 // the other kernels take per-matrix tables.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -19,6 +20,7 @@ namespace {
 
 constexpr int TB = kFlowTile;
 constexpr int kSpinLimit = 1 << 22;  // polls before a dependency wait gives up
+
 
 int64_t nblocks(int64_t m) { return (m + TB - 1) / TB; }
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -37,7 +39,9 @@ hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *
                     int pk, double flops, int wgs, hipStream_t st)
 {
     if (nt == 0) return hipSuccess;
-    hipError_t r = launch_fill_int(ctrl, 2, 0, st);
+    // the ticket counter only: the error word (ctrl[1]) is cleared once per run,
+    // so that a wait that gave up in an earlier sweep of the run is still reported
+    hipError_t r = launch_fill_int(ctrl, 1, 0, st);
     if (r != hipSuccess) return r;
     FlowArgs<F> a;
     std::memset(&a, 0, sizeof(a));
@@ -46,7 +50,7 @@ hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *
     a.ntasks = (int)nt;
     a.ctrl = ctrl;
     a.flags = flags;
-    a.spin_limit = kSpinLimit;
+    a.spin_limit = flow_spin_limit();
     prof_begin(st);
     r = launch_flow<F, KIND, C>(a, wgs, st);
     prof_end(st, pk, flops);
@@ -198,6 +202,13 @@ SweepFlops item_flops(const int8_t *s, const RealItem &it)
 }
 
 }  // namespace
+
+int flow_spin_limit()
+{
+    const char *v = getenv("SIGNTRI_DEBUG_SPIN_LIMIT");
+    if (v && *v) return atoi(v);
+    return kSpinLimit;
+}
 
 void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_bytes,
                size_t *host_bytes)
@@ -406,7 +417,9 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     };
     HIPCHK(resid(norms[0]));
 
-    const int max_steps = (opts && opts->max_refine_steps > 0) ? opts->max_refine_steps : 2;
+    // 0 = the default of two steps; a negative value takes none (every block then
+    // counts as not converged: the FP64 recomputation, or SIGNTRI_ENOCONV)
+    const int max_steps = !opts || opts->max_refine_steps == 0 ? 2 : std::max(0, opts->max_refine_steps);
     const double stall = (opts && opts->stall_ratio > 0) ? opts->stall_ratio : 0.5;
     const double conv = 1e-5;  // residual reduction that counts as converged
     const int64_t force = opts ? opts->force_stall : 0;

@@ -128,6 +128,26 @@ def test_planner_matches_bruteforce(n, cplx):
             assert info["path"] == 0  # +-I, no solve
 
 
+def test_planner_hand_counted():
+    """The library's O(n) planner on the cases counted by hand from Section 3's
+    terms (see tests/test_workmodel_and_inputs.py::test_hand_counted_small_cases)."""
+    info = signtri.plan_host(np.array([1, 1, -1], dtype=np.int8))
+    assert info["w_ph"] == 4 and info["swaps"] == 0 and info["w_ps"] == 2 * 1 * 3
+    info = signtri.plan_host(np.array([1, -1, 1, -1], dtype=np.int8))
+    assert info["w_ph"] == 12 and info["swaps"] == 1 and info["w_ps"] == 112
+    info = signtri.plan_host(np.array([1, -1, 1, -1], dtype=np.int8), complex_=True)
+    assert info["w_ph"] == 48 and info["w_ps"] == 448
+
+
+def test_complex_takes_every_mode_and_negative_refine_steps():
+    # option checks run before any device work; n = 0 returns right after them
+    assert _call_opts(0, dtype=1, mode=1) == 0
+    assert _call_opts(0, dtype=1, mode=2) == 0
+    assert _call_opts(0, dtype=1, mode=1, max_refine_steps=-1) == 0
+    assert signtri.workspace_size(256, complex_=True, mode="mixed") > 0
+    assert signtri.workspace_size(256, complex_=True, mode="fp32") > 0
+
+
 def test_planner_choice_rule():
     n = 200
     # grouped by sign: Parlett-Sylvester (no reordering needed)

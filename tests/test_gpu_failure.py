@@ -1,0 +1,151 @@
+"""Failure handling forced from the host, and exponent extremes.
+
+Every failure here is forced by a testing hook the host sets, so that every
+kernel still runs to its end:
+  * SIGNTRI_DEBUG_SPIN_LIMIT=-1: the first dependency wait of each dataflow
+    sweep gives up at once and sets the error word; every entry point that
+    waits must then return SIGNTRI_EHIP, and the next normal call must succeed;
+  * SIGNTRI_DEBUG_FAIL_ALLOC=1: the library-owned workspace cannot be
+    allocated (SIGNTRI_ENOMEM), and nothing is launched;
+  * max_refine_steps < 0: no refinement step, so every block of the mixed mode
+    counts as not converged and is recomputed in FP64 (or SIGNTRI_ENOCONV).
+
+Exponent extremes: sign(2^k T) = sign(T) exactly (a power-of-two scaling
+passes through every product, sum and division of the substitution), so the
+FP64 paths must give bitwise the same U for T * 2^600, T and T * 2^-600, and
+that U must match the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_1607_06303_amd import workloads as wl
+from tests.conftest import rel_fro
+from tests.test_gpu_parity import TOL_FP64, check, dev, run_gpu, to_dev_colmajor  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+EHIP, ENOCONV, ENOMEM = 2, 4, 6
+
+
+def nblocks32(n):
+    b = (n + 31) // 32
+    return b * (b - 1) // 2
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "mixed"])
+def test_wait_that_gives_up_is_reported(dev, monkeypatch, mode):
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    T = wl.make_T(300, np.random.default_rng(11))
+    Tg = to_dev_colmajor(T, dev)
+    opts = {"sweep": "dataflow"}
+    monkeypatch.setenv("SIGNTRI_DEBUG_SPIN_LIMIT", "-1")
+    with pytest.raises(signtri.SignTriError) as e:
+        signtri.sign_tri(Tg, mode=mode, algo="ph", options=opts)
+    assert e.value.code == EHIP
+    with pytest.raises(signtri.SignTriError) as e:
+        signtri.sign_tri_batched([Tg, Tg], mode=mode)
+    assert e.value.code == EHIP
+    torch.cuda.synchronize()
+    monkeypatch.delenv("SIGNTRI_DEBUG_SPIN_LIMIT")
+    # the next calls run normally
+    U, info = signtri.sign_tri(Tg, mode=mode, algo="ph", options=opts)
+    tol = 1e-4 if mode == "fp32" else TOL_FP64
+    import oracle
+
+    ref = oracle.sign_tri(T)
+    assert rel_fro(U.cpu().numpy(), ref) <= tol
+    Us, _ = signtri.sign_tri_batched([Tg, Tg], mode=mode)
+    assert rel_fro(Us[1].cpu().numpy(), ref) <= tol
+
+
+def test_plain_form_reports_a_wait_that_gave_up(dev, monkeypatch):
+    """sign_tri() of the C ABI (no info argument) waits, so it reports it too."""
+    import ctypes
+
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    # interleaved signs: AUTO runs the Parlett-Higham dataflow sweep
+    T = wl.make_T(256, np.random.default_rng(12))
+    Tg = to_dev_colmajor(T, dev)
+    U = torch.empty_like(Tg)
+    L = signtri.lib()
+    monkeypatch.setenv("SIGNTRI_DEBUG_SPIN_LIMIT", "-1")
+    assert L.sign_tri(ctypes.c_void_p(Tg.data_ptr()), 256, 256, 0,
+                      ctypes.c_void_p(U.data_ptr())) == EHIP
+    monkeypatch.delenv("SIGNTRI_DEBUG_SPIN_LIMIT")
+    assert L.sign_tri(ctypes.c_void_p(Tg.data_ptr()), 256, 256, 0,
+                      ctypes.c_void_p(U.data_ptr())) == 0
+    import oracle
+
+    assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+def test_allocation_failure(dev, monkeypatch):
+    from paper_1607_06303_amd import signtri
+
+    T = wl.make_T(200, np.random.default_rng(13))
+    Tg = to_dev_colmajor(T, dev)
+    signtri.release()
+    monkeypatch.setenv("SIGNTRI_DEBUG_FAIL_ALLOC", "1")
+    with pytest.raises(signtri.SignTriError) as e:
+        signtri.sign_tri(Tg)
+    assert e.value.code == ENOMEM
+    with pytest.raises(signtri.SignTriError) as e:
+        signtri.sign_tri_batched([Tg])
+    assert e.value.code == ENOMEM
+    monkeypatch.delenv("SIGNTRI_DEBUG_FAIL_ALLOC")
+    check(T, dev)
+
+
+def test_zero_refinement_steps_recompute_everything(dev):
+    from paper_1607_06303_amd import signtri
+
+    n = 300
+    T = wl.make_T(n, np.random.default_rng(14))
+    U, info, err = check(T, dev, mode="mixed", algo="ph", options={"max_refine_steps": -1})
+    assert info["refine_steps"] == 0 and info["fallback_tiles"] == nblocks32(n)
+    with pytest.raises(signtri.SignTriError) as e:
+        run_gpu(T, dev, mode="mixed", algo="ph",
+                options={"max_refine_steps": -1, "no_fallback": 1})
+    assert e.value.code == ENOCONV
+
+
+def _scaled_case(name):
+    rng = np.random.default_rng(15)
+    if name == "proj_real":
+        return wl.make_T(700, rng, signs=wl.signs_with_negatives(700, 5, rng)), {"algo": "proj"}
+    if name == "proj_complex":
+        return (wl.make_T(300, rng, complex_=True, signs=wl.signs_with_negatives(300, 7, rng)),
+                {"algo": "proj"})
+    if name == "ph_dataflow_real":
+        return wl.make_T(300, rng), {"algo": "ph", "options": {"sweep": "dataflow"}}
+    if name == "ph_superdiag_real":
+        return wl.make_T(300, rng), {"algo": "ph", "options": {"sweep": "superdiag"}}
+    if name == "ph_dataflow_complex":
+        return wl.make_T(200, rng, complex_=True), {"algo": "ph", "options": {"sweep": "dataflow"}}
+    if name == "ph_superdiag_complex":
+        return wl.make_T(200, rng, complex_=True), {"algo": "ph", "options": {"sweep": "superdiag"}}
+    if name == "ps_real":
+        return wl.sorted_positive_first(wl.make_T(300, rng, p_pos=0.6)), {"algo": "ps"}
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["proj_real", "proj_complex", "ph_dataflow_real",
+                                  "ph_superdiag_real", "ph_dataflow_complex",
+                                  "ph_superdiag_complex", "ps_real"])
+def test_power_of_two_scaling_is_exact(dev, name):
+    import oracle
+
+    T, kw = _scaled_case(name)
+    U0, info = run_gpu(T, dev, **kw)
+    assert rel_fro(U0, oracle.sign_tri(T)) <= TOL_FP64, info
+    for k in (600, -600):
+        Ts = T * 2.0 ** k
+        assert np.all(np.isfinite(Ts)) and np.all(np.abs(np.diag(Ts)) > 0)
+        U, _ = run_gpu(Ts, dev, **kw)
+        assert np.array_equal(U, U0), (name, k, float(np.max(np.abs(U - U0))))

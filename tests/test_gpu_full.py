@@ -1,15 +1,22 @@
 """GPU parity at the full sizes of the benchmark workloads, through the same
 entry points bench.py times.
 
-The oracle cannot run sign(T) of the whole matrix in seconds at these sizes, so
-each result is checked on samples it can compute: for an upper-triangular T,
-the principal block U[a:a+m, a:a+m] of U = sign(T) is sign(T[a:a+m, a:a+m])
-(a function of a triangular matrix restricted to a contiguous diagonal range),
-so leading, trailing and random interior windows are compared entry by entry
-with the oracle at the 1e-11 bar.  At full size the invariants U^2 = I and
-TU = UT are checked as well (computed on the GPU in FP64), which covers the
-entries outside the windows.  The 2000-matrix batched workload is checked
-matrix by matrix in full.
+Workloads 2 (complex n = 4096, interleaved and grouped by sign) and 3 (real
+n = 8192, 64 negatives; FP64 and mixed precision) are compared with the CPU
+oracle on the WHOLE matrix, entry by entry, at the 1e-11 bar: the oracle runs
+them in a few seconds on the host's cores, once per workload (cached for the
+module).  The 2000-matrix batched workload 4 is checked matrix by matrix in
+full.
+
+Workload 5 (complex n = 16384) is the exception: its oracle run is about
+8.8e12 real flops, several minutes of the host's cores, more than a test may
+take.  It is checked on windows the oracle computes in seconds -- for an
+upper-triangular T the principal block U[a:a+m, a:a+m] of U = sign(T) is
+sign(T[a:a+m, a:a+m]) (a function of a triangular matrix restricted to a
+contiguous diagonal range), so leading, trailing and random interior windows
+are compared entry by entry -- and, at full size, on the invariants U^2 = I
+and TU = UT (computed on the GPU in FP64), which cover the entries outside the
+windows.
 """
 import numpy as np
 import pytest
@@ -19,6 +26,19 @@ from tests.conftest import rel_fro
 from tests.test_gpu_parity import TOL_FP64, dev, to_dev_colmajor  # noqa: F401
 
 pytestmark = pytest.mark.gpu
+
+_oracle_cache = {}
+
+
+def oracle_full(key, make):
+    """(T, oracle sign(T)) for a named workload, computed once per module."""
+    import oracle
+
+    if key not in _oracle_cache:
+        _oracle_cache.clear()  # keep one full-size pair in host memory at a time
+        T = make()
+        _oracle_cache[key] = (T, oracle.sign_tri(T))
+    return _oracle_cache[key]
 
 
 def windows(n, m, rng, count=2):
@@ -67,8 +87,8 @@ def run_full(T, dev, mode):
 
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_workload3_full(dev, mode):
-    """Real n = 8192 with 64 negative diagonal entries (the benchmark)."""
-    T = wl.workload3()
+    """Real n = 8192 with 64 negative diagonal entries (the benchmark), whole U."""
+    T, ref = oracle_full("w3", wl.workload3)
     Tg, U, info = run_full(T, dev, mode)
     print("workload3 %s: path %s sweep %s refine %d fallback %d"
           % (mode, info["path_name"], info["sweep_name"], info["refine_steps"],
@@ -76,25 +96,30 @@ def test_workload3_full(dev, mode):
     assert info["fallback_tiles"] == 0
     inv, com, lower = invariants(Tg, U)
     assert lower == 0 and inv <= 1e-13 and com <= 1e-13, (inv, com)
-    check_windows(T, U.cpu().numpy(), 1024, 31)
+    err = rel_fro(U.cpu().numpy(), ref)
+    print("workload3 %s: whole-matrix rel err %.3e" % (mode, err))
+    assert err <= TOL_FP64, err
 
 
 @pytest.mark.parametrize("sorted_", [False, True])
 def test_workload2_full(dev, sorted_):
-    """Complex n = 4096, balanced inertia, interleaved or grouped by sign."""
-    T = wl.workload2(sorted_=sorted_)
+    """Complex n = 4096, balanced inertia, interleaved or grouped by sign, whole U."""
+    T, ref = oracle_full(("w2", sorted_), lambda: wl.workload2(sorted_=sorted_))
     Tg, U, info = run_full(T, dev, "fp64")
     # grouped by sign, the Section 3 model takes the Sylvester form
     assert info["path_name"] == ("ps" if sorted_ else "ph")
     inv, com, lower = invariants(Tg, U)
     assert lower == 0 and inv <= 1e-12 and com <= 1e-12, (inv, com)
-    check_windows(T, U.cpu().numpy(), 768, 32)
+    err = rel_fro(U.cpu().numpy(), ref)
+    print("workload2 sorted=%s: whole-matrix rel err %.3e" % (sorted_, err))
+    assert err <= TOL_FP64, err
 
 
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_workload5_full(dev, mode):
     """Complex n = 16384 with diagonal real parts down to 1e-3 (near the imaginary axis);
-    mixed precision refines, and recomputes in FP64 any block whose refinement stalls."""
+    mixed precision refines, and recomputes in FP64 any block whose refinement stalls.
+    Windows against the oracle, invariants at full size (see the module docstring)."""
     import torch
 
     T = wl.workload5()

@@ -35,6 +35,34 @@ def test_ps_work_bounds():
     assert workmodel.swaps(half) == (0, n * n // 4)
 
 
+def test_hand_counted_small_cases():
+    """Section 3 counts worked out by hand, term by term.
+
+    [+, +, -]: pairs (0,1) and (1,2) have empty sums; pair (0,2) has one term
+    (k = 1) and opposite signs, so Eq. (1) costs two multiply-adds: 4 flops.
+    [+, -, +, -]: (0,2) and (1,3) have one term each with equal signs (Eq. (2),
+    one multiply-add, 2 flops each); (0,3) has two terms with opposite signs
+    (2 x 2 multiply-adds, 8 flops); the adjacent pairs have none: 12 flops.
+    Swaps of [+, -, +, -]: positives first needs the pair (1,2) exchanged (1);
+    negatives first needs (0,1), (0,3), (2,3) (3).  The Parlett-Sylvester
+    estimate with k = 1: reordering 12 n k = 48, Sylvester n- n+ (n- + n+) =
+    2 * 2 * 4 = 16, transformation back 12 n k = 48: 112.
+    """
+    assert workmodel.ph_flops([1, 1, -1]) == 4
+    assert workmodel.ph_flops([1, 1, -1], complex_=True) == 16
+    assert workmodel.ph_flops([1, -1, 1, -1]) == 12
+    # [+, +, +, +]: terms (0,2): 1, (1,3): 1, (0,3): 2, C(4,3) = 4 in all, 2 flops each
+    assert workmodel.ph_flops([1, 1, 1, 1]) == 8
+    assert workmodel.swaps([1, -1, 1, -1]) == (1, 3)
+    assert workmodel.swaps([-1, 1]) == (1, 0)
+    assert workmodel.ps_flops([1, -1, 1, -1]) == 112
+    assert workmodel.ps_flops([1, -1, 1, -1], complex_=True) == 448
+    # [+, -, -]: positives first: nothing to move (0); negatives first: the +
+    # passes both - (2).  k = 0, so no reordering term: Sylvester 2 * 1 * 3 = 6
+    assert workmodel.swaps([1, -1, -1]) == (0, 2)
+    assert workmodel.ps_flops([1, -1, -1]) == 6
+
+
 def test_workloads_deterministic_and_shaped():
     a = wl.workload1(64)
     b = wl.workload1(64)
