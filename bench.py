@@ -58,7 +58,7 @@ def kernel_name(family, mode, tile):
             "syl": "k_flow<%s, 2, false>" % fp,
             "resid": "k_resid64", "gemm": "k_wave_gemm<double, %d>" % tile,
             "solve": "k_solve_r<double, %d, 256>" % tile,
-            "proj": "k_proj_step", "proj_out": "k_proj_u"}.get(family)
+            "proj": "k_proj_run", "proj_out": "k_proj_u"}.get(family)
 
 
 def measured_traffic(kernel):

@@ -536,11 +536,16 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     }
     HostPlan p = plan_from_signs(hs, n, cplx);
     fill_info(info, p);
+    double dmin = 0.0, dmax = 0.0;
+    std::memcpy(&dmin, &sr.absmin, sizeof(double));
+    std::memcpy(&dmax, &sr.absmax, sizeof(double));
+    const bool rcp_guard = !(dmin >= 0x1p-1020 && dmax <= 0x1p1019);
 
     int path = p.auto_path;
     // AUTO takes the projector form in FP64 mode when no sweep or block size is pinned
     const bool pinned_sweep = opts && (opts->sweep != 0 || opts->tile != 0);
-    if (algo == SIGNTRI_AUTO && p.proj_pick && mode == SIGNTRI_FP64 && !pinned_sweep)
+    if (algo == SIGNTRI_AUTO && p.proj_pick && mode == SIGNTRI_FP64 && !pinned_sweep &&
+        (cplx || proj_fits(n)))
         path = SIGNTRI_PATH_PROJ;
     if (algo == SIGNTRI_PH && path != SIGNTRI_PATH_TRIVIAL) path = SIGNTRI_PATH_PH;
     if (algo == SIGNTRI_PS && path != SIGNTRI_PATH_TRIVIAL) {
@@ -549,6 +554,7 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     }
     if (algo == SIGNTRI_PROJ && path != SIGNTRI_PATH_TRIVIAL) {
         if (p.n_min < 1 || p.n_min > kProjMaxMinority) return SIGNTRI_ENOTSUP;
+        if (!cplx && !proj_fits(n)) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PROJ;
     }
     if (path == SIGNTRI_PATH_PROJ) {
@@ -565,8 +571,9 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         const int prc = cplx ? run_proj_c(Tc, ldtc, Uc, lduc, n, sgn, hs, p.min_sign,
                                           (int)p.n_min, 4.0 * flops, ws + L0.prefix, st)
                              : run_proj((const double *)Tc, ldtc, (double *)Uc, lduc, n, sgn, hs,
-                                        p.min_sign, (int)p.n_min, flops, ws + L0.prefix, st);
-        if (prc != SIGNTRI_OK) return SIGNTRI_EHIP;
+                                        p.min_sign, (int)p.n_min, flops, ws + L0.prefix, st,
+                                        info ? (int *)hflow : nullptr, rcp_guard);
+        if (prc != SIGNTRI_OK) return prc == SIGNTRI_ENOTSUP ? SIGNTRI_ENOTSUP : SIGNTRI_EHIP;
         if (layout == SIGNTRI_ROW_MAJOR && launch_transpose(Uc, lduc, U, ldu, n, cplx, st) != hipSuccess)
             return SIGNTRI_EHIP;
         if (info) {

@@ -147,6 +147,8 @@ __device__ inline fx4 mfma_f32(float a, float b, fx4 c)
 struct ScanResult {
     int64_t bad_index;  // smallest 0-based index with an undefined sign, or n
     int64_t n_pos;
+    uint64_t absmin, absmax;  // bits of min and max |Re t_ii| (nonnegative doubles order as
+                              // their bit patterns), over the entries with a defined sign
 };
 
 // Host planner (Section 3), shared by signtri() and signtri_plan_host().
@@ -334,8 +336,17 @@ size_t proj_workspace_bytes(int64_t n, bool cplx);
 // m = its count.  Queues every launch on st.
 // flops: algorithmic flops of the two substitutions, for the kernel timers.
 // hsgn: the same signs on the host.
+// herr: NULL, or host memory for the error word: then the call waits for the
+// result and returns SIGNTRI_EHIP if a dependency wait of the persistent
+// substitution kernel gave up.
+// SIGNTRI_ENOTSUP when m is out of range or n too large for one resident grid.
+// rcp_guard: some |t_ii| lies outside [2^-1020, 2^1019], where a reciprocal of
+// t_ii - t_jj by the hardware estimate could leave the normal range.
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
-             const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st);
+             const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st,
+             int *herr, bool rcp_guard);
+// Whether run_proj takes order n on the current device (its grid fits at once).
+bool proj_fits(int64_t n);
 // The same for complex T (interleaved complex128).
 int run_proj_c(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, const int8_t *sgn,
                const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st);
@@ -473,8 +484,8 @@ void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_b
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
              hipStream_t st);
-// Polls a dependency wait of the dataflow sweeps makes before it gives up and
-// sets the error word.  Testing hook: SIGNTRI_DEBUG_SPIN_LIMIT=-1 makes the first
+// Polls a dependency wait of the persistent kernels (the dataflow sweeps, the
+// projector form's substitutions) makes before it gives up and sets the error word.  Testing hook: SIGNTRI_DEBUG_SPIN_LIMIT=-1 makes the first
 // wait of every sweep give up at once (the kernels still run to their end, on
 // whatever the operands hold), so that the host's check of the error word can be
 // exercised.

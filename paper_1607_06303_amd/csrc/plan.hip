@@ -16,12 +16,15 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
 {
     __shared__ unsigned long long bad;
     __shared__ unsigned long long npos;
+    __shared__ unsigned long long amin, amax;
     if (threadIdx.x == 0) {
         bad = (unsigned long long)n;
         npos = 0;
+        amin = ~0ull;
+        amax = 0;
     }
     __syncthreads();
-    unsigned long long my_pos = 0;
+    unsigned long long my_pos = 0, my_min = ~0ull, my_max = 0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         double re, im = 0.0;
         if (cplx) {
@@ -43,12 +46,21 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
         }
         if (s == 0) atomicMin(&bad, (unsigned long long)i);
         my_pos += (s > 0);
+        if (s != 0) {
+            const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(re));
+            my_min = a < my_min ? a : my_min;
+            my_max = a > my_max ? a : my_max;
+        }
     }
     atomicAdd(&npos, my_pos);
+    atomicMin(&amin, my_min);
+    atomicMax(&amax, my_max);
     __syncthreads();
     if (threadIdx.x == 0) {
         res->bad_index = (int64_t)bad;
         res->n_pos = (int64_t)npos;
+        res->absmin = amin;
+        res->absmax = amax;
     }
 }
 

@@ -32,14 +32,15 @@
 //
 // Kernels (real T):
 //   k_proj_prep    minority rows and row types of both bases, from the signs;
-//   k_proj_step    one launch per block of 64 rows, bottom up: a workgroup
-//                  per basis runs the substitution above as a wavefront over
-//                  waves of eight columns (wave w at row r1 - 1 - s + (w - wmin)
-//                  at step s, wmin the wave of the first column not still zero
-//                  in the block; the coupling among a wave's own columns solved
-//                  in order within the wave; block operands in LDS), and
-//                  FP64 MFMA products keep acc, the sums over the rows below
-//                  each block, up to date for the next blocks;
+//   k_proj_run     one persistent launch for both bases: a workgroup per
+//                  basis runs the substitution above block by block (64 rows,
+//                  bottom up) as a wavefront over waves of eight columns (wave w
+//                  at row r1 - 1 - s + (w - wmin) at step s, wmin the wave of the
+//                  first column not still zero in the block; the coupling among a
+//                  wave's own columns solved in order within the wave; block
+//                  operands in LDS), while the other workgroups keep acc, the
+//                  sums over the rows below each block, up to date with FP64 MFMA
+//                  products as the blocks are published (per-block flags);
 //   k_proj_gram    partial sums of W^T Z over 64-row chunks (MFMA);
 //   k_proj_gsum    W^T Z, the partials summed;
 //   k_proj_minv    its inverse (unit upper triangular, m x m);
@@ -48,6 +49,7 @@
 //                  (FP64 MFMA, 64 x 64 output tiles).
 // Complex T runs simpler kernels of the same structure (k_projc_*, below).
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -67,7 +69,6 @@ struct ProjBasis {
     int flip;             // 1: entry (i, j) of this basis's matrix is T[n-1-j, n-1-i]
     double *Z;            // n x PM, leading dimension n
     double *acc;          // n x PM: sum over the rows below the current block
-    double *lam;          // PM x PM, lam[lp * PM + l] = L[lp][l]
     const int *rowtype;   // n: minority column of row i, or -1
     const int *pos;       // PM: row of minority column l, or -1 (l >= m)
 };
@@ -178,311 +179,435 @@ __device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
     mm64_acc<OP, OP>(As, Bs, d);
 }
 
-// Stage As[k * OP + r] = T[row0 + r, k0 + k] (rows < rlim, k < k1 - k0) and, when
-// Bs is given, Bs[k * OP + c] = Z[k0 + k, c] (c < m); zeros elsewhere.
-__device__ inline void stage_tz(const ProjBasis &B, int64_t n, int m, int64_t row0, int64_t rlim,
-                                int64_t k0, int64_t k1, double *As, double *Bs)
-{
-    const int t = threadIdx.x, lr = t & 63;
-    const int nk = (int)(k1 - k0);
-    // As down the matrix's columns (in J T^T J: along T's columns, lane = k),
-    // Bs down Z's columns (lane = k): all coalesced
-    for (int k = t >> 6; k < 64; k += 4) {
-        if (B.flip) {
-            const int64_t row = row0 + k;
-            As[lr * OP + k] = (lr < nk && row < rlim) ? B.T[toff(B, n, row, k0 + lr)] : 0.0;
-        } else {
-            const int64_t row = row0 + lr;
-            As[k * OP + lr] = (k < nk && row < rlim) ? B.T[toff(B, n, row, k0 + k)] : 0.0;
-        }
-        if (Bs) Bs[lr * OP + k] = (lr < nk && k < m) ? B.Z[(k0 + lr) + (int64_t)k * n] : 0.0;
-    }
-}
-
-// acc[row0 + i, j] += d (rows < rlim, columns < m)
-__device__ inline void add_acc(const ProjBasis &B, int64_t n, int m, int64_t row0, int64_t rlim,
-                               const dx4 (&d)[2][2])
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t row = row0 + rb + 16 * x + mfma64_row(lane, e);
-                const int c = cb + 16 * y + (lane & 15);
-                if (row < rlim && c < m) B.acc[row + (int64_t)c * n] += d[x][y][e];
-            }
-}
-
 // ---------------------------------------------------------------------------
-// Front: rows [r0, r1) of Z for both bases (blockIdx.x = basis).  NQ lanes
-// per column: column l is served by lanes NQ (l % (64 / NQ)) + q of wave
-// l / (64 / NQ), lane q taking the terms NQ u + q of the two 64-term sums of
-// every entry (reduced over the NQ lanes by DPP), so that the LDS reads of one
-// 16-lane pass fall in distinct banks (pitch = NQ mod 16 doubles).  Column l's
-// coefficients L[NQ u + q][l] stay in registers.
+// The substitutions of both bases in one persistent launch.
+//
+// Rows are taken in blocks of PB = 64 from the bottom up: block b holds rows
+// [r0(b), r1(b)) with r1(b) = n - 64 b (the top block may be short).  Row i of
+// T Z = Z L needs the sums acc[i, l] = sum_{j > i} t_ij z_jl over the rows below
+// it; for the rows of block b these split into the rows of block b itself
+// (solved in order within the block), of block b - 1 (the block just below),
+// and of the blocks further down.
+//
+// Workgroups 0 and 1 ("fronts") run the two bases, block after block: each
+// adds block b - 1's part of its sums itself (one 64 x 64 x 64 FP64 MFMA
+// product, with block b - 1's Z still in LDS), solves block b row by row as a
+// wavefront over waves of eight columns, and publishes block b's rows of Z.
+// The other workgroups ("owners") each own row blocks i >= 2 of one basis and
+// keep the far part of their sums, sum over the blocks j <= i - 2, in MFMA
+// accumulators: as each block j is published they add T[block i, block j]
+// Z[block j], and after the last one (j = i - 2) they publish acc of block i.
+// A front therefore waits only for work that finished a whole block earlier,
+// and its operands for the next block (T's diagonal block and the panel
+// against the block below) are fetched while the current block is solved.
+//
+// Hand-offs go through flags in device memory.  The data behind a flag is
+// written with device-coherent stores that complete before the flag's store,
+// and read with device-coherent loads issued after the flag was seen, so no L2
+// is written back or invalidated (the eight L2s of the chip are not coherent
+// with each other).  Every wait is bounded: past the limit it sets the error
+// word, which the host reports, and goes on, so the grid always drains.  All
+// workgroups of the launch are resident at once (the host sizes the grid to
+// the compute units), and a front never waits for an owner that waits for it.
 // ---------------------------------------------------------------------------
 constexpr int NQ = 8;          // lanes per column, each taking every NQ-th term
 constexpr int NU = PB / NQ;    // terms per lane
-constexpr int NTS = 64 * NQ;   // threads of a front workgroup (one column per NQ lanes)
+constexpr int NTS = 64 * NQ;   // threads of a workgroup (one column per NQ lanes)
 constexpr int NWS = NTS / 64;  // its waves
 constexpr int FP = PB + NQ;    // LDS pitch of the staged T block and of the Z block: one
                                // 16-lane pass of a read falls in distinct banks
+constexpr int KMAX = 2;        // row blocks per owner at most
 
-//
-// One launch per block [r0, r1), with the block below it, [r1, p1), already
-// solved (p1 == r1 for the bottom block).  Workgroups 0 and 1 run the front of
-// the two bases; each first adds the block below's contribution to its own
-// rows' sums, in LDS, with operands fetched together with the block's.
-// Workgroups 2.. add the block below's contribution to every row above the
-// block, concurrently (the fronts read only the sums of rows [r0, r1)).  So
-// the sums of a block's rows hold every block below it when its front starts.
-// lmin0, lmin1: per basis, the minority columns whose row lies above the block
-// (b_l < r0): they stay zero throughout it, and the wavefront starts at the
-// first column after them.
-__global__ __launch_bounds__(NTS) void k_proj_step(ProjArgs a, int64_t r0, int64_t r1, int64_t p1,
-                                                   int lmin0, int lmin1)
+struct ProjSync {
+    int *zdone;     // [basis * nb + b]: block b's rows of Z published
+    int *accready;  // [basis * nb + b]: acc of block b's rows holds the blocks j <= b - 2
+    int *err;       // error word: a wait gave up
+    int spin_limit; // polls before a wait gives up (negative: at once; a testing hook)
+    int nb;         // row blocks
+    int nown;       // owner workgroups per basis
+    int kper;       // row blocks per owner (<= KMAX)
+    int rcp_guard;  // some |t_ii| outside [2^-1020, 2^1019]: reciprocals checked for range
+};
+
+__device__ inline int flag_load(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double coherent_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void coherent_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish: every wave's stores complete, then one flag store.
+__device__ inline void publish_flag(int *flag)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (thread 0 polls, the workgroup meets at a barrier after it) until *flag
+// is set, at most spin_limit polls.
+__device__ inline void wait_flag(const int *flag, const ProjSync &S)
+{
+    if (threadIdx.x == 0) {
+        bool ok = S.spin_limit >= 0;
+        for (int it = 0; ok && flag_load(flag) == 0; ++it)
+            if (it >= S.spin_limit || flag_load(S.err) != 0) {
+                ok = false;
+            } else {
+                __builtin_amdgcn_s_sleep(1);
+            }
+        if (!ok) atomicOr(S.err, 1);
+    }
+    __syncthreads();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the poll
+}
+
+__device__ inline int64_t blk_r1(int64_t n, int b) { return n - (int64_t)PB * b; }
+__device__ inline int64_t blk_r0(int64_t n, int b)
+{
+    const int64_t r = n - (int64_t)PB * (b + 1);
+    return r > 0 ? r : 0;
+}
+
+// Owner: row blocks i = 2 + w + k nown (k < kper) of basis `beta`; block i's sum
+// over the blocks j <= i - 2 in MFMA accumulators (eight waves, each two 16 x 16
+// pieces of the 64 x 64 block: rows 16 (wave / 2), columns 32 (wave % 2)).
+__device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, double *Bs)
+{
+    const int o = (int)blockIdx.x - 2;
+    const int beta = o & 1, w = o >> 1;
+    const ProjBasis &B = a.b[beta];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int rb = 16 * (wv >> 1), cb = 32 * (wv & 1);
+    const int kr = lane >> 4, cc = lane & 15;
+    int ilast = -1;
+    for (int k = 0; k < S.kper; ++k)
+        if (2 + w + k * S.nown < S.nb) ilast = 2 + w + k * S.nown;
+    ilast = uniform(ilast);
+    dx4 d[KMAX][2];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) d[k][0] = d[k][1] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j + 2 <= ilast; ++j) {
+        const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
+        wait_flag(S.zdone + beta * S.nb + j, S);
+        // Bs[kk * OP + c] = Z[k0 + kk, c]: published in this launch, coherent loads
+        for (int c = wv; c < 64; c += NWS)
+            Bs[lane * OP + c] = (c < m && k0 + lane < k1) ? coherent_load(B.Z + (k0 + lane) + (int64_t)c * n) : 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int i = 2 + w + k * S.nown;
+            if (k >= S.kper || i > ilast || i < j + 2) continue;  // uniform
+            const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
+            // As[kk * OP + r] = entry (r0 + r, k0 + kk) of the basis's matrix (its
+            // upper triangle: block i lies above block j)
+            for (int x = wv; x < 64; x += NWS) {
+                if (B.flip) {
+                    // entry (r0 + x, k0 + lane) is T[n-1-k0-lane, n-1-r0-x]: lane along T's column
+                    As[lane * OP + x] = (r0 + x < r1 && k0 + lane < k1)
+                                            ? B.T[(n - 1 - k0 - lane) + (n - 1 - r0 - x) * B.ldt] : 0.0;
+                } else {
+                    As[x * OP + lane] = (r0 + lane < r1 && k0 + x < k1)
+                                            ? B.T[(r0 + lane) + (k0 + x) * B.ldt] : 0.0;
+                }
+            }
+            __syncthreads();
+            for (int kk = 0; kk < 64; kk += 4) {
+                const double av = As[(kk + kr) * OP + rb + cc];
+                const double b0 = Bs[(kk + kr) * OP + cb + cc];
+                const double b1 = Bs[(kk + kr) * OP + cb + 16 + cc];
+                d[k][0] = mfma_f64(av, b0, d[k][0]);
+                d[k][1] = mfma_f64(av, b1, d[k][1]);
+            }
+            __syncthreads();
+            if (i == j + 2) {
+                // the last block below: publish acc of block i
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t row = r0 + rb + mfma64_row(lane, e);
+                        const int c = cb + 16 * y + cc;
+                        if (row < r1 && c < m) coherent_store(B.acc + row + (int64_t)c * n, d[k][y][e]);
+                    }
+                publish_flag(S.accready + beta * S.nb + i);
+            }
+        }
+    }
+}
+
+// Front of one basis (blockIdx.x): every block, bottom up.
+__global__ __launch_bounds__(NTS) void k_proj_run(ProjArgs a, ProjSync S)
 {
     // one arena, so that a step's row of T and row of Z sit within the reach of
     // one base address and the loads' immediate offsets
     __shared__ double arena[PB * FP + PB * FP + PM * FP + PB * AP];
     double *const Tt = arena;         // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
     double *const Zr = Tt + PB * FP;  // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
-    double *const Zc = Zr + PB * FP;  // Zc[l * FP + r] = Z[r0 + r, l], the same values by column
+    double *const Zc = Zr + PB * FP;  // Zc[l * FP + r] = Z[r0 + r, l], the same values by column;
+                                      // at a block's start, the panel against the block below
     double *const Ab = Zc + PM * FP;  // Ab[r * AP + l] = acc[r0 + r, l]
 
-    const int64_t n = a.n;
-    const int m = a.m;
-    const int t = threadIdx.x;
-    const int nr = (int)(r1 - r0);
-    const bool below = p1 > r1;
-
     if (blockIdx.x >= 2) {
-        // rows [64 x, 64 x + 64) above the block, of one basis, times the block below
-        // (on the first four waves; the others only meet the barrier)
-        const int bid = (int)blockIdx.x - 2;
-        const ProjBasis B = a.b[bid & 1];
-        const int64_t row0 = (int64_t)(bid >> 1) * 64;
-        if (t < 256) stage_tz(B, n, m, row0, r0, r1, p1, Tt, Ab);
-        __syncthreads();
-        if (t < 256) {
-            dx4 d[2][2];
-            mm64(Tt, Ab, d);
-            add_acc(B, n, m, row0, r0, d);
-        }
+        proj_owner(a, S, Tt, Zr);
         return;
     }
 
     const ProjBasis B = a.b[blockIdx.x];
-    const int col = (t >> 6) * (64 / NQ) + ((t & 63) / NQ);
-    const int q = t % NQ;
-    // column l's coefficients, its minority row and the block's row types: loaded
-    // first, so that their latency overlaps the staging below
+    const int beta = blockIdx.x;
+    const int64_t n = a.n;
+    const int m = a.m;
     constexpr int CW = 64 / NQ;  // columns per wave
-    const int wv = uniform(t >> 6), kw = (t & 63) / NQ;  // col = CW wv + kw
-    double lreg[NU], lw[CW];
+    constexpr int NK = 64 / NWS;
+    const int wv = uniform(threadIdx.x >> 6);
+    // The thread's index, opaque to the compiler where it is read: what derives
+    // from it is computed again per block instead of being held in registers
+    // across the block loop (which would not leave enough for the wavefront).
+    auto tid = [] {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
+    // Per column, across blocks: the coefficients L[NQ u + q][l], and L[CW wv + k'][l]
+    // for the rows of this wave's columns (k' < kw), in every lane of the column;
+    // L[l][l] (t at row b_l, set at that row); all zero until the rows that define
+    // them are reached.  The column's minority row, and lane x's minority row x.
+    double lreg[NU], lw[CW], lamll = 0.0;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) lreg[u] = B.lam[(NQ * u + q) * PM + col];
-    // the same column of L for the rows of this wave's columns, in every lane of
-    // the column: lw[k'] = L[CW wv + k', l] for k' < kw, zero from the diagonal on
+    for (int u = 0; u < NU; ++u) lreg[u] = 0.0;
 #pragma unroll
-    for (int kp = 0; kp < CW; ++kp) lw[kp] = kp < kw ? B.lam[(CW * wv + kp) * PM + col] : 0.0;
-    // L[l, l] (t at row b_l; set at that row when it lies in this block)
-    double lamll = B.lam[col * PM + col];
-    const int pl = B.pos[col];  // (PM entries, -1 from m on)
-    // the block's row types, lane i holding row i's (every wave)
-    const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
+    for (int kp = 0; kp < CW; ++kp) lw[kp] = 0.0;
+    const int pl = B.pos[(threadIdx.x >> 6) * CW + (threadIdx.x & 63) / NQ];  // (-1 from m on)
+    const int posl = B.pos[threadIdx.x & 63];
+    const bool fl = B.flip != 0;
 
-    // ---- stage the block's operands and the block below's (64 consecutive rows
-    // per wave, coalesced; every load issued before the first store)
-    {
-        const int row = t & 63, c0 = t >> 6;
-        const int nk = (int)(p1 - r1);
-        constexpr int NK = 64 / NWS;
-        // (in J T^T J the lane runs along the block's columns, which are T's rows)
-        const bool fl = B.flip != 0;
-        double tv[NK], av[NK], pv[NK], zv[NK];
+    // operands of a block fetched ahead: its diagonal block of T and its panel
+    // against the block below (T[r0 + i, r1 + k]); lane = block row, wave =
+    // column offset (in J T^T J the lane runs along the block's columns, which
+    // are T's rows)
+    double tv[NK], pv[NK];
+    auto fetch = [&](int b) {
+        const int t = tid(), row = t & 63, c0 = t >> 6;
+        const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+        const int nr = (int)(r1 - r0);
+        const int nk = b > 0 ? (int)(blk_r1(n, b - 1) - r1) : 0;
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int c = c0 + NWS * k;
             const int tr = fl ? c : row, tc = fl ? row : c;  // block row and column
             tv[k] = (tr < nr && tc < nr && tr <= tc) ? B.T[toff(B, n, r0 + tr, r0 + tc)] : 0.0;
             pv[k] = (tr < nr && tc < nk) ? B.T[toff(B, n, r0 + tr, r1 + tc)] : 0.0;
-            av[k] = (row < nr && c < m) ? B.acc[(r0 + row) + (int64_t)c * n] : 0.0;
-            zv[k] = (row < nk && c < m) ? B.Z[(r1 + row) + (int64_t)c * n] : 0.0;
         }
+    };
+    fetch(0);
+
+    for (int b = 0; b < S.nb; ++b) {
+        const int t = tid();
+        const int col = (t >> 6) * CW + ((t & 63) / NQ);
+        const int q = t % NQ;
+        const int row = t & 63, c0 = t >> 6;       // staging: lane = row, wave = column offset
+        const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+        const int nr = (int)(r1 - r0);
+        const bool below = b > 0;
+        // the block's sums over the blocks j <= b - 2, from its owner
+        double av[NK];
+        if (b >= 2) wait_flag(S.accready + beta * S.nb + b, S);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int c = c0 + NWS * k;
+            av[k] = (b >= 2 && row < nr && c < m) ? coherent_load(B.acc + (r0 + row) + (int64_t)c * n) : 0.0;
+        }
+        // the block's row types, lane i holding row i's (every wave)
+        const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
+        __syncthreads();  // the previous block's wavefront and stores of Z are done
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int c = c0 + NWS * k;
             const int tr = fl ? c : row, tc = fl ? row : c;
             Tt[tr * FP + tc] = tv[k];
-            Zr[tc * FP + tr] = pv[k];  // k-major: Zr[k * FP + r] = T[r0 + r, r1 + k]
+            Zc[tc * FP + tr] = pv[k];  // k-major: Zc[k * FP + r] = T[r0 + r, r1 + k]
             Ab[row * AP + c] = av[k];
-            Zc[row * FP + c] = zv[k];  // k-major: Zc[k * FP + l] = Z[r1 + k, l]
-        }
-    }
-    __syncthreads();
-    if (below) {
-        if (t < 256) {  // the product runs on four waves
-            dx4 d[2][2];
-            mm64_acc_zero(d);
-            mm64_acc<FP, FP>(Zr, Zc, d);
-            const int lane = t & 63, w = t >> 6;
-            const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = rb + 16 * x + mfma64_row(lane, e);
-                        const int c = cb + 16 * y + (lane & 15);
-                        Ab[r * AP + c] += d[x][y][e];
-                    }
         }
         __syncthreads();
-    }
-    for (int e = t; e < PB * FP; e += NTS) {
-        Zr[e] = 0.0;
-        Zc[e] = 0.0;
-    }
-    __syncthreads();
+        if (below) {
+            // block b - 1's part of the sums: Zr still holds its rows of Z (k-major)
+            if (t < 256) {  // the product runs on four waves
+                dx4 d[2][2];
+                mm64_acc_zero(d);
+                mm64_acc<FP, FP>(Zc, Zr, d);
+                const int lane = t & 63, w = t >> 6;
+                const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = rb + 16 * x + mfma64_row(lane, e);
+                            const int c = cb + 16 * y + (lane & 15);
+                            Ab[r * AP + c] += d[x][y][e];
+                        }
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < PB * FP; e += NTS) {
+            Zr[e] = 0.0;
+            Zc[e] = 0.0;
+        }
+        // block b - 1's rows of Z, stored at the end of its wavefront, are complete:
+        // flag them for the owners
+        if (below) {
+            publish_flag(S.zdone + beta * S.nb + (b - 1));
+        }
+        __syncthreads();
+        // the next block's operands, fetched during this block's wavefront
+        if (b + 1 < S.nb) fetch(b + 1);
 
-    // ---- wavefront by waves: at step s the columns of wave w all handle block
-    // row r = nr - 1 - s + (w - wmin), wmin the wave of the first active column.
-    // A column's sums read its own column (earlier steps) and row r of the
-    // columns of the waves before it (written at step s - 1 and earlier); the
-    // coupling among the wave's own columns, whose entries of row r are still
-    // zero in those sums, is solved after the reduction, column by column within
-    // the wave.  At a minority row that coupling is zero (the row of Z is e_typ
-    // and L's row typ is not set yet), so only majority rows take that chain.
-    const int lmin = uniform(blockIdx.x == 0 ? lmin0 : lmin1);
-    const int wmin = lmin / CW, wlast = (m - 1) / CW;
-    const int steps = uniform(m > lmin ? nr + (wlast - wmin) : 0);
-    // the column's minority row within the block (-1: above it, PB: below it)
-    const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
-    const int rhi = col < m ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
-    const double *const zcol = Zc + col * FP + q;
-    // The coupling terms of wave w come from the columns of the waves before it
-    // (chunks u < w); the others are still zero when read.  The step loop is
-    // instantiated per wave with that chunk count, so no step tests it.
-    auto front = [&](auto wtag) {
-    constexpr int NCU = decltype(wtag)::value;  // coupling chunks of this wave
-    for (int s = 0; s < steps; ++s) {
-        const int r = nr - 1 - s + (wv - wmin);  // the wave's row (uniform)
-        const bool act = r >= 0 && r <= rhi;
-        // the wave's active columns: a contiguous range (b_l grows with l)
-        const uint64_t am = __builtin_amdgcn_ballot_w64(act);
-        if (am != 0) {  // then 0 <= r < nr
-            // chain steps: the active columns but the last, as a bit mask
-            const int klo = __builtin_ctzll(am) / NQ, khi = (64 - __builtin_clzll(am)) / NQ;
-            const int chain = uniform(((1 << (khi - 1)) - 1) & ~((1 << klo) - 1));
-            int ro = r * FP;
-            // opaque to loop strength reduction: one base address for the step's
-            // reads of both rows, with immediate offsets
-            asm volatile("" : "+v"(ro));
-            const double *trow = Tt + ro;
-            const double *zrow = Zr + ro;
-            const double tii = Tt[r * FP + r];
-            // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
-            // and one Newton step, which squares it (below 2.3e-15); outside
-            // 2^-1020 <= |dx| <= 2^1020, where the estimate or its reciprocal would
-            // leave the normal range, the IEEE division instead
-            const double dx = tii - lamll;
-            double rcp = __builtin_amdgcn_rcp(dx);
-            rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
-            const double adx = fabs(dx);
-            if (__builtin_expect(adx > 0x1p1020 || adx < 0x1p-1020, 0)) rcp = 1.0 / dx;
-            // Full sums: every term outside the ranges that count is zero (the
-            // lower triangle of the staged block, entries of Z not computed yet).
-            // all operands first (paired LDS reads), then the multiply-adds
-            double tv[NU], zv[NU], rv[NCU > 0 ? NCU : 1];
+        // ---- wavefront by waves: at step s the columns of wave w all handle block
+        // row r = nr - 1 - s + (w - wmin), wmin the wave of the first active column.
+        // A column's sums read its own column (earlier steps) and row r of the
+        // columns of the waves before it (written at step s - 1 and earlier); the
+        // coupling among the wave's own columns, whose entries of row r are still
+        // zero in those sums, is solved after the reduction, column by column within
+        // the wave.  At a minority row that coupling is zero (the row of Z is e_typ
+        // and L's row typ is not set yet), so only majority rows take that chain.
+        // lmin: the minority columns whose row lies above the block (b_l < r0) stay
+        // zero throughout it, and the wavefront starts at the first column after them.
+        const int lmin = __builtin_popcountll(
+            __builtin_amdgcn_ballot_w64((t & 63) < m && posl >= 0 && posl < r0));
+        const int wmin = lmin / CW, wlast = (m - 1) / CW;
+        const int steps = uniform(m > lmin ? nr + (wlast - wmin) : 0);
+        // the column's minority row within the block (-1: above it, PB: below it)
+        const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
+        const int rhi = col < m ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
+        const double *const zcol = Zc + col * FP + q;
+        // The coupling terms of wave w come from the columns of the waves before it
+        // (chunks u < w); the others are still zero when read.  The step loop is
+        // instantiated per wave with that chunk count, so no step tests it.
+        auto front = [&](auto wtag) {
+        constexpr int NCU = decltype(wtag)::value;  // coupling chunks of this wave
+        for (int s = 0; s < steps; ++s) {
+            const int r = nr - 1 - s + (wv - wmin);  // the wave's row (uniform)
+            const bool act = r >= 0 && r <= rhi;
+            // the wave's active columns: a contiguous range (b_l grows with l)
+            const uint64_t am = __builtin_amdgcn_ballot_w64(act);
+            if (am != 0) {  // then 0 <= r < nr
+                // chain steps: the active columns but the last, as a bit mask
+                const int klo = __builtin_ctzll(am) / NQ, khi = (64 - __builtin_clzll(am)) / NQ;
+                const int chain = uniform(((1 << (khi - 1)) - 1) & ~((1 << klo) - 1));
+                int ro = r * FP;
+                // opaque to loop strength reduction: one base address for the step's
+                // reads of both rows, with immediate offsets
+                asm volatile("" : "+v"(ro));
+                const double *trow = Tt + ro;
+                const double *zrow = Zr + ro;
+                // Full sums: every term outside the ranges that count is zero (the
+                // lower triangle of the staged block, entries of Z not computed yet).
+                // all operands first (paired LDS reads), then the multiply-adds
+                double tv_[NU], zv[NU], rv[NCU > 0 ? NCU : 1];
 #pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                tv[u] = trow[NQ * u + q];
-                zv[u] = zcol[NQ * u];
-                if (u < NCU) rv[u] = zrow[NQ * u + q];
-            }
-            // (the block's sum read by all the column's lanes, one address: a broadcast,
-            // no branch)
-            const double ab = Ab[r * AP + col];
-            double v0 = q == 0 ? ab : 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
-#pragma unroll
-            for (int u = 0; u < NU; u += 2) {
-                v0 += tv[u] * zv[u];
-                v1 += tv[u + 1] * zv[u + 1];
-            }
-#pragma unroll
-            for (int u = 0; u < NCU; u += 2) {
-                c0 += rv[u] * lreg[u];
-                if (u + 1 < NCU) c1 += rv[u + 1] * lreg[u + 1];
-            }
-            // d = coupling (waves before this one) - sum
-            const double d = group_sum<NQ>((c0 + c1) - (v0 + v1));
-            const int typ = __builtin_amdgcn_readlane(rtl, r);
-            double z = 0.0;
-            if (typ >= 0) {
-                // (the active columns only: an inactive one's column of L stays as is)
-                if (act && r == plr) {
-                    z = 1.0;
-                    lamll = tii;
-#pragma unroll
-                    for (int u = 0; u < NU; ++u)
-                        if (NQ * u + q == col) lreg[u] = tii;
-                } else if (act) {
-                    // minority row b_typ (typ < l): row typ of L
-#pragma unroll
-                    for (int u = 0; u < NU; ++u)
-                        if (NQ * u + q == typ) lreg[u] = -d;
-#pragma unroll
-                    for (int kp = 0; kp < CW; ++kp)
-                        if (CW * wv + kp == typ) lw[kp] = -d;
+                for (int u = 0; u < NU; ++u) {
+                    tv_[u] = trow[NQ * u + q];
+                    zv[u] = zcol[NQ * u];
+                    if (u < NCU) rv[u] = zrow[NQ * u + q];
                 }
-            } else {
-                // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
-                // wave's active columns in order, with the reciprocal folded into
-                // the coefficients (one multiply-add per link); lw is zero from the
-                // diagonal on, so the later terms add nothing to a column solved
-                double lwr[CW - 1];
+                const double tii = Tt[r * FP + r];
+                // (the block's sum read by all the column's lanes, one address: a broadcast,
+                // no branch)
+                const double ab = Ab[r * AP + col];
+                // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
+                // and one Newton step, which squares it (below 2.3e-15).  The signs of
+                // t_ii and L[l, l] differ, so |dx| >= min |t_kk| and |dx| <= 2 max |t_kk|;
+                // only when the diagonal leaves [2^-1020, 2^1019] (a uniform test) can
+                // |dx| leave [2^-1020, 2^1020], where the estimate or its reciprocal would
+                // not be normal: then the IEEE division for those entries
+                const double dx = tii - lamll;
+                double rcp = __builtin_amdgcn_rcp(dx);
+                rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
+                if (__builtin_expect(S.rcp_guard != 0, 0)) {
+                    const double adx = fabs(dx);
+                    if (adx > 0x1p1020 || adx < 0x1p-1020) rcp = 1.0 / dx;
+                }
+                double v0 = q == 0 ? ab : 0.0, v1 = 0.0, cp0 = 0.0, cp1 = 0.0;
 #pragma unroll
-                for (int kp = 0; kp < CW - 1; ++kp) lwr[kp] = lw[kp] * rcp;
-                z = d * rcp;
+                for (int u = 0; u < NU; u += 2) {
+                    v0 += tv_[u] * zv[u];
+                    v1 += tv_[u + 1] * zv[u + 1];
+                }
 #pragma unroll
-                for (int kp = 0; kp < CW - 1; ++kp)
-                    if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+                for (int u = 0; u < NCU; u += 2) {
+                    cp0 += rv[u] * lreg[u];
+                    if (u + 1 < NCU) cp1 += rv[u + 1] * lreg[u + 1];
+                }
+                // d = coupling (waves before this one) - sum
+                const double d = group_sum<NQ>((cp0 + cp1) - (v0 + v1));
+                const int typ = __builtin_amdgcn_readlane(rtl, r);
+                double z = 0.0;
+                if (typ >= 0) {
+                    // (the active columns only: an inactive one's column of L stays as is)
+                    if (act && r == plr) {
+                        z = 1.0;
+                        lamll = tii;
+#pragma unroll
+                        for (int u = 0; u < NU; ++u)
+                            if (NQ * u + q == col) lreg[u] = tii;
+                    } else if (act) {
+                        // minority row b_typ (typ < l): row typ of L
+#pragma unroll
+                        for (int u = 0; u < NU; ++u)
+                            if (NQ * u + q == typ) lreg[u] = -d;
+#pragma unroll
+                        for (int kp = 0; kp < CW; ++kp)
+                            if (CW * wv + kp == typ) lw[kp] = -d;
+                    }
+                } else {
+                    // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
+                    // wave's active columns in order, with the reciprocal folded into
+                    // the coefficients (one multiply-add per link); lw is zero from the
+                    // diagonal on, so the later terms add nothing to a column solved
+                    double lwr[CW - 1];
+#pragma unroll
+                    for (int kp = 0; kp < CW - 1; ++kp) lwr[kp] = lw[kp] * rcp;
+                    z = d * rcp;
+#pragma unroll
+                    for (int kp = 0; kp < CW - 1; ++kp)
+                        if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+                }
+                if (q == 0 && act) {
+                    Zr[r * FP + col] = z;
+                    Zc[col * FP + r] = z;
+                }
             }
-            if (q == 0 && act) {
-                Zr[r * FP + col] = z;
-                Zc[col * FP + r] = z;
-            }
+            __syncthreads();
+        }
+        };
+        static_assert(NWS == 8, "one instance per wave");
+        switch (wv) {
+            case 0: front(std::integral_constant<int, 0>{}); break;
+            case 1: front(std::integral_constant<int, 1>{}); break;
+            case 2: front(std::integral_constant<int, 2>{}); break;
+            case 3: front(std::integral_constant<int, 3>{}); break;
+            case 4: front(std::integral_constant<int, 4>{}); break;
+            case 5: front(std::integral_constant<int, 5>{}); break;
+            case 6: front(std::integral_constant<int, 6>{}); break;
+            default: front(std::integral_constant<int, 7>{}); break;
         }
         __syncthreads();
-    }
-    };
-    static_assert(NWS == 8, "one instance per wave");
-    switch (wv) {
-        case 0: front(std::integral_constant<int, 0>{}); break;
-        case 1: front(std::integral_constant<int, 1>{}); break;
-        case 2: front(std::integral_constant<int, 2>{}); break;
-        case 3: front(std::integral_constant<int, 3>{}); break;
-        case 4: front(std::integral_constant<int, 4>{}); break;
-        case 5: front(std::integral_constant<int, 5>{}); break;
-        case 6: front(std::integral_constant<int, 6>{}); break;
-        default: front(std::integral_constant<int, 7>{}); break;
-    }
 
-    // ---- publish the rows and L
-    {
-        const int row = t & 63;
-        for (int c = t >> 6; c < m; c += NWS)
-            if (row < nr) B.Z[(r0 + row) + (int64_t)c * n] = Zr[row * FP + c];
+        // ---- the block's rows of Z, for the owners and the output stage (flagged
+        // at the next block's start, by when the stores have long completed); the
+        // columns from m on are stored too (zeros), so that Z is fully defined
+        for (int c = t >> 6; c < PM; c += NWS)
+            if (row < nr) coherent_store(B.Z + (r0 + row) + (int64_t)c * n, Zr[row * FP + c]);
     }
-#pragma unroll
-    for (int u = 0; u < NU; ++u) B.lam[(NQ * u + q) * PM + col] = lreg[u];
-
+    if (S.nb > 0) publish_flag(S.zdone + beta * S.nb + (S.nb - 1));
 }
 
 // Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'] (row-major l).
@@ -995,6 +1120,9 @@ __global__ __launch_bounds__(256) void k_projc_u(const cd *__restrict__ A,
 
 }  // namespace
 
+// flags of the persistent run: two per block and basis, and the error word
+size_t proj_sync_bytes(int64_t n) { return (size_t)(4 * ((n + PB - 1) / PB) + 1) * sizeof(int); }
+
 size_t proj_workspace_bytes(int64_t n, bool cplx)
 {
     const size_t nn = (size_t)n, es = cplx ? 16 : 8;
@@ -1004,7 +1132,8 @@ size_t proj_workspace_bytes(int64_t n, bool cplx)
            + 2 * al(nn * 4) + 2 * al(PM * 4)  // row types and minority rows
            + al(nparts * PM * PM * es)      // partial Gram matrices
            + al(PM * PM * es)               // Minv
-           + al(nn * PM * es);              // A
+           + al(nn * PM * es)               // A
+           + al(proj_sync_bytes(n));        // flags (real T)
 }
 
 int run_proj_c(const void *Tv, int64_t ldt, void *Uv, int64_t ldu, int64_t n, const int8_t *sgn,
@@ -1073,16 +1202,64 @@ int run_proj_c(const void *Tv, int64_t ldt, void *Uv, int64_t ldu, int64_t n, co
     return hipGetLastError() == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
 }
 
+// Compute units of the current device (cached per device), for the size of the
+// persistent grid.
+int device_cus()
+{
+    static std::vector<int> cache;
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+// Owners per basis and row blocks per owner for a persistent run over nb blocks:
+// every workgroup must be resident at once (one per compute unit: the front's
+// LDS arena leaves room for no second one).  False when nb is too large.
+bool proj_grid(int64_t nb, int cus, int *nown, int *kper)
+{
+    const int64_t tiles = nb > 2 ? nb - 2 : 0;
+    if (tiles == 0) {
+        *nown = 0;
+        *kper = 0;
+        return true;
+    }
+    const int64_t slots = (int64_t)(cus - 2) / 2;
+    if (slots < 1) return false;
+    const int64_t no = std::min<int64_t>(tiles, slots);
+    const int64_t kp = (tiles + no - 1) / no;
+    if (kp > KMAX) return false;
+    // as few owners as keep kp: fewer workgroups polling
+    *nown = (int)((tiles + kp - 1) / kp);
+    *kper = (int)kp;
+    return true;
+}
+
+bool proj_fits(int64_t n)
+{
+    int nown = 0, kper = 0;
+    return n >= 2 && proj_grid((n + PB - 1) / PB, device_cus(), &nown, &kper);
+}
+
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
-             const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st)
+             const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st,
+             int *herr, bool rcp_guard)
 {
     if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
-    // the minority rows on the host (ascending), for the first active column of each block
-    std::vector<int64_t> mrow;
-    mrow.reserve(m);
-    for (int64_t i = 0; i < n; ++i)
-        if (hsgn[i] == minority) mrow.push_back(i);
-    if ((int)mrow.size() != m) return SIGNTRI_ENOTSUP;
+    int nown = 0, kper = 0;
+    const int64_t nb = (n + PB - 1) / PB;
+    if (!proj_grid(nb, device_cus(), &nown, &kper)) return SIGNTRI_ENOTSUP;
+    int cnt = 0;
+    for (int64_t i = 0; i < n; ++i) cnt += hsgn[i] == minority;
+    if (cnt != m) return SIGNTRI_ENOTSUP;
     const size_t nn = (size_t)n;
     const int64_t nparts = (n + 63) / 64;
     char *p = (char *)ws;
@@ -1093,42 +1270,40 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     };
     double *Z0 = (double *)take(nn * PM * 8), *Z1 = (double *)take(nn * PM * 8);
     double *C0 = (double *)take(nn * PM * 8), *C1 = (double *)take(nn * PM * 8);
-    double *L0 = (double *)take(PM * PM * 8), *L1 = (double *)take(PM * PM * 8);
+    take(PM * PM * 8);  // (L of both bases: only the complex kernels keep it in memory)
+    take(PM * PM * 8);
     int *rt0 = (int *)take(nn * 4), *rt1 = (int *)take(nn * 4);
     int *ps0 = (int *)take(PM * 4), *ps1 = (int *)take(PM * 4);
     double *part = (double *)take((size_t)nparts * PM * PM * 8);
     double *minv = (double *)take(PM * PM * 8);
     double *A = (double *)take(nn * PM * 8);
+    int *sync = (int *)take(proj_sync_bytes(n));
 
-    // Z, acc and L of both bases are contiguous: one clear
-    if (hipMemsetAsync(Z0, 0, (char *)rt0 - (char *)Z0, st) != hipSuccess) return SIGNTRI_EHIP;
+    // flags and error word: a fill kernel (no memset node, should the call be captured)
     prof_begin(st);
     hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
                        ps1);
-    prof_end(st, PK_AUX, 0.0, 1);
+    if (launch_fill_int(sync, (int64_t)(4 * nb + 1), 0, st) != hipSuccess) return SIGNTRI_EHIP;
+    prof_end(st, PK_AUX, 0.0, 2);
 
     ProjArgs a;
     a.n = n;
     a.m = m;
-    a.b[0] = ProjBasis{T, ldt, 0, Z0, C0, L0, rt0, ps0};
-    a.b[1] = ProjBasis{T, ldt, 1, Z1, C1, L1, rt1, ps1};
-    // blocks of PB rows from the bottom up; the top block may be short
+    a.b[0] = ProjBasis{T, ldt, 0, Z0, C0, rt0, ps0};
+    a.b[1] = ProjBasis{T, ldt, 1, Z1, C1, rt1, ps1};
+    ProjSync S;
+    S.zdone = sync;
+    S.accready = sync + 2 * nb;
+    S.err = sync + 4 * nb;
+    S.spin_limit = flow_spin_limit();
+    S.nb = (int)nb;
+    S.nown = nown;
+    S.kper = kper;
+    S.rcp_guard = rcp_guard ? 1 : 0;
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
-    int launches = 0;
-    for (int64_t r1 = n, p1 = n; r1 > 0; ++launches) {
-        const int64_t r0 = std::max<int64_t>(0, r1 - PB);
-        const int64_t nbulk = p1 > r1 ? 2 * ((r0 + 63) / 64) : 0;
-        // basis 0: columns with b_l < r0; basis 1 (rows n-1-b_l): those with b_l > n-1-r0
-        const int lmin0 = (int)(std::lower_bound(mrow.begin(), mrow.end(), r0) - mrow.begin());
-        const int lmin1 =
-            (int)(mrow.end() - std::upper_bound(mrow.begin(), mrow.end(), n - 1 - r0));
-        hipLaunchKernelGGL(k_proj_step, dim3(2 + nbulk), dim3(NTS), 0, st, a, r0, r1, p1, lmin0,
-                           lmin1);
-        p1 = r1;
-        r1 = r0;
-    }
-    prof_end(st, PK_PROJ, flops, launches);
+    hipLaunchKernelGGL(k_proj_run, dim3(2 + 2 * nown), dim3(NTS), 0, st, a, S);
+    prof_end(st, PK_PROJ, flops, 1);
     prof_begin(st);
     // four launches: W^T Z partials, their sum, its inverse, A; then the product
     hipLaunchKernelGGL(k_proj_gram, dim3(nparts), dim3(256), 0, st, Z0, Z1, n, m, part);
@@ -1141,7 +1316,15 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
                        minority > 0 ? -1.0 : 1.0, U, ldu);
     // W^T Z and A = Z Minv (3 n m^2), the rank-m product on the upper triangle (n^2 m)
     prof_end(st, PK_PROJ_OUT, nd * nd * md + 3.0 * nd * md * md, 5);
-    return hipGetLastError() == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
+    if (hipGetLastError() != hipSuccess) return SIGNTRI_EHIP;
+    if (herr) {
+        // wait, and report a wait of the substitutions that gave up
+        if (hipMemcpyAsync(herr, S.err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SIGNTRI_EHIP;
+        if (*herr) return SIGNTRI_EHIP;
+    }
+    return SIGNTRI_OK;
 }
 
 }  // namespace sgt

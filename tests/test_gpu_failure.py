@@ -61,6 +61,27 @@ def test_wait_that_gives_up_is_reported(dev, monkeypatch, mode):
     assert rel_fro(Us[1].cpu().numpy(), ref) <= tol
 
 
+def test_projector_wait_that_gives_up_is_reported(dev, monkeypatch):
+    """The projector form's persistent substitution kernel waits on per-block
+    flags; a wait that gives up is reported by the calls that wait."""
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(16)
+    n = 700  # eleven 64-row blocks: fronts wait for owners from the third block on
+    T = wl.make_T(n, rng, signs=wl.signs_with_negatives(n, 9, rng))
+    Tg = to_dev_colmajor(T, dev)
+    monkeypatch.setenv("SIGNTRI_DEBUG_SPIN_LIMIT", "-1")
+    with pytest.raises(signtri.SignTriError) as e:
+        signtri.sign_tri(Tg, algo="proj")
+    assert e.value.code == EHIP
+    monkeypatch.delenv("SIGNTRI_DEBUG_SPIN_LIMIT")
+    U, info = signtri.sign_tri(Tg, algo="proj")
+    import oracle
+
+    assert info["path_name"] == "proj"
+    assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
 def test_plain_form_reports_a_wait_that_gave_up(dev, monkeypatch):
     """sign_tri() of the C ABI (no info argument) waits, so it reports it too."""
     import ctypes
