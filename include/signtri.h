@@ -98,7 +98,8 @@ enum {
     SIGNTRI_EWORKSPACE = 3,  /* ws_bytes smaller than signtri_workspace_size() */
     SIGNTRI_ENOCONV = 4,     /* refinement did not converge, fallback disabled */
     SIGNTRI_ENOTSUP = 5,     /* a combination this build does not implement    */
-    SIGNTRI_ENOMEM = 6       /* the library could not allocate its workspace   */
+    SIGNTRI_ENOMEM = 6,      /* the library could not allocate its workspace   */
+    SIGNTRI_ETOOBIG = 7      /* signtri_noalloc(): n beyond its fixed scratch   */
 };
 
 /* Filled on return when non-NULL (host memory). */
@@ -214,6 +215,24 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U,
 /* Device workspace needed by signtri_batched() for these orders. */
 size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch,
                                       signtri_dtype dtype, signtri_mode mode);
+
+/*
+ * The entry point that allocates nothing: for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Computes what signtri() computes for FP64 mode,
+ * column-major storage, AUTO path and default options (the dataflow sweeps or
+ * the projector form), with no device or pinned-host allocation: the scratch
+ * memory comes from a fixed device array of 56 MiB that each GPU the library
+ * runs on holds until the process ends, and the planner's host staging from a
+ * fixed host array.  Orders up to 8192 (real or complex); larger n returns
+ * SIGNTRI_ETOOBIG before any device work.  The call plans (one stream
+ * synchronisation), runs, and waits for its result before returning, and
+ * calls from different host threads of a process are serialised: the fixed
+ * arrays are shared by every call, and hold the last call's contents.
+ * Arguments, return codes and the info output as for signtri().
+ */
+int signtri_noalloc(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n,
+                    signtri_dtype dtype, void *stream, signtri_info *info);
 
 /* Human-readable text for a return code (static storage). */
 const char *signtri_strerror(int code);

@@ -435,6 +435,8 @@ const char *signtri_strerror(int code)
     case SIGNTRI_ENOCONV: return "iterative refinement did not converge and fallback is disabled";
     case SIGNTRI_ENOTSUP: return "this combination of arguments is not implemented";
     case SIGNTRI_ENOMEM: return "the library could not allocate its workspace";
+    case SIGNTRI_ETOOBIG:
+        return "the order exceeds what the no-allocation entry point's fixed scratch holds";
     default: break;
     }
     if (code < 0) return "invalid argument";
@@ -469,6 +471,32 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
             signtri_layout layout, signtri_mode mode, signtri_algo algo, void *workspace,
             size_t ws_bytes, void *stream, const signtri_options *opts, signtri_info *info)
 {
+    return sgt::signtri_run(T, ldt, U, ldu, n, dtype, layout, mode, algo, workspace, ws_bytes,
+                            stream, opts, info, nullptr);
+}
+
+}  // extern "C"
+
+namespace sgt {
+
+size_t noalloc_device_bytes(int64_t n, signtri_dtype dtype)
+{
+    const Layout F = layout_for(n, dtype, SIGNTRI_COL_MAJOR, SIGNTRI_FP64, 32, true);
+    return std::max(F.total, F.prefix + align_up(proj_workspace_bytes(n, dtype == SIGNTRI_C128)));
+}
+
+size_t noalloc_host_bytes(int64_t n, signtri_dtype dtype)
+{
+    size_t run_host = 0;
+    run_sizes(&n, 1, false, dtype == SIGNTRI_C128, nullptr, &run_host);
+    return align_up(sizeof(ScanResult)) + align_up((size_t)n) + run_host;
+}
+
+int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri_dtype dtype,
+                signtri_layout layout, signtri_mode mode, signtri_algo algo, void *workspace,
+                size_t ws_bytes, void *stream, const signtri_options *opts, signtri_info *info,
+                const NoAllocBuffers *na)
+{
     if (info) std::memset(info, 0, sizeof(*info));
     // argument checks, in argument order (LAPACK style -p)
     if (n > 0 && !T) return -1;
@@ -488,18 +516,29 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     if (n == 0) return SIGNTRI_OK;
 
     const Layout L0 = layout_for(n, dtype, layout, mode, 32, false);  // the common prefix
-    const size_t need = max_total(n, dtype, layout, mode, algo);
-    if (workspace) {
-        if (ws_bytes < need) return SIGNTRI_EWORKSPACE;
-    } else {
-        int rc = owned_workspace(need, &workspace);
-        if (rc != SIGNTRI_OK) return rc;
-    }
     void *hostbuf = nullptr;
     size_t run_host = 0;
     run_sizes(&n, 1, mode != SIGNTRI_FP64, cplx, nullptr, &run_host);
     const size_t host_bytes = align_up(sizeof(ScanResult)) + align_up((size_t)n) + run_host;
-    if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
+    if (na) {
+        // the caller's fixed buffers: FP64, column-major, dataflow sweeps or the projector
+        // form only (no captured graph, which would allocate)
+        if (mode != SIGNTRI_FP64 || layout != SIGNTRI_COL_MAJOR || algo != SIGNTRI_AUTO || opts)
+            return SIGNTRI_ENOTSUP;
+        if (na->dev_bytes < noalloc_device_bytes(n, dtype) || na->host_bytes < host_bytes)
+            return SIGNTRI_ETOOBIG;
+        workspace = na->dev;
+        hostbuf = na->host;
+    } else {
+        const size_t need = max_total(n, dtype, layout, mode, algo);
+        if (workspace) {
+            if (ws_bytes < need) return SIGNTRI_EWORKSPACE;
+        } else {
+            int rc = owned_workspace(need, &workspace);
+            if (rc != SIGNTRI_OK) return rc;
+        }
+        if (int rc = owned_host(host_bytes, &hostbuf)) return rc;
+    }
     char *hb = (char *)hostbuf;
     void *hflow = hb + align_up(sizeof(ScanResult)) + align_up((size_t)n);
 
@@ -585,6 +624,12 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
         return SIGNTRI_OK;
     }
     signtri_options eo = resolve_options(opts, dtype, mode, path, n);
+    if (na) {
+        // no captured graph: the dataflow sweep, whatever the tuning table recorded
+        eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
+        eo.tile = 32;
+        eo.wgs_per_cu = flow_max_wgs_per_cu(false, cplx);
+    }
     if (path == SIGNTRI_PATH_PS && eo.sweep != SIGNTRI_SWEEP_DATAFLOW) {
         // the Sylvester form runs on the dataflow sweeps only
         const bool pinned = opts && (opts->sweep == SIGNTRI_SWEEP_SUPERDIAG || opts->tile == 64);
@@ -662,6 +707,10 @@ int signtri(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri
     }
     return SIGNTRI_OK;
 }
+
+}  // namespace sgt
+
+extern "C" {
 
 int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U)
 {

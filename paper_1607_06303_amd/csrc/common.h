@@ -484,6 +484,25 @@ void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_b
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
              hipStream_t st);
+// Fixed buffers of the no-allocation entry point (device scratch and host
+// staging) in place of the library-owned workspace.
+struct NoAllocBuffers {
+    void *dev;
+    size_t dev_bytes;
+    void *host;
+    size_t host_bytes;
+};
+// signtri() with, when na is given, na's buffers instead of any allocation
+// (FP64, column-major, AUTO, default options only: the dataflow sweeps or the
+// projector form; SIGNTRI_ETOOBIG when the buffers are too small).
+int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, signtri_dtype dtype,
+                signtri_layout layout, signtri_mode mode, signtri_algo algo, void *workspace,
+                size_t ws_bytes, void *stream, const signtri_options *opts, signtri_info *info,
+                const NoAllocBuffers *na);
+// Device and host bytes signtri_run() takes from NoAllocBuffers for order n.
+size_t noalloc_device_bytes(int64_t n, signtri_dtype dtype);
+size_t noalloc_host_bytes(int64_t n, signtri_dtype dtype);
+
 // Polls a dependency wait of the persistent kernels (the dataflow sweeps, the
 // projector form's substitutions) makes before it gives up and sets the error word.  Testing hook: SIGNTRI_DEBUG_SPIN_LIMIT=-1 makes the first
 // wait of every sweep give up at once (the kernels still run to their end, on

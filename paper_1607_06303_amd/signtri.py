@@ -25,7 +25,7 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_batched_workspace_size", "signtri_strerror", "sign_tri",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
            "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
-           "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear")
+           "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear", "signtri_noalloc")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
             "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10, "proj": 11,
             "proj_out": 12}
@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
             L.signtri_strerror.restype = ctypes.c_char_p
             L.sign_tri.argtypes = [p, i64, i64, i32, p]
             L.sign_tri.restype = i32
+            L.signtri_noalloc.argtypes = [p, i64, p, i64, i64, i32, p, ctypes.POINTER(Info)]
+            L.signtri_noalloc.restype = i32
             L.signtri_plan_host.argtypes = [p, i64, i32, ctypes.POINTER(Info)]
             L.signtri_plan_host.restype = i32
             L.signtri_release.argtypes = []
@@ -235,6 +237,29 @@ def sign_tri(T, mode: str = "fp64", algo: str = "auto", out=None, workspace=None
     rc = lib().signtri(T.data_ptr() if n else None, ldt, U.data_ptr() if n else None, ldu, n, dt,
                        layout, MODES[mode], ALGOS[algo], ws_ptr, ws_bytes,
                        _stream_handle(T, stream), _opts(options), ctypes.byref(info))
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc), info.as_dict())
+    return U, info.as_dict()
+
+
+def sign_tri_noalloc(T, out=None, stream=None):
+    """sign(T) through signtri_noalloc(): FP64, column-major T (and U), AUTO path,
+    no allocation by the library (its fixed scratch; orders up to 8192).
+    Returns (U, info dict); waits for the result."""
+    if T.dim() != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    n = T.shape[0]
+    lay = _layout(T)
+    if lay is None or (n > 1 and lay[0] != COL_MAJOR):
+        raise ValueError("signtri_noalloc takes a column-major T")
+    U = out if out is not None else empty_like_layout(T)
+    ulay = _layout(U)
+    if ulay is None or (n > 1 and ulay[0] != COL_MAJOR) or U.shape != T.shape or U.dtype != T.dtype:
+        raise ValueError("out must be column-major with T's shape and dtype")
+    info = Info()
+    rc = lib().signtri_noalloc(T.data_ptr() if n else None, lay[1], U.data_ptr() if n else None,
+                               ulay[1], n, _dtype_code(T), _stream_handle(T, stream),
+                               ctypes.byref(info))
     if rc != 0:
         raise SignTriError(rc, strerror(rc), info.as_dict())
     return U, info.as_dict()

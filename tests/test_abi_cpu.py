@@ -73,6 +73,25 @@ def test_argument_validation_without_device_work():
     assert _call(None, 1, None, 1, 0) == 0
 
 
+def test_noalloc_validation_without_device_work():
+    L = signtri.lib()
+    t, u = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000000)
+    info = signtri.Info()
+    call = lambda T, ldt, U, ldu, n, dt=0: L.signtri_noalloc(T, ldt, U, ldu, n, dt, None,
+                                                             ctypes.byref(info))
+    assert call(None, 4, u, 4, 4) == -1
+    assert call(t, 3, u, 4, 4) == -2
+    assert call(t, 4, None, 4, 4) == -3
+    assert call(t, 4, u, 3, 4) == -4
+    assert call(t, 4, u, 4, -1) == -5
+    assert call(t, 4, u, 4, 4, dt=9) == -6
+    assert call(None, 1, None, 1, 0) == 0
+    # beyond the fixed scratch: rejected before any device work
+    assert call(t, 8193, u, 8193, 8193) == 7
+    assert call(t, 9000, u, 9000, 9000, dt=1) == 7
+    assert "scratch" in signtri.strerror(7)
+
+
 def _call_opts(n, dtype=0, mode=0, **opts):
     o = signtri.Options()
     for k, v in opts.items():
