@@ -189,17 +189,28 @@ __device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
 // (solved in order within the block), of block b - 1 (the block just below),
 // and of the blocks further down.
 //
-// Workgroups 0 and 1 ("fronts") run the two bases, block after block: each
-// adds block b - 1's part of its sums itself (one 64 x 64 x 64 FP64 MFMA
-// product, with block b - 1's Z still in LDS), solves block b row by row as a
-// wavefront over waves of eight columns, and publishes block b's rows of Z.
+// The minority columns are split into groups of GC = 8 consecutive columns.
+// Column l is zero below its minority row b_l and couples only with the
+// columns l' < l (through L[l', l]), so group g needs, besides its own rows,
+// only the finished values of the groups before it, which start higher up (their
+// minority rows lie above g's) and so run ahead of it.  Each group of each
+// basis has its own workgroup ("front"): wave 0 solves the group's columns row
+// by row (eight lanes per column, one row per step, no barrier inside a block;
+// the coupling among the group's own columns solved in order by lane
+// broadcasts), from the block of the group's lowest minority row to the top;
+// waves 1..3 meanwhile publish the previous block's rows of the group and fetch
+// the next block's operands (T's diagonal block, the panel against the block
+// below, the earlier groups' values on the block's rows, and the far sums).
+// Between blocks all four waves add the block just below's part of the sums
+// (one 64 x 64 x 8 FP64 MFMA product, with the group's rows of that block still
+// in LDS).  The bottom group, which covers nearly every row, is the critical
+// path; a row costs it one single-wave step.
+//
 // The other workgroups ("owners") each own row blocks i >= 2 of one basis and
 // keep the far part of their sums, sum over the blocks j <= i - 2, in MFMA
-// accumulators: as each block j is published they add T[block i, block j]
-// Z[block j], and after the last one (j = i - 2) they publish acc of block i.
-// A front therefore waits only for work that finished a whole block earlier,
-// and its operands for the next block (T's diagonal block and the panel
-// against the block below) are fetched while the current block is solved.
+// accumulators: as block j is published by every group that reaches it, they
+// add T[block i, block j] Z[block j], and after the last one (j = i - 2) they
+// publish acc of block i for every group with terms there.
 //
 // Hand-offs go through flags in device memory.  The data behind a flag is
 // written with device-coherent stores that complete before the flag's store,
@@ -208,25 +219,34 @@ __device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
 // with each other).  Every wait is bounded: past the limit it sets the error
 // word, which the host reports, and goes on, so the grid always drains.  All
 // workgroups of the launch are resident at once (the host sizes the grid to
-// the compute units), and a front never waits for an owner that waits for it.
+// the compute units).  Waits only point from a group to earlier groups and to
+// owners, and from owners to fronts of earlier blocks: there is no cycle.
 // ---------------------------------------------------------------------------
-constexpr int NQ = 8;          // lanes per column, each taking every NQ-th term
-constexpr int NU = PB / NQ;    // terms per lane
-constexpr int NTS = 64 * NQ;   // threads of a workgroup (one column per NQ lanes)
-constexpr int NWS = NTS / 64;  // its waves
-constexpr int FP = PB + NQ;    // LDS pitch of the staged T block and of the Z block: one
-                               // 16-lane pass of a read falls in distinct banks
-constexpr int KMAX = 2;        // row blocks per owner at most
+constexpr int NQ = 8;             // lanes per column, each taking every NQ-th term
+constexpr int GC = 64 / NQ;       // columns per group (one wave)
+constexpr int NU = PB / NQ;       // block-row terms per lane
+constexpr int MAXG = PM / GC;     // groups at most
+constexpr int NT = 256;           // threads of a workgroup (four waves)
+constexpr int TP = PB + 1;        // LDS pitch of the T block, the Z rows and the panel
+constexpr int ZCP = PB + NQ;      // LDS pitch of a group column (conflict-free column reads)
+constexpr int ABP = GC + 1;       // LDS pitch of the group's sums
+constexpr int KMAX = 2;           // row blocks per owner at most
+constexpr int NH = NT - 64;       // helper lanes (waves 1..3)
+constexpr int HK = (PB * PB + NH - 1) / NH;        // a 64 x 64 operand: entries per helper lane
+constexpr int HC = (PB * (PM - GC) + NH - 1) / NH;  // earlier groups' values on a block's rows
+constexpr int HA = (PB * GC + NH - 1) / NH;         // the group's sums of a block
 
 struct ProjSync {
-    int *zdone;     // [basis * nb + b]: block b's rows of Z published
-    int *accready;  // [basis * nb + b]: acc of block b's rows holds the blocks j <= b - 2
+    int *zdone;     // [(basis * G + g) * nb + b]: group g's rows of block b published
+    int *accready;  // same index: group g's far sums of block b published
     int *err;       // error word: a wait gave up
     int spin_limit; // polls before a wait gives up (negative: at once; a testing hook)
     int nb;         // row blocks
+    int G;          // column groups
     int nown;       // owner workgroups per basis
     int kper;       // row blocks per owner (<= KMAX)
     int rcp_guard;  // some |t_ii| outside [2^-1020, 2^1019]: reciprocals checked for range
+    int bstart[2 * MAXG];  // [basis * G + g]: the block of the group's lowest minority row
 };
 
 __device__ inline int flag_load(const int *p)
@@ -241,30 +261,27 @@ __device__ inline void coherent_store(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-// Publish: every wave's stores complete, then one flag store.
-__device__ inline void publish_flag(int *flag)
+__device__ inline void set_flag(int *p)
 {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait (thread 0 polls, the workgroup meets at a barrier after it) until *flag
-// is set, at most spin_limit polls.
-__device__ inline void wait_flag(const int *flag, const ProjSync &S)
+// Wave-level wait (lane 0 polls, the wave goes on together after it) until *flag
+// is set, at most spin_limit polls; on giving up it sets the error word and
+// returns.
+__device__ inline void wave_wait(const int *flag, const ProjSync &S)
 {
-    if (threadIdx.x == 0) {
-        bool ok = S.spin_limit >= 0;
+    int ok = 1;
+    if ((threadIdx.x & 63) == 0) {
+        ok = S.spin_limit >= 0;
         for (int it = 0; ok && flag_load(flag) == 0; ++it)
             if (it >= S.spin_limit || flag_load(S.err) != 0) {
-                ok = false;
+                ok = 0;
             } else {
                 __builtin_amdgcn_s_sleep(1);
             }
         if (!ok) atomicOr(S.err, 1);
     }
-    __syncthreads();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the poll
 }
 
@@ -275,32 +292,94 @@ __device__ inline int64_t blk_r0(int64_t n, int b)
     return r > 0 ? r : 0;
 }
 
-// Owner: row blocks i = 2 + w + k nown (k < kper) of basis `beta`; block i's sum
-// over the blocks j <= i - 2 in MFMA accumulators (eight waves, each two 16 x 16
-// pieces of the 64 x 64 block: rows 16 (wave / 2), columns 32 (wave % 2)).
+// Entry (e) of a 64 x 64 operand staged by a helper lane: (row, col) chosen so
+// that consecutive lanes read consecutive addresses of T (its columns for T
+// itself; for J T^T J the operand's rows run along T's columns).
+__device__ inline void op_entry(bool flip, int e, int &row, int &col)
+{
+    if (flip) {
+        row = e >> 6;
+        col = e & 63;
+    } else {
+        col = e >> 6;
+        row = e & 63;
+    }
+}
+
+// Owner: row blocks i = 2 + w + k nown (k < kper) of basis `beta`; block i's sums
+// over the blocks j <= i - 2 in MFMA accumulators (four waves, each 16 rows x 64
+// columns: rows 16 wave, four 16 x 16 pieces, a group's eight columns in half a
+// piece).  Each group is followed on its own, block by block as it publishes
+// them (the groups run at their own pace, far apart): thread 0 picks a group
+// whose next block is published, the bottom groups (the critical path) first,
+// and the workgroup adds T[block i, block j] Z[block j, the group's columns].
 __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, double *Bs)
 {
-    const int o = (int)blockIdx.x - 2;
+    const int o = (int)blockIdx.x - 2 * S.G;
     const int beta = o & 1, w = o >> 1;
     const ProjBasis &B = a.b[beta];
     const int64_t n = a.n;
     const int m = a.m;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int rb = 16 * (wv >> 1), cb = 32 * (wv & 1);
+    const int rb = 16 * wv;
     const int kr = lane >> 4, cc = lane & 15;
+    const int *bst = S.bstart + beta * S.G;
     int ilast = -1;
     for (int k = 0; k < S.kper; ++k)
         if (2 + w + k * S.nown < S.nb) ilast = 2 + w + k * S.nown;
     ilast = uniform(ilast);
-    dx4 d[KMAX][2];
+    __shared__ int s_next[MAXG];  // per group: its next block
+    __shared__ int s_pick;
+    if (t < MAXG) s_next[t] = t < S.G ? bst[t] : S.nb;
+    __syncthreads();
+    dx4 d[KMAX][4];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) d[k][0] = d[k][1] = dx4{0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j + 2 <= ilast; ++j) {
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) d[k][y] = dx4{0.0, 0.0, 0.0, 0.0};
+    int idle = 0;
+    for (;;) {
+        if (t == 0) {
+            // a group whose next block is published (-1: none yet; -2: all done)
+            int pick = -2, first = -1;
+            for (int g = S.G - 1; g >= 0; --g) {
+                const int j = s_next[g];
+                if (j > ilast - 2) continue;
+                if (first < 0) first = g;
+                if (pick < 0 && flag_load(S.zdone + (beta * S.G + g) * S.nb + j) != 0) pick = g;
+            }
+            if (pick == -2 && first >= 0) pick = -1;
+            if (pick == -1) {
+                // bounded: past the limit (or after another wait gave up) take the
+                // first unfinished group anyway, so that the grid drains
+                if (S.spin_limit < 0 || ++idle > S.spin_limit || flag_load(S.err) != 0) {
+                    atomicOr(S.err, 1);
+                    pick = first;
+                } else {
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            s_pick = pick;
+        }
+        __syncthreads();
+        const int g = uniform(s_pick);
+        if (g == -2) break;
+        if (g < 0) {
+            __syncthreads();
+            continue;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flag
+        const int j = s_next[g];
+        const int c0 = g * GC, cw = min(GC, m - c0), half = (g & 1) * GC;
         const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
-        wait_flag(S.zdone + beta * S.nb + j, S);
-        // Bs[kk * OP + c] = Z[k0 + kk, c]: published in this launch, coherent loads
-        for (int c = wv; c < 64; c += NWS)
-            Bs[lane * OP + c] = (c < m && k0 + lane < k1) ? coherent_load(B.Z + (k0 + lane) + (int64_t)c * n) : 0.0;
+        // Bs[kk * OP + c] (c < 16): the group's columns of block j in half `half` of
+        // the 16-column piece, zero in the other half; coherent loads (published in
+        // this launch)
+        for (int c = wv; c < 16; c += 4) {
+            const int cg = c - half;
+            const bool live = cg >= 0 && cg < cw && k0 + lane < k1;
+            Bs[lane * OP + c] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)(c0 + cg) * n) : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int i = 2 + w + k * S.nown;
@@ -308,7 +387,7 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
             const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
             // As[kk * OP + r] = entry (r0 + r, k0 + kk) of the basis's matrix (its
             // upper triangle: block i lies above block j)
-            for (int x = wv; x < 64; x += NWS) {
+            for (int x = wv; x < 64; x += 4) {
                 if (B.flip) {
                     // entry (r0 + x, k0 + lane) is T[n-1-k0-lane, n-1-r0-x]: lane along T's column
                     As[lane * OP + x] = (r0 + x < r1 && k0 + lane < k1)
@@ -319,277 +398,383 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
                 }
             }
             __syncthreads();
-            for (int kk = 0; kk < 64; kk += 4) {
-                const double av = As[(kk + kr) * OP + rb + cc];
-                const double b0 = Bs[(kk + kr) * OP + cb + cc];
-                const double b1 = Bs[(kk + kr) * OP + cb + 16 + cc];
-                d[k][0] = mfma_f64(av, b0, d[k][0]);
-                d[k][1] = mfma_f64(av, b1, d[k][1]);
+            auto mul = [&](dx4 &acc) {
+                for (int kk = 0; kk < 64; kk += 4)
+                    acc = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + cc], acc);
+            };
+            switch (g >> 1) {  // the group's 16-column piece (uniform)
+                case 0: mul(d[k][0]); break;
+                case 1: mul(d[k][1]); break;
+                case 2: mul(d[k][2]); break;
+                default: mul(d[k][3]); break;
             }
             __syncthreads();
             if (i == j + 2) {
-                // the last block below: publish acc of block i
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
+                // the group's last block below block i: publish its sums of block i
+                auto put = [&](const dx4 &acc, int y) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int64_t row = r0 + rb + mfma64_row(lane, e);
-                        const int c = cb + 16 * y + cc;
-                        if (row < r1 && c < m) coherent_store(B.acc + row + (int64_t)c * n, d[k][y][e]);
+                        const int cg = cc - half;
+                        if (row < r1 && cg >= 0 && cg < cw)
+                            coherent_store(B.acc + row + (int64_t)(c0 + cg) * n, acc[e]);
                     }
-                publish_flag(S.accready + beta * S.nb + i);
+                };
+                switch (g >> 1) {
+                    case 0: put(d[k][0], 0); break;
+                    case 1: put(d[k][1], 1); break;
+                    case 2: put(d[k][2], 2); break;
+                    default: put(d[k][3], 3); break;
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (t == 0) set_flag(S.accready + (beta * S.G + g) * S.nb + i);
             }
         }
+        if (t == 0) s_next[g] = j + 1;
+        idle = 0;
+        __syncthreads();
     }
 }
 
-// Front of one basis (blockIdx.x): every block, bottom up.
-__global__ __launch_bounds__(NTS) void k_proj_run(ProjArgs a, ProjSync S)
+__global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
 {
-    // one arena, so that a step's row of T and row of Z sit within the reach of
-    // one base address and the loads' immediate offsets
-    __shared__ double arena[PB * FP + PB * FP + PM * FP + PB * AP];
-    double *const Tt = arena;         // Tt[r * FP + c] = T[r0 + r, r0 + c], zero below the diagonal
-    double *const Zr = Tt + PB * FP;  // Zr[r * FP + l] = Z[r0 + r, l] (zero until computed)
-    double *const Zc = Zr + PB * FP;  // Zc[l * FP + r] = Z[r0 + r, l], the same values by column;
-                                      // at a block's start, the panel against the block below
-    double *const Ab = Zc + PM * FP;  // Ab[r * AP + l] = acc[r0 + r, l]
+    __shared__ double arena[3 * PB * TP + GC * ZCP + PB * ABP];
+    if ((int)blockIdx.x >= 2 * S.G) {
+        proj_owner(a, S, arena, arena + PB * OP);
+        return;
+    }
+    double *const Tt = arena;              // Tt[r * TP + c] = T[r0 + r, r0 + c], zero below the diagonal
+    double *const Zr = Tt + PB * TP;       // Zr[r * TP + l] = Z[r0 + r, l]: earlier groups' values,
+                                           // the group's own as they are solved (zero before)
+    double *const Pn = Zr + PB * TP;       // Pn[k * TP + r] = T[r0 + r, r1 + k], the panel below
+    double *const Zc = Pn + PB * TP;       // Zc[k * ZCP + r] = Z[r0 + r, c0 + k], the group's columns
+    double *const Ab = Zc + GC * ZCP;      // Ab[r * ABP + k] = acc[r0 + r, c0 + k]
 
-    if (blockIdx.x >= 2) {
-        proj_owner(a, S, Tt, Zr);
+    const int beta = (int)blockIdx.x & 1, g = uniform((int)blockIdx.x >> 1);
+    const ProjBasis B = a.b[beta];
+    const int64_t n = a.n;
+    const int m = a.m;
+    const int c0 = g * GC;                 // the group's first column
+    const int cw = uniform(min(GC, m - c0));  // its columns
+    const int bs = uniform(S.bstart[beta * S.G + g]);
+    const int *bst = S.bstart + beta * S.G;
+    const int t = threadIdx.x, wv = uniform(t >> 6);
+    const bool fl = B.flip != 0;
+    int *const zdone = S.zdone + (beta * S.G + g) * S.nb;
+
+    // Block b - 1's part of the group's sums, between blocks (all four waves):
+    // Ab += Pn^T Zc with Zc still holding the group's rows of block b - 1; each
+    // wave 16 rows, the columns padded to 16.
+    auto below_product = [&]() {
+        const int lane = t & 63, kr = lane >> 4, cc = lane & 15, rb = 16 * wv;
+        dx4 dd = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < PB; k += 4) {
+            const double av = Pn[(k + kr) * TP + rb + cc];
+            const double bv = cc < GC ? Zc[cc * ZCP + k + kr] : 0.0;
+            dd = mfma_f64(av, bv, dd);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (cc < GC) Ab[(rb + mfma64_row(lane, e)) * ABP + cc] += dd[e];
+    };
+    // The two roles run separate loops with the same barriers per block (four),
+    // so that neither holds the other's registers.
+
+    if (wv > 0) {
+        // ==== waves 1..3: the next block's operands.  T's diagonal block and the
+        // panel (inputs) are fetched into registers while the current block is
+        // solved; so are the earlier groups' values on the next block's rows and the
+        // group's far sums when their flags are already set, and otherwise after the
+        // boundary's first barrier.  (Only the inputs are fetched ahead
+        // unconditionally: a wait before that barrier could close a cycle with the
+        // owners, which wait for every group's earlier blocks.)
+        double hT[HK], hP[HK], hC[HC], hA[HA];
+        const int h = t - 64;  // helper lane
+        auto fetch_inputs = [&](int b) {
+            const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+            const int nr = (int)(r1 - r0);
+            const int nk = b > 0 ? (int)(blk_r1(n, b - 1) - r1) : 0;
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                const int e = h + NH * k;
+                int row, col;
+                op_entry(fl, e, row, col);
+                const bool in = e < PB * PB;
+                hT[k] = (in && row < nr && col < nr && row <= col) ? B.T[toff(B, n, r0 + row, r0 + col)]
+                                                                   : 0.0;
+                hP[k] = (in && row < nr && col < nk) ? B.T[toff(B, n, r0 + row, r1 + col)] : 0.0;
+            }
+        };
+        // the earlier groups' values on block b's rows: their flags (uniform test)
+        auto coupling_ready = [&](int b) {
+            int ok = 1;
+            for (int gp = 0; gp < g; ++gp)
+                if (bst[gp] <= b) ok &= flag_load(S.zdone + (beta * S.G + gp) * S.nb + b) != 0;
+            return uniform(ok) != 0;
+        };
+        auto fetch_coupling = [&](int b) {
+            const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+            const int nr = (int)(r1 - r0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flags
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int e = h + NH * k, l = e >> 6, row = e & 63;
+                hC[k] = (l < c0 && row < nr && bst[l / GC] <= b)
+                            ? coherent_load(B.Z + (r0 + row) + (int64_t)l * n) : 0.0;
+            }
+        };
+        // the group's sums over the blocks j <= b - 2, from their owner
+        auto acc_ready = [&](int b) {
+            return uniform(flag_load(S.accready + (beta * S.G + g) * S.nb + b) != 0) != 0;
+        };
+        auto fetch_acc = [&](int b) {
+            const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+            const int nr = (int)(r1 - r0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int k = 0; k < HA; ++k) {
+                const int e = h + NH * k, c = e >> 6, row = e & 63;
+                hA[k] = (c < cw && row < nr) ? coherent_load(B.acc + (r0 + row) + (int64_t)(c0 + c) * n)
+                                             : 0.0;
+            }
+        };
+        bool have_c = false, have_a = false;
+        fetch_inputs(bs);
+        for (int b = bs; b < S.nb; ++b) {
+            __syncthreads();  // (1) wave 0 has solved block b - 1
+#pragma unroll
+            for (int k = 0; k < HK; ++k) {
+                const int e = h + NH * k;
+                int row, col;
+                op_entry(fl, e, row, col);
+                if (e < PB * PB) {
+                    Tt[row * TP + col] = hT[k];
+                    Pn[col * TP + row] = hP[k];  // k-major
+                    Zr[(e & 63) * TP + (e >> 6)] = 0.0;
+                }
+            }
+            if (!have_c) {
+                for (int gp = 0; gp < g; ++gp)
+                    if (bst[gp] <= b) wave_wait(S.zdone + (beta * S.G + gp) * S.nb + b, S);
+                fetch_coupling(b);
+            }
+            // (after the zeros above: the same lane writes an entry's zero and its value,
+            // in this order)
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int e = h + NH * k, l = e >> 6, row = e & 63;
+                if (l < c0) Zr[row * TP + l] = hC[k];
+            }
+            const bool far = b - 2 >= bs;
+            if (far && !have_a) {
+                wave_wait(S.accready + (beta * S.G + g) * S.nb + b, S);
+                fetch_acc(b);
+            }
+#pragma unroll
+            for (int k = 0; k < HA; ++k) {
+                const int e = h + NH * k, c = e >> 6, row = e & 63;
+                if (c < GC) Ab[row * ABP + c] = far ? hA[k] : 0.0;
+            }
+            __syncthreads();  // (2)
+            if (b > bs) below_product();
+            __syncthreads();  // (3)
+            for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
+            __syncthreads();  // (4)
+            have_c = have_a = false;
+            if (b + 1 < S.nb) {
+                fetch_inputs(b + 1);
+                if (coupling_ready(b + 1)) {
+                    fetch_coupling(b + 1);
+                    have_c = true;
+                }
+                if (b + 1 - 2 >= bs && acc_ready(b + 1)) {
+                    fetch_acc(b + 1);
+                    have_a = true;
+                }
+            }
+        }
+        __syncthreads();  // wave 0 has solved the top block
         return;
     }
 
-    const ProjBasis B = a.b[blockIdx.x];
-    const int beta = blockIdx.x;
-    const int64_t n = a.n;
-    const int m = a.m;
-    constexpr int CW = 64 / NQ;  // columns per wave
-    constexpr int NK = 64 / NWS;
-    const int wv = uniform(threadIdx.x >> 6);
-    // The thread's index, opaque to the compiler where it is read: what derives
-    // from it is computed again per block instead of being held in registers
-    // across the block loop (which would not leave enough for the wavefront).
-    auto tid = [] {
-        int t = threadIdx.x;
-        asm volatile("" : "+v"(t));
-        return t;
-    };
-    // Per column, across blocks: the coefficients L[NQ u + q][l], and L[CW wv + k'][l]
-    // for the rows of this wave's columns (k' < kw), in every lane of the column;
-    // L[l][l] (t at row b_l, set at that row); all zero until the rows that define
-    // them are reached.  The column's minority row, and lane x's minority row x.
-    double lreg[NU], lw[CW], lamll = 0.0;
+    // ==== wave 0: the group's columns, block after block.  Per column, across
+    // blocks: the coefficients L[NQ u + q][l] for the earlier groups' columns
+    // (u < g), and L[c0 + k'][l] for the group's own earlier columns (k' < kw), in
+    // every lane of the column; L[l][l] (t at row b_l, set at that row).  All zero
+    // until the rows that define them are reached.
+    const int kw = (t & 63) / NQ, q = t % NQ;
+    double lreg[NU], lw[GC], lamll = 0.0;
 #pragma unroll
     for (int u = 0; u < NU; ++u) lreg[u] = 0.0;
 #pragma unroll
-    for (int kp = 0; kp < CW; ++kp) lw[kp] = 0.0;
-    const int pl = B.pos[(threadIdx.x >> 6) * CW + (threadIdx.x & 63) / NQ];  // (-1 from m on)
-    const int posl = B.pos[threadIdx.x & 63];
-    const bool fl = B.flip != 0;
+    for (int kp = 0; kp < GC; ++kp) lw[kp] = 0.0;
+    const int pl = kw < cw ? B.pos[c0 + kw] : -1;
+    const double *const zcol = Zc + kw * ZCP + q;
 
-    // operands of a block fetched ahead: its diagonal block of T and its panel
-    // against the block below (T[r0 + i, r1 + k]); lane = block row, wave =
-    // column offset (in J T^T J the lane runs along the block's columns, which
-    // are T's rows)
-    double tv[NK], pv[NK];
-    auto fetch = [&](int b) {
-        const int t = tid(), row = t & 63, c0 = t >> 6;
-        const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
-        const int nr = (int)(r1 - r0);
-        const int nk = b > 0 ? (int)(blk_r1(n, b - 1) - r1) : 0;
+    // the group's rows of block b, stored at the end of its wavefront; their flag
+    // is set after the next barrier, once the stores have completed
+    auto store_rows = [&](int b) {
+        const int64_t p0 = blk_r0(n, b), p1 = blk_r1(n, b);
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int c = c0 + NWS * k;
-            const int tr = fl ? c : row, tc = fl ? row : c;  // block row and column
-            tv[k] = (tr < nr && tc < nr && tr <= tc) ? B.T[toff(B, n, r0 + tr, r0 + tc)] : 0.0;
-            pv[k] = (tr < nr && tc < nk) ? B.T[toff(B, n, r0 + tr, r1 + tc)] : 0.0;
-        }
+        for (int k = 0; k < GC; ++k)
+            if (k < cw && p0 + (t & 63) < p1)
+                coherent_store(B.Z + (p0 + (t & 63)) + (int64_t)(c0 + k) * n, Zc[k * ZCP + (t & 63)]);
     };
-    fetch(0);
-
-    for (int b = 0; b < S.nb; ++b) {
-        const int t = tid();
-        const int col = (t >> 6) * CW + ((t & 63) / NQ);
-        const int q = t % NQ;
-        const int row = t & 63, c0 = t >> 6;       // staging: lane = row, wave = column offset
+    auto flag_rows = [&](int b) {
+        __builtin_amdgcn_s_waitcnt(0);
+        if (t == 0) set_flag(S.zdone + (beta * S.G + g) * S.nb + b);
+    };
+    for (int b = bs; b < S.nb; ++b) {
         const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
         const int nr = (int)(r1 - r0);
-        const bool below = b > 0;
-        // the block's sums over the blocks j <= b - 2, from its owner
-        double av[NK];
-        if (b >= 2) wait_flag(S.accready + beta * S.nb + b, S);
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int c = c0 + NWS * k;
-            av[k] = (b >= 2 && row < nr && c < m) ? coherent_load(B.acc + (r0 + row) + (int64_t)c * n) : 0.0;
-        }
-        // the block's row types, lane i holding row i's (every wave)
+        // the block's row types, lane i holding row i's (loaded ahead of its use)
         const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
-        __syncthreads();  // the previous block's wavefront and stores of Z are done
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int c = c0 + NWS * k;
-            const int tr = fl ? c : row, tc = fl ? row : c;
-            Tt[tr * FP + tc] = tv[k];
-            Zc[tc * FP + tr] = pv[k];  // k-major: Zc[k * FP + r] = T[r0 + r, r1 + k]
-            Ab[row * AP + c] = av[k];
-        }
-        __syncthreads();
-        if (below) {
-            // block b - 1's part of the sums: Zr still holds its rows of Z (k-major)
-            if (t < 256) {  // the product runs on four waves
-                dx4 d[2][2];
-                mm64_acc_zero(d);
-                mm64_acc<FP, FP>(Zc, Zr, d);
-                const int lane = t & 63, w = t >> 6;
-                const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int r = rb + 16 * x + mfma64_row(lane, e);
-                            const int c = cb + 16 * y + (lane & 15);
-                            Ab[r * AP + c] += d[x][y][e];
-                        }
-            }
-            __syncthreads();
-        }
-        for (int e = t; e < PB * FP; e += NTS) {
-            Zr[e] = 0.0;
-            Zc[e] = 0.0;
-        }
-        // block b - 1's rows of Z, stored at the end of its wavefront, are complete:
-        // flag them for the owners
-        if (below) {
-            publish_flag(S.zdone + beta * S.nb + (b - 1));
-        }
-        __syncthreads();
-        // the next block's operands, fetched during this block's wavefront
-        if (b + 1 < S.nb) fetch(b + 1);
+        __syncthreads();  // (1)
+        if (b > bs) flag_rows(b - 1);
+        __syncthreads();  // (2) the helpers have staged block b's operands
+        if (b > bs) below_product();
+        __syncthreads();  // (3)
+        for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
+        __syncthreads();  // (4)
 
-        // ---- wavefront by waves: at step s the columns of wave w all handle block
-        // row r = nr - 1 - s + (w - wmin), wmin the wave of the first active column.
-        // A column's sums read its own column (earlier steps) and row r of the
-        // columns of the waves before it (written at step s - 1 and earlier); the
-        // coupling among the wave's own columns, whose entries of row r are still
-        // zero in those sums, is solved after the reduction, column by column within
-        // the wave.  At a minority row that coupling is zero (the row of Z is e_typ
-        // and L's row typ is not set yet), so only majority rows take that chain.
-        // lmin: the minority columns whose row lies above the block (b_l < r0) stay
-        // zero throughout it, and the wavefront starts at the first column after them.
-        const int lmin = __builtin_popcountll(
-            __builtin_amdgcn_ballot_w64((t & 63) < m && posl >= 0 && posl < r0));
-        const int wmin = lmin / CW, wlast = (m - 1) / CW;
-        const int steps = uniform(m > lmin ? nr + (wlast - wmin) : 0);
-        // the column's minority row within the block (-1: above it, PB: below it)
+        // Row by row from the bottom; every column of the group takes the same row.
+        // A column's sum for row r takes the rows below it within the block (its
+        // own column) and the earlier groups' values on row r (chunks u < g); the
+        // coupling among the group's own columns, still zero in that sum, is solved
+        // after the reduction, column by column.  At a minority row that coupling is
+        // zero (the row of Z is e_typ and L's row typ is not set yet), so only
+        // majority rows take that chain.  A column is active on the rows at and above
+        // its minority row.
+        //
+        // Pipelined: while row r is solved, the sum of row r - 1 is formed (its LDS
+        // reads, the multiply-adds and the reduction) from what is known before row
+        // r: every term but the one of row r itself, -t[r-1][r] z_r, which is added
+        // once z_r is known (one multiply-add on the chain from row to row).  A
+        // minority row changes L (and so row r - 1's coupling terms, coefficients or
+        // divisor): after one, row r - 1's sum is formed again, with z_r included.
+        // One wave: the LDS reads see the earlier stores in program order, with no
+        // barrier.
         const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
-        const int rhi = col < m ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
-        const double *const zcol = Zc + col * FP + q;
-        // The coupling terms of wave w come from the columns of the waves before it
-        // (chunks u < w); the others are still zero when read.  The step loop is
-        // instantiated per wave with that chunk count, so no step tests it.
-        auto front = [&](auto wtag) {
-        constexpr int NCU = decltype(wtag)::value;  // coupling chunks of this wave
-        for (int s = 0; s < steps; ++s) {
-            const int r = nr - 1 - s + (wv - wmin);  // the wave's row (uniform)
-            const bool act = r >= 0 && r <= rhi;
-            // the wave's active columns: a contiguous range (b_l grows with l)
+        const int rhi = kw < cw ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
+        auto front = [&](auto gtag) {
+        constexpr int NCU = decltype(gtag)::value;  // coupling chunks: the earlier groups
+        // Row r's prepared state: dpart = coupling - sum without row r + 1's term,
+        // tnext = t[r][r+1] (that term's coefficient; 0 when already included or
+        // outside the block), t_rr, 1 / (t_rr - L[l, l]) and the chain coefficients.
+        struct Prep {
+            double dpart, tnext, tii, rcp, lwr[GC - 1];
+        };
+        auto prep = [&](int r, bool included) {
+            Prep P;
+            int ro = r * TP;
+            // opaque to loop strength reduction: one base address for the step's
+            // reads of both rows, with immediate offsets
+            asm volatile("" : "+v"(ro));
+            const double *trow = Tt + ro;
+            const double *zrow = Zr + ro;
+            double tv[NU], zv[NU], rv[NCU > 0 ? NCU : 1];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                tv[u] = trow[NQ * u + q];
+                zv[u] = zcol[NQ * u];
+                if (u < NCU) rv[u] = zrow[NQ * u + q];
+            }
+            P.tii = trow[r];
+            P.tnext = (!included && r + 1 < nr) ? trow[r + 1] : 0.0;
+            // (the group's sum of the row, read by all the column's lanes: a broadcast)
+            const double ab = Ab[r * ABP + kw];
+            // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
+            // and one Newton step, which squares it (below 2.3e-15).  The signs of
+            // t_ii and L[l, l] differ, so |dx| >= min |t_kk| and |dx| <= 2 max |t_kk|;
+            // only when the diagonal leaves [2^-1020, 2^1019] (a uniform test) can
+            // |dx| leave [2^-1020, 2^1020], where the estimate or its reciprocal would
+            // not be normal: then the IEEE division for those entries
+            const double dx = P.tii - lamll;
+            double rcp = __builtin_amdgcn_rcp(dx);
+            rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
+            if (__builtin_expect(S.rcp_guard != 0, 0)) {
+                const double adx = fabs(dx);
+                if (adx > 0x1p1020 || adx < 0x1p-1020) rcp = 1.0 / dx;
+            }
+            P.rcp = rcp;
+            // the chain's coefficients with the reciprocal folded in
+#pragma unroll
+            for (int kp = 0; kp < GC - 1; ++kp) P.lwr[kp] = lw[kp] * rcp;
+            double v0 = q == 0 ? ab : 0.0, v1 = 0.0, cp0 = 0.0, cp1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < NU; u += 2) {
+                v0 += tv[u] * zv[u];
+                v1 += tv[u + 1] * zv[u + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < NCU; u += 2) {
+                cp0 += rv[u] * lreg[u];
+                if (u + 1 < NCU) cp1 += rv[u + 1] * lreg[u + 1];
+            }
+            // coupling (earlier groups) - sum
+            P.dpart = group_sum<NQ>((cp0 + cp1) - (v0 + v1));
+            return P;
+        };
+        Prep P = prep(nr - 1, false);
+        double zprev = 0.0;  // z of the row below, in every lane of its column
+        for (int s = 0; s < nr; ++s) {
+            const int r = nr - 1 - s;
+            // the next row's sum, from what is known before this row is solved
+            Prep Pn;
+            if (r > 0) Pn = prep(r - 1, false);
+            const bool act = r <= rhi;
+            // the active columns: a contiguous range at the end of the group
             const uint64_t am = __builtin_amdgcn_ballot_w64(act);
-            if (am != 0) {  // then 0 <= r < nr
+            double z = 0.0;
+            bool redo = false;
+            if (am != 0) {
                 // chain steps: the active columns but the last, as a bit mask
                 const int klo = __builtin_ctzll(am) / NQ, khi = (64 - __builtin_clzll(am)) / NQ;
                 const int chain = uniform(((1 << (khi - 1)) - 1) & ~((1 << klo) - 1));
-                int ro = r * FP;
-                // opaque to loop strength reduction: one base address for the step's
-                // reads of both rows, with immediate offsets
-                asm volatile("" : "+v"(ro));
-                const double *trow = Tt + ro;
-                const double *zrow = Zr + ro;
-                // Full sums: every term outside the ranges that count is zero (the
-                // lower triangle of the staged block, entries of Z not computed yet).
-                // all operands first (paired LDS reads), then the multiply-adds
-                double tv_[NU], zv[NU], rv[NCU > 0 ? NCU : 1];
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    tv_[u] = trow[NQ * u + q];
-                    zv[u] = zcol[NQ * u];
-                    if (u < NCU) rv[u] = zrow[NQ * u + q];
-                }
-                const double tii = Tt[r * FP + r];
-                // (the block's sum read by all the column's lanes, one address: a broadcast,
-                // no branch)
-                const double ab = Ab[r * AP + col];
-                // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
-                // and one Newton step, which squares it (below 2.3e-15).  The signs of
-                // t_ii and L[l, l] differ, so |dx| >= min |t_kk| and |dx| <= 2 max |t_kk|;
-                // only when the diagonal leaves [2^-1020, 2^1019] (a uniform test) can
-                // |dx| leave [2^-1020, 2^1020], where the estimate or its reciprocal would
-                // not be normal: then the IEEE division for those entries
-                const double dx = tii - lamll;
-                double rcp = __builtin_amdgcn_rcp(dx);
-                rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
-                if (__builtin_expect(S.rcp_guard != 0, 0)) {
-                    const double adx = fabs(dx);
-                    if (adx > 0x1p1020 || adx < 0x1p-1020) rcp = 1.0 / dx;
-                }
-                double v0 = q == 0 ? ab : 0.0, v1 = 0.0, cp0 = 0.0, cp1 = 0.0;
-#pragma unroll
-                for (int u = 0; u < NU; u += 2) {
-                    v0 += tv_[u] * zv[u];
-                    v1 += tv_[u + 1] * zv[u + 1];
-                }
-#pragma unroll
-                for (int u = 0; u < NCU; u += 2) {
-                    cp0 += rv[u] * lreg[u];
-                    if (u + 1 < NCU) cp1 += rv[u + 1] * lreg[u + 1];
-                }
-                // d = coupling (waves before this one) - sum
-                const double d = group_sum<NQ>((cp0 + cp1) - (v0 + v1));
+                // d = coupling - sum, with row r + 1's term
+                const double d = fma(-P.tnext, zprev, P.dpart);
                 const int typ = __builtin_amdgcn_readlane(rtl, r);
-                double z = 0.0;
                 if (typ >= 0) {
+                    redo = true;
                     // (the active columns only: an inactive one's column of L stays as is)
                     if (act && r == plr) {
                         z = 1.0;
-                        lamll = tii;
-#pragma unroll
-                        for (int u = 0; u < NU; ++u)
-                            if (NQ * u + q == col) lreg[u] = tii;
+                        lamll = P.tii;
                     } else if (act) {
                         // minority row b_typ (typ < l): row typ of L
+                        if (typ < c0) {
 #pragma unroll
-                        for (int u = 0; u < NU; ++u)
-                            if (NQ * u + q == typ) lreg[u] = -d;
+                            for (int u = 0; u < NU; ++u)
+                                if (NQ * u + q == typ) lreg[u] = -d;
+                        } else {
 #pragma unroll
-                        for (int kp = 0; kp < CW; ++kp)
-                            if (CW * wv + kp == typ) lw[kp] = -d;
+                            for (int kp = 0; kp < GC; ++kp)
+                                if (c0 + kp == typ) lw[kp] = -d;
+                        }
                     }
                 } else {
                     // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
-                    // wave's active columns in order, with the reciprocal folded into
+                    // group's active columns in order, with the reciprocal folded into
                     // the coefficients (one multiply-add per link); lw is zero from the
                     // diagonal on, so the later terms add nothing to a column solved
-                    double lwr[CW - 1];
+                    z = d * P.rcp;
 #pragma unroll
-                    for (int kp = 0; kp < CW - 1; ++kp) lwr[kp] = lw[kp] * rcp;
-                    z = d * rcp;
-#pragma unroll
-                    for (int kp = 0; kp < CW - 1; ++kp)
-                        if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+                    for (int kp = 0; kp < GC - 1; ++kp)
+                        if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), P.lwr[kp], z);
                 }
-                if (q == 0 && act) {
-                    Zr[r * FP + col] = z;
-                    Zc[col * FP + r] = z;
-                }
+                if (q == 0 && act) Zc[kw * ZCP + r] = z;
+                if (!act) z = 0.0;
             }
-            __syncthreads();
+            // after a minority row (a uniform test), row r - 1's sum again, with the
+            // state L has now and z_r included
+            if (redo && r > 0) Pn = prep(r - 1, true);
+            P = Pn;
+            zprev = z;
         }
         };
-        static_assert(NWS == 8, "one instance per wave");
-        switch (wv) {
+        static_assert(MAXG == 8, "one instance per group");
+        switch (g) {
             case 0: front(std::integral_constant<int, 0>{}); break;
             case 1: front(std::integral_constant<int, 1>{}); break;
             case 2: front(std::integral_constant<int, 2>{}); break;
@@ -599,15 +784,10 @@ __global__ __launch_bounds__(NTS) void k_proj_run(ProjArgs a, ProjSync S)
             case 6: front(std::integral_constant<int, 6>{}); break;
             default: front(std::integral_constant<int, 7>{}); break;
         }
-        __syncthreads();
-
-        // ---- the block's rows of Z, for the owners and the output stage (flagged
-        // at the next block's start, by when the stores have long completed); the
-        // columns from m on are stored too (zeros), so that Z is fully defined
-        for (int c = t >> 6; c < PM; c += NWS)
-            if (row < nr) coherent_store(B.Z + (r0 + row) + (int64_t)c * n, Zr[row * FP + c]);
+        store_rows(b);
     }
-    if (S.nb > 0) publish_flag(S.zdone + beta * S.nb + (S.nb - 1));
+    __syncthreads();
+    flag_rows(S.nb - 1);
 }
 
 // Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'] (row-major l).
@@ -1121,7 +1301,8 @@ __global__ __launch_bounds__(256) void k_projc_u(const cd *__restrict__ A,
 }  // namespace
 
 // flags of the persistent run: two per block and basis, and the error word
-size_t proj_sync_bytes(int64_t n) { return (size_t)(4 * ((n + PB - 1) / PB) + 1) * sizeof(int); }
+// flags of the persistent run: two per block, group and basis, and the error word
+size_t proj_sync_bytes(int64_t n) { return (size_t)(4 * MAXG * ((n + PB - 1) / PB) + 1) * sizeof(int); }
 
 size_t proj_workspace_bytes(int64_t n, bool cplx)
 {
@@ -1221,18 +1402,19 @@ int device_cus()
     return cache[dev];
 }
 
-// Owners per basis and row blocks per owner for a persistent run over nb blocks:
-// every workgroup must be resident at once (one per compute unit: the front's
-// LDS arena leaves room for no second one).  False when nb is too large.
-bool proj_grid(int64_t nb, int cus, int *nown, int *kper)
+// Owners per basis and row blocks per owner for a persistent run over nb blocks
+// with `fronts` front workgroups: every workgroup must be resident at once (one
+// per compute unit: the front's LDS arena leaves room for no second one).  False
+// when nb is too large.
+bool proj_grid(int64_t nb, int cus, int fronts, int *nown, int *kper)
 {
     const int64_t tiles = nb > 2 ? nb - 2 : 0;
     if (tiles == 0) {
         *nown = 0;
         *kper = 0;
-        return true;
+        return cus >= fronts;
     }
-    const int64_t slots = (int64_t)(cus - 2) / 2;
+    const int64_t slots = (int64_t)(cus - fronts) / 2;
     if (slots < 1) return false;
     const int64_t no = std::min<int64_t>(tiles, slots);
     const int64_t kp = (tiles + no - 1) / no;
@@ -1246,7 +1428,7 @@ bool proj_grid(int64_t nb, int cus, int *nown, int *kper)
 bool proj_fits(int64_t n)
 {
     int nown = 0, kper = 0;
-    return n >= 2 && proj_grid((n + PB - 1) / PB, device_cus(), &nown, &kper);
+    return n >= 2 && proj_grid((n + PB - 1) / PB, device_cus(), 2 * MAXG, &nown, &kper);
 }
 
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
@@ -1254,12 +1436,29 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
              int *herr, bool rcp_guard)
 {
     if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
+    const int G = (m + GC - 1) / GC;
     int nown = 0, kper = 0;
     const int64_t nb = (n + PB - 1) / PB;
-    if (!proj_grid(nb, device_cus(), &nown, &kper)) return SIGNTRI_ENOTSUP;
-    int cnt = 0;
-    for (int64_t i = 0; i < n; ++i) cnt += hsgn[i] == minority;
-    if (cnt != m) return SIGNTRI_ENOTSUP;
+    if (!proj_grid(nb, device_cus(), 2 * G, &nown, &kper)) return SIGNTRI_ENOTSUP;
+    // the minority rows of both bases, ascending (basis 1: rows of J T^T J), and
+    // each group's first block (that of its lowest minority row)
+    int bsh[2 * MAXG];
+    {
+        int cnt = 0;
+        int64_t rows0[PM], rows1[PM];
+        for (int64_t i = 0; i < n; ++i)
+            if (hsgn[i] == minority) {
+                if (cnt >= m) return SIGNTRI_ENOTSUP;
+                rows0[cnt++] = i;
+            }
+        if (cnt != m) return SIGNTRI_ENOTSUP;
+        for (int l = 0; l < m; ++l) rows1[l] = n - 1 - rows0[m - 1 - l];
+        for (int g = 0; g < G; ++g) {
+            const int last = std::min(m, (g + 1) * GC) - 1;
+            bsh[g] = (int)((n - 1 - rows0[last]) / PB);
+            bsh[G + g] = (int)((n - 1 - rows1[last]) / PB);
+        }
+    }
     const size_t nn = (size_t)n;
     const int64_t nparts = (n + 63) / 64;
     char *p = (char *)ws;
@@ -1279,12 +1478,16 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     double *A = (double *)take(nn * PM * 8);
     int *sync = (int *)take(proj_sync_bytes(n));
 
-    // flags and error word: a fill kernel (no memset node, should the call be captured)
+    // Z of both bases (contiguous) cleared: a group writes only the blocks it
+    // reaches; flags and error word cleared.  Fill kernels, no memset node
+    // (should the call be captured).
     prof_begin(st);
     hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
                        ps1);
-    if (launch_fill_int(sync, (int64_t)(4 * nb + 1), 0, st) != hipSuccess) return SIGNTRI_EHIP;
-    prof_end(st, PK_AUX, 0.0, 2);
+    if (launch_fill_int((int *)Z0, (int64_t)(((char *)C0 - (char *)Z0) / 4), 0, st) != hipSuccess ||
+        launch_fill_int(sync, (int64_t)(4 * G * nb + 1), 0, st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    prof_end(st, PK_AUX, 0.0, 3);
 
     ProjArgs a;
     a.n = n;
@@ -1293,16 +1496,18 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     a.b[1] = ProjBasis{T, ldt, 1, Z1, C1, rt1, ps1};
     ProjSync S;
     S.zdone = sync;
-    S.accready = sync + 2 * nb;
-    S.err = sync + 4 * nb;
+    S.accready = sync + 2 * G * nb;
+    S.err = sync + 4 * G * nb;
+    for (int x = 0; x < 2 * G; ++x) S.bstart[x] = bsh[x];
     S.spin_limit = flow_spin_limit();
     S.nb = (int)nb;
+    S.G = G;
     S.nown = nown;
     S.kper = kper;
     S.rcp_guard = rcp_guard ? 1 : 0;
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
-    hipLaunchKernelGGL(k_proj_run, dim3(2 + 2 * nown), dim3(NTS), 0, st, a, S);
+    hipLaunchKernelGGL(k_proj_run, dim3(2 * G + 2 * nown), dim3(NT), 0, st, a, S);
     prof_end(st, PK_PROJ, flops, 1);
     prof_begin(st);
     // four launches: W^T Z partials, their sum, its inverse, A; then the product
