@@ -309,10 +309,12 @@ __device__ inline void op_entry(bool flip, int e, int &row, int &col)
 // Owner: row blocks i = 2 + w + k nown (k < kper) of basis `beta`; block i's sums
 // over the blocks j <= i - 2 in MFMA accumulators (four waves, each 16 rows x 64
 // columns: rows 16 wave, four 16 x 16 pieces, a group's eight columns in half a
-// piece).  Each group is followed on its own, block by block as it publishes
-// them (the groups run at their own pace, far apart): thread 0 picks a group
-// whose next block is published, the bottom groups (the critical path) first,
-// and the workgroup adds T[block i, block j] Z[block j, the group's columns].
+// piece).  The groups run at their own pace, far apart, and each is followed on
+// its own: thread 0 takes the lowest block j that some group has published and
+// the owner has not yet added, with every group that has published it, and the
+// workgroup adds T[block i, block j] Z[block j, those groups' columns] (one
+// fetch of T's tile for them all; the 16-column pieces without such a group are
+// skipped).  All of a step's loads are issued before any is used.
 __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, double *Bs)
 {
     const int o = (int)blockIdx.x - 2 * S.G;
@@ -329,7 +331,7 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
         if (2 + w + k * S.nown < S.nb) ilast = 2 + w + k * S.nown;
     ilast = uniform(ilast);
     __shared__ int s_next[MAXG];  // per group: its next block
-    __shared__ int s_pick;
+    __shared__ int s_j, s_mask;
     if (t < MAXG) s_next[t] = t < S.G ? bst[t] : S.nb;
     __syncthreads();
     dx4 d[KMAX][4];
@@ -340,99 +342,118 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
     int idle = 0;
     for (;;) {
         if (t == 0) {
-            // a group whose next block is published (-1: none yet; -2: all done)
-            int pick = -2, first = -1;
-            for (int g = S.G - 1; g >= 0; --g) {
+            // the lowest published block not yet added, and the groups that have it
+            // (j = -1: none published yet; -2: all done)
+            int jmin = 1 << 30, mask = 0, first = -1, jfirst = 1 << 30;
+            for (int g = 0; g < S.G; ++g) {
                 const int j = s_next[g];
                 if (j > ilast - 2) continue;
-                if (first < 0) first = g;
-                if (pick < 0 && flag_load(S.zdone + (beta * S.G + g) * S.nb + j) != 0) pick = g;
+                if (j < jfirst) {
+                    jfirst = j;
+                    first = g;
+                }
+                if (flag_load(S.zdone + (beta * S.G + g) * S.nb + j) == 0) continue;
+                if (j < jmin) {
+                    jmin = j;
+                    mask = 0;
+                }
+                if (j == jmin) mask |= 1 << g;
             }
-            if (pick == -2 && first >= 0) pick = -1;
-            if (pick == -1) {
+            int jp = mask ? jmin : (first < 0 ? -2 : -1);
+            if (jp == -1) {
                 // bounded: past the limit (or after another wait gave up) take the
-                // first unfinished group anyway, so that the grid drains
+                // lowest unfinished group anyway, so that the grid drains
                 if (S.spin_limit < 0 || ++idle > S.spin_limit || flag_load(S.err) != 0) {
                     atomicOr(S.err, 1);
-                    pick = first;
+                    jp = jfirst;
+                    for (int g = 0; g < S.G; ++g)
+                        if (s_next[g] == jfirst) mask |= 1 << g;
                 } else {
                     __builtin_amdgcn_s_sleep(1);
                 }
+            } else {
+                idle = 0;
             }
-            s_pick = pick;
+            s_j = jp;
+            s_mask = mask;
         }
         __syncthreads();
-        const int g = uniform(s_pick);
-        if (g == -2) break;
-        if (g < 0) {
+        const int j = uniform(s_j), mask = uniform(s_mask);
+        if (j == -2) break;
+        if (j < 0) {
             __syncthreads();
             continue;
         }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flag
-        const int j = s_next[g];
-        const int c0 = g * GC, cw = min(GC, m - c0), half = (g & 1) * GC;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flags
         const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
-        // Bs[kk * OP + c] (c < 16): the group's columns of block j in half `half` of
-        // the 16-column piece, zero in the other half; coherent loads (published in
-        // this launch)
-        for (int c = wv; c < 16; c += 4) {
-            const int cg = c - half;
-            const bool live = cg >= 0 && cg < cw && k0 + lane < k1;
-            Bs[lane * OP + c] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)(c0 + cg) * n) : 0.0;
+        // the step's loads: block j's rows of the groups in the mask (coherent: they
+        // were published in this launch), and T's tiles [block i, block j]
+        double zb[16], ta[KMAX][16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+            const int c = wv + 4 * x;  // column
+            const bool live = c < m && ((mask >> (c / GC)) & 1) && k0 + lane < k1;
+            zb[x] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)c * n) : 0.0;
         }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int i = 2 + w + k * S.nown;
+            const bool use = k < S.kper && i <= ilast && i >= j + 2;
+            const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                const int y = wv + 4 * x;
+                if (B.flip) {
+                    // entry (r0 + y, k0 + lane) is T[n-1-k0-lane, n-1-r0-y]: lane along T's column
+                    ta[k][x] = (use && r0 + y < r1 && k0 + lane < k1)
+                                   ? B.T[(n - 1 - k0 - lane) + (n - 1 - r0 - y) * B.ldt] : 0.0;
+                } else {
+                    ta[k][x] = (use && r0 + lane < r1 && k0 + y < k1)
+                                   ? B.T[(r0 + lane) + (k0 + y) * B.ldt] : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < 16; ++x) Bs[lane * OP + wv + 4 * x] = zb[x];  // Bs[kk * OP + c]
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int i = 2 + w + k * S.nown;
             if (k >= S.kper || i > ilast || i < j + 2) continue;  // uniform
             const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
-            // As[kk * OP + r] = entry (r0 + r, k0 + kk) of the basis's matrix (its
-            // upper triangle: block i lies above block j)
-            for (int x = wv; x < 64; x += 4) {
-                if (B.flip) {
-                    // entry (r0 + x, k0 + lane) is T[n-1-k0-lane, n-1-r0-x]: lane along T's column
-                    As[lane * OP + x] = (r0 + x < r1 && k0 + lane < k1)
-                                            ? B.T[(n - 1 - k0 - lane) + (n - 1 - r0 - x) * B.ldt] : 0.0;
-                } else {
-                    As[x * OP + lane] = (r0 + lane < r1 && k0 + x < k1)
-                                            ? B.T[(r0 + lane) + (k0 + x) * B.ldt] : 0.0;
-                }
+            // As[kk * OP + r] = entry (r0 + r, k0 + kk) of the basis's matrix
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                const int y = wv + 4 * x;
+                if (B.flip) As[lane * OP + y] = ta[k][x];
+                else As[y * OP + lane] = ta[k][x];
             }
             __syncthreads();
-            auto mul = [&](dx4 &acc) {
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                if (!((mask >> (2 * y)) & 3)) continue;  // no group of this piece (uniform)
                 for (int kk = 0; kk < 64; kk += 4)
-                    acc = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + cc], acc);
-            };
-            switch (g >> 1) {  // the group's 16-column piece (uniform)
-                case 0: mul(d[k][0]); break;
-                case 1: mul(d[k][1]); break;
-                case 2: mul(d[k][2]); break;
-                default: mul(d[k][3]); break;
+                    d[k][y] = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + 16 * y + cc],
+                                       d[k][y]);
             }
-            __syncthreads();
             if (i == j + 2) {
-                // the group's last block below block i: publish its sums of block i
-                auto put = [&](const dx4 &acc, int y) {
+                // block j is the last below block i: publish the mask's groups' sums
+                // of block i
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int64_t row = r0 + rb + mfma64_row(lane, e);
-                        const int cg = cc - half;
-                        if (row < r1 && cg >= 0 && cg < cw)
-                            coherent_store(B.acc + row + (int64_t)(c0 + cg) * n, acc[e]);
+                        const int c = 16 * y + cc;
+                        if (row < r1 && c < m && ((mask >> (c / GC)) & 1))
+                            coherent_store(B.acc + row + (int64_t)c * n, d[k][y][e]);
                     }
-                };
-                switch (g >> 1) {
-                    case 0: put(d[k][0], 0); break;
-                    case 1: put(d[k][1], 1); break;
-                    case 2: put(d[k][2], 2); break;
-                    default: put(d[k][3], 3); break;
-                }
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
-                if (t == 0) set_flag(S.accready + (beta * S.G + g) * S.nb + i);
+                if (t < S.G && ((mask >> t) & 1)) set_flag(S.accready + (beta * S.G + t) * S.nb + i);
             }
+            __syncthreads();
         }
-        if (t == 0) s_next[g] = j + 1;
-        idle = 0;
+        if (t < S.G && ((mask >> t) & 1)) s_next[t] = j + 1;
         __syncthreads();
     }
 }
