@@ -34,9 +34,9 @@
  *     stream).  Single-matrix calls synchronise the stream once, after a
  *     device scan of the diagonal, to plan the work; the result in U is ready
  *     when the stream has been synchronised again.  Calls that also wait for
- *     their result before returning: MIXED_REFINED (its convergence test runs
- *     on the host), sign_tri(), signtri_batched(), and signtri() with a
- *     non-NULL `info`.  Those calls also return SIGNTRI_EHIP if a dependency
+ *     their result before returning: MIXED_REFINED (it reads the refinement's
+ *     outcome once at the end; its convergence tests run on the device),
+ *     sign_tri(), signtri_batched(), and signtri() with a non-NULL `info`.  Those calls also return SIGNTRI_EHIP if a dependency
  *     wait of a dataflow sweep hit its safety bound (which does not happen in
  *     a correct run; U then holds unusable values).  signtri() with a NULL
  *     `info` and no refinement returns without waiting and cannot report it.
@@ -45,6 +45,9 @@
  *     before it gives up (-1: the first wait of each sweep gives up at once);
  *     SIGNTRI_DEBUG_FAIL_ALLOC=1 makes every allocation of the library-owned
  *     workspace fail with SIGNTRI_ENOMEM.
+ *   - signtri_dtype, signtri_mode, signtri_algo and signtri_layout are
+ *     int32_t with the named constants below, so that any value a caller
+ *     passes is a valid argument and is checked (-p when out of range).
  *   - Return codes: 0 on success; -p if argument p (1-based) is invalid;
  *     positive SIGNTRI_E* codes below.  On any nonzero return, U is untouched
  *     except after SIGNTRI_EHIP (a device error mid-computation).
@@ -59,7 +62,8 @@
 extern "C" {
 #endif
 
-typedef enum { SIGNTRI_R64 = 0, SIGNTRI_C128 = 1 } signtri_dtype;
+typedef int32_t signtri_dtype;
+enum { SIGNTRI_R64 = 0, SIGNTRI_C128 = 1 };
 
 /* FP64: every operation in FP64 (complex128).
  * MIXED_REFINED: bulk products on FP32 MFMA with FP32 accumulation, divisions by
@@ -67,7 +71,8 @@ typedef enum { SIGNTRI_R64 = 0, SIGNTRI_C128 = 1 } signtri_dtype;
  *   TU = UT and an FP32 correction solve (iterative refinement); blocks whose
  *   refinement stalls are recomputed in FP64.
  * FP32: the mixed path without refinement (about 1e-6 relative accuracy). */
-typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } signtri_mode;
+typedef int32_t signtri_mode;
+enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 };
 
 /* PH: the Parlett-Higham substitution (Algorithm 3 in block form).
  * PS: the Parlett-Sylvester form (Algorithm 2 with diagonal blocks +-I) on a
@@ -78,15 +83,19 @@ typedef enum { SIGNTRI_FP64 = 0, SIGNTRI_MIXED_REFINED = 1, SIGNTRI_FP32 = 2 } s
  *   and left invariant subspaces of the minority sign class, each from a
  *   triangular substitution, give the spectral projector P of that class, and
  *   U = s (I - 2 P) with s the majority sign.  Real or complex T, in FP64 (every
- *   mode runs it in FP64), at most 64 entries in the minority class.
+ *   mode runs it in FP64), at most 512 (real T) or 64 (complex T) entries in
+ *   the minority class; real T also needs 2 ceil(m / 8) + 2 compute units for
+ *   its persistent launch (else SIGNTRI_ENOTSUP).
  * AUTO picks by work estimates: PS when the diagonal is grouped and the
  *   Section 3 model favours it; in FP64 mode with no sweep or block size pinned
- *   in the options, PROJ when the minority class is small (real T, 1..64
- *   entries) and its estimate 3 n^2 m is below the PH estimate; else PH.
- *   signtri_plan_host() reports the FP64-mode choice. */
-typedef enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2, SIGNTRI_PROJ = 3 } signtri_algo;
+ *   in the options, PROJ when the minority class is within those limits and the
+ *   estimate 3 n^2 m (four times that for complex T) is below the PH estimate;
+ *   else PH.  signtri_plan_host() reports the FP64-mode choice. */
+typedef int32_t signtri_algo;
+enum { SIGNTRI_AUTO = 0, SIGNTRI_PH = 1, SIGNTRI_PS = 2, SIGNTRI_PROJ = 3 };
 
-typedef enum { SIGNTRI_COL_MAJOR = 0, SIGNTRI_ROW_MAJOR = 1 } signtri_layout;
+typedef int32_t signtri_layout;
+enum { SIGNTRI_COL_MAJOR = 0, SIGNTRI_ROW_MAJOR = 1 };
 
 /* Path actually run. */
 enum { SIGNTRI_PATH_TRIVIAL = 0, SIGNTRI_PATH_PH = 1, SIGNTRI_PATH_PS = 2, SIGNTRI_PATH_PROJ = 3 };
@@ -136,9 +145,12 @@ typedef struct {
     int32_t tile;                /* block size: 0 = tuned choice or 32; 64 is available on
                                     the superdiagonal sweep of real FP64 only (and selects
                                     that sweep when `sweep` is AUTO)                      */
-    int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2);
-                                    negative: none, so every block counts as not converged
-                                    (recomputed in FP64, or SIGNTRI_ENOCONV)             */
+    int32_t max_refine_steps;    /* mixed mode: refinement steps at most, 0 = default (2),
+                                    at most 64 (else -13); negative: none, so every block
+                                    counts as not converged (recomputed in FP64, or
+                                    SIGNTRI_ENOCONV).  The convergence tests run on the
+                                    device: a step found unnecessary runs as empty
+                                    kernels, and nothing waits on the host until the end  */
     double stall_ratio;          /* mixed mode: a block stalls when a step leaves its
                                     residual above this fraction of the previous one
                                     (0 = default 0.5)                                    */
@@ -165,8 +177,8 @@ typedef struct {
  *   layout      storage order of both T and U
  *   mode        SIGNTRI_FP64, SIGNTRI_MIXED_REFINED or SIGNTRI_FP32
  *   algo        SIGNTRI_AUTO, SIGNTRI_PH, SIGNTRI_PS or SIGNTRI_PROJ (PS requires a
- *               diagonal already grouped by sign; PROJ 1..64 entries in the minority
- *               sign class; else SIGNTRI_ENOTSUP)
+ *               diagonal already grouped by sign; PROJ 1..512 (real) or 1..64
+ *               (complex) entries in the minority sign class; else SIGNTRI_ENOTSUP)
  *   Real and complex T take every mode; the projector form (PROJ) computes in
  *   FP64 whatever the mode.
  *   workspace   device scratch of ws_bytes bytes, or NULL to let the library
@@ -220,8 +232,9 @@ size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch,
  * The entry point that allocates nothing: for callers that cannot allocate
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation).  Computes what signtri() computes for FP64 mode,
- * column-major storage, AUTO path and default options (the dataflow sweeps or
- * the projector form), with no device or pinned-host allocation: the scratch
+ * column-major storage, AUTO path and default options (the dataflow sweeps, or
+ * the projector form for at most 64 minority entries: with more, the dataflow
+ * sweeps), with no device or pinned-host allocation: the scratch
  * memory comes from a fixed device array of 56 MiB that each GPU the library
  * runs on holds until the process ends, and the planner's host staging from a
  * fixed host array.  Orders up to 8192 (real or complex); larger n returns
@@ -263,8 +276,9 @@ int signtri_plan_host(const int8_t *s, int64_t n, signtri_dtype dtype,
  * it back.
  */
 typedef struct {
-    int32_t dtype, mode, path;  /* key: signtri_dtype, signtri_mode, SIGNTRI_PATH_PH/_PS */
-    int32_t log2n;              /* key: ceil(log2 n)                                      */
+    int32_t dtype, mode, path;  /* key: signtri_dtype, signtri_mode, SIGNTRI_PATH_PH/_PS,
+                                   or SIGNTRI_TUNE_BATCHED for signtri_batched()          */
+    int32_t log2n;              /* key: ceil(log2 n) (batched: of the largest order)      */
     int32_t sweep, tile, wgs_per_cu;  /* the choice                                       */
     double ms;                  /* its measured time per call, milliseconds               */
 } signtri_tune_entry;
@@ -282,6 +296,28 @@ typedef struct {
 int signtri_autotune(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n,
                      signtri_dtype dtype, signtri_mode mode, signtri_algo algo,
                      void *stream, int32_t reps, signtri_tune_entry *best);
+
+/*
+ * The batched form's key: signtri_batched() runs every matrix of a batch in
+ * one persistent dataflow sweep (32 x 32 blocks), so its one choice is the
+ * grid, wgs_per_cu; it consults the entry (dtype, mode, SIGNTRI_TUNE_BATCHED,
+ * ceil(log2 of the batch's largest order)) when options leave wgs_per_cu at 0.
+ */
+enum { SIGNTRI_TUNE_BATCHED = 8 };
+
+/*
+ * signtri_autotune() for a batch (arguments as signtri_batched(), column-major):
+ * times each dataflow grid (workgroups per compute unit) on this batch, `reps`
+ * timed calls each after one untimed call, records the fastest under the key
+ * above and returns it in *best (host).  U is overwritten with sign(T).
+ * Waits for the stream.  Returns 0, -p for argument p (as signtri_batched();
+ * -12 for reps out of [1, 1000], -13 for best == NULL), or the first error of a
+ * call.
+ */
+int signtri_autotune_batched(const void *const *T, const int64_t *ldt, void *const *U,
+                             const int64_t *ldu, const int64_t *n, int64_t batch,
+                             signtri_dtype dtype, signtri_mode mode, void *stream, int32_t reps,
+                             signtri_tune_entry *best);
 
 /* The recorded choice for this key, copied to *out: 1 if found, else 0. */
 int signtri_tune_lookup(signtri_dtype dtype, signtri_mode mode, int32_t path, int64_t n,

@@ -28,7 +28,9 @@ from . import workmodel  # noqa: F401  (re-exported)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "signtri_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SIGNTRI_ORACLE_LIB: another build of the same C file (the sanitizer build of
+# the CPU checks); by default the one built here
+_LIB = os.environ.get("SIGNTRI_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 

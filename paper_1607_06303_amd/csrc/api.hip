@@ -79,9 +79,12 @@ size_t max_total(int64_t n, signtri_dtype dtype, signtri_layout layout, signtri_
         m = std::max(m, layout_for(n, dtype, layout, mode, 32, false).total);
         if (dtype == SIGNTRI_R64) m = std::max(m, layout_for(n, dtype, layout, mode, 64, false).total);
     }
-    if (algo == SIGNTRI_AUTO || algo == SIGNTRI_PROJ)
+    if (algo == SIGNTRI_AUTO || algo == SIGNTRI_PROJ) {
+        // the projector form for any minority count it takes (at most n / 2)
+        const int mub = (int)std::min<int64_t>(n / 2, kProjMaxMinorityReal);
         m = std::max(m, layout_for(n, dtype, layout, mode, 32, true).prefix +
-                            align_up(proj_workspace_bytes(n, dtype == SIGNTRI_C128)));
+                            align_up(proj_workspace_bytes(n, mub, dtype == SIGNTRI_C128)));
+    }
     return m;
 }
 
@@ -93,6 +96,7 @@ int check_options(const signtri_options *o, signtri_dtype dtype, signtri_mode mo
     if (o->tile != 0 && o->tile != 32 && o->tile != 64) return -13;
     if (o->sweep < SIGNTRI_SWEEP_AUTO || o->sweep > SIGNTRI_SWEEP_SUPERDIAG) return -13;
     if (o->wgs_per_cu < 0) return -13;
+    if (o->max_refine_steps > kMaxRefineSteps) return -13;
     const bool cplx = dtype == SIGNTRI_C128;
     if (cplx && o->tile == 64) return SIGNTRI_ENOTSUP;
     if (mode != SIGNTRI_FP64 && (o->sweep == SIGNTRI_SWEEP_SUPERDIAG || o->tile == 64))
@@ -355,6 +359,15 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
                              (int64_t)ws_generation().load(), (int64_t)items.size(),
                              (int64_t)(opts ? opts->wgs_per_cu : 0), (int64_t)cplx,
                              (int64_t)flow_spin_limit()};
+    if (mode == SIGNTRI_MIXED_REFINED) {
+        // the refinement's options are part of what was captured
+        int64_t stall_bits = 0;
+        const double stall = opts ? opts->stall_ratio : 0.0;
+        std::memcpy(&stall_bits, &stall, sizeof(stall_bits));
+        key.insert(key.end(), {(int64_t)(opts ? opts->max_refine_steps : 0), stall_bits,
+                               (int64_t)(opts ? opts->no_fallback : 0),
+                               (int64_t)(opts ? opts->force_stall : 0)});
+    }
     std::vector<int64_t> ns;
     for (const RealItem &it : items) {
         key.insert(key.end(), {(int64_t)(intptr_t)it.T, it.ldt, (int64_t)(intptr_t)it.U, it.ldu,
@@ -387,7 +400,7 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
         drop_batch_graph(g);
         return SIGNTRI_EHIP;
     }
-    const int rc = run_real(items, mode, opts, run_dev, g.host, false, nullptr, cs);
+    const int rc = run_real(items, mode, opts, run_dev, g.host, false, nullptr, cs, false);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (rc != SIGNTRI_OK || ec != hipSuccess) {
@@ -482,7 +495,9 @@ namespace sgt {
 size_t noalloc_device_bytes(int64_t n, signtri_dtype dtype)
 {
     const Layout F = layout_for(n, dtype, SIGNTRI_COL_MAJOR, SIGNTRI_FP64, 32, true);
-    return std::max(F.total, F.prefix + align_up(proj_workspace_bytes(n, dtype == SIGNTRI_C128)));
+    // the projector form only up to kProjMaxMinority minority entries here
+    return std::max(F.total, F.prefix + align_up(proj_workspace_bytes(n, kProjMaxMinority,
+                                                                      dtype == SIGNTRI_C128)));
 }
 
 size_t noalloc_host_bytes(int64_t n, signtri_dtype dtype)
@@ -583,8 +598,10 @@ int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, sig
     int path = p.auto_path;
     // AUTO takes the projector form in FP64 mode when no sweep or block size is pinned
     const bool pinned_sweep = opts && (opts->sweep != 0 || opts->tile != 0);
+    // (with the caller's fixed buffers, up to kProjMaxMinority minority entries)
+    const int mmax = cplx || na ? kProjMaxMinority : kProjMaxMinorityReal;
     if (algo == SIGNTRI_AUTO && p.proj_pick && mode == SIGNTRI_FP64 && !pinned_sweep &&
-        (cplx || proj_fits(n)))
+        p.n_min <= mmax && (cplx || proj_fits(n, (int)p.n_min)))
         path = SIGNTRI_PATH_PROJ;
     if (algo == SIGNTRI_PH && path != SIGNTRI_PATH_TRIVIAL) path = SIGNTRI_PATH_PH;
     if (algo == SIGNTRI_PS && path != SIGNTRI_PATH_TRIVIAL) {
@@ -592,8 +609,8 @@ int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, sig
         path = SIGNTRI_PATH_PS;
     }
     if (algo == SIGNTRI_PROJ && path != SIGNTRI_PATH_TRIVIAL) {
-        if (p.n_min < 1 || p.n_min > kProjMaxMinority) return SIGNTRI_ENOTSUP;
-        if (!cplx && !proj_fits(n)) return SIGNTRI_ENOTSUP;
+        if (p.n_min < 1 || p.n_min > mmax) return SIGNTRI_ENOTSUP;
+        if (!cplx && !proj_fits(n, (int)p.n_min)) return SIGNTRI_ENOTSUP;
         path = SIGNTRI_PATH_PROJ;
     }
     if (path == SIGNTRI_PATH_PROJ) {
@@ -772,7 +789,16 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
     eo.tile = kFlowTile;
     {
+        // the grid: the caller's, else the autotuner's for this size class of the
+        // batch's largest order, else as many workgroups as fit
         const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, cplx);
+        if (eo.wgs_per_cu <= 0) {
+            int64_t nmax = 0;
+            for (int64_t b = 0; b < batch; ++b) nmax = std::max(nmax, n[b]);
+            signtri_tune_entry te;
+            if (nmax > 0 && tune_find(dtype, mode, SIGNTRI_TUNE_BATCHED, nmax, &te))
+                eo.wgs_per_cu = te.wgs_per_cu;
+        }
         if (eo.wgs_per_cu <= 0 || eo.wgs_per_cu > mx) eo.wgs_per_cu = mx;
     }
 
@@ -845,21 +871,24 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     std::vector<int64_t> ns(items.size());
     for (size_t m = 0; m < items.size(); ++m) ns[m] = items[m].n;
     char *run_dev = ws + BL.run, *run_host = hb + BL.run_host;
+    // every mode as one graph (captured at the first call with these arguments,
+    // replayed after): the refinement decides on the device, so nothing in it
+    // waits for the host
     int rc;
-    if (mode != SIGNTRI_MIXED_REFINED && graphs_enabled() && !prof_on()) {
+    const bool graph = graphs_enabled() && !prof_on();
+    if (graph) {
         int device = 0;
         if (hipGetDevice(&device) != hipSuccess) return SIGNTRI_EHIP;
         rc = launch_batch_graph(items, mode, &eo, run_dev, st, device);
     } else {
-        rc = run_real(items, mode, &eo, run_dev, run_host, prof_on(), hsigns.data(), st);
+        rc = run_real(items, mode, &eo, run_dev, run_host, prof_on(), hsigns.data(), st, false);
     }
     if (rc != SIGNTRI_OK) return rc;
-    // wait, and report a dependency wait of the sweep that gave up (the mixed mode
-    // has read the error word already, at each of its convergence tests)
-    if (mode != SIGNTRI_MIXED_REFINED)
-        return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx,
-                           run_host, st, nullptr);
-    return SIGNTRI_OK;
+    // wait; report a dependency wait of the sweep that gave up (and the refinement's
+    // outcome in the infos)
+    if (mode == SIGNTRI_MIXED_REFINED) return refine_finish(items, &eo, run_dev, run_host, st);
+    return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx, run_host, st,
+                       nullptr);
 }
 
 void signtri_release(void)

@@ -328,10 +328,14 @@ constexpr int kFlowTile = 32;
 
 // ---------------------------------------------------------------------------
 // Projector form (proj.hip): the Parlett-Sylvester result for an ungrouped
-// diagonal with at most kProjMaxMinority entries in its minority sign class.
+// diagonal with at most kProjMaxMinorityReal (real T) or kProjMaxMinority
+// (complex T) entries in its minority sign class.
 // ---------------------------------------------------------------------------
 constexpr int kProjMaxMinority = 64;
-size_t proj_workspace_bytes(int64_t n, bool cplx);
+constexpr int kProjMaxMinorityReal = 512;
+// Workspace of the form for order n and m minority entries (real: m up to
+// kProjMaxMinorityReal; complex: kProjMaxMinority, whatever m).
+size_t proj_workspace_bytes(int64_t n, int m, bool cplx);
 // T, U column-major real; sgn the device sign vector; minority = its sign (+1/-1),
 // m = its count.  Queues every launch on st.
 // flops: algorithmic flops of the two substitutions, for the kernel timers.
@@ -345,8 +349,9 @@ size_t proj_workspace_bytes(int64_t n, bool cplx);
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
              const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st,
              int *herr, bool rcp_guard);
-// Whether run_proj takes order n on the current device (its grid fits at once).
-bool proj_fits(int64_t n);
+// Whether run_proj takes order n with m minority entries on the current device
+// (its grid fits at once).
+bool proj_fits(int64_t n, int m);
 // The same for complex T (interleaved complex128).
 int run_proj_c(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, const int8_t *sgn,
                const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st);
@@ -385,6 +390,10 @@ template <typename F> struct FlowArgs {
     int *flags;                // completion flags (zeroed before, or 1 for blocks not recomputed)
     int spin_limit;            // polls before a wait gives up and sets the error word
                                // (negative: the first wait gives up at once; testing)
+    const int *live;           // if not null: the sweep runs only if *live != 0 (a refinement
+                               // step that the device decided is needed)
+    const int *ntasks_dev;     // if not null: the task count, at most ntasks, read on the
+                               // device (a task list built on the device)
 };
 // C: complex entries (interleaved re, im).
 template <typename F, int KIND, bool C>
@@ -395,8 +404,9 @@ int flow_max_wgs_per_cu(bool fp32, bool cplx);
 hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
 hipError_t launch_tasks_tri(int nb, int mat, int2 *out, hipStream_t st);
 hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t st);
-hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
-                                   int *flags, hipStream_t st);
+// (ntasks_dev: if not null, the count, at most ntasks, read on the device)
+hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const int *ntasks_dev,
+                                   const FlowMat<double> *mats, int *flags, hipStream_t st);
 
 // Algorithmic flops of the launches of one call (Section 3 counting), for the
 // opt-in kernel timers; all zero when the timers are off.
@@ -419,12 +429,14 @@ struct RefMat {
     int nbr, nbc;
     double two_s;              // Sylvester: 2 s
     int64_t f0;                // this matrix's first entry in the per-block arrays
+    int64_t fr0;               // its first entry in the per-block-row arrays (nbr + 1 of them)
     unsigned long long *maxes; // max |t|, max |u0|, max |correction| (non-negative bits)
 };
 struct RefArgs {
     RefMat m0;
     const RefMat *mats;
     int nmat;
+    const int *live;           // if not null: the kernels run only if *live != 0
 };
 hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
 hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
@@ -434,6 +446,44 @@ hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks
 // Real substitution form on 64 x 64 tiles (matrix, a << 16 | b), a <= b.
 hipError_t launch_resid64(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
                           hipStream_t st);
+
+// The refinement's decisions on the device, so that the whole refinement is
+// queued without a wait on the host (and can be captured in a graph).
+// After step `step` (run only if *live_in): per block f of the task list,
+// with a = sqrt(cur[f]) and aprev = sqrt(prev[f]) (rinit[f] = aprev at step 1):
+// converged if a <= max(rounding floor, conv * rinit[f]) and not forced; stalled
+// (sticky) if not converged and forced or a > stall * aprev; *live_out = 1 if
+// some block is neither.
+struct DecideArgs {
+    const RefMat *mats;
+    const int2 *tasks;         // the substitution blocks, then the Sylvester blocks
+    int ntasks;
+    const double *prev, *cur;  // squared residual norms before and after the step
+    double *rinit;             // residual norm before the first step
+    int8_t *ok, *hopeless;     // per block: converged; stalled
+    const int *live_in;
+    int *live_out;
+    int step, nmat;
+    double stall, conv;
+    int64_t force;             // -1: every block forced to stall; k > 0 (one matrix): block k - 1
+};
+hipError_t launch_refine_decide(const DecideArgs &d, hipStream_t st);
+// The FP64 recomputation's task lists: the blocks that did not converge and every
+// block whose products read them (block (I, J) is read by (I', J') with I' <= I
+// and J' >= J), in the order of the task lists, built on the device; counts in
+// cnt[0] (substitution) and cnt[1] (Sylvester), per matrix in nfb.
+struct ConeArgs {
+    const RefMat *mats;
+    const int2 *tasks;
+    int nph, nps;              // the task list's two parts
+    const int8_t *ok;
+    int *rowmin;               // per block row (fr0 + I): the least J not converged there, and
+                               // then over the rows below too
+    int2 *out_ph, *out_ps;     // the recomputation's task lists
+    int *cnt;                  // [2]
+    int64_t *nfb;              // per matrix: blocks recomputed
+};
+hipError_t launch_refine_cone(const ConeArgs &c, int nmat, int64_t nrows, hipStream_t st);
 
 // batch.hip: table-driven scan, output preparation and diagonal blocks.
 struct ScanMat {
@@ -480,10 +530,21 @@ struct RealItem {
 void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_bytes,
                size_t *host_bytes);
 // Run the sweeps of a set of real matrices: FP64, FP32, or FP32 with FP64
-// refinement (mode), every phase one launch over all matrices.
+// refinement (mode), every phase one launch over all matrices.  The refinement
+// decides on the device; with finish, the call then waits and reads its
+// summary (refine_finish); without, nothing waits on the host (graph capture),
+// and the caller calls refine_finish after the work has been queued.
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
-             hipStream_t st);
+             hipStream_t st, bool finish = true);
+// The refinement's outcome: waits for st, fills the items' infos (steps run,
+// correction size, blocks recomputed); SIGNTRI_EHIP if a dependency wait gave
+// up, SIGNTRI_ENOCONV if blocks did not converge and options forbid the FP64
+// recomputation.
+int refine_finish(std::vector<RealItem> &items, const signtri_options *opts, void *dev_ws,
+                  void *host_ws, hipStream_t st);
+// Refinement steps at most (options beyond it are rejected).
+constexpr int kMaxRefineSteps = 64;
 // Fixed buffers of the no-allocation entry point (device scratch and host
 // staging) in place of the library-owned workspace.
 struct NoAllocBuffers {

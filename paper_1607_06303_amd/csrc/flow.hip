@@ -177,10 +177,13 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
     // condition the compiler sees as divergent, or single-lane branches on both
     // sides of the back edge, the loop gets restructured so that lane 0 and the
     // other lanes pass the barriers in different iterations.
+    // a sweep of a refinement step the device decided against: nothing to do
+    if (a.live && uniform(*a.live) == 0) return;
+    const int ntasks = a.ntasks_dev ? uniform(min(*a.ntasks_dev, a.ntasks)) : a.ntasks;
     if (tid == 0) s_task = atomicAdd(&a.ctrl[0], 1);
     __syncthreads();
     int t = uniform(s_task);
-    while (t < a.ntasks) {
+    while (t < ntasks) {
         const int2 tk = a.tasks[t];
         const int mat = uniform(tk.x), ij = uniform(tk.y);
         const FlowMat<F> M = a.mats ? a.mats[mat] : a.m0;
@@ -797,11 +800,11 @@ __global__ void k_fill_int(int *p, int64_t n, int v)
 }
 
 // Mark the blocks of a task list as not finished (flag 0).
-__global__ void k_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
-                                   int *flags)
+__global__ void k_clear_task_flags(const int2 *tasks, int64_t ntasks, const int *ntasks_dev,
+                                   const FlowMat<double> *mats, int *flags)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntasks) return;
+    if (t >= ntasks || (ntasks_dev && t >= *ntasks_dev)) return;
     const int2 tk = tasks[t];
     const int I = tk.y >> 16, J = tk.y & 0xffff;
     flags[mats[tk.x].flag0 + (int64_t)I * mats[tk.x].nbc + J] = 0;
@@ -834,12 +837,12 @@ hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const FlowMat<double> *mats,
-                                   int *flags, hipStream_t st)
+hipError_t launch_clear_task_flags(const int2 *tasks, int64_t ntasks, const int *ntasks_dev,
+                                   const FlowMat<double> *mats, int *flags, hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_clear_task_flags, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0,
-                       st, tasks, ntasks, mats, flags);
+                       st, tasks, ntasks, ntasks_dev, mats, flags);
     return hipGetLastError();
 }
 

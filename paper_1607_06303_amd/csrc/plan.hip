@@ -122,12 +122,17 @@ HostPlan plan_from_signs(const int8_t *s, int64_t n, bool is_complex)
     p.auto_path = (p.ps_sign != 0 && w_ps_grouped < p.w_ph) ? SIGNTRI_PATH_PS : SIGNTRI_PATH_PH;
     // Otherwise the same result through the minority class's spectral projector:
     // two substitutions of about n^2 m / 2 multiply-adds each and the n^2 m / 2
-    // multiply-adds of the rank-m product, 3 n^2 m flops in all (real T).
+    // multiply-adds of the rank-m product, 3 n^2 m flops in all (real T; complex
+    // multiply-adds count four times as much, as in W_PH).
     p.n_min = std::min(p.n_pos, p.n_neg);
     p.min_sign = p.n_neg <= p.n_pos ? -1 : 1;
-    const double w_proj = 3.0 * nd * nd * (double)p.n_min;
-    p.proj_pick = !is_complex && p.auto_path == SIGNTRI_PATH_PH && p.n_min >= 1 &&
-                  p.n_min <= kProjMaxMinority && w_proj < p.w_ph;
+    // Complex T: the complex projector kernels (per-block launches, plain FMA
+    // products) reach about an eighth of complex Parlett-Higham's rate (n = 4096:
+    // 1.05 against 9.1 TFLOP/s), so their estimate is weighted by 8 against W_PH.
+    const double w_proj = (is_complex ? 8.0 * c : 1.0) * 3.0 * nd * nd * (double)p.n_min;
+    p.proj_pick = p.auto_path == SIGNTRI_PATH_PH && p.n_min >= 1 &&
+                  p.n_min <= (is_complex ? kProjMaxMinority : kProjMaxMinorityReal) &&
+                  w_proj < p.w_ph;
     return p;
 }
 

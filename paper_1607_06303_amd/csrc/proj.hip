@@ -67,10 +67,10 @@ struct ProjBasis {
     const double *T;      // T (column-major); the left basis reads it as J T^T J
     int64_t ldt;
     int flip;             // 1: entry (i, j) of this basis's matrix is T[n-1-j, n-1-i]
-    double *Z;            // n x PM, leading dimension n
-    double *acc;          // n x PM: sum over the rows below the current block
+    double *Z;            // n x mp (m rounded up to 64), leading dimension n
+    double *acc;          // n x mp: sum over the rows below the current block
     const int *rowtype;   // n: minority column of row i, or -1
-    const int *pos;       // PM: row of minority column l, or -1 (l >= m)
+    const int *pos;       // mp: row of minority column l, or -1 (l >= m)
 };
 
 struct ProjArgs {
@@ -98,11 +98,16 @@ __device__ inline int64_t toff(const ProjBasis &B, int64_t n, int64_t i, int64_t
 // Minority rows of both bases from the signs (one workgroup).
 // Basis 0 (T):      pos[l] = b_l,              rowtype[b_l] = l
 // Basis 1 (J T^T J): pos[l] = n-1-b_{m-1-l},   rowtype[n-1-b_l] = m-1-l
+// pos is padded with -1 to mp entries.  kx (if not null): for each basis and
+// 64-row block b counted from the bottom (rows [r0(b), r1(b)), r0(b) =
+// max(0, n - 64 (b + 1))), kx[basis * (nb + 2) + b + 2] = K(b), the number of
+// minority rows above the block (pos[l] < r0(b)), for b = -2 .. nb - 1.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_proj_prep(const int8_t *__restrict__ sgn, int64_t n,
-                                                    int minority, int m, int *__restrict__ rt0,
-                                                    int *__restrict__ pos0, int *__restrict__ rt1,
-                                                    int *__restrict__ pos1)
+                                                    int minority, int m, int mp, int nb,
+                                                    int *__restrict__ rt0, int *__restrict__ pos0,
+                                                    int *__restrict__ rt1, int *__restrict__ pos1,
+                                                    int *__restrict__ kx)
 {
     __shared__ int part[1024];
     const int t = threadIdx.x;
@@ -133,9 +138,26 @@ __global__ __launch_bounds__(1024) void k_proj_prep(const int8_t *__restrict__ s
             rt1[f] = -1;
         }
     }
-    for (int q = m + t; q < PM; q += 1024) {
+    for (int q = m + t; q < mp; q += 1024) {
         pos0[q] = -1;
         pos1[q] = -1;
+    }
+    if (kx) {
+        // the minority rows above each block, by bisection of the finished pos
+        __threadfence_block();
+        __syncthreads();
+        for (int e = t; e < 2 * (nb + 2); e += 1024) {
+            const int *pos = e < nb + 2 ? pos0 : pos1;
+            const int b = e % (nb + 2) - 2;
+            const int64_t r0 = n - (int64_t)PB * (b + 1);
+            int lo2 = 0, hi2 = m;  // the first l with pos[l] >= r0
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2) / 2;
+                if (pos[mid] < r0) lo2 = mid + 1;
+                else hi2 = mid;
+            }
+            kx[e] = lo2;
+        }
     }
 }
 
@@ -199,18 +221,24 @@ __device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
 // the coupling among the group's own columns solved in order by lane
 // broadcasts), from the block of the group's lowest minority row to the top;
 // waves 1..3 meanwhile publish the previous block's rows of the group and fetch
-// the next block's operands (T's diagonal block, the panel against the block
-// below, the earlier groups' values on the block's rows, and the far sums).
-// Between blocks all four waves add the block just below's part of the sums
-// (one 64 x 64 x 8 FP64 MFMA product, with the group's rows of that block still
-// in LDS).  The bottom group, which covers nearly every row, is the critical
-// path; a row costs it one single-wave step.
+// the next block's operands.  The coupling with the earlier columns l' < c0 on
+// block b's rows, sum_{l'} z_il' L[l', l], is split by where b_l' lies (L[l', l]
+// is set at row b_l', so it is known once that row is solved):
+//   * in block b: at most 64 columns, taken term by term in the steps;
+//   * in block b - 1: one 64 x 64 x 8 FP64 MFMA product between the blocks,
+//     together with the block just below's part of the sums (the group's rows
+//     of block b - 1 still in LDS);
+//   * further down: a 64 x (up to 504) x 8 product that waves 1..3 form while
+//     block b - 1 is solved.
+// The bottom group, which covers nearly every row, is the critical path; a row
+// costs it one single-wave step.
 //
-// The other workgroups ("owners") each own row blocks i >= 2 of one basis and
-// keep the far part of their sums, sum over the blocks j <= i - 2, in MFMA
-// accumulators: as block j is published by every group that reaches it, they
-// add T[block i, block j] Z[block j], and after the last one (j = i - 2) they
-// publish acc of block i for every group with terms there.
+// The other workgroups ("owners") each take tasks (row block i >= 2, chunk of
+// eight groups) of one basis in turn and keep the far part of the task's sums,
+// sum over the blocks j <= i - 2, in MFMA accumulators: as block j is published
+// by a group of the chunk, they add T[block i, block j] Z[block j, its
+// columns], and after the last one (j = i - 2) they publish acc of block i for
+// that group.
 //
 // Hand-offs go through flags in device memory.  The data behind a flag is
 // written with device-coherent stores that complete before the flag's store,
@@ -219,32 +247,39 @@ __device__ inline void mm64(const double *As, const double *Bs, dx4 (&d)[2][2])
 // with each other).  Every wait is bounded: past the limit it sets the error
 // word, which the host reports, and goes on, so the grid always drains.  All
 // workgroups of the launch are resident at once (the host sizes the grid to
-// the compute units).  Waits only point from a group to earlier groups and to
-// owners, and from owners to fronts of earlier blocks: there is no cycle.
+// the compute units).  A front's waits point to earlier groups at the same
+// block and to owners; an owner's, to fronts at blocks at least two below the
+// task's block and to its own earlier tasks, whose blocks are not higher: no
+// cycle.
 // ---------------------------------------------------------------------------
 constexpr int NQ = 8;             // lanes per column, each taking every NQ-th term
 constexpr int GC = 64 / NQ;       // columns per group (one wave)
 constexpr int NU = PB / NQ;       // block-row terms per lane
-constexpr int MAXG = PM / GC;     // groups at most
+constexpr int MPM = kProjMaxMinorityReal;  // minority columns at most (real T)
+constexpr int MAXG = MPM / GC;    // groups at most
+constexpr int CG = 64 / GC;       // groups per 64-column chunk (an owner task's columns)
 constexpr int NT = 256;           // threads of a workgroup (four waves)
-constexpr int TP = PB + 1;        // LDS pitch of the T block, the Z rows and the panel
+constexpr int TP = PB + 1;        // LDS pitch of the T block, the window values and the panel
 constexpr int ZCP = PB + NQ;      // LDS pitch of a group column (conflict-free column reads)
 constexpr int ABP = GC + 1;       // LDS pitch of the group's sums
-constexpr int KMAX = 2;           // row blocks per owner at most
+constexpr int LFP = GC;           // LDS pitch of the coupling coefficients
 constexpr int NH = NT - 64;       // helper lanes (waves 1..3)
-constexpr int HK = (PB * PB + NH - 1) / NH;        // a 64 x 64 operand: entries per helper lane
-constexpr int HC = (PB * (PM - GC) + NH - 1) / NH;  // earlier groups' values on a block's rows
-constexpr int HA = (PB * GC + NH - 1) / NH;         // the group's sums of a block
+constexpr int HK = (PB * PB + NH - 1) / NH;  // a 64 x 64 operand: entries per helper lane
+constexpr int HW = 8;             // a window's values fetched ahead per helper lane
+constexpr int HWC = HW * NH / PB; // columns of a window fetched ahead
+constexpr int HA = (PB * GC + NH - 1) / NH;  // the group's sums of a block
+static_assert(HW * NH % PB == 0, "whole window columns per fetch");
 
 struct ProjSync {
     int *zdone;     // [(basis * G + g) * nb + b]: group g's rows of block b published
     int *accready;  // same index: group g's far sums of block b published
     int *err;       // error word: a wait gave up
+    const int *kx;  // [basis * (nb + 2) + b + 2] = K(b): the minority columns whose row lies
+                    // above block b (b_l < r0(b)), for b = -2 .. nb - 1 (K(-1) = K(-2) = m)
     int spin_limit; // polls before a wait gives up (negative: at once; a testing hook)
     int nb;         // row blocks
     int G;          // column groups
     int nown;       // owner workgroups per basis
-    int kper;       // row blocks per owner (<= KMAX)
     int rcp_guard;  // some |t_ii| outside [2^-1020, 2^1019]: reciprocals checked for range
     int bstart[2 * MAXG];  // [basis * G + g]: the block of the group's lowest minority row
 };
@@ -306,15 +341,21 @@ __device__ inline void op_entry(bool flip, int e, int &row, int &col)
     }
 }
 
-// Owner: row blocks i = 2 + w + k nown (k < kper) of basis `beta`; block i's sums
-// over the blocks j <= i - 2 in MFMA accumulators (four waves, each 16 rows x 64
-// columns: rows 16 wave, four 16 x 16 pieces, a group's eight columns in half a
-// piece).  The groups run at their own pace, far apart, and each is followed on
-// its own: thread 0 takes the lowest block j that some group has published and
-// the owner has not yet added, with every group that has published it, and the
-// workgroup adds T[block i, block j] Z[block j, those groups' columns] (one
-// fetch of T's tile for them all; the 16-column pieces without such a group are
-// skipped).  All of a step's loads are issued before any is used.
+// A range of earlier columns [lo, lo + cnt) (cnt <= 0: none).
+struct Win {
+    int lo, cnt;
+};
+
+// Owner: tasks (row block i, chunk c of CG groups) of basis `beta`, in the order
+// of i, then c, every nown-th one; one task at a time.  A task keeps block i's
+// sums over the blocks j <= i - 2 for the chunk's 64 columns in MFMA
+// accumulators (four waves, each 16 rows x 64 columns: four 16 x 16 pieces, a
+// group's eight columns in half a piece).  The groups run at their own pace and
+// each is followed on its own: thread 0 takes the lowest block j that some group
+// of the chunk has published and the task has not yet added, with every group
+// that has published it, and the workgroup adds T[block i, block j] Z[block j,
+// those groups' columns] (the 16-column pieces without such a group skipped).
+// All of a step's loads are issued before any is used.
 __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, double *Bs)
 {
     const int o = (int)blockIdx.x - 2 * S.G;
@@ -326,114 +367,101 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
     const int rb = 16 * wv;
     const int kr = lane >> 4, cc = lane & 15;
     const int *bst = S.bstart + beta * S.G;
-    int ilast = -1;
-    for (int k = 0; k < S.kper; ++k)
-        if (2 + w + k * S.nown < S.nb) ilast = 2 + w + k * S.nown;
-    ilast = uniform(ilast);
-    __shared__ int s_next[MAXG];  // per group: its next block
+    const int nch = (S.G + CG - 1) / CG;
+    __shared__ int s_next[CG];  // per group of the chunk: its next block (> i - 2: done)
     __shared__ int s_j, s_mask;
-    if (t < MAXG) s_next[t] = t < S.G ? bst[t] : S.nb;
-    __syncthreads();
-    dx4 d[KMAX][4];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) d[k][y] = dx4{0.0, 0.0, 0.0, 0.0};
     int idle = 0;
-    for (;;) {
-        if (t == 0) {
-            // the lowest published block not yet added, and the groups that have it
-            // (j = -1: none published yet; -2: all done)
-            int jmin = 1 << 30, mask = 0, first = -1, jfirst = 1 << 30;
-            for (int g = 0; g < S.G; ++g) {
-                const int j = s_next[g];
-                if (j > ilast - 2) continue;
-                if (j < jfirst) {
-                    jfirst = j;
-                    first = g;
-                }
-                if (flag_load(S.zdone + (beta * S.G + g) * S.nb + j) == 0) continue;
-                if (j < jmin) {
-                    jmin = j;
-                    mask = 0;
-                }
-                if (j == jmin) mask |= 1 << g;
-            }
-            int jp = mask ? jmin : (first < 0 ? -2 : -1);
-            if (jp == -1) {
-                // bounded: past the limit (or after another wait gave up) take the
-                // lowest unfinished group anyway, so that the grid drains
-                if (S.spin_limit < 0 || ++idle > S.spin_limit || flag_load(S.err) != 0) {
-                    atomicOr(S.err, 1);
-                    jp = jfirst;
-                    for (int g = 0; g < S.G; ++g)
-                        if (s_next[g] == jfirst) mask |= 1 << g;
-                } else {
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            } else {
-                idle = 0;
-            }
-            s_j = jp;
-            s_mask = mask;
-        }
-        __syncthreads();
-        const int j = uniform(s_j), mask = uniform(s_mask);
-        if (j == -2) break;
-        if (j < 0) {
+    for (int task = w;; task += S.nown) {
+        const int i = uniform(2 + task / nch), c = uniform(task % nch);
+        if (i >= S.nb) break;
+        const int g0 = c * CG, gn = min(CG, S.G - g0);
+        __syncthreads();  // the previous task's last reads of s_next are done
+        if (t < CG) s_next[t] = (t < gn && bst[g0 + t] <= i - 2) ? bst[g0 + t] : i - 1;
+        const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
+        dx4 d[4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) d[y] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (;;) {
             __syncthreads();
-            continue;
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flags
-        const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
-        // the step's loads: block j's rows of the groups in the mask (coherent: they
-        // were published in this launch), and T's tiles [block i, block j]
-        double zb[16], ta[KMAX][16];
+            if (t == 0) {
+                // the lowest published block not yet added, and the groups that have it
+                // (j = -1: none published yet; -2: the task is done)
+                int jmin = 1 << 30, mask = 0, first = -1, jfirst = 1 << 30;
+                for (int gg = 0; gg < gn; ++gg) {
+                    const int j = s_next[gg];
+                    if (j > i - 2) continue;
+                    if (j < jfirst) {
+                        jfirst = j;
+                        first = gg;
+                    }
+                    if (flag_load(S.zdone + (beta * S.G + g0 + gg) * S.nb + j) == 0) continue;
+                    if (j < jmin) {
+                        jmin = j;
+                        mask = 0;
+                    }
+                    if (j == jmin) mask |= 1 << gg;
+                }
+                int jp = mask ? jmin : (first < 0 ? -2 : -1);
+                if (jp == -1) {
+                    // bounded: past the limit (or after another wait gave up) take the
+                    // lowest unfinished group anyway, so that the grid drains
+                    if (S.spin_limit < 0 || ++idle > S.spin_limit || flag_load(S.err) != 0) {
+                        atomicOr(S.err, 1);
+                        jp = jfirst;
+                        for (int gg = 0; gg < gn; ++gg)
+                            if (s_next[gg] == jfirst) mask |= 1 << gg;
+                    } else {
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                } else {
+                    idle = 0;
+                }
+                s_j = jp;
+                s_mask = mask;
+            }
+            __syncthreads();
+            const int j = uniform(s_j), mask = uniform(s_mask);
+            if (j == -2) break;
+            if (j < 0) continue;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flags
+            const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
+            // the step's loads: block j's rows of the groups in the mask (coherent: they
+            // were published in this launch), and T's tile [block i, block j]
+            double zb[16], ta[16];
 #pragma unroll
-        for (int x = 0; x < 16; ++x) {
-            const int c = wv + 4 * x;  // column
-            const bool live = c < m && ((mask >> (c / GC)) & 1) && k0 + lane < k1;
-            zb[x] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)c * n) : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int i = 2 + w + k * S.nown;
-            const bool use = k < S.kper && i <= ilast && i >= j + 2;
-            const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
+            for (int x = 0; x < 16; ++x) {
+                const int cl = wv + 4 * x;  // column within the chunk
+                const int col = 64 * c + cl;
+                const bool live = col < m && ((mask >> (cl / GC)) & 1) && k0 + lane < k1;
+                zb[x] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)col * n) : 0.0;
+            }
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 const int y = wv + 4 * x;
                 if (B.flip) {
                     // entry (r0 + y, k0 + lane) is T[n-1-k0-lane, n-1-r0-y]: lane along T's column
-                    ta[k][x] = (use && r0 + y < r1 && k0 + lane < k1)
-                                   ? B.T[(n - 1 - k0 - lane) + (n - 1 - r0 - y) * B.ldt] : 0.0;
+                    ta[x] = (r0 + y < r1 && k0 + lane < k1)
+                                ? B.T[(n - 1 - k0 - lane) + (n - 1 - r0 - y) * B.ldt] : 0.0;
                 } else {
-                    ta[k][x] = (use && r0 + lane < r1 && k0 + y < k1)
-                                   ? B.T[(r0 + lane) + (k0 + y) * B.ldt] : 0.0;
+                    ta[x] = (r0 + lane < r1 && k0 + y < k1) ? B.T[(r0 + lane) + (k0 + y) * B.ldt]
+                                                            : 0.0;
                 }
             }
-        }
-#pragma unroll
-        for (int x = 0; x < 16; ++x) Bs[lane * OP + wv + 4 * x] = zb[x];  // Bs[kk * OP + c]
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int i = 2 + w + k * S.nown;
-            if (k >= S.kper || i > ilast || i < j + 2) continue;  // uniform
-            const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
-            // As[kk * OP + r] = entry (r0 + r, k0 + kk) of the basis's matrix
+            // Bs[kk * OP + cl] = Z[k0 + kk, 64 c + cl]; As[kk * OP + r] = entry (r0 + r, k0 + kk)
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 const int y = wv + 4 * x;
-                if (B.flip) As[lane * OP + y] = ta[k][x];
-                else As[y * OP + lane] = ta[k][x];
+                Bs[lane * OP + y] = zb[x];
+                if (B.flip) As[lane * OP + y] = ta[x];
+                else As[y * OP + lane] = ta[x];
             }
             __syncthreads();
 #pragma unroll
             for (int y = 0; y < 4; ++y) {
                 if (!((mask >> (2 * y)) & 3)) continue;  // no group of this piece (uniform)
                 for (int kk = 0; kk < 64; kk += 4)
-                    d[k][y] = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + 16 * y + cc],
-                                       d[k][y]);
+                    d[y] = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + 16 * y + cc],
+                                    d[y]);
             }
             if (i == j + 2) {
                 // block j is the last below block i: publish the mask's groups' sums
@@ -443,34 +471,39 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int64_t row = r0 + rb + mfma64_row(lane, e);
-                        const int c = 16 * y + cc;
-                        if (row < r1 && c < m && ((mask >> (c / GC)) & 1))
-                            coherent_store(B.acc + row + (int64_t)c * n, d[k][y][e]);
+                        const int cl = 16 * y + cc, col = 64 * c + cl;
+                        if (row < r1 && col < m && ((mask >> (cl / GC)) & 1))
+                            coherent_store(B.acc + row + (int64_t)col * n, d[y][e]);
                     }
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
-                if (t < S.G && ((mask >> t) & 1)) set_flag(S.accready + (beta * S.G + t) * S.nb + i);
+                if (t < gn && ((mask >> t) & 1))
+                    set_flag(S.accready + (beta * S.G + g0 + t) * S.nb + i);
             }
             __syncthreads();
+            if (t < CG && ((mask >> t) & 1)) s_next[t] = j + 1;
         }
-        if (t < S.G && ((mask >> t) & 1)) s_next[t] = j + 1;
-        __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
 {
-    __shared__ double arena[3 * PB * TP + GC * ZCP + PB * ABP];
+    __shared__ double arena[3 * PB * TP + GC * ZCP + 2 * PB * ABP + MPM * LFP];
     if ((int)blockIdx.x >= 2 * S.G) {
         proj_owner(a, S, arena, arena + PB * OP);
         return;
     }
     double *const Tt = arena;              // Tt[r * TP + c] = T[r0 + r, r0 + c], zero below the diagonal
-    double *const Zr = Tt + PB * TP;       // Zr[r * TP + l] = Z[r0 + r, l]: earlier groups' values,
-                                           // the group's own as they are solved (zero before)
+    double *const Zr = Tt + PB * TP;       // the earlier columns' values on the block's rows: between
+                                           // blocks, the window of block b - 1's minority rows,
+                                           // Zr[k * TP + r] = Z[r0 + r, lo + k]; in the steps, that
+                                           // of block b's own, Zr[r * TP + k] = Z[r0 + r, lo + k]
     double *const Pn = Zr + PB * TP;       // Pn[k * TP + r] = T[r0 + r, r1 + k], the panel below
     double *const Zc = Pn + PB * TP;       // Zc[k * ZCP + r] = Z[r0 + r, c0 + k], the group's columns
-    double *const Ab = Zc + GC * ZCP;      // Ab[r * ABP + k] = acc[r0 + r, c0 + k]
+    double *const Ab = Zc + GC * ZCP;      // Ab[r * ABP + k]: the group's sums minus the coupling
+                                           // with the columns of the blocks below
+    double *const Cf = Ab + PB * ABP;      // Cf[r * ABP + k]: the coupling with the far columns
+    double *const Lf = Cf + PB * ABP;      // Lf[l * LFP + k] = L[l, c0 + k], earlier columns l < c0
 
     const int beta = (int)blockIdx.x & 1, g = uniform((int)blockIdx.x >> 1);
     const ProjBasis B = a.b[beta];
@@ -480,14 +513,32 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
     const int cw = uniform(min(GC, m - c0));  // its columns
     const int bs = uniform(S.bstart[beta * S.G + g]);
     const int *bst = S.bstart + beta * S.G;
+    const int *const kx = S.kx + beta * (S.nb + 2);
     const int t = threadIdx.x, wv = uniform(t >> 6);
     const bool fl = B.flip != 0;
     int *const zdone = S.zdone + (beta * S.G + g) * S.nb;
 
-    // Block b - 1's part of the group's sums, between blocks (all four waves):
-    // Ab += Pn^T Zc with Zc still holding the group's rows of block b - 1; each
-    // wave 16 rows, the columns padded to 16.
-    auto below_product = [&]() {
+    // The earlier columns by where their minority row lies: in block b (near), in
+    // block b - 1 (prev), further down (far).  Columns are ordered by their row,
+    // so each is a range.
+    auto K = [&](int b) { return uniform(kx[b + 2]); };
+    auto near = [&](int b) {
+        const int lo = K(b);
+        return Win{lo, min(K(b - 1), c0) - lo};
+    };
+    auto prev = [&](int b) {
+        const int lo = K(b - 1);
+        return Win{lo, min(K(b - 2), c0) - lo};
+    };
+    auto far = [&](int b) {
+        const int lo = K(b - 2);
+        return Win{lo, c0 - lo};
+    };
+
+    // Between blocks (all four waves): Ab += Pn^T Zc - Zr^T L[prev, group] - Cf,
+    // with Zc still holding the group's rows of block b - 1 and Zr the prev
+    // window's values on block b's rows; each wave 16 rows, the columns padded to 16.
+    auto below_product = [&](int b) {
         const int lane = t & 63, kr = lane >> 4, cc = lane & 15, rb = 16 * wv;
         dx4 dd = dx4{0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < PB; k += 4) {
@@ -495,9 +546,18 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             const double bv = cc < GC ? Zc[cc * ZCP + k + kr] : 0.0;
             dd = mfma_f64(av, bv, dd);
         }
+        const Win pw = prev(b);
+        for (int k = 0; k < pw.cnt; k += 4) {
+            const int kk = k + kr;
+            const double bv = (cc < GC && kk < pw.cnt) ? -Lf[(pw.lo + kk) * LFP + cc] : 0.0;
+            dd = mfma_f64(Zr[kk * TP + rb + cc], bv, dd);
+        }
+        const bool hf = far(b).cnt > 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (cc < GC) Ab[(rb + mfma64_row(lane, e)) * ABP + cc] += dd[e];
+        for (int e = 0; e < 4; ++e) {
+            const int r = rb + mfma64_row(lane, e);
+            if (cc < GC) Ab[r * ABP + cc] += hf ? dd[e] - Cf[r * ABP + cc] : dd[e];
+        }
     };
     // The two roles run separate loops with the same barriers per block (four),
     // so that neither holds the other's registers.
@@ -505,13 +565,14 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
     if (wv > 0) {
         // ==== waves 1..3: the next block's operands.  T's diagonal block and the
         // panel (inputs) are fetched into registers while the current block is
-        // solved; so are the earlier groups' values on the next block's rows and the
-        // group's far sums when their flags are already set, and otherwise after the
-        // boundary's first barrier.  (Only the inputs are fetched ahead
+        // solved; so are the earlier groups' values on the next block's rows (the
+        // near and prev windows, up to HWC columns each), with the far product, and
+        // the group's far sums, when their flags are already set, and otherwise
+        // after the boundary's first barrier.  (Only the inputs are fetched ahead
         // unconditionally: a wait before that barrier could close a cycle with the
         // owners, which wait for every group's earlier blocks.)
-        double hT[HK], hP[HK], hC[HC], hA[HA];
-        const int h = t - 64;  // helper lane
+        double hT[HK], hP[HK], hN[HW], hV[HW], hA[HA];
+        const int h = t - 64, hw = wv - 1;  // helper lane, helper wave
         auto fetch_inputs = [&](int b) {
             const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
             const int nr = (int)(r1 - r0);
@@ -534,15 +595,75 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 if (bst[gp] <= b) ok &= flag_load(S.zdone + (beta * S.G + gp) * S.nb + b) != 0;
             return uniform(ok) != 0;
         };
-        auto fetch_coupling = [&](int b) {
+        // a window's first HWC columns on block b's rows, into registers
+        auto fetch_win = [&](int b, Win wn, double(&hv)[HW]) {
             const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
             const int nr = (int)(r1 - r0);
             __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load moves above the flags
 #pragma unroll
-            for (int k = 0; k < HC; ++k) {
-                const int e = h + NH * k, l = e >> 6, row = e & 63;
-                hC[k] = (l < c0 && row < nr && bst[l / GC] <= b)
-                            ? coherent_load(B.Z + (r0 + row) + (int64_t)l * n) : 0.0;
+            for (int k = 0; k < HW; ++k) {
+                const int e = h + NH * k, col = e >> 6, row = e & 63;
+                hv[k] = (col < wn.cnt && row < nr)
+                            ? coherent_load(B.Z + (r0 + row) + (int64_t)(wn.lo + col) * n) : 0.0;
+            }
+        };
+        // a window into Zr (k-major for the product between blocks, else row-major
+        // for the steps), zeros up to the padding its reader takes; the columns past
+        // HWC, or all of them when not fetched ahead, loaded now
+        auto put_win = [&](int b, Win wn, const double(&hv)[HW], bool have, bool kmaj) {
+            const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+            const int nr = (int)(r1 - r0);
+            const int cpad = kmaj ? (wn.cnt + 3) & ~3 : (wn.cnt + NQ - 1) / NQ * NQ;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int k = 0; k < HW; ++k) {
+                const int e = h + NH * k, col = e >> 6, row = e & 63;
+                if (col < cpad) {
+                    double v = 0.0;
+                    if (col < wn.cnt && row < nr)
+                        v = have ? hv[k] : coherent_load(B.Z + (r0 + row) + (int64_t)(wn.lo + col) * n);
+                    if (kmaj) Zr[col * TP + row] = v;
+                    else Zr[row * TP + col] = v;
+                }
+            }
+            for (int e = h + HW * NH; e < cpad * PB; e += NH) {
+                const int col = e >> 6, row = e & 63;
+                const double v = (col < wn.cnt && row < nr)
+                                     ? coherent_load(B.Z + (r0 + row) + (int64_t)(wn.lo + col) * n) : 0.0;
+                if (kmaj) Zr[col * TP + row] = v;
+                else Zr[row * TP + col] = v;
+            }
+        };
+        // Cf = Z[block b, far] L[far, group] (FP64 MFMA, operands straight from
+        // memory and from Lf; helper wave 0 takes the 16-row pieces 0 and 3, waves 1
+        // and 2 the pieces 1 and 2).  Lf holds the far columns' coefficients: their
+        // rows were solved at least a block ago.
+        auto far_product = [&](int b) {
+            const Win fw = far(b);
+            if (fw.cnt <= 0) return;
+            const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
+            const int nr = (int)(r1 - r0);
+            const int lane = t & 63, kr = lane >> 4, cc = lane & 15;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            for (int p = hw; p < 4; p += 3) {
+                const int rr = 16 * p + cc;
+                const double *zp = B.Z + (r0 + rr) + (int64_t)fw.lo * n;
+                dx4 dd = dx4{0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < fw.cnt; k0 += 32) {
+                    double av[8], bv[8];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const int kk = k0 + 4 * s + kr;
+                        const bool in = kk < fw.cnt;
+                        av[s] = (in && rr < nr) ? coherent_load(zp + (int64_t)kk * n) : 0.0;
+                        bv[s] = (in && cc < GC) ? Lf[(fw.lo + kk) * LFP + cc] : 0.0;
+                    }
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) dd = mfma_f64(av[s], bv[s], dd);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (cc < GC) Cf[(16 * p + mfma64_row(lane, e)) * ABP + cc] = dd[e];
             }
         };
         // the group's sums over the blocks j <= b - 2, from their owner
@@ -563,7 +684,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         bool have_c = false, have_a = false;
         fetch_inputs(bs);
         for (int b = bs; b < S.nb; ++b) {
-            __syncthreads();  // (1) wave 0 has solved block b - 1
+            __syncthreads();  // (1) wave 0 has solved block b - 1 (and set Lf for its rows)
 #pragma unroll
             for (int k = 0; k < HK; ++k) {
                 const int e = h + NH * k;
@@ -572,41 +693,37 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 if (e < PB * PB) {
                     Tt[row * TP + col] = hT[k];
                     Pn[col * TP + row] = hP[k];  // k-major
-                    Zr[(e & 63) * TP + (e >> 6)] = 0.0;
                 }
             }
             if (!have_c) {
                 for (int gp = 0; gp < g; ++gp)
                     if (bst[gp] <= b) wave_wait(S.zdone + (beta * S.G + gp) * S.nb + b, S);
-                fetch_coupling(b);
+                far_product(b);
             }
-            // (after the zeros above: the same lane writes an entry's zero and its value,
-            // in this order)
-#pragma unroll
-            for (int k = 0; k < HC; ++k) {
-                const int e = h + NH * k, l = e >> 6, row = e & 63;
-                if (l < c0) Zr[row * TP + l] = hC[k];
-            }
-            const bool far = b - 2 >= bs;
-            if (far && !have_a) {
+            if (b > bs) put_win(b, prev(b), hV, have_c, true);
+            const bool farsum = b - 2 >= bs;
+            if (farsum && !have_a) {
                 wave_wait(S.accready + (beta * S.G + g) * S.nb + b, S);
                 fetch_acc(b);
             }
 #pragma unroll
             for (int k = 0; k < HA; ++k) {
                 const int e = h + NH * k, c = e >> 6, row = e & 63;
-                if (c < GC) Ab[row * ABP + c] = far ? hA[k] : 0.0;
+                if (c < GC) Ab[row * ABP + c] = farsum ? hA[k] : 0.0;
             }
             __syncthreads();  // (2)
-            if (b > bs) below_product();
+            if (b > bs) below_product(b);
             __syncthreads();  // (3)
             for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
+            put_win(b, near(b), hN, have_c, false);
             __syncthreads();  // (4)
             have_c = have_a = false;
             if (b + 1 < S.nb) {
                 fetch_inputs(b + 1);
                 if (coupling_ready(b + 1)) {
-                    fetch_coupling(b + 1);
+                    fetch_win(b + 1, near(b + 1), hN);
+                    fetch_win(b + 1, prev(b + 1), hV);
+                    far_product(b + 1);
                     have_c = true;
                 }
                 if (b + 1 - 2 >= bs && acc_ready(b + 1)) {
@@ -619,15 +736,13 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         return;
     }
 
-    // ==== wave 0: the group's columns, block after block.  Per column, across
-    // blocks: the coefficients L[NQ u + q][l] for the earlier groups' columns
-    // (u < g), and L[c0 + k'][l] for the group's own earlier columns (k' < kw), in
-    // every lane of the column; L[l][l] (t at row b_l, set at that row).  All zero
-    // until the rows that define them are reached.
+    // ==== wave 0: the group's columns, block after block.  Per column: the
+    // coefficients L[lo + NQ u + q][l] of the near window's columns (lreg; zero at
+    // the block's start, set at their rows, stored to Lf after the block) and
+    // L[c0 + k'][l] of the group's own earlier columns (k' < kw), in every lane
+    // of the column; L[l][l] (t at row b_l, set at that row).
     const int kw = (t & 63) / NQ, q = t % NQ;
     double lreg[NU], lw[GC], lamll = 0.0;
-#pragma unroll
-    for (int u = 0; u < NU; ++u) lreg[u] = 0.0;
 #pragma unroll
     for (int kp = 0; kp < GC; ++kp) lw[kp] = 0.0;
     const int pl = kw < cw ? B.pos[c0 + kw] : -1;
@@ -649,19 +764,22 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
     for (int b = bs; b < S.nb; ++b) {
         const int64_t r1 = blk_r1(n, b), r0 = blk_r0(n, b);
         const int nr = (int)(r1 - r0);
+        const Win nw = near(b);
         // the block's row types, lane i holding row i's (loaded ahead of its use)
         const int rtl = (t & 63) < nr ? B.rowtype[r0 + (t & 63)] : -1;
         __syncthreads();  // (1)
         if (b > bs) flag_rows(b - 1);
         __syncthreads();  // (2) the helpers have staged block b's operands
-        if (b > bs) below_product();
+        if (b > bs) below_product(b);
         __syncthreads();  // (3)
         for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
         __syncthreads();  // (4)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) lreg[u] = 0.0;
 
         // Row by row from the bottom; every column of the group takes the same row.
         // A column's sum for row r takes the rows below it within the block (its
-        // own column) and the earlier groups' values on row r (chunks u < g); the
+        // own column) and the near window's values on row r (chunks u < NCU); the
         // coupling among the group's own columns, still zero in that sum, is solved
         // after the reduction, column by column.  At a minority row that coupling is
         // zero (the row of Z is e_typ and L's row typ is not set yet), so only
@@ -679,7 +797,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
         const int rhi = kw < cw ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
         auto front = [&](auto gtag) {
-        constexpr int NCU = decltype(gtag)::value;  // coupling chunks: the earlier groups
+        constexpr int NCU = decltype(gtag)::value;  // coupling chunks: the near window's
         // Row r's prepared state: dpart = coupling - sum without row r + 1's term,
         // tnext = t[r][r+1] (that term's coefficient; 0 when already included or
         // outside the block), t_rr, 1 / (t_rr - L[l, l]) and the chain coefficients.
@@ -733,7 +851,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 cp0 += rv[u] * lreg[u];
                 if (u + 1 < NCU) cp1 += rv[u + 1] * lreg[u + 1];
             }
-            // coupling (earlier groups) - sum
+            // coupling (near window) - sum
             P.dpart = group_sum<NQ>((cp0 + cp1) - (v0 + v1));
             return P;
         };
@@ -765,9 +883,11 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                     } else if (act) {
                         // minority row b_typ (typ < l): row typ of L
                         if (typ < c0) {
+                            // an earlier column of the near window
+                            const int idx = typ - nw.lo;
 #pragma unroll
                             for (int u = 0; u < NU; ++u)
-                                if (NQ * u + q == typ) lreg[u] = -d;
+                                if (NQ * u + q == idx) lreg[u] = -d;
                         } else {
 #pragma unroll
                             for (int kp = 0; kp < GC; ++kp)
@@ -787,6 +907,11 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 if (q == 0 && act) Zc[kw * ZCP + r] = z;
                 if (!act) z = 0.0;
             }
+            // The column's other lanes read this value from LDS in later steps, with
+            // no barrier: the hardware keeps one wave's LDS operations in order, and
+            // this fence (wavefront scope: no instruction) keeps the compiler from
+            // moving those reads above the store.
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             // after a minority row (a uniform test), row r - 1's sum again, with the
             // state L has now and z_r included
             if (redo && r > 0) Pn = prep(r - 1, true);
@@ -794,8 +919,8 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             zprev = z;
         }
         };
-        static_assert(MAXG == 8, "one instance per group");
-        switch (g) {
+        static_assert(NU == 8, "one instance per chunk count");
+        switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
             case 0: front(std::integral_constant<int, 0>{}); break;
             case 1: front(std::integral_constant<int, 1>{}); break;
             case 2: front(std::integral_constant<int, 2>{}); break;
@@ -803,36 +928,68 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             case 4: front(std::integral_constant<int, 4>{}); break;
             case 5: front(std::integral_constant<int, 5>{}); break;
             case 6: front(std::integral_constant<int, 6>{}); break;
-            default: front(std::integral_constant<int, 7>{}); break;
+            case 7: front(std::integral_constant<int, 7>{}); break;
+            default: front(std::integral_constant<int, 8>{}); break;
         }
         store_rows(b);
+        // the near window's coefficients, for the products of the blocks above
+        // (read after the next barrier)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int c = NQ * u + q;
+            if (c < nw.cnt) Lf[(nw.lo + c) * LFP + kw] = lreg[u];
+        }
     }
     __syncthreads();
     flag_rows(S.nb - 1);
 }
 
-// Partial W^T Z over rows [64 g, 64 g + 64): part[g][l * PM + l'] (row-major l).
-// W[j, l] = Zf[n-1-j, m-1-l] with Zf the basis of the flipped matrix.
+// The upper block triangle of an mp x mp matrix in 64 x 64 tiles (mp = 64 nc),
+// numbered row by row: tile (a, c), a <= c, is number a nc - a (a - 1) / 2 + c - a.
+__host__ __device__ inline int utile_index(int a, int c, int nc) { return a * nc - a * (a - 1) / 2 + (c - a); }
+__device__ inline void utile_of(int idx, int nc, int &a, int &c)
+{
+    a = 0;
+    while (idx >= nc - a) {
+        idx -= nc - a;
+        ++a;
+    }
+    c = a + idx;
+}
+
+// Partial W^T Z: part[(p * ntiles + tile) * 4096 + r * 64 + c] = sum over the rows
+// j of part p (rows [p rpp, p rpp + rpp), rpp a multiple of 64) of W[j, 64 a + r]
+// Z[j, 64 c + c'] for tile (a, c) (blockIdx.y).  W[j, l] = Zf[n-1-j, m-1-l] with
+// Zf the basis of the flipped matrix.  W^T Z is upper triangular (W[j, l] = 0
+// for j < b_l, Z[j, l'] = 0 for j > b_l'), so only tiles a <= c are formed.
 __global__ __launch_bounds__(256) void k_proj_gram(const double *__restrict__ Z,
                                                    const double *__restrict__ Zf, int64_t n, int m,
-                                                   double *__restrict__ part)
+                                                   int nc, int64_t rpp, double *__restrict__ part)
 {
-    __shared__ double As[64 * OP];  // As[k * OP + l]  = W[j0 + k, l]
-    __shared__ double Bs[64 * OP];  // Bs[k * OP + l'] = Z[j0 + k, l']
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    __shared__ double As[64 * OP];  // As[k * OP + l]  = W[j0 + k, 64 a + l]
+    __shared__ double Bs[64 * OP];  // Bs[k * OP + l'] = Z[j0 + k, 64 c + l']
+    int ta = 0, tc = 0;
+    utile_of((int)blockIdx.y, nc, ta, tc);
+    ta = uniform(ta);
+    tc = uniform(tc);
     const int t = threadIdx.x, lr = t & 63, q = t >> 6;
-    for (int k = q; k < 64; k += 4) {
-        const int64_t j = j0 + k;
-        const bool ok = j < n && lr < m;
-        As[k * OP + lr] = ok ? Zf[(n - 1 - j) + (int64_t)(m - 1 - lr) * n] : 0.0;
-        Bs[k * OP + lr] = ok ? Z[j + (int64_t)lr * n] : 0.0;
-    }
-    __syncthreads();
+    const int la = 64 * ta + lr, lc = 64 * tc + lr;
     dx4 d[2][2];
-    mm64(As, Bs, d);
+    mm64_acc_zero(d);
+    const int64_t jb = (int64_t)blockIdx.x * rpp, je = std::min<int64_t>(n, jb + rpp);
+    for (int64_t j0 = jb; j0 < je; j0 += 64) {
+        for (int k = q; k < 64; k += 4) {
+            const int64_t j = j0 + k;
+            As[k * OP + lr] = (j < n && la < m) ? Zf[(n - 1 - j) + (int64_t)(m - 1 - la) * n] : 0.0;
+            Bs[k * OP + lr] = (j < n && lc < m) ? Z[j + (int64_t)lc * n] : 0.0;
+        }
+        __syncthreads();
+        mm64_acc<OP, OP>(As, Bs, d);
+        __syncthreads();
+    }
     const int lane = t & 63, w = t >> 6;
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    double *out = part + (int64_t)blockIdx.x * PM * PM;
+    double *out = part + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * 4096;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -841,35 +998,42 @@ __global__ __launch_bounds__(256) void k_proj_gram(const double *__restrict__ Z,
             for (int e = 0; e < 4; ++e) {
                 const int r = rb + 16 * x + mfma64_row(lane, e);
                 const int c = cb + 16 * y + (lane & 15);
-                out[r * PM + c] = d[x][y][e];
+                out[r * 64 + c] = d[x][y][e];
             }
 }
 
-// M = sum of the partials (one entry per thread, coalesced over the partials).
+// M = sum of the partials, row-major with pitch mp (one entry per thread,
+// coalesced over the partials); zero below the block diagonal, the identity
+// beyond the leading m x m block.
 __global__ __launch_bounds__(64) void k_proj_gsum(const double *__restrict__ part, int nparts,
-                                                  int m, double *__restrict__ M)
+                                                  int m, int mp, double *__restrict__ M)
 {
-    const int e = blockIdx.x * 64 + threadIdx.x;
-    const int r = e / PM, c = e % PM;
+    const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int r = (int)(e / mp), c = (int)(e % mp);
+    const int nc = mp / 64, ntiles = nc * (nc + 1) / 2;
     double s = 0.0;
     if (r < m && c < m) {
-        // eight independent partial sums, so that the loads are issued ahead
-        double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int g = 0;
-        for (; g + 8 <= nparts; g += 8)
+        if (r / 64 <= c / 64) {
+            const int64_t off = (int64_t)utile_index(r / 64, c / 64, nc) * 4096 + (r % 64) * 64 + c % 64;
+            const int64_t stride = (int64_t)ntiles * 4096;
+            // eight independent partial sums, so that the loads are issued ahead
+            double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int g = 0;
+            for (; g + 8 <= nparts; g += 8)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) p[k] += part[(int64_t)(g + k) * PM * PM + e];
-        for (; g < nparts; ++g) p[0] += part[(int64_t)g * PM * PM + e];
-        s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+                for (int k = 0; k < 8; ++k) p[k] += part[(int64_t)(g + k) * stride + off];
+            for (; g < nparts; ++g) p[0] += part[(int64_t)g * stride + off];
+            s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+        }
     } else {
         s = r == c ? 1.0 : 0.0;
     }
     M[e] = s;
 }
 
-// Minv = M^-1 for the upper triangular M (unit diagonal on the leading m x m
-// block, identity beyond; zero below the diagonal), by elimination from the last
-// row up: row k of the inverse is row k of the running right-hand side R
+// Minv = M^-1 for the upper triangular M of order 64 (unit diagonal on the leading
+// m x m block, identity beyond; zero below the diagonal), by elimination from the
+// last row up: row k of the inverse is row k of the running right-hand side R
 // (initially I) divided by M[k][k], and then every row i of R loses M[i][k]
 // times it (no change for i > k, where M[i][k] = 0; row k itself is not read
 // again).  Thread (l, q) keeps R[4 j + q][l] for j < 16 in registers; a
@@ -909,26 +1073,69 @@ __global__ __launch_bounds__(256) void k_proj_minv(const double *Mg, double *min
     }
 }
 
-// A = Z Minv over the rows [64 g, 64 g + 64): A[i, l] = sum_k Z[i, k] Minv[k][l]
-// (Minv is the identity beyond m, where Z's columns are zero).  Computed as the
-// transposed product C[l][i] = sum_k Minv[k][l] Z[i, k] (FP64 MFMA), so that the
-// accumulator's lanes run down A's columns.
+// Minv = M^-1 for the same kind of M of order mp > 64 (pitch mp): one wave per
+// column c, by substitution from row c up: x_c = 1 / M[c][c] and
+// x_k = -(sum_{k < j <= c} M[k][j] x_j) / M[k][k] for k = c - 1 down to 0.  Lane
+// i keeps x_{i + 64 p}; the x not yet computed (and those beyond c) are zero, so
+// each row's sum runs over all of them.  The sum is reduced in a fixed order.
+__global__ __launch_bounds__(256) void k_proj_minv_col(const double *__restrict__ M, int mp,
+                                                       double *__restrict__ minv)
+{
+    constexpr int NPX = MPM / 64;
+    const int lane = threadIdx.x & 63;
+    const int c = uniform((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
+    if (c >= mp) return;
+    double x[NPX];
+#pragma unroll
+    for (int p = 0; p < NPX; ++p) x[p] = 0.0;
+    const double xc = 1.0 / M[(int64_t)c * mp + c];
+#pragma unroll
+    for (int p = 0; p < NPX; ++p)
+        if (lane + 64 * p == c) x[p] = xc;
+    for (int k = c - 1; k >= 0; --k) {
+        const double *row = M + (int64_t)k * mp;
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < NPX; ++p)
+            if (64 * p < mp) s = fma(row[lane + 64 * p], x[p], s);
+        s = group_sum<16>(s);
+        s = (readlane_f64(s, 0) + readlane_f64(s, 16)) + (readlane_f64(s, 32) + readlane_f64(s, 48));
+        const double xk = -s / row[k];
+#pragma unroll
+        for (int p = 0; p < NPX; ++p)
+            if (lane + 64 * p == k) x[p] = xk;
+    }
+#pragma unroll
+    for (int p = 0; p < NPX; ++p)
+        if (lane + 64 * p < mp) minv[(int64_t)(lane + 64 * p) * mp + c] = x[p];
+}
+
+// A = Z Minv over the rows [64 g, 64 g + 64) and the columns [64 lb, 64 lb + 64)
+// (blockIdx.y = lb): A[i, l] = sum_k Z[i, k] Minv[k][l], over k < 64 lb + 64
+// (Minv is upper triangular; the identity beyond m, where Z's columns are zero).
+// Computed as the transposed product C[l][i] = sum_k Minv[k][l] Z[i, k] (FP64
+// MFMA), so that the accumulator's lanes run down A's columns.
 __global__ __launch_bounds__(256) void k_proj_a(const double *__restrict__ Z,
-                                                const double *__restrict__ minv, int64_t n,
+                                                const double *__restrict__ minv, int64_t n, int mp,
                                                 double *__restrict__ A)
 {
-    __shared__ double Ms[PM * OP];  // Ms[k * OP + l]  = Minv[k][l]
-    __shared__ double Zs[PM * OP];  // Zs[k * OP + ii] = Z[i0 + ii, k]
+    __shared__ double Ms[64 * OP];  // Ms[k * OP + l]  = Minv[64 kb + k][64 lb + l]
+    __shared__ double Zs[64 * OP];  // Zs[k * OP + ii] = Z[i0 + ii, 64 kb + k]
     const int t = threadIdx.x, lr = t & 63, q = t >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * 64;
-    for (int k = q; k < PM; k += 4) {
-        const int64_t i = i0 + lr;
-        Ms[k * OP + lr] = minv[k * PM + lr];
-        Zs[k * OP + lr] = i < n ? Z[i + (int64_t)k * n] : 0.0;
-    }
-    __syncthreads();
+    const int lb = (int)blockIdx.y;
     dx4 d[2][2];
-    mm64(Ms, Zs, d);
+    mm64_acc_zero(d);
+    for (int kb = 0; kb <= lb; ++kb) {
+        for (int k = q; k < 64; k += 4) {
+            const int64_t i = i0 + lr;
+            Ms[k * OP + lr] = minv[(int64_t)(64 * kb + k) * mp + 64 * lb + lr];
+            Zs[k * OP + lr] = i < n ? Z[i + (int64_t)(64 * kb + k) * n] : 0.0;
+        }
+        __syncthreads();
+        mm64_acc<OP, OP>(Ms, Zs, d);
+        __syncthreads();
+    }
     const int lane = t & 63, w = t >> 6;
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
 #pragma unroll
@@ -937,12 +1144,11 @@ __global__ __launch_bounds__(256) void k_proj_a(const double *__restrict__ Z,
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int l = rb + 16 * x + mfma64_row(lane, e);
+                const int l = 64 * lb + rb + 16 * x + mfma64_row(lane, e);
                 const int64_t i = i0 + cb + 16 * y + (lane & 15);
                 if (i < n) A[i + (int64_t)l * n] = d[x][y][e];
             }
 }
-
 // U[i, j] = s (delta_ij - 2 sum_l A[i, l] W[j, l]) for i <= j, 0 for i > j.
 // Computed as the transpose product C[j][i] = sum_l W[j, l] A[i, l], so that
 // the accumulator's lane index runs down a column of U.  A[i, l] is zero for
@@ -1321,22 +1527,29 @@ __global__ __launch_bounds__(256) void k_projc_u(const cd *__restrict__ A,
 
 }  // namespace
 
-// flags of the persistent run: two per block and basis, and the error word
 // flags of the persistent run: two per block, group and basis, and the error word
-size_t proj_sync_bytes(int64_t n) { return (size_t)(4 * MAXG * ((n + PB - 1) / PB) + 1) * sizeof(int); }
-
-size_t proj_workspace_bytes(int64_t n, bool cplx)
+size_t proj_sync_bytes(int64_t n, int m)
 {
-    const size_t nn = (size_t)n, es = cplx ? 16 : 8;
+    const int64_t G = (std::max(1, m) + GC - 1) / GC;
+    return (size_t)(4 * G * ((n + PB - 1) / PB) + 1) * sizeof(int);
+}
+
+namespace {
+
+// The complex form's workspace (at most PM minority columns).
+size_t projc_workspace_bytes(int64_t n)
+{
+    const size_t nn = (size_t)n, es = 16;
     const size_t nparts = (nn + 63) / 64;
     return 4 * al(nn * PM * es)             // Z and acc, two bases
            + 2 * al(PM * PM * es)           // L, two bases
            + 2 * al(nn * 4) + 2 * al(PM * 4)  // row types and minority rows
            + al(nparts * PM * PM * es)      // partial Gram matrices
            + al(PM * PM * es)               // Minv
-           + al(nn * PM * es)               // A
-           + al(proj_sync_bytes(n));        // flags (real T)
+           + al(nn * PM * es);              // A
 }
+
+}  // namespace
 
 int run_proj_c(const void *Tv, int64_t ldt, void *Uv, int64_t ldu, int64_t n, const int8_t *sgn,
                const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st)
@@ -1367,8 +1580,8 @@ int run_proj_c(const void *Tv, int64_t ldt, void *Uv, int64_t ldu, int64_t n, co
     cd *A = (cd *)take(nn * PM * 16);
     if (hipMemsetAsync(Z0, 0, (char *)rt0 - (char *)Z0, st) != hipSuccess) return SIGNTRI_EHIP;
     prof_begin(st);
-    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
-                       ps1);
+    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, PM, 0, rt0, ps0,
+                       rt1, ps1, (int *)nullptr);
     prof_end(st, PK_AUX, 0.0, 1);
     CArgs a;
     a.n = n;
@@ -1423,56 +1636,87 @@ int device_cus()
     return cache[dev];
 }
 
-// Owners per basis and row blocks per owner for a persistent run over nb blocks
-// with `fronts` front workgroups: every workgroup must be resident at once (one
-// per compute unit: the front's LDS arena leaves room for no second one).  False
-// when nb is too large.
-bool proj_grid(int64_t nb, int cus, int fronts, int *nown, int *kper)
+// Owners per basis for a persistent run over nb blocks with G column groups (2 G
+// fronts): every workgroup must be resident at once (one per compute unit: the
+// front's LDS arena leaves room for no second one).  False when the fronts and
+// at least one owner per basis do not fit.
+bool proj_grid(int64_t nb, int cus, int G, int *nown)
 {
-    const int64_t tiles = nb > 2 ? nb - 2 : 0;
-    if (tiles == 0) {
+    const int fronts = 2 * G;
+    if (fronts > cus) return false;
+    const int64_t tasks = (nb > 2 ? nb - 2 : 0) * ((G + CG - 1) / CG);
+    if (tasks == 0) {
         *nown = 0;
-        *kper = 0;
-        return cus >= fronts;
+        return true;
     }
     const int64_t slots = (int64_t)(cus - fronts) / 2;
     if (slots < 1) return false;
-    const int64_t no = std::min<int64_t>(tiles, slots);
-    const int64_t kp = (tiles + no - 1) / no;
-    if (kp > KMAX) return false;
-    // as few owners as keep kp: fewer workgroups polling
-    *nown = (int)((tiles + kp - 1) / kp);
-    *kper = (int)kp;
+    *nown = (int)std::min<int64_t>(slots, tasks);
     return true;
 }
 
-bool proj_fits(int64_t n)
+bool proj_fits(int64_t n, int m)
 {
-    int nown = 0, kper = 0;
-    return n >= 2 && proj_grid((n + PB - 1) / PB, device_cus(), 2 * MAXG, &nown, &kper);
+    int nown = 0;
+    return n >= 2 && m >= 1 && m <= MPM &&
+           proj_grid((n + PB - 1) / PB, device_cus(), (m + GC - 1) / GC, &nown);
 }
+
+namespace {
+
+// The real form's workspace, in the order run_proj takes it.
+struct ProjLayout {
+    int mp, nc, ntiles, nparts;
+    int64_t nb, rpp;
+    size_t bytes;
+};
+
+ProjLayout proj_layout(int64_t n, int m)
+{
+    ProjLayout L;
+    L.mp = (std::max(1, std::min(m, MPM)) + 63) / 64 * 64;
+    L.nc = L.mp / 64;
+    L.ntiles = L.nc * (L.nc + 1) / 2;
+    L.nb = (n + PB - 1) / PB;
+    // partial sums of W^T Z over row ranges: about 256 workgroups in all
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(L.nb, 256 / L.ntiles));
+    L.rpp = (L.nb + want - 1) / want * PB;
+    L.nparts = (int)((n + L.rpp - 1) / L.rpp);
+    const size_t nn = (size_t)n, mp = (size_t)L.mp;
+    L.bytes = 4 * al(nn * mp * 8)                       // Z and acc, two bases
+              + 2 * al(nn * 4) + 2 * al(mp * 4)         // row types and minority rows
+              + al((size_t)2 * (L.nb + 2) * 4)          // K(b) of both bases
+              + al((size_t)L.nparts * L.ntiles * 4096 * 8)  // partial Gram matrices
+              + 2 * al(mp * mp * 8)                     // W^T Z and its inverse
+              + al(nn * mp * 8)                         // A
+              + al(proj_sync_bytes(n, m));              // flags
+    return L;
+}
+
+}  // namespace
 
 int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, const int8_t *sgn,
              const int8_t *hsgn, int minority, int m, double flops, void *ws, hipStream_t st,
              int *herr, bool rcp_guard)
 {
-    if (m < 1 || m > PM || n < 2) return SIGNTRI_ENOTSUP;
+    if (m < 1 || m > MPM || n < 2) return SIGNTRI_ENOTSUP;
     const int G = (m + GC - 1) / GC;
-    int nown = 0, kper = 0;
-    const int64_t nb = (n + PB - 1) / PB;
-    if (!proj_grid(nb, device_cus(), 2 * G, &nown, &kper)) return SIGNTRI_ENOTSUP;
+    int nown = 0;
+    const ProjLayout PL = proj_layout(n, m);
+    const int64_t nb = PL.nb;
+    if (!proj_grid(nb, device_cus(), G, &nown)) return SIGNTRI_ENOTSUP;
     // the minority rows of both bases, ascending (basis 1: rows of J T^T J), and
     // each group's first block (that of its lowest minority row)
     int bsh[2 * MAXG];
     {
-        int cnt = 0;
-        int64_t rows0[PM], rows1[PM];
+        std::vector<int64_t> rows0, rows1((size_t)m);
+        rows0.reserve((size_t)m);
         for (int64_t i = 0; i < n; ++i)
             if (hsgn[i] == minority) {
-                if (cnt >= m) return SIGNTRI_ENOTSUP;
-                rows0[cnt++] = i;
+                if ((int)rows0.size() >= m) return SIGNTRI_ENOTSUP;
+                rows0.push_back(i);
             }
-        if (cnt != m) return SIGNTRI_ENOTSUP;
+        if ((int)rows0.size() != m) return SIGNTRI_ENOTSUP;
         for (int l = 0; l < m; ++l) rows1[l] = n - 1 - rows0[m - 1 - l];
         for (int g = 0; g < G; ++g) {
             const int last = std::min(m, (g + 1) * GC) - 1;
@@ -1480,31 +1724,30 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
             bsh[G + g] = (int)((n - 1 - rows1[last]) / PB);
         }
     }
-    const size_t nn = (size_t)n;
-    const int64_t nparts = (n + 63) / 64;
+    const size_t nn = (size_t)n, mp = (size_t)PL.mp;
     char *p = (char *)ws;
     auto take = [&](size_t bytes) {
         char *q = p;
         p += al(bytes);
         return (void *)q;
     };
-    double *Z0 = (double *)take(nn * PM * 8), *Z1 = (double *)take(nn * PM * 8);
-    double *C0 = (double *)take(nn * PM * 8), *C1 = (double *)take(nn * PM * 8);
-    take(PM * PM * 8);  // (L of both bases: only the complex kernels keep it in memory)
-    take(PM * PM * 8);
+    double *Z0 = (double *)take(nn * mp * 8), *Z1 = (double *)take(nn * mp * 8);
+    double *C0 = (double *)take(nn * mp * 8), *C1 = (double *)take(nn * mp * 8);
     int *rt0 = (int *)take(nn * 4), *rt1 = (int *)take(nn * 4);
-    int *ps0 = (int *)take(PM * 4), *ps1 = (int *)take(PM * 4);
-    double *part = (double *)take((size_t)nparts * PM * PM * 8);
-    double *minv = (double *)take(PM * PM * 8);
-    double *A = (double *)take(nn * PM * 8);
-    int *sync = (int *)take(proj_sync_bytes(n));
+    int *ps0 = (int *)take(mp * 4), *ps1 = (int *)take(mp * 4);
+    int *kx = (int *)take((size_t)2 * (nb + 2) * 4);
+    double *part = (double *)take((size_t)PL.nparts * PL.ntiles * 4096 * 8);
+    double *Mg = (double *)take(mp * mp * 8);
+    double *minv = (double *)take(mp * mp * 8);
+    double *A = (double *)take(nn * mp * 8);
+    int *sync = (int *)take(proj_sync_bytes(n, m));
 
     // Z of both bases (contiguous) cleared: a group writes only the blocks it
     // reaches; flags and error word cleared.  Fill kernels, no memset node
     // (should the call be captured).
     prof_begin(st);
-    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, rt0, ps0, rt1,
-                       ps1);
+    hipLaunchKernelGGL(k_proj_prep, dim3(1), dim3(1024), 0, st, sgn, n, minority, m, (int)mp,
+                       (int)nb, rt0, ps0, rt1, ps1, kx);
     if (launch_fill_int((int *)Z0, (int64_t)(((char *)C0 - (char *)Z0) / 4), 0, st) != hipSuccess ||
         launch_fill_int(sync, (int64_t)(4 * G * nb + 1), 0, st) != hipSuccess)
         return SIGNTRI_EHIP;
@@ -1519,24 +1762,30 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
     S.zdone = sync;
     S.accready = sync + 2 * G * nb;
     S.err = sync + 4 * G * nb;
+    S.kx = kx;
     for (int x = 0; x < 2 * G; ++x) S.bstart[x] = bsh[x];
     S.spin_limit = flow_spin_limit();
     S.nb = (int)nb;
     S.G = G;
     S.nown = nown;
-    S.kper = kper;
     S.rcp_guard = rcp_guard ? 1 : 0;
     const double nd = (double)n, md = (double)m;
     prof_begin(st);
     hipLaunchKernelGGL(k_proj_run, dim3(2 * G + 2 * nown), dim3(NT), 0, st, a, S);
     prof_end(st, PK_PROJ, flops, 1);
     prof_begin(st);
-    // four launches: W^T Z partials, their sum, its inverse, A; then the product
-    hipLaunchKernelGGL(k_proj_gram, dim3(nparts), dim3(256), 0, st, Z0, Z1, n, m, part);
-    hipLaunchKernelGGL(k_proj_gsum, dim3(PM * PM / 64), dim3(64), 0, st, part, (int)nparts, m,
-                       minv);
-    hipLaunchKernelGGL(k_proj_minv, dim3(1), dim3(256), 0, st, minv, minv);
-    hipLaunchKernelGGL(k_proj_a, dim3((n + 63) / 64), dim3(256), 0, st, Z0, minv, n, A);
+    // W^T Z (partials, their sum), its inverse, A; then the product
+    hipLaunchKernelGGL(k_proj_gram, dim3(PL.nparts, PL.ntiles), dim3(256), 0, st, Z0, Z1, n, m,
+                       PL.nc, PL.rpp, part);
+    hipLaunchKernelGGL(k_proj_gsum, dim3((unsigned)(mp * mp / 64)), dim3(64), 0, st, part,
+                       PL.nparts, m, (int)mp, Mg);
+    if (mp == 64)
+        hipLaunchKernelGGL(k_proj_minv, dim3(1), dim3(256), 0, st, Mg, minv);
+    else
+        hipLaunchKernelGGL(k_proj_minv_col, dim3((unsigned)(mp / 4)), dim3(256), 0, st, Mg, (int)mp,
+                           minv);
+    hipLaunchKernelGGL(k_proj_a, dim3((unsigned)((n + 63) / 64), PL.nc), dim3(256), 0, st, Z0, minv,
+                       n, (int)mp, A);
     const int64_t nu = (n + 63) / 64;
     hipLaunchKernelGGL(k_proj_u, dim3(nu, nu), dim3(256), 0, st, A, Z1, ps0, n, m,
                        minority > 0 ? -1.0 : 1.0, U, ldu);
@@ -1551,6 +1800,11 @@ int run_proj(const double *T, int64_t ldt, double *U, int64_t ldu, int64_t n, co
         if (*herr) return SIGNTRI_EHIP;
     }
     return SIGNTRI_OK;
+}
+
+size_t proj_workspace_bytes(int64_t n, int m, bool cplx)
+{
+    return cplx ? projc_workspace_bytes(n) : proj_layout(n, m).bytes;
 }
 
 }  // namespace sgt

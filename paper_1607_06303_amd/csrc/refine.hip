@@ -57,6 +57,9 @@ template <int P, typename S> __device__ inline double mag(const S *p, int64_t e)
 
 #define REF_MAT(a) (a.mats ? a.mats[blockIdx.z] : a.m0)
 
+// A kernel of a refinement step the device decided against: nothing to do.
+__device__ inline bool gated_off(const RefArgs &a) { return a.live && uniform(*a.live) == 0; }
+
 // FP32 copies for the reduced-precision sweeps: the upper triangle of T, and
 // the (FP64-computed) diagonal blocks of U; max |t_ij| on the side.  Matrix
 // blockIdx.z of the table; columns strided over blockIdx.y.
@@ -112,6 +115,7 @@ template <int P> __global__ __launch_bounds__(NT) void k_widen(RefArgs a)
 template <int P> __global__ __launch_bounds__(NT) void k_add_correction(RefArgs a)
 {
     __shared__ double red[NT / 64];
+    if (gated_off(a)) return;
     const RefMat d = REF_MAT(a);
     double m = 0.0;
     for (int64_t j = blockIdx.y; j < d.n; j += gridDim.y) {
@@ -130,6 +134,7 @@ template <int P> __global__ __launch_bounds__(NT) void k_add_correction(RefArgs 
 
 __global__ void k_clear_correction_max(RefArgs a)
 {
+    if (gated_off(a)) return;
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z < a.nmat) (a.mats ? a.mats[z] : a.m0).maxes[2] = 0;
 }
@@ -163,6 +168,7 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     __shared__ int8_t rs[TB], cs[TB];
     __shared__ double red[NT / 64];
 
+    if (gated_off(a)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
@@ -293,6 +299,7 @@ void k_resid64(RefArgs a, const int2 *__restrict__ tiles, int ntiles, double *__
     __shared__ double sBU[(TB / 4) * RBS], sBT[(TB / 4) * RBS];
     __shared__ int8_t rs[2 * TB], cs[2 * TB];
 
+    if (gated_off(a)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pr = wave >> 1, pc = wave & 1;
     const int mg = lane >> 4, mt = lane & 15;
@@ -442,6 +449,7 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
     __shared__ double sB[P * BS];
     __shared__ double red[NT / 64];
 
+    if (gated_off(a)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
@@ -550,6 +558,113 @@ dim3 col_grid(int64_t nmax, int nmat)
     return dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)by, (unsigned)nmat);
 }
 
+// ---------------------------------------------------------------------------
+// The refinement's decisions, on the device.
+// ---------------------------------------------------------------------------
+
+// One thread per block of the task list: converged, stalled, and whether another
+// step is needed (as the host loop of the refinement would decide).
+__global__ __launch_bounds__(256) void k_refine_decide(DecideArgs d)
+{
+    if (uniform(*d.live_in) == 0) return;  // this step did not run: nothing changes
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= d.ntasks) return;
+    const int2 tk = d.tasks[t];
+    const RefMat &m = d.mats[tk.x];
+    const int I = tk.y >> 16, J = tk.y & 0xffff;
+    const int64_t lf = (int64_t)I * m.nbc + J, f = m.f0 + lf;
+    const double aprev = sqrt(d.prev[f]), a = sqrt(d.cur[f]);
+    if (d.step == 1) d.rinit[f] = aprev;
+    const double r0 = d.rinit[f];
+    const double tmax = __longlong_as_double((long long)m.maxes[0]);
+    const double umax = __longlong_as_double((long long)m.maxes[1]);
+    // K blocks in each entry's residual products
+    const bool syl = m.split > 0;
+    const int kb = syl ? (m.nbr - I) + (J + 1) : (J - I + 1);
+    // the rounding level of an FP64 residual block: kb * TB products per entry of
+    // size up to umax * max(umax, tmax)
+    const double floor_ = 0x1p-52 * (double)kb * TB * TB * umax * fmax(umax, tmax);
+    const bool forced = d.force == -1 || (d.nmat == 1 && d.force > 0 && d.force - 1 == lf);
+    const bool good = !forced && a <= fmax(floor_, d.conv * r0);
+    d.ok[f] = good ? 1 : 0;
+    const bool hop = d.hopeless[f] != 0 || (!good && (forced || a > d.stall * aprev));
+    d.hopeless[f] = hop ? 1 : 0;
+    if (!good && !hop) __hip_atomic_store(d.live_out, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// rowmin[fr0 + I] = min J over the blocks of row I that did not converge
+// (initially INT_MAX), one thread per block.
+__global__ __launch_bounds__(256) void k_refine_rowmin(ConeArgs c)
+{
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= c.nph + c.nps) return;
+    const int2 tk = c.tasks[t];
+    const RefMat &m = c.mats[tk.x];
+    const int I = tk.y >> 16, J = tk.y & 0xffff;
+    if (!c.ok[m.f0 + (int64_t)I * m.nbc + J]) atomicMin(&c.rowmin[m.fr0 + I], J);
+}
+
+// Over the rows below, per matrix (one thread each): rowmin[I] = min over I' >= I.
+// Block (I, J) is then recomputed iff J >= rowmin[I]: some block (I', J') with
+// I' >= I and J' <= J did not converge, and (I, J) reads it, directly or through
+// the blocks between.
+__global__ __launch_bounds__(256) void k_refine_rowsuffix(ConeArgs c, int nmat)
+{
+    const int z = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (z >= nmat) return;
+    const RefMat &m = c.mats[z];
+    int *r = c.rowmin + m.fr0;
+    for (int I = m.nbr - 2; I >= 0; --I) r[I] = min(r[I], r[I + 1]);
+}
+
+// The recomputation's task lists in the task lists' order (one workgroup of 1024
+// threads, 1024 tasks at a time: ballot counts per wave, then the waves' counts
+// in order), their lengths, and the blocks per matrix.
+__global__ __launch_bounds__(1024) void k_refine_compact(ConeArgs c)
+{
+    __shared__ int wcnt[2][16];
+    __shared__ int base[2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < 2) base[tid] = 0;
+    __syncthreads();
+    const int total = c.nph + c.nps;
+    for (int start = 0; start < total; start += 1024) {
+        const int t = start + tid;
+        int keep = 0, part = 0;
+        int2 tk = make_int2(0, 0);
+        if (t < total) {
+            tk = c.tasks[t];
+            const RefMat &m = c.mats[tk.x];
+            const int I = tk.y >> 16, J = tk.y & 0xffff;
+            keep = J >= c.rowmin[m.fr0 + I];
+            part = t < c.nph ? 0 : 1;
+        }
+        const uint64_t b0 = __builtin_amdgcn_ballot_w64(keep && part == 0);
+        const uint64_t b1 = __builtin_amdgcn_ballot_w64(keep && part == 1);
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        if (lane == 0) {
+            wcnt[0][wv] = __popcll(b0);
+            wcnt[1][wv] = __popcll(b1);
+        }
+        __syncthreads();
+        if (keep) {
+            int off = base[part];
+            for (int w = 0; w < wv; ++w) off += wcnt[part][w];
+            off += __popcll((part ? b1 : b0) & below);
+            (part ? c.out_ps : c.out_ph)[off] = tk;
+            atomicAdd((unsigned long long *)&c.nfb[tk.x], 1ull);
+        }
+        __syncthreads();
+        if (tid < 2) {
+            int sum = 0;
+            for (int w = 0; w < 16; ++w) sum += wcnt[tid][w];
+            base[tid] += sum;
+        }
+        __syncthreads();
+    }
+    if (tid < 2) c.cnt[tid] = base[tid];
+}
+
 }  // namespace
 
 hipError_t launch_to_f32(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st)
@@ -604,6 +719,31 @@ hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks
         hipLaunchKernelGGL(k_resid<2>, g, b, 0, st, a, tasks, ntasks, norm2);
     else
         hipLaunchKernelGGL(k_resid<1>, g, b, 0, st, a, tasks, ntasks, norm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_decide(const DecideArgs &d, hipStream_t st)
+{
+    if (d.ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_decide, dim3((unsigned)((d.ntasks + 255) / 256)), dim3(256), 0, st,
+                       d);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_cone(const ConeArgs &c, int nmat, int64_t nrows, hipStream_t st)
+{
+    hipError_t r = launch_fill_int(c.rowmin, nrows, 0x7fffffff, st);
+    if (r == hipSuccess) r = launch_fill_int(c.cnt, 2, 0, st);
+    if (r == hipSuccess) r = launch_fill_int((int *)c.nfb, 2 * (int64_t)nmat, 0, st);
+    if (r != hipSuccess) return r;
+    const int total = c.nph + c.nps;
+    if (total > 0)
+        hipLaunchKernelGGL(k_refine_rowmin, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           c);
+    if (nmat > 0)
+        hipLaunchKernelGGL(k_refine_rowsuffix, dim3((unsigned)((nmat + 255) / 256)), dim3(256), 0,
+                           st, c, nmat);
+    hipLaunchKernelGGL(k_refine_compact, dim3(1), dim3(1024), 0, st, c);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ template <typename Fn> hipError_t timed(hipStream_t st, int pk, double flops, Fn
 // One dataflow sweep over a task list (after zeroing the control words).
 template <typename F, int KIND, bool C>
 hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *ctrl, int *flags,
-                    int pk, double flops, int wgs, hipStream_t st)
+                    int pk, double flops, int wgs, hipStream_t st, const int *live,
+                    const int *ntasks_dev)
 {
     if (nt == 0) return hipSuccess;
     // the ticket counter only: the error word (ctrl[1]) is cleared once per run,
@@ -51,18 +52,25 @@ hipError_t run_flow(const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *
     a.ctrl = ctrl;
     a.flags = flags;
     a.spin_limit = flow_spin_limit();
+    a.live = live;
+    a.ntasks_dev = ntasks_dev;
     prof_begin(st);
     r = launch_flow<F, KIND, C>(a, wgs, st);
     prof_end(st, pk, flops);
     return r;
 }
 
+// live: the sweep runs only if *live != 0 (a refinement step); ntasks_dev: the
+// task count, read on the device (a task list built there); both optional.
 template <typename F, int KIND>
 hipError_t run_flow_any(bool cplx, const FlowMat<F> *mats, const int2 *tasks, int64_t nt, int *ctrl,
-                        int *flags, int pk, double flops, int wgs, hipStream_t st)
+                        int *flags, int pk, double flops, int wgs, hipStream_t st,
+                        const int *live = nullptr, const int *ntasks_dev = nullptr)
 {
-    return cplx ? run_flow<F, KIND, true>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st)
-                : run_flow<F, KIND, false>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st);
+    return cplx ? run_flow<F, KIND, true>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st, live,
+                                          ntasks_dev)
+                : run_flow<F, KIND, false>(mats, tasks, nt, ctrl, flags, pk, flops, wgs, st, live,
+                                           ntasks_dev);
 }
 
 template <typename F>
@@ -107,15 +115,21 @@ FlowMat<F> syl_mat(const F *T, int64_t ldt, F *V, int64_t ldv, const F *Rh, int6
     return m;
 }
 
+// The refinement's summary, read back once at the end: live[0 .. kMaxRefineSteps]
+// (live[k - 1]: step k ran), the recomputation's task counts (two), and the
+// blocks recomputed per matrix.
+constexpr int kSumInts = kMaxRefineSteps + 1 + 2;
+size_t sum_bytes(int nm) { return al(kSumInts * sizeof(int)) + (size_t)nm * sizeof(int64_t); }
+
 // Byte layout of a run.  The tables and task lists are built in pinned host
 // memory at the same offsets they take in device memory (one copy uploads
 // them); the rest of each buffer is its own.  Sizes are upper bounds valid for
 // any diagonal: a matrix has at most nb^2 blocks in either form.
 struct Lay {
     size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, rtiles, shared;   // shared part
-    size_t ctrl, flags, ftasks, norms0, norms1, maxes, f32, dev;
-    size_t h_norm0, h_norm1, h_maxes, h_err, h_ftasks, host;
-    int64_t nflags_max, ntasks_max, ndiag_max;
+    size_t ctrl, flags, ftasks, norms0, norms1, maxes, rinit, okf, hop, rowmin, sum, f32, dev;
+    size_t h_err, h_sum, h_maxes, host;
+    int64_t nflags_max, ntasks_max, ndiag_max, nrows;
     std::vector<int64_t> off32;  // per matrix, in floats, of its three FP32 n x n arrays
                                  // (complex: interleaved pairs, twice the floats)
 };
@@ -135,6 +149,7 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     }
     L.nflags_max = L.ntasks_max = std::max<int64_t>(sq, 1);
     L.ndiag_max = std::max<int64_t>(nbsum, 1);
+    L.nrows = nbsum + nm;  // block rows, one more per matrix
     size_t o = 0;
     L.fm64 = o; o += al(nm * sizeof(FlowMat<double>));
     L.fm32 = o; o += al(mixed ? nm * sizeof(FlowMat<float>) : 0);
@@ -152,24 +167,28 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     L.norms0 = d; d += al(mixed ? L.nflags_max * sizeof(double) : 0);
     L.norms1 = d; d += al(mixed ? L.nflags_max * sizeof(double) : 0);
     L.maxes = d; d += al(mixed ? 3 * nm * sizeof(unsigned long long) : 0);
+    L.rinit = d; d += al(mixed ? L.nflags_max * sizeof(double) : 0);
+    L.okf = d; d += al(mixed ? (size_t)L.nflags_max : 0);
+    L.hop = d; d += al(mixed ? (size_t)L.nflags_max : 0);
+    L.rowmin = d; d += al(mixed ? L.nrows * sizeof(int) : 0);
+    L.sum = d; d += al(mixed ? sum_bytes(nm) : 0);
     L.f32 = d; d += al((size_t)f32 * sizeof(float));
     L.dev = d;
     size_t h = o;
-    L.h_norm0 = h; h += al(mixed ? L.nflags_max * sizeof(double) : 0);
-    L.h_norm1 = h; h += al(mixed ? L.nflags_max * sizeof(double) : 0);
-    L.h_maxes = h; h += al(mixed ? 3 * nm * sizeof(unsigned long long) : 0);
     L.h_err = h; h += al(64);
-    L.h_ftasks = h; h += al(mixed ? L.ntasks_max * sizeof(int2) : 0);
+    L.h_sum = h; h += al(mixed ? sum_bytes(nm) : 0);
+    L.h_maxes = h; h += al(mixed ? 3 * nm * sizeof(unsigned long long) : 0);
     L.host = h;
     return L;
 }
 
-double ulp_floor(int kblocks, double umax, double tmax)
+// Refinement steps at most: 0 = the default of two; a negative value takes none
+// (every block then counts as not converged: the FP64 recomputation, or
+// SIGNTRI_ENOCONV).
+int refine_step_count(const signtri_options *opts)
 {
-    // rounding level of an FP64 residual block: kblocks * TB products per entry
-    // of size up to umax * max(umax, tmax), TB x TB entries
-    const double eps = std::ldexp(1.0, -52);
-    return eps * (double)kblocks * TB * TB * umax * std::max(umax, tmax);
+    if (!opts || opts->max_refine_steps == 0) return 2;
+    return std::min(std::max(0, opts->max_refine_steps), kMaxRefineSteps);
 }
 
 // Algorithmic flops (Section 3 counting, real) of one matrix's launches.
@@ -233,7 +252,7 @@ int sweep_error(void *dev_ws, const int64_t *ns, int nmat, bool mixed, bool cplx
 
 int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_options *opts,
              void *dev_ws, void *host_ws, bool prof, const int8_t *const *host_signs,
-             hipStream_t st)
+             hipStream_t st, bool finish)
 {
     const int nm = (int)items.size();
     if (nm == 0) return SIGNTRI_OK;
@@ -264,7 +283,7 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     // ---- per-matrix geometry and tables
     std::vector<int64_t> f0(nm, 0);
     std::vector<int> nbr(nm, 0), nbc(nm, 0);
-    int64_t nflags = 0, ndiag = 0;
+    int64_t nflags = 0, ndiag = 0, fr0 = 0;
     SweepFlops fl;
     for (int m = 0; m < nm; ++m) {
         const RealItem &it = items[m];
@@ -312,8 +331,10 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
             r.nbc = nbc[m];
             r.two_s = 2.0 * it.s;
             r.f0 = f0[m];
+            r.fr0 = fr0;
             r.maxes = maxes + 3 * m;
         }
+        fr0 += nbr[m] + 1;
         if (prof && host_signs) {
             const SweepFlops g = item_flops(host_signs[m], it);
             fl.diag += g.diag;
@@ -381,10 +402,14 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     HIPCHK(timed(st, PK_AUX, 0.0, [&] {
         hipError_t r = launch_fill_int(ctrl, 16, 0, st);
         if (r == hipSuccess) r = launch_prepare_b(dpm, nm, nmax, cplx, st);
+        // the refinement's summary and maxima start at zero (also when nothing is refined)
+        if (r == hipSuccess && refine) r = launch_fill_int((int *)(D + L.sum), (int64_t)(sum_bytes(nm) / 4), 0, st);
+        if (r == hipSuccess && refine) r = launch_fill_int((int *)maxes, 6 * nm, 0, st);
         return r;
     }));
     HIPCHK(timed(st, PK_DIAG, fl.diag, [&] { return launch_diag_b(dpm, ddt, (int)ndiag, cplx, st); }));
-    if (nph + nps == 0) return SIGNTRI_OK;
+    if (nph + nps == 0)
+        return refine && finish ? refine_finish(items, opts, dev_ws, host_ws, st) : SIGNTRI_OK;
 
     if (!mixed) {
         HIPCHK(clear_flags(0));
@@ -407,130 +432,141 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     if (!refine) return SIGNTRI_OK;
 
     double *norms[2] = {(double *)(D + L.norms0), (double *)(D + L.norms1)};
-    auto resid = [&](double *norm2) -> hipError_t {
+    auto resid = [&](const RefArgs &rg, double *norm2) -> hipError_t {
         return timed(st, PK_RESID, fl.resid, [&] {
-            hipError_t r = cplx ? launch_resid(ra, false, cplx, dtk, (int)nph, norm2, st)
-                                : launch_resid64(ra, drt, (int)nrt, norm2, st);
-            if (r == hipSuccess) r = launch_resid(ra, true, cplx, dtk_ps, (int)nps, norm2, st);
+            hipError_t r = cplx ? launch_resid(rg, false, cplx, dtk, (int)nph, norm2, st)
+                                : launch_resid64(rg, drt, (int)nrt, norm2, st);
+            if (r == hipSuccess) r = launch_resid(rg, true, cplx, dtk_ps, (int)nps, norm2, st);
             return r;
         });
     };
-    HIPCHK(resid(norms[0]));
 
-    // 0 = the default of two steps; a negative value takes none (every block then
-    // counts as not converged: the FP64 recomputation, or SIGNTRI_ENOCONV)
-    const int max_steps = !opts || opts->max_refine_steps == 0 ? 2 : std::max(0, opts->max_refine_steps);
+    // ---- refinement steps, every decision taken on the device: nothing below waits
+    // for the host, so the batched form captures the whole of it in its graph.
+    // live[k - 1] != 0: step k runs (live[0] = 1; step k sets live[k] when some
+    // block is neither converged nor stalled); the kernels of a step that is not
+    // needed return at once.
+    const int max_steps = refine_step_count(opts);
     const double stall = (opts && opts->stall_ratio > 0) ? opts->stall_ratio : 0.5;
     const double conv = 1e-5;  // residual reduction that counts as converged
     const int64_t force = opts ? opts->force_stall : 0;
-    double *h0 = (double *)(H + L.h_norm0), *h1 = (double *)(H + L.h_norm1);
-    unsigned long long *hm = (unsigned long long *)(H + L.h_maxes);
-    int *herr = (int *)(H + L.h_err);
-    int2 *hft = (int2 *)(H + L.h_ftasks);
-
-    // per block: residual norm before the first step, converged, hopeless (stalled)
-    std::vector<double> rinit((size_t)nflags, 0.0);
-    std::vector<char> ok((size_t)nflags, 0), hopeless((size_t)nflags, 0);
-    std::vector<double> crel(nm, 0.0);
-    int steps = 0, cur = 0;
+    double *rinit = (double *)(D + L.rinit);
+    int8_t *okf = (int8_t *)(D + L.okf), *hop = (int8_t *)(D + L.hop);
+    int *sum = (int *)(D + L.sum);
+    int *live = sum, *cnt = sum + kMaxRefineSteps + 1;
+    int64_t *nfb = (int64_t *)((char *)sum + al(kSumInts * sizeof(int)));
+    HIPCHK(timed(st, PK_AUX, 0.0, [&] {
+        hipError_t r = launch_fill_int(live, kMaxRefineSteps + 1, 0, st);
+        if (r == hipSuccess) r = launch_fill_int(live, 1, 1, st);
+        // converged and stalled flags (bytes), cleared as whole words
+        if (r == hipSuccess) r = launch_fill_int((int *)okf, (int64_t)((L.rowmin - L.okf) / 4), 0, st);
+        return r;
+    }));
+    HIPCHK(resid(ra, norms[0]));
+    int cur = 0;
     for (int step = 1; step <= max_steps; ++step) {
+        RefArgs rs = ra;
+        rs.live = live + step - 1;
         // correction E (FP32): the residual in E32 on entry, E on exit
         HIPCHK(clear_flags(0));
-        HIPCHK((run_flow_any<float, FLOW_CORR>(cplx, dfc, dtk, nph, ctrl, flags, PK_CORR, fl.corr, wgs, st)));
-        HIPCHK((run_flow_any<float, FLOW_SYL>(cplx, dfc, dtk_ps, nps, ctrl, flags, PK_CORR, fl.syl, wgs, st)));
-        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_add_correction(ra, nmax, cplx, st); }));
-        HIPCHK(resid(norms[cur ^ 1]));
-        steps = step;
-        // convergence decision on the host
-        HIPCHK(hipMemcpyAsync(h0, norms[cur], nflags * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h1, norms[cur ^ 1], nflags * sizeof(double), hipMemcpyDeviceToHost,
-                              st));
-        HIPCHK(hipMemcpyAsync(hm, maxes, 3 * nm * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(herr, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (herr[1]) return SIGNTRI_EHIP;
-        bool pending = false;
-        for (int m = 0; m < nm; ++m) {
-            if (nbr[m] == 0) continue;
-            double tmax, umax, emax;
-            std::memcpy(&tmax, &hm[3 * m], 8);
-            std::memcpy(&umax, &hm[3 * m + 1], 8);
-            std::memcpy(&emax, &hm[3 * m + 2], 8);
-            crel[m] = umax > 0 ? emax / umax : emax;
-            const bool syl = items[m].path == SIGNTRI_PATH_PS;
-            for (int64_t I = 0; I < nbr[m]; ++I)
-                for (int64_t J = syl ? 0 : I + 1; J < nbc[m]; ++J) {
-                    const int64_t lf = I * nbc[m] + J, f = f0[m] + lf;
-                    const double aprev = std::sqrt(h0[f]), a = std::sqrt(h1[f]);
-                    if (step == 1) rinit[f] = aprev;
-                    // K blocks in each entry's residual products
-                    const int kb = syl ? (int)((nbr[m] - I) + (J + 1)) : (int)(J - I + 1);
-                    const bool forced = force == -1 || (nm == 1 && force > 0 && force - 1 == lf);
-                    const bool good = !forced && a <= std::max(ulp_floor(kb, umax, tmax),
-                                                               conv * rinit[f]);
-                    ok[f] = good;
-                    if (!good && (forced || a > stall * aprev)) hopeless[f] = 1;
-                    if (!good && !hopeless[f]) pending = true;
-                }
-        }
+        HIPCHK((run_flow_any<float, FLOW_CORR>(cplx, dfc, dtk, nph, ctrl, flags, PK_CORR, fl.corr, wgs,
+                                               st, rs.live)));
+        HIPCHK((run_flow_any<float, FLOW_SYL>(cplx, dfc, dtk_ps, nps, ctrl, flags, PK_CORR, fl.syl, wgs,
+                                              st, rs.live)));
+        HIPCHK(timed(st, PK_CONVERT, 0.0, [&] { return launch_add_correction(rs, nmax, cplx, st); }));
+        HIPCHK(resid(rs, norms[cur ^ 1]));
+        DecideArgs da;
+        da.mats = drm;
+        da.tasks = dtk;
+        da.ntasks = (int)(nph + nps);
+        da.prev = norms[cur];
+        da.cur = norms[cur ^ 1];
+        da.rinit = rinit;
+        da.ok = okf;
+        da.hopeless = hop;
+        da.live_in = live + step - 1;
+        da.live_out = live + step;
+        da.step = step;
+        da.nmat = nm;
+        da.stall = stall;
+        da.conv = conv;
+        da.force = force;
+        HIPCHK(timed(st, PK_AUX, 0.0, [&] { return launch_refine_decide(da, st); }));
         cur ^= 1;
-        if (!pending) break;
     }
 
     // ---- FP64 recomputation of the blocks that did not converge and of every
     // block whose products read them.  In both forms block (I, J) is read by the
     // blocks (I', J') with I' <= I and J' >= J (Parlett-Higham: U_IK U_KJ with
-    // K = I or J; Sylvester: A_I'K X_KJ with K = I, X_IK B_KJ' with K = J), so
-    // the cone is grown from below and from the left.
-    std::vector<char> mk((size_t)nflags, 0);
-    std::vector<int64_t> nfb(nm, 0);
-    for (int m = 0; m < nm; ++m) {
-        const bool syl = items[m].path == SIGNTRI_PATH_PS;
-        for (int64_t I = nbr[m] - 1; I >= 0; --I)
-            for (int64_t J = syl ? 0 : I + 1; J < nbc[m]; ++J) {
-                const int64_t f = f0[m] + I * nbc[m] + J;
-                char v = !ok[f];
-                if (I + 1 < nbr[m] && (syl || I + 1 < J)) v |= mk[f + nbc[m]];
-                if (J - 1 >= (syl ? 0 : I + 1)) v |= mk[f - 1];
-                mk[f] = v;
-                nfb[m] += v;
-            }
-    }
-    int64_t fph = 0, fps = 0;
-    for (int Dd = 1; Dd < nbmax; ++Dd)
-        for (int m : order)
-            if (items[m].path == SIGNTRI_PATH_PH)
-                for (int I = 0; I + Dd < nbr[m]; ++I)
-                    if (mk[f0[m] + (int64_t)I * nbc[m] + I + Dd])
-                        hft[fph++] = make_int2(m, (I << 16) | (I + Dd));
-    for (int d = 0; d < 2 * nbmax; ++d)
-        for (int m : order)
-            if (items[m].path == SIGNTRI_PATH_PS)
-                for (int I = nbr[m] - 1; I >= 0; --I) {
-                    const int J = d - (nbr[m] - 1 - I);
-                    if (J >= 0 && J < nbc[m] && mk[f0[m] + (int64_t)I * nbc[m] + J])
-                        hft[fph + fps++] = make_int2(m, (I << 16) | J);
-                }
-    for (int m = 0; m < nm; ++m)
-        if (items[m].info) {
-            items[m].info->refine_steps = nbr[m] ? steps : 0;
-            items[m].info->correction_rel = crel[m];
-            items[m].info->fallback_tiles = nfb[m];
-        }
-    if (fph + fps == 0) return SIGNTRI_OK;
-    if (opts && opts->no_fallback) return SIGNTRI_ENOCONV;
+    // K = I or J; Sylvester: A_I'K X_KJ with K = I, X_IK B_KJ' with K = J), so a
+    // block is recomputed iff some block (I', J') with I' >= I and J' <= J did not
+    // converge.  The task lists are built on the device, in dependency order.
     int2 *dft = (int2 *)(D + L.ftasks);
-    HIPCHK(hipMemcpyAsync(dft, hft, (fph + fps) * sizeof(int2), hipMemcpyHostToDevice, st));
-    HIPCHK(clear_flags(1));
-    HIPCHK(timed(st, PK_AUX, 0.0,
-                 [&] { return launch_clear_task_flags(dft, fph + fps, df64, flags, st); }));
-    HIPCHK((run_flow_any<double, FLOW_MAIN>(cplx, df64, dft, fph, ctrl, flags, PK_FLOW, 0.0, wgs, st)));
-    HIPCHK((run_flow_any<double, FLOW_SYL>(cplx, df64, dft + fph, fps, ctrl, flags, PK_SYL, 0.0, wgs, st)));
-    HIPCHK(hipMemcpyAsync(herr, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (herr[1]) return SIGNTRI_EHIP;
+    ConeArgs ca;
+    ca.mats = drm;
+    ca.tasks = dtk;
+    ca.nph = (int)nph;
+    ca.nps = (int)nps;
+    ca.ok = okf;
+    ca.rowmin = (int *)(D + L.rowmin);
+    ca.out_ph = dft;
+    ca.out_ps = dft + nph;
+    ca.cnt = cnt;
+    ca.nfb = nfb;
+    HIPCHK(timed(st, PK_AUX, 0.0, [&] { return launch_refine_cone(ca, nm, L.nrows, st); }));
+    if (!(opts && opts->no_fallback)) {
+        HIPCHK(clear_flags(1));
+        HIPCHK(timed(st, PK_AUX, 0.0, [&] {
+            hipError_t r = launch_clear_task_flags(dft, nph, cnt, df64, flags, st);
+            if (r == hipSuccess) r = launch_clear_task_flags(dft + nph, nps, cnt + 1, df64, flags, st);
+            return r;
+        }));
+        HIPCHK((run_flow_any<double, FLOW_MAIN>(cplx, df64, dft, nph, ctrl, flags, PK_FLOW, 0.0, wgs, st,
+                                                nullptr, cnt)));
+        HIPCHK((run_flow_any<double, FLOW_SYL>(cplx, df64, dft + nph, nps, ctrl, flags, PK_SYL, 0.0,
+                                               wgs, st, nullptr, cnt + 1)));
+    }
 #undef HIPCHK
+    return finish ? refine_finish(items, opts, dev_ws, host_ws, st) : SIGNTRI_OK;
+}
+
+int refine_finish(std::vector<RealItem> &items, const signtri_options *opts, void *dev_ws,
+                  void *host_ws, hipStream_t st)
+{
+    const int nm = (int)items.size();
+    if (nm == 0) return SIGNTRI_OK;
+    const bool cplx = items[0].cplx;
+    std::vector<int64_t> ns(nm);
+    for (int m = 0; m < nm; ++m) ns[m] = items[m].n;
+    const Lay L = make_lay(ns.data(), nm, true, cplx);
+    char *D = (char *)dev_ws, *H = (char *)host_ws;
+    int *herr = (int *)(H + L.h_err);
+    int *hsum = (int *)(H + L.h_sum);
+    unsigned long long *hm = (unsigned long long *)(H + L.h_maxes);
+    if (hipMemcpyAsync(herr, D + L.ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hsum, D + L.sum, sum_bytes(nm), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hm, D + L.maxes, 3 * nm * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    // steps run: live[k - 1] != 0 for k = 1 .. steps
+    const int max_steps = refine_step_count(opts);
+    int steps = 0;
+    while (steps < max_steps && hsum[steps] != 0) ++steps;
+    const int *hcnt = hsum + kMaxRefineSteps + 1;
+    const int64_t *hnfb = (const int64_t *)((char *)hsum + al(kSumInts * sizeof(int)));
+    for (int m = 0; m < nm; ++m) {
+        if (!items[m].info) continue;
+        double umax, emax;
+        std::memcpy(&umax, &hm[3 * m + 1], 8);
+        std::memcpy(&emax, &hm[3 * m + 2], 8);
+        const bool triv = items[m].path == SIGNTRI_PATH_TRIVIAL;
+        items[m].info->refine_steps = triv ? 0 : steps;
+        items[m].info->correction_rel = triv ? 0.0 : (umax > 0 ? emax / umax : emax);
+        items[m].info->fallback_tiles = hnfb[m];
+    }
+    if (herr[1]) return SIGNTRI_EHIP;
+    if (opts && opts->no_fallback && hcnt[0] + hcnt[1] > 0) return SIGNTRI_ENOCONV;
     return SIGNTRI_OK;
 }
 

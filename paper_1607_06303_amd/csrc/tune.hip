@@ -43,8 +43,12 @@ bool valid_entry(const signtri_tune_entry &e)
 {
     const bool key = (e.dtype == SIGNTRI_R64 || e.dtype == SIGNTRI_C128) &&
                      e.mode >= SIGNTRI_FP64 && e.mode <= SIGNTRI_FP32 &&
-                     (e.path == SIGNTRI_PATH_PH || e.path == SIGNTRI_PATH_PS) && e.log2n >= 0 &&
-                     e.log2n <= 62;
+                     (e.path == SIGNTRI_PATH_PH || e.path == SIGNTRI_PATH_PS ||
+                      e.path == SIGNTRI_TUNE_BATCHED) &&
+                     e.log2n >= 0 && e.log2n <= 62;
+    // the batched form runs the dataflow sweep on 32 x 32 blocks only
+    if (e.path == SIGNTRI_TUNE_BATCHED && (e.sweep != SIGNTRI_SWEEP_DATAFLOW || e.tile != 32))
+        return false;
     const bool choice = (e.sweep == SIGNTRI_SWEEP_DATAFLOW || e.sweep == SIGNTRI_SWEEP_SUPERDIAG) &&
                         (e.tile == 32 || e.tile == 64) && e.wgs_per_cu >= 0 && e.wgs_per_cu <= 64;
     return key && choice && std::isfinite(e.ms) && e.ms >= 0.0;
@@ -247,6 +251,77 @@ int signtri_autotune(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n
             best->sweep = c.sweep;
             best->tile = c.tile;
             best->wgs_per_cu = ci.wgs_per_cu;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SIGNTRI_OK) return rc;
+    best->ms = best_ms;
+    TuneTable &t = table();
+    std::lock_guard<std::mutex> g(t.mu);
+    load_env_once(t);
+    put(t, *best);
+    return SIGNTRI_OK;
+}
+
+int signtri_autotune_batched(const void *const *T, const int64_t *ldt, void *const *U,
+                             const int64_t *ldu, const int64_t *n, int64_t batch,
+                             signtri_dtype dtype, signtri_mode mode, void *stream, int32_t reps,
+                             signtri_tune_entry *best)
+{
+    if (reps < 1 || reps > 1000) return -12;
+    if (!best) return -13;
+    std::memset(best, 0, sizeof(*best));
+    // argument checks and the first (untimed) run: the default grid
+    int rc = signtri_batched(T, ldt, U, ldu, n, batch, dtype, SIGNTRI_COL_MAJOR, mode, nullptr, 0,
+                             stream, nullptr, nullptr);
+    if (rc != SIGNTRI_OK) return rc;
+    int64_t nmax = 0;
+    for (int64_t b = 0; b < batch; ++b) nmax = std::max(nmax, n[b]);
+    best->dtype = dtype;
+    best->mode = mode;
+    best->path = SIGNTRI_TUNE_BATCHED;
+    best->log2n = size_class(nmax);
+    best->sweep = SIGNTRI_SWEEP_DATAFLOW;
+    best->tile = 32;
+    if (nmax == 0) return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? SIGNTRI_OK
+                                                                                : SIGNTRI_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, dtype == SIGNTRI_C128);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SIGNTRI_EHIP;
+    }
+    double best_ms = -1.0;
+    for (int w = 1; w <= mx && rc == SIGNTRI_OK; ++w) {
+        signtri_options o;
+        std::memset(&o, 0, sizeof(o));
+        o.sweep = SIGNTRI_SWEEP_DATAFLOW;
+        o.tile = 32;
+        o.wgs_per_cu = w;
+        // one untimed call (it also captures this grid's graph)
+        rc = signtri_batched(T, ldt, U, ldu, n, batch, dtype, SIGNTRI_COL_MAJOR, mode, nullptr, 0,
+                             stream, &o, nullptr);
+        if (rc != SIGNTRI_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            rc = SIGNTRI_EHIP;
+            break;
+        }
+        for (int r = 0; r < reps && rc == SIGNTRI_OK; ++r)
+            rc = signtri_batched(T, ldt, U, ldu, n, batch, dtype, SIGNTRI_COL_MAJOR, mode, nullptr,
+                                 0, stream, &o, nullptr);
+        if (rc != SIGNTRI_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = SIGNTRI_EHIP;
+            break;
+        }
+        const double per = (double)ms / reps;
+        if (best_ms < 0.0 || per < best_ms) {
+            best_ms = per;
+            best->wgs_per_cu = w;
         }
     }
     (void)hipEventDestroy(e0);

@@ -11,7 +11,9 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsigntri.so")
+# SIGNTRI_LIB: another build of the same library (the host-sanitizer build of
+# the CPU checks); by default the in-tree one
+LIB_PATH = os.environ.get("SIGNTRI_LIB") or os.path.join(HERE, "libsigntri.so")
 
 R64, C128 = 0, 1
 COL_MAJOR, ROW_MAJOR = 0, 1
@@ -25,7 +27,8 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_batched_workspace_size", "signtri_strerror", "sign_tri",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
            "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
-           "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear", "signtri_noalloc")
+           "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear", "signtri_noalloc",
+           "signtri_autotune_batched")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
             "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10, "proj": 11,
             "proj_out": 12}
@@ -123,6 +126,11 @@ def lib() -> ctypes.CDLL:
             L.signtri_autotune.argtypes = [p, i64, p, i64, i64, i32, i32, i32, p, i32,
                                            ctypes.POINTER(TuneEntry)]
             L.signtri_autotune.restype = i32
+            L.signtri_autotune_batched.argtypes = [ctypes.POINTER(p), ctypes.POINTER(i64),
+                                                   ctypes.POINTER(p), ctypes.POINTER(i64),
+                                                   ctypes.POINTER(i64), i64, i32, i32, p, i32,
+                                                   ctypes.POINTER(TuneEntry)]
+            L.signtri_autotune_batched.restype = i32
             L.signtri_tune_lookup.argtypes = [i32, i32, i32, i64, ctypes.POINTER(TuneEntry)]
             L.signtri_tune_lookup.restype = i32
             L.signtri_tune_save.argtypes = [ctypes.c_char_p]
@@ -265,6 +273,43 @@ def sign_tri_noalloc(T, out=None, stream=None):
     return U, info.as_dict()
 
 
+def _batch_args(Ts, outs):
+    """Host arrays of pointers, leading dimensions and orders for a batch."""
+    layouts = [_layout(t) if t.shape[0] else (COL_MAJOR, 1) for t in Ts]
+    if any(l is None for l in layouts):
+        raise ValueError("every T must be column- or row-major strided")
+    nonempty = [l for t, l in zip(Ts, layouts) if t.shape[0] > 1]
+    layout = nonempty[0][0] if nonempty else COL_MAJOR
+    Us = outs if outs is not None else [empty_like_layout(t) for t in Ts]
+    B = len(Ts)
+    P = ctypes.c_void_p * B
+    I = ctypes.c_int64 * B
+    tp = P(*[t.data_ptr() if t.shape[0] else None for t in Ts])
+    up = P(*[u.data_ptr() if u.shape[0] else None for u in Us])
+    ldt = I(*[l[1] for l in layouts])
+    ldu = I(*[_layout(u)[1] if u.shape[0] else 1 for u in Us])
+    ns = I(*[t.shape[0] for t in Ts])
+    return layout, Us, tp, ldt, up, ldu, ns
+
+
+def autotune_batched(Ts, mode: str = "fp64", reps: int = 3, outs=None, stream=None) -> dict:
+    """Time every dataflow grid on this batch (column-major) and record the fastest
+    for the size class of its largest order (used by later batched calls that
+    leave wgs_per_cu at 0)."""
+    if not Ts:
+        raise ValueError("empty batch")
+    layout, Us, tp, ldt, up, ldu, ns = _batch_args(Ts, outs)
+    if layout != COL_MAJOR:
+        raise ValueError("autotune_batched takes column-major matrices")
+    best = TuneEntry()
+    rc = lib().signtri_autotune_batched(tp, ldt, up, ldu, ns, len(Ts), _dtype_code(Ts[0]),
+                                        MODES[mode], _stream_handle(Ts[0], stream), int(reps),
+                                        ctypes.byref(best))
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc))
+    return best.as_dict()
+
+
 def sign_tri_batched(Ts, mode: str = "fp64", outs=None, workspace=None, stream=None,
                      options: dict | None = None):
     """Batched form: list of square upper-triangular tensors (same dtype, device
@@ -340,7 +385,7 @@ def autotune(T, mode: str = "fp64", algo: str = "auto", reps: int = 3, out=None,
 
 def tune_lookup(complex_: bool, mode: str, path: str, n: int) -> dict | None:
     e = TuneEntry()
-    code = {"ph": 1, "ps": 2}[path]
+    code = {"ph": 1, "ps": 2, "batched": 8}[path]
     if lib().signtri_tune_lookup(C128 if complex_ else R64, MODES[mode], code, int(n),
                                  ctypes.byref(e)):
         return e.as_dict()

@@ -182,20 +182,32 @@ def test_planner_choice_rule():
     assert info["path_name"] == "ph" and info["model_pick_name"] == "ph"
     # few negatives at random positions: the model (with reordering) prefers PS
     # (the paper's Fig. 3 regime); the library reaches that result through the
-    # minority class's projector (real T, at most 64 minority entries), and runs
-    # PH for complex T
+    # minority class's projector (at most 512 minority entries for real T, 64
+    # for complex T)
     few = np.ones(n, dtype=np.int8)
     few[rng.choice(n, 3, replace=False)] = -1
     info = signtri.plan_host(few)
     assert info["model_pick_name"] == "ps" and info["path_name"] == "proj"
     assert signtri.plan_host(-few)["path_name"] == "proj"       # positive minority
-    assert signtri.plan_host(few, complex_=True)["path_name"] == "ph"
-    # projector estimate 3 n^2 m against the PH estimate; at most 64 minority entries
+    assert signtri.plan_host(few, complex_=True)["path_name"] == "ph"  # n = 200: PH cheaper
+    # projector estimate 3 n^2 m against the PH estimate (complex: 32 times that,
+    # the complex multiply-adds' weight 4 and the complex kernels' rate, an eighth)
     big = np.ones(4096, dtype=np.int8)
-    big[rng.choice(4096, 64, replace=False)] = -1
-    assert signtri.plan_host(big)["path_name"] == "proj"
+    big[rng.choice(4096, 16, replace=False)] = -1
+    info = signtri.plan_host(big, complex_=True)
+    assert 32 * 3.0 * 4096 ** 2 * 16 < info["w_ph"] and info["path_name"] == "proj"
+    big[rng.choice(np.flatnonzero(big > 0), 48, replace=False)] = -1
+    assert signtri.plan_host(big)["path_name"] == "proj"        # 64 minority entries
+    info = signtri.plan_host(big, complex_=True)
+    assert 32 * 3.0 * 4096 ** 2 * 64 > info["w_ph"] and info["path_name"] == "ph"
     big[rng.choice(np.flatnonzero(big > 0), 1, replace=False)] = -1
-    assert signtri.plan_host(big)["path_name"] == "ph"          # 65 minority entries
+    assert signtri.plan_host(big)["path_name"] == "proj"        # 65 minority entries
+    huge = np.ones(8192, dtype=np.int8)
+    huge[rng.choice(8192, 512, replace=False)] = -1
+    info = signtri.plan_host(huge)
+    assert 3.0 * 8192 ** 2 * 513 < info["w_ph"] and info["path_name"] == "proj"
+    huge[rng.choice(np.flatnonzero(huge > 0), 1, replace=False)] = -1
+    assert signtri.plan_host(huge)["path_name"] == "ph"         # 513 minority entries
     mid = np.ones(n, dtype=np.int8)
     mid[rng.choice(n, 40, replace=False)] = -1                  # 3 n^2 m above W_PH
     info = signtri.plan_host(mid)

@@ -162,3 +162,51 @@ def test_batched_complex(dev, mode, tol):
     assert {i["path_name"] for i in infos} == {"trivial", "ph", "ps"}
     if mode == "mixed":
         assert all(i["fallback_tiles"] == 0 for i in infos)
+
+
+def test_batched_mixed_graph_replays(dev):
+    """The refined mode runs as one captured graph (its convergence tests and the
+    FP64 recomputation decided on the device): three replays with other work
+    between them, each checked, the infos of each replay filled; then T changed in
+    place; then a forced stall of every block (a different graph), whose FP64
+    recomputation covers every block."""
+    import torch
+
+    from paper_1607_06303_amd import signtri
+
+    Ts = make_batch(8500, [70, 130, 33, 200, 300])
+    Tg = [to_dev_colmajor(T, dev) for T in Ts]
+    Us = [signtri.empty_like_layout(t) for t in Tg]
+    for rep in range(3):
+        for U in Us:
+            U.fill_(float("nan"))
+        _, infos = signtri.sign_tri_batched(Tg, outs=Us, mode="mixed")
+        torch.cuda.synchronize()
+        check_all(Ts, [U.cpu().numpy() for U in Us], TOL_FP64)
+        for T, inf in zip(Ts, infos):
+            if inf["path_name"] != "trivial" and T.shape[0] > 32:
+                assert inf["refine_steps"] >= 1 and inf["fallback_tiles"] == 0, (rep, inf)
+        # eager work on the same stream between replays
+        Uo, _, _, _ = run_batch(make_batch(8600 + rep, [64, 90]), dev, mode="fp64")
+    rng = np.random.default_rng(8700)
+    Ts2 = []
+    for T, g in zip(Ts, Tg):
+        T2 = T.copy()
+        T2[np.triu_indices(T.shape[0], 1)] = rng.standard_normal(T.shape[0] * (T.shape[0] - 1) // 2) / 10
+        g.copy_(torch.from_numpy(T2).to(dev))
+        Ts2.append(T2)
+    signtri.sign_tri_batched(Tg, outs=Us, mode="mixed")
+    torch.cuda.synchronize()
+    check_all(Ts2, [U.cpu().numpy() for U in Us], TOL_FP64)
+    for rep in range(2):
+        _, infos = signtri.sign_tri_batched(Tg, outs=Us, mode="mixed", options={"force_stall": -1})
+        torch.cuda.synchronize()
+        check_all(Ts2, [U.cpu().numpy() for U in Us], TOL_FP64)
+        for T, inf in zip(Ts2, infos):
+            if inf["path_name"] == "ph":
+                nb = (T.shape[0] + 31) // 32
+                assert inf["fallback_tiles"] == nb * (nb - 1) // 2, inf
+    with pytest.raises(signtri.SignTriError) as ei:
+        signtri.sign_tri_batched(Tg, outs=Us, mode="mixed",
+                                 options={"force_stall": -1, "no_fallback": 1})
+    assert ei.value.code == 4

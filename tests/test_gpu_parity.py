@@ -85,7 +85,8 @@ def test_skewed_few_negatives(dev, n, cplx):
     T = wl.make_T(n, rng, complex_=cplx, signs=s)
     _, info, _ = check(T, dev, algo="ph")
     assert info["path_name"] == "ph"
-    # AUTO: the projector form for real T (a small minority class), PH for complex
+    # AUTO: the projector form for real T (a small minority class); for complex T the
+    # complex form's estimate, weighted by its rate, stays above W_PH at these sizes
     _, info, _ = check(T, dev)
     assert info["path_name"] == ("ph" if cplx else "proj")
 

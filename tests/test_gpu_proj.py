@@ -5,9 +5,9 @@ The oracle sides: the element-by-element Parlett-Higham substitution (C), and
 on some cases also the Section 3 route itself (Schur reordering by adjacent
 swaps, the sign-split Sylvester equation, the transformation back).  Bar:
 1e-11 relative Frobenius error.  Sizes span one to several 64-row blocks with
-ragged tops; minority counts span 1..64 including 32/33 and 63/64; the
-minority class is negative or positive; its rows sit at the ends, in runs and
-adjacent pairs.
+ragged tops; minority counts span 1..512 (real T) including 32/33, 63/64/65,
+128 and 300; the minority class is negative or positive; its rows sit at the
+ends, in runs and adjacent pairs, and in whole blocks of minority rows.
 """
 import numpy as np
 import pytest
@@ -125,7 +125,9 @@ def test_proj_unsupported(dev):
     from paper_1607_06303_amd import signtri
 
     with pytest.raises(signtri.SignTriError):
-        run_gpu(skewed(300, 65, 8), dev, algo="proj")
+        run_gpu(skewed(1100, 513, 8), dev, algo="proj")
+    with pytest.raises(signtri.SignTriError):
+        run_gpu(cskewed(300, 65, 8), dev, algo="proj")
     # all one sign: the trivial path, whatever the algorithm asked for
     U, info = run_gpu(wl.make_T(40, wl.rng_for(1, salt=4), signs=np.ones(40)), dev, algo="proj")
     assert info["path_name"] == "trivial" and np.array_equal(U, np.eye(40))
@@ -279,3 +281,64 @@ def test_proj_clustered_minority(dev, n, where, minority):
     assert info["path_name"] == "proj"
     assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64
     assert not np.any(np.tril(U, -1))
+
+
+# More than 64 minority columns (real T): the coupling with the earlier columns
+# whose rows lie in the blocks below is applied as FP64 MFMA products (the block
+# just below between blocks, the rest ahead of time), and the owners take the
+# columns in chunks of 64.
+WIDE = [
+    (300, 65, None),
+    (520, 128, None),
+    (700, 300, None),
+    (1100, 512, None),
+    # whole blocks of minority rows: near windows of 64 columns, and windows of the
+    # block below wider than what the helpers fetch ahead
+    (600, 200, list(range(150, 350))),
+    (700, 130, list(range(0, 40)) + list(range(200, 250)) + list(range(660, 700))),
+    # one column per group on every other block, then a dense run at the bottom
+    (900, 100, [9 * k for k in range(60)] + list(range(860, 900))),
+]
+
+
+@pytest.mark.parametrize("n,m,where", WIDE,
+                         ids=["65", "128", "300", "512", "run200", "three-runs", "sparse-dense"])
+@pytest.mark.parametrize("minority", [-1, 1])
+def test_proj_wide_minority(dev, n, m, where, minority):
+    import oracle
+
+    T = skewed(n, m, 13 * n + m, minority, where)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj", info
+    assert rel_fro(U, oracle.sign_tri(T)) <= TOL_FP64, (n, m)
+    assert not np.any(np.tril(U, -1))
+
+
+@pytest.mark.parametrize("n,m", [(330, 65), (400, 128)])
+def test_proj_wide_matches_reordering_route(dev, n, m):
+    from oracle import reorder
+
+    T = skewed(n, m, 17 + n)
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj"
+    ref, rinfo = reorder.sign_tri_reordered(T)
+    assert rinfo["k"] > 0
+    assert rel_fro(U, ref) <= TOL_FP64
+
+
+def test_proj_wide_auto_and_repeat(dev):
+    """AUTO takes the projector form past 64 minority entries while 3 n^2 m stays
+    below W_PH; the same call twice gives the same bits."""
+    import oracle
+
+    from paper_1607_06303_amd import signtri
+
+    T = skewed(2048, 100, 23)
+    plan = signtri.plan_host(np.where(np.diag(T) > 0, 1, -1).astype(np.int8))
+    assert 3.0 * 2048 ** 2 * 100 < plan["w_ph"]
+    U1, info = run_gpu(T, dev)
+    assert info["path_name"] == "proj"
+    U2, _ = run_gpu(T, dev)
+    assert np.array_equal(U1, U2)
+    assert rel_fro(U1, oracle.sign_tri(T)) <= TOL_FP64
+

@@ -144,3 +144,27 @@ def test_tuning_table_file_round_trip(dev, clean_table, tmp_path):
                                                              best["wgs_per_cu"])
     _, info, _ = check(T, dev)
     assert (info["sweep"], info["tile"]) == (best["sweep"], best["tile"])
+
+
+def test_autotune_batched_records_and_is_used(dev, clean_table):
+    """The batched tuner times each grid on the batch, records the fastest for the
+    size class of the largest order, and later batched calls (grid left at 0)
+    run it; every matrix stays sign(T)."""
+    import torch
+
+    import oracle
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(9700)
+    Ts = [wl.make_T(n, rng) for n in (30, 100, 200)]
+    Tg = [to_dev_colmajor(T, dev) for T in Ts]
+    for mode, tol in (("fp64", TOL_FP64), ("mixed", TOL_FP64)):
+        best = signtri.autotune_batched(Tg, mode=mode, reps=1)
+        assert best["path"] == 8 and best["log2n"] == 8 and best["wgs_per_cu"] >= 1
+        assert signtri.tune_lookup(False, mode, "batched", 256)["wgs_per_cu"] == best["wgs_per_cu"]
+        Us, infos = signtri.sign_tri_batched(Tg, mode=mode)
+        torch.cuda.synchronize()
+        for T, U, inf in zip(Ts, Us, infos):
+            assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= tol
+            assert inf["wgs_per_cu"] == best["wgs_per_cu"]
+

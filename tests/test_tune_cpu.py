@@ -59,6 +59,35 @@ def test_save_load_round_trip_and_replace(lib, tmp_path):
     assert lib.tune_lookup(True, "fp64", "ph", 4000)["ms"] == pytest.approx(40.0)
 
 
+def test_batched_key(lib, tmp_path):
+    """Batched entries (path 8): the dataflow sweep on 32 x 32 blocks only, keyed by
+    the size class of the batch's largest order."""
+    p = tmp_path / "b.txt"
+    write(p, ["0 1 8 9 1 32 2 5.0"])
+    lib.tune_load(str(p))
+    e = lib.tune_lookup(False, "mixed", "batched", 400)
+    assert e["wgs_per_cu"] == 2 and e["path"] == 8
+    assert lib.tune_lookup(False, "mixed", "ph", 400) is None
+    for bad in ("0 1 8 9 2 32 2 5.0", "0 1 8 9 1 64 2 5.0"):  # superdiag, 64 blocks
+        write(p, [bad])
+        with pytest.raises(OSError):
+            lib.tune_load(str(p))
+
+
+def test_autotune_batched_argument_checks(lib):
+    import ctypes
+
+    L = lib.lib()
+    e = lib.TuneEntry()
+    # reps and the result pointer are checked before any call
+    assert L.signtri_autotune_batched(None, None, None, None, None, 1, 0, 0, None, 0,
+                                      ctypes.byref(e)) == -12
+    assert L.signtri_autotune_batched(None, None, None, None, None, 1, 0, 0, None, 1, None) == -13
+    # then the batched call's own checks (-1: T is NULL)
+    assert L.signtri_autotune_batched(None, None, None, None, None, 1, 0, 0, None, 1,
+                                      ctypes.byref(e)) == -1
+
+
 @pytest.mark.parametrize("bad", [
     "0 0 1 12 1 32 2",            # too few fields
     "0 0 1 12 1 32 2 1.0 extra",  # too many
