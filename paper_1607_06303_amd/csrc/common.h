@@ -443,9 +443,9 @@ hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t s
 hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
 hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks, int ntasks,
                         double *norm2, hipStream_t st);
-// Real substitution form on 64 x 64 tiles (matrix, a << 16 | b), a <= b.
-hipError_t launch_resid64(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
-                          hipStream_t st);
+// Real substitution form on 128 x 128 tiles (matrix, a << 16 | b), a <= b.
+hipError_t launch_resid128(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
+                           hipStream_t st);
 
 // The refinement's decisions on the device, so that the whole refinement is
 // queued without a wait on the host (and can be captured in a graph).

@@ -281,27 +281,35 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     if (tid == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = red[0] + red[1] + red[2] + red[3];
 }
 
-// FP64 residual of the real substitution form on 64 x 64 tiles: tile (a, b)
-// covers blocks 2a, 2a+1 x 2b, 2b+1 and each wave owns one of them (2 x 2 MFMA
-// pieces); a tile reads half the operand bytes per flop of four 32 x 32
-// blocks.  K runs over the blocks 2a .. 2b+1 with every operand masked to its
-// upper triangle (row <= column), which zeroes the terms outside a block's own
-// range I .. J and T's strict lower triangle.  Blocks outside the strict upper
-// block triangle are skipped.  Output as k_resid: R in FP32 into E32, squared
+// FP64 residual of the real substitution form on 128 x 128 tiles: tile (a, b)
+// covers blocks 4a .. 4a+3 x 4b .. 4b+3.  Eight waves; wave w owns the 32 x 64
+// region at rows 32 (w >> 1), columns 64 (w & 1): two 32 x 32 blocks, 2 x 4
+// MFMA pieces, each piece's products chosen by the signs of its rows and
+// columns (U U for equal signs, U T - T U for opposite ones).  K runs over
+// [128 a, 128 b + 128) in 16-deep stages with every operand masked to its upper
+// triangle (row <= column), which zeroes the terms outside a block's own range
+// I .. J and T's strict lower triangle; a piece skips the stages in which its
+// operands are all zero.  Two LDS buffers: the next stage's operands are loaded
+// into registers while the current one is multiplied, then stored into the
+// other buffer, one barrier per stage.  Blocks outside the strict upper block
+// triangle are skipped.  Output as k_resid: R in FP32 into E32, squared
 // Frobenius norm per block.  Tiles in reverse task order (longest first).
-constexpr int RAP = 2 * TB + 16;    // LDS: A as [k][m], 64 rows + pad
-constexpr int RBS = 8 * TB + 4;     // LDS: B as [k/4][n][k%4], 64 columns
+constexpr int RT = 4 * TB;          // tile rows and columns
+constexpr int RK = 16;              // K per stage
+constexpr int RAP = RT + 16;        // LDS: A as [k][row], padded
+constexpr int RBS = 4 * RT + 4;     // LDS: B as [k / 4][column][k % 4], padded
+constexpr int NT8 = 512;
 
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
-void k_resid64(RefArgs a, const int2 *__restrict__ tiles, int ntiles, double *__restrict__ norm2)
+__global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restrict__ tiles,
+                                                  int ntiles, double *__restrict__ norm2)
 {
-    __shared__ double sAU[TB * RAP], sAT[TB * RAP];
-    __shared__ double sBU[(TB / 4) * RBS], sBT[(TB / 4) * RBS];
-    __shared__ int8_t rs[2 * TB], cs[2 * TB];
+    __shared__ double sAU[2][RK * RAP], sAT[2][RK * RAP];
+    __shared__ double sBU[2][(RK / 4) * RBS], sBT[2][(RK / 4) * RBS];
+    __shared__ int8_t rs[RT], cs[RT];
 
     if (gated_off(a)) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int pr = wave >> 1, pc = wave & 1;
+    const int wr = wave >> 1, wc = wave & 1;
     const int mg = lane >> 4, mt = lane & 15;
     const int2 tk = tiles[ntiles - 1 - (int)blockIdx.x];
     const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
@@ -310,98 +318,107 @@ void k_resid64(RefArgs a, const int2 *__restrict__ tiles, int ntiles, double *__
     const int nb = uniform(d.nbc);
     const double *T = d.T, *U = d.U;
     const int64_t ldt = d.ldt, ldu = d.ldu;
-    const int64_t r0 = (int64_t)ta * 2 * TB, c0 = (int64_t)tb * 2 * TB;
-    const int I = 2 * ta + pr, J = 2 * tb + pc;
-    const bool mine = I < J && J < nb;  // this wave's block is an off-diagonal block
-    if (tid < 2 * TB) {
+    const int64_t r0 = (int64_t)ta * RT, c0 = (int64_t)tb * RT;
+    const int I = 4 * ta + wr, J0 = 4 * tb + 2 * wc;
+    const bool mine[2] = {I < J0 && J0 < nb, I < J0 + 1 && J0 + 1 < nb};
+    if (tid < RT) {
         rs[tid] = r0 + tid < n ? d.sgn[r0 + tid] : 0;
         cs[tid] = c0 + tid < n ? d.sgn[c0 + tid] : 0;
     }
     __syncthreads();
-    bool nY[2][2], nX[2][2];
+    bool nY[2][4], nX[2][4];
     bool wx = false;
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < 4; ++cb) {
             bool rp = false, rn = false, cp = false, cn = false;
             for (int u = 0; u < 16; ++u) {
-                const int vr = rs[32 * pr + 16 * ra + u], vc = cs[32 * pc + 16 * cb + u];
+                const int vr = rs[32 * wr + 16 * ra + u], vc = cs[64 * wc + 16 * cb + u];
                 rp |= vr > 0;
                 rn |= vr < 0;
                 cp |= vc > 0;
                 cn |= vc < 0;
             }
-            nY[ra][cb] = mine && ((rp && cp) || (rn && cn));
-            nX[ra][cb] = mine && ((rp && cn) || (rn && cp));
+            const bool m = mine[cb >> 1];
+            nY[ra][cb] = m && ((rp && cp) || (rn && cn));
+            nX[ra][cb] = m && ((rp && cn) || (rn && cp));
             wx |= nX[ra][cb];
         }
     const bool any_x = __syncthreads_or(wx);
 
-    dx4 accY[2][2], accX[2][2];
+    dx4 accY[2][4], accX[2][4];
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < 4; ++cb)
             for (int r = 0; r < 4; ++r) accY[ra][cb][r] = accX[ra][cb][r] = 0.0;
 
-    // staging of one 32-deep K step: A 64 x 32 (U, T), B 32 x 64 (U, T);
-    // every thread 4 consecutive rows of 2 columns of each
-    double gaU[2][4], gaT[2][4], gbU[2][4], gbT[2][4];
-    const int alc = tid >> 4, alr = (tid & 15) * 4;  // A: columns alc, alc + 16; rows alr ..
-    const int blc = tid >> 3, blr = (tid & 7) * 4;   // B: columns blc, blc + 32; rows blr ..
-    auto load = [&](int K) {
-        const int64_t k0 = (int64_t)K * TB;
+    // staging of one stage: A 128 x 16 (U, T), B 16 x 128 (U, T); thread t loads
+    // A rows t & 127 at k = 4 (t >> 7) .. + 3 and B column t >> 2 at k = 4 (t & 3) .. + 3
+    const int arow = tid & (RT - 1), akh = tid >> 7;
+    const int bcol = tid >> 2, bkq = tid & 3;
+    double gaU[4], gaT[4], gbU[4], gbT[4];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t ra = r0 + alr + e, ca = k0 + alc + 16 * h;
-                const int64_t rb = k0 + blr + e, cb = c0 + blc + 32 * h;
-                const bool okA = ra < n && ca < n && ra <= ca;
-                const bool okB = rb < n && cb < n && rb <= cb;
-                gaU[h][e] = okA ? U[ra + ca * ldu] : 0.0;
-                gaT[h][e] = (okA && any_x) ? T[ra + ca * ldt] : 0.0;
-                gbU[h][e] = okB ? U[rb + cb * ldu] : 0.0;
-                gbT[h][e] = (okB && any_x) ? T[rb + cb * ldt] : 0.0;
-            }
+        for (int e = 0; e < 4; ++e) {
+            const int64_t ra = r0 + arow, ka = k0 + 4 * akh + e;
+            const int64_t kb = k0 + 4 * bkq + e, cb = c0 + bcol;
+            const bool okA = ra < n && ka < n && ra <= ka;
+            const bool okB = kb < n && cb < n && kb <= cb;
+            gaU[e] = okA ? U[ra + ka * ldu] : 0.0;
+            gaT[e] = (okA && any_x) ? T[ra + ka * ldt] : 0.0;
+            gbU[e] = okB ? U[kb + cb * ldu] : 0.0;
+            gbT[e] = (okB && any_x) ? T[kb + cb * ldt] : 0.0;
+        }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ka = alc + 16 * h;
-                sAU[ka * RAP + alr + e] = gaU[h][e];
-                sAT[ka * RAP + alr + e] = -gaT[h][e];
-                const int nbb = blc + 32 * h;
-                sBU[(blr >> 2) * RBS + nbb * 4 + e] = gbU[h][e];
-                sBT[(blr >> 2) * RBS + nbb * 4 + e] = gbT[h][e];
-            }
+        for (int e = 0; e < 4; ++e) {
+            sAU[buf][(4 * akh + e) * RAP + arow] = gaU[e];
+            sAT[buf][(4 * akh + e) * RAP + arow] = -gaT[e];
+            sBU[buf][bkq * RBS + bcol * 4 + e] = gbU[e];
+            sBT[buf][bkq * RBS + bcol * 4 + e] = gbT[e];
+        }
     };
-    const int K0 = 2 * ta, K1 = uniform(min(2 * tb + 1, nb - 1));
-    load(K0);
-    store();
+    const int64_t kbeg = r0, kend = min(n, c0 + RT);
+    const int nst = uniform((int)((kend - kbeg + RK - 1) / RK));
+    load(kbeg);
+    store(0);
     __syncthreads();
-    for (int K = K0; K <= K1; ++K) {
-        const bool more = K < K1;
-        if (more) load(K + 1);
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        const int64_t k0 = kbeg + (int64_t)s * RK;
+        const bool more = s + 1 < nst;
+        if (more) load(k0 + RK);
+        // pieces with a nonzero term in this stage: A[i][k] needs i <= k, B[k][j] k <= j
+        bool live[2][4];
 #pragma unroll
-        for (int k4 = 0; k4 < TB / 4; ++k4) {
-            double aU[2], aT[2], bU[2], bT[2];
+        for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ao = (k4 * 4 + mg) * RAP + 32 * pr + 16 * h + mt;
-                const int bo = k4 * RBS + (32 * pc + 16 * h + mt) * 4 + mg;
-                aU[h] = sAU[ao];
-                aT[h] = sAT[ao];
-                bU[h] = sBU[bo];
-                bT[h] = sBT[bo];
+            for (int cb = 0; cb < 4; ++cb)
+                live[ra][cb] = r0 + 32 * wr + 16 * ra <= k0 + RK - 1 &&
+                               c0 + 64 * wc + 16 * cb + 15 >= k0;
+#pragma unroll
+        for (int k4 = 0; k4 < RK / 4; ++k4) {
+            double aU[2], aT[2], bU[4], bT[4];
+#pragma unroll
+            for (int ra = 0; ra < 2; ++ra) {
+                const int ao = (4 * k4 + mg) * RAP + 32 * wr + 16 * ra + mt;
+                aU[ra] = sAU[buf][ao];
+                aT[ra] = sAT[buf][ao];
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int bo = k4 * RBS + (64 * wc + 16 * cb + mt) * 4 + mg;
+                bU[cb] = sBU[buf][bo];
+                bT[cb] = sBT[buf][bo];
             }
 #pragma unroll
             for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (!live[ra][cb]) continue;
                     if (nY[ra][cb]) accY[ra][cb] = mfma_f64(aU[ra], bU[cb], accY[ra][cb]);
                     if (nX[ra][cb]) {
                         accX[ra][cb] = mfma_f64(aU[ra], bT[cb], accX[ra][cb]);
@@ -409,30 +426,31 @@ void k_resid64(RefArgs a, const int2 *__restrict__ tiles, int ntiles, double *__
                     }
                 }
         }
+        if (more) store(buf ^ 1);
         __syncthreads();
-        if (more) {
-            store();
-            __syncthreads();
-        }
     }
-    if (mine) {
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+        if (!mine[hb]) continue;  // uniform
         double ss = 0.0;
 #pragma unroll
         for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+            for (int cbb = 0; cbb < 2; ++cbb) {
+                const int cb = 2 * hb + cbb;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int i = 32 * pr + 16 * ra + mfma64_row(lane, r);
-                    const int j = 32 * pc + 16 * cb + mt;
+                    const int i = 32 * wr + 16 * ra + mfma64_row(lane, r);
+                    const int j = 64 * wc + 16 * cb + mt;
                     if (c0 + j < n) {
                         const double v = rs[i] == cs[j] ? accY[ra][cb][r] : accX[ra][cb][r];
                         d.E32[(r0 + i) + (c0 + j) * d.ld32] = (float)v;
                         ss += v * v;
                     }
                 }
+            }
         for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
-        if (lane == 0) norm2[d.f0 + (int64_t)I * d.nbc + J] = ss;
+        if (lane == 0) norm2[d.f0 + (int64_t)I * d.nbc + J0 + hb] = ss;
     }
 }
 
@@ -698,11 +716,11 @@ hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_resid64(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
-                          hipStream_t st)
+hipError_t launch_resid128(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
+                           hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid64, dim3(ntiles), dim3(NT), 0, st, a, tiles, ntiles, norm2);
+    hipLaunchKernelGGL(k_resid128, dim3(ntiles), dim3(NT8), 0, st, a, tiles, ntiles, norm2);
     return hipGetLastError();
 }
 

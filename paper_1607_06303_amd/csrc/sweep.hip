@@ -137,12 +137,12 @@ struct Lay {
 Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
 {
     Lay L;
-    int64_t sq = 0, sq2 = 0, nbsum = 0, f32 = 0;
+    int64_t sq = 0, sq4 = 0, nbsum = 0, f32 = 0;
     L.off32.resize(nm);
     for (int m = 0; m < nm; ++m) {
-        const int64_t nb = nblocks(ns[m]), nb2 = (nb + 1) / 2;
+        const int64_t nb = nblocks(ns[m]), nb4 = (nb + 3) / 4;
         sq += nb * nb;
-        sq2 += nb2 * nb2;
+        sq4 += nb4 * nb4;
         nbsum += nb;
         L.off32[m] = f32;
         if (mixed) f32 += (cplx ? 6 : 3) * ns[m] * ns[m];
@@ -158,7 +158,7 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     L.pm = o; o += al(nm * sizeof(PrepMat));
     L.dtasks = o; o += al(L.ndiag_max * sizeof(int2));
     L.tasks = o; o += al(L.ntasks_max * sizeof(int2));
-    L.rtiles = o; o += al((mixed ? std::max<int64_t>(sq2, 1) : 0) * sizeof(int2));
+    L.rtiles = o; o += al((mixed ? std::max<int64_t>(sq4, 1) : 0) * sizeof(int2));
     L.shared = o;
     size_t d = o;
     L.ctrl = d; d += al(64 * sizeof(int));
@@ -363,19 +363,20 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
                     const int J = d - (nbr[m] - 1 - I);
                     if (J >= 0 && J < nbc[m]) htk[nph + nps++] = make_int2(m, (I << 16) | J);
                 }
-    // 64 x 64 tiles of the real substitution form's residual, shortest first
-    // (the kernel takes them in reverse)
+    // 128 x 128 tiles (four blocks a side) of the real substitution form's
+    // residual, shortest first (the kernel takes them in reverse); a diagonal
+    // tile only if it holds a block above the diagonal
     int64_t nrt = 0;
     if (mixed && !cplx) {
         int2 *hrt = (int2 *)(H + L.rtiles);
-        const int nb2max = (int)((nblocks(nmax) + 1) / 2);
-        for (int dd = 0; dd < nb2max; ++dd)
+        const int nb4max = (int)((nblocks(nmax) + 3) / 4);
+        for (int dd = 0; dd < nb4max; ++dd)
             for (auto it = order.rbegin(); it != order.rend(); ++it) {
                 const int m = *it;
                 if (items[m].path != SIGNTRI_PATH_PH) continue;
-                const int nb2 = (nbc[m] + 1) / 2;
-                for (int ta = 0; ta + dd < nb2; ++ta)
-                    if (dd > 0 || 2 * ta + 1 < nbc[m]) hrt[nrt++] = make_int2(m, (ta << 16) | (ta + dd));
+                const int nb4 = (nbc[m] + 3) / 4;
+                for (int ta = 0; ta + dd < nb4; ++ta)
+                    if (dd > 0 || 4 * ta + 1 < nbc[m]) hrt[nrt++] = make_int2(m, (ta << 16) | (ta + dd));
             }
     }
     const int2 *drt = (const int2 *)(D + L.rtiles);
@@ -435,7 +436,7 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
     auto resid = [&](const RefArgs &rg, double *norm2) -> hipError_t {
         return timed(st, PK_RESID, fl.resid, [&] {
             hipError_t r = cplx ? launch_resid(rg, false, cplx, dtk, (int)nph, norm2, st)
-                                : launch_resid64(rg, drt, (int)nrt, norm2, st);
+                                : launch_resid128(rg, drt, (int)nrt, norm2, st);
             if (r == hipSuccess) r = launch_resid(rg, true, cplx, dtk_ps, (int)nps, norm2, st);
             return r;
         });
