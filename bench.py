@@ -42,6 +42,8 @@ def parse():
                          "(0: the whole matrix)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="block size 32 or 64 (0: library default)")
+    ap.add_argument("--algo", default="auto", choices=["auto", "ph", "ps", "proj"],
+                    help="the path (profiling runs of a path AUTO does not take; default auto)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the side measurement of the 2000-matrix batched workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -133,10 +135,10 @@ def calibrate_copy(torch, mib):
     log("copy calibration: 3 launches, each %d MiB read + %d MiB written" % (mib, mib))
 
 
-def time_mode(signtri, torch, Tg, mode, steps, warmup, opts):
+def time_mode(signtri, torch, Tg, mode, steps, warmup, opts, algo="auto"):
     U = signtri.empty_like_layout(Tg)
     for _ in range(warmup):
-        signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
+        signtri.sign_tri(Tg, mode=mode, out=U, options=opts, algo=algo)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -145,7 +147,7 @@ def time_mode(signtri, torch, Tg, mode, steps, warmup, opts):
     start.record()
     info = None
     for _ in range(steps):
-        _, info = signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
+        _, info = signtri.sign_tri(Tg, mode=mode, out=U, options=opts, algo=algo)
     stop.record()
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
@@ -214,11 +216,12 @@ def main():
         try:
             if not args.no_tune and not opts:
                 # part of setup, outside the timed region: pick the sweep variant and grid
-                tuned[mode] = signtri.autotune(Tg, mode=mode, reps=2)
+                tuned[mode] = signtri.autotune(Tg, mode=mode, algo=args.algo, reps=2)
                 log("mode %s: tuned -> %s tile %d, %d workgroups/CU (%.3f ms)"
                     % (mode, tuned[mode]["sweep_name"], tuned[mode]["tile"],
                        tuned[mode]["wgs_per_cu"], tuned[mode]["ms"]))
-            U, info, ms = time_mode(signtri, torch, Tg, mode, args.steps, args.warmup, opts)
+            U, info, ms = time_mode(signtri, torch, Tg, mode, args.steps, args.warmup, opts,
+                                    args.algo)
         except signtri.SignTriError as e:
             log("mode %s unavailable: %s" % (mode, e))
             continue
@@ -231,7 +234,7 @@ def main():
                 % (mode, err, inv1, inv2))
         # kernel timers over one more step (HIP events on the library's stream)
         signtri.profile_enable(True)
-        signtri.sign_tri(Tg, mode=mode, out=U, options=opts)
+        signtri.sign_tri(Tg, mode=mode, out=U, options=opts, algo=args.algo)
         torch.cuda.synchronize()
         r["kernels"] = signtri.profile_read()
         signtri.profile_enable(False)

@@ -855,31 +855,28 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             P.dpart = group_sum<NQ>((cp0 + cp1) - (v0 + v1));
             return P;
         };
-        Prep P = prep(nr - 1, false);
+        // One row: solve row r with its prepared state Pc while row r - 1's is
+        // prepared into Pnx.  The loop below takes two rows per iteration with the
+        // two states in fixed roles, so that no state is copied from row to row.
         double zprev = 0.0;  // z of the row below, in every lane of its column
-        for (int s = 0; s < nr; ++s) {
-            const int r = nr - 1 - s;
+        auto step = [&](int r, const Prep &Pc, Prep &Pnx) {
             // the next row's sum, from what is known before this row is solved
-            Prep Pn;
-            if (r > 0) Pn = prep(r - 1, false);
+            if (r > 0) Pnx = prep(r - 1, false);
             const bool act = r <= rhi;
             // the active columns: a contiguous range at the end of the group
             const uint64_t am = __builtin_amdgcn_ballot_w64(act);
             double z = 0.0;
             bool redo = false;
             if (am != 0) {
-                // chain steps: the active columns but the last, as a bit mask
-                const int klo = __builtin_ctzll(am) / NQ, khi = (64 - __builtin_clzll(am)) / NQ;
-                const int chain = uniform(((1 << (khi - 1)) - 1) & ~((1 << klo) - 1));
                 // d = coupling - sum, with row r + 1's term
-                const double d = fma(-P.tnext, zprev, P.dpart);
+                const double d = fma(-Pc.tnext, zprev, Pc.dpart);
                 const int typ = __builtin_amdgcn_readlane(rtl, r);
                 if (typ >= 0) {
                     redo = true;
                     // (the active columns only: an inactive one's column of L stays as is)
                     if (act && r == plr) {
                         z = 1.0;
-                        lamll = P.tii;
+                        lamll = Pc.tii;
                     } else if (act) {
                         // minority row b_typ (typ < l): row typ of L
                         if (typ < c0) {
@@ -896,13 +893,15 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                     }
                 } else {
                     // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
-                    // group's active columns in order, with the reciprocal folded into
-                    // the coefficients (one multiply-add per link); lw is zero from the
-                    // diagonal on, so the later terms add nothing to a column solved
-                    z = d * P.rcp;
+                    // group's columns in order, with the reciprocal folded into the
+                    // coefficients (one multiply-add per link).  Every link runs: an
+                    // inactive column's z is zero, and lw is zero from the diagonal on
+                    // and for the coefficients not set yet, so those links add exact
+                    // zeros.
+                    z = act ? d * Pc.rcp : 0.0;
 #pragma unroll
                     for (int kp = 0; kp < GC - 1; ++kp)
-                        if (chain & (1 << kp)) z = fma(readlane_f64(z, kp * NQ), P.lwr[kp], z);
+                        z = fma(readlane_f64(z, kp * NQ), Pc.lwr[kp], z);
                 }
                 if (q == 0 && act) Zc[kw * ZCP + r] = z;
                 if (!act) z = 0.0;
@@ -914,10 +913,16 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             // after a minority row (a uniform test), row r - 1's sum again, with the
             // state L has now and z_r included
-            if (redo && r > 0) Pn = prep(r - 1, true);
-            P = Pn;
+            if (redo && r > 0) Pnx = prep(r - 1, true);
             zprev = z;
+        };
+        Prep P0 = prep(nr - 1, false), P1;
+        int s2 = 0;
+        for (; s2 + 1 < nr; s2 += 2) {
+            step(nr - 1 - s2, P0, P1);
+            step(nr - 2 - s2, P1, P0);
         }
+        if (s2 < nr) step(nr - 1 - s2, P0, P1);
         };
         static_assert(NU == 8, "one instance per chunk count");
         switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
