@@ -796,13 +796,14 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         // barrier.
         const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
         const int rhi = kw < cw ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
-        auto front = [&](auto gtag) {
+        auto front = [&](auto gtag, auto guardtag) {
         constexpr int NCU = decltype(gtag)::value;  // coupling chunks: the near window's
+        constexpr bool GUARD = decltype(guardtag)::value;  // reciprocals checked for range
         // Row r's prepared state: dpart = coupling - sum without row r + 1's term,
         // tnext = t[r][r+1] (that term's coefficient; 0 when already included or
-        // outside the block), t_rr, 1 / (t_rr - L[l, l]) and the chain coefficients.
+        // outside the block), t_rr and 1 / (t_rr - L[l, l]).
         struct Prep {
-            double dpart, tnext, tii, rcp, lwr[GC - 1];
+            double dpart, tnext, tii, rcp;
         };
         auto prep = [&](int r, bool included) {
             Prep P;
@@ -820,26 +821,25 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 if (u < NCU) rv[u] = zrow[NQ * u + q];
             }
             P.tii = trow[r];
-            P.tnext = (!included && r + 1 < nr) ? trow[r + 1] : 0.0;
+            // (read from an address inside the row in every case, then chosen)
+            const double tn = trow[r + 1 < PB ? r + 1 : r];
+            P.tnext = (!included && r + 1 < nr) ? tn : 0.0;
             // (the group's sum of the row, read by all the column's lanes: a broadcast)
             const double ab = Ab[r * ABP + kw];
             // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
             // and one Newton step, which squares it (below 2.3e-15).  The signs of
             // t_ii and L[l, l] differ, so |dx| >= min |t_kk| and |dx| <= 2 max |t_kk|;
-            // only when the diagonal leaves [2^-1020, 2^1019] (a uniform test) can
+            // only when the diagonal leaves [2^-1020, 2^1019] (the GUARD instances) can
             // |dx| leave [2^-1020, 2^1020], where the estimate or its reciprocal would
             // not be normal: then the IEEE division for those entries
             const double dx = P.tii - lamll;
             double rcp = __builtin_amdgcn_rcp(dx);
             rcp = fma(rcp, fma(-dx, rcp, 1.0), rcp);
-            if (__builtin_expect(S.rcp_guard != 0, 0)) {
+            if constexpr (GUARD) {
                 const double adx = fabs(dx);
                 if (adx > 0x1p1020 || adx < 0x1p-1020) rcp = 1.0 / dx;
             }
             P.rcp = rcp;
-            // the chain's coefficients with the reciprocal folded in
-#pragma unroll
-            for (int kp = 0; kp < GC - 1; ++kp) P.lwr[kp] = lw[kp] * rcp;
             double v0 = q == 0 ? ab : 0.0, v1 = 0.0, cp0 = 0.0, cp1 = 0.0;
 #pragma unroll
             for (int u = 0; u < NU; u += 2) {
@@ -860,60 +860,61 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         // two states in fixed roles, so that no state is copied from row to row.
         double zprev = 0.0;  // z of the row below, in every lane of its column
         auto step = [&](int r, const Prep &Pc, Prep &Pnx) {
-            // the next row's sum, from what is known before this row is solved
-            if (r > 0) Pnx = prep(r - 1, false);
+            // The common case, a majority row, in one straight run of code (the next
+            // row's sum, formed from what is known before this row is solved, and
+            // this row's coupling chain, independent of each other), so that the
+            // compiler can interleave the two; a minority row replaces the result
+            // afterwards.  (Row 0 prepares row 0 again: unused.)
+            Pnx = prep(r > 0 ? r - 1 : 0, false);
             const bool act = r <= rhi;
-            // the active columns: a contiguous range at the end of the group
-            const uint64_t am = __builtin_amdgcn_ballot_w64(act);
-            double z = 0.0;
-            bool redo = false;
-            if (am != 0) {
-                // d = coupling - sum, with row r + 1's term
-                const double d = fma(-Pc.tnext, zprev, Pc.dpart);
-                const int typ = __builtin_amdgcn_readlane(rtl, r);
-                if (typ >= 0) {
-                    redo = true;
-                    // (the active columns only: an inactive one's column of L stays as is)
-                    if (act && r == plr) {
-                        z = 1.0;
-                        lamll = Pc.tii;
-                    } else if (act) {
-                        // minority row b_typ (typ < l): row typ of L
-                        if (typ < c0) {
-                            // an earlier column of the near window
-                            const int idx = typ - nw.lo;
+            // d = coupling - sum, with row r + 1's term
+            const double d = fma(-Pc.tnext, zprev, Pc.dpart);
+            // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
+            // group's columns in order, with the reciprocal folded into the
+            // coefficients (one multiply-add per link).  Every link runs: an inactive
+            // column's z is zero, and lw is zero from the diagonal on and for the
+            // coefficients not set yet, so those links add exact zeros.
+            // (the chain's coefficients with the reciprocal folded in, formed off the
+            // chain)
+            double lwr[GC - 1];
 #pragma unroll
-                            for (int u = 0; u < NU; ++u)
-                                if (NQ * u + q == idx) lreg[u] = -d;
-                        } else {
+            for (int kp = 0; kp < GC - 1; ++kp) lwr[kp] = lw[kp] * Pc.rcp;
+            double z = act ? d * Pc.rcp : 0.0;
 #pragma unroll
-                            for (int kp = 0; kp < GC; ++kp)
-                                if (c0 + kp == typ) lw[kp] = -d;
-                        }
+            for (int kp = 0; kp < GC - 1; ++kp) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+            const int typ = __builtin_amdgcn_readlane(rtl, r);
+            const bool minority = typ >= 0;  // (uniform)
+            if (minority) {
+                // At minority row b_typ the row of Z is e_typ: z is 1 in column typ's
+                // own lanes and 0 elsewhere, and the row defines row typ of L (for
+                // the active columns only: an inactive one's column of L stays as is).
+                const bool own = act && r == plr;
+                z = own ? 1.0 : 0.0;
+                if (own) {
+                    lamll = Pc.tii;
+                } else if (act) {
+                    if (typ < c0) {
+                        // an earlier column of the near window
+                        const int idx = typ - nw.lo;
+#pragma unroll
+                        for (int u = 0; u < NU; ++u)
+                            if (NQ * u + q == idx) lreg[u] = -d;
+                    } else {
+#pragma unroll
+                        for (int kp = 0; kp < GC; ++kp)
+                            if (c0 + kp == typ) lw[kp] = -d;
                     }
-                } else {
-                    // z_l = (d_l + sum_{k' < k} z_k' L[k', l]) / (t_ii - L[l, l]) over the
-                    // group's columns in order, with the reciprocal folded into the
-                    // coefficients (one multiply-add per link).  Every link runs: an
-                    // inactive column's z is zero, and lw is zero from the diagonal on
-                    // and for the coefficients not set yet, so those links add exact
-                    // zeros.
-                    z = act ? d * Pc.rcp : 0.0;
-#pragma unroll
-                    for (int kp = 0; kp < GC - 1; ++kp)
-                        z = fma(readlane_f64(z, kp * NQ), Pc.lwr[kp], z);
                 }
-                if (q == 0 && act) Zc[kw * ZCP + r] = z;
-                if (!act) z = 0.0;
             }
+            if (q == 0 && act) Zc[kw * ZCP + r] = z;
             // The column's other lanes read this value from LDS in later steps, with
             // no barrier: the hardware keeps one wave's LDS operations in order, and
             // this fence (wavefront scope: no instruction) keeps the compiler from
             // moving those reads above the store.
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            // after a minority row (a uniform test), row r - 1's sum again, with the
-            // state L has now and z_r included
-            if (redo && r > 0) Pnx = prep(r - 1, true);
+            // after a minority row, row r - 1's sum again, with the state L has now
+            // and z_r included
+            if (minority && r > 0) Pnx = prep(r - 1, true);
             zprev = z;
         };
         Prep P0 = prep(nr - 1, false), P1;
@@ -926,15 +927,42 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         };
         static_assert(NU == 8, "one instance per chunk count");
         switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
-            case 0: front(std::integral_constant<int, 0>{}); break;
-            case 1: front(std::integral_constant<int, 1>{}); break;
-            case 2: front(std::integral_constant<int, 2>{}); break;
-            case 3: front(std::integral_constant<int, 3>{}); break;
-            case 4: front(std::integral_constant<int, 4>{}); break;
-            case 5: front(std::integral_constant<int, 5>{}); break;
-            case 6: front(std::integral_constant<int, 6>{}); break;
-            case 7: front(std::integral_constant<int, 7>{}); break;
-            default: front(std::integral_constant<int, 8>{}); break;
+            case 0:
+                if (S.rcp_guard) front(std::integral_constant<int, 0>{}, std::true_type{});
+                else front(std::integral_constant<int, 0>{}, std::false_type{});
+                break;
+            case 1:
+                if (S.rcp_guard) front(std::integral_constant<int, 1>{}, std::true_type{});
+                else front(std::integral_constant<int, 1>{}, std::false_type{});
+                break;
+            case 2:
+                if (S.rcp_guard) front(std::integral_constant<int, 2>{}, std::true_type{});
+                else front(std::integral_constant<int, 2>{}, std::false_type{});
+                break;
+            case 3:
+                if (S.rcp_guard) front(std::integral_constant<int, 3>{}, std::true_type{});
+                else front(std::integral_constant<int, 3>{}, std::false_type{});
+                break;
+            case 4:
+                if (S.rcp_guard) front(std::integral_constant<int, 4>{}, std::true_type{});
+                else front(std::integral_constant<int, 4>{}, std::false_type{});
+                break;
+            case 5:
+                if (S.rcp_guard) front(std::integral_constant<int, 5>{}, std::true_type{});
+                else front(std::integral_constant<int, 5>{}, std::false_type{});
+                break;
+            case 6:
+                if (S.rcp_guard) front(std::integral_constant<int, 6>{}, std::true_type{});
+                else front(std::integral_constant<int, 6>{}, std::false_type{});
+                break;
+            case 7:
+                if (S.rcp_guard) front(std::integral_constant<int, 7>{}, std::true_type{});
+                else front(std::integral_constant<int, 7>{}, std::false_type{});
+                break;
+            default:
+                if (S.rcp_guard) front(std::integral_constant<int, 8>{}, std::true_type{});
+                else front(std::integral_constant<int, 8>{}, std::false_type{});
+                break;
         }
         store_rows(b);
         // the near window's coefficients, for the products of the blocks above
