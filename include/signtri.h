@@ -201,6 +201,27 @@ size_t signtri_workspace_size(int64_t n, signtri_dtype dtype, signtri_layout lay
                               signtri_mode mode, signtri_algo algo);
 
 /*
+ * A general function of T (Section 2, Algorithm 1): F = phi(T) by Parlett's
+ * substitution, f_ij = [t_ij (f_ii - f_jj) + sum_{i<k<j} (f_ik t_kj - t_ik f_kj)]
+ * / (t_ii - t_jj), the element equation of TF = FT, with the caller's values of
+ * phi on the diagonal.  Computed in FP64 (complex128) by the dataflow sweep of
+ * the substitution, every pair of entries by that equation.
+ *   T, ldt      device input, upper triangle read (conventions above), column-major
+ *   fdiag       device array of n values phi(t_ii) (SIGNTRI_C128: interleaved pairs)
+ *   F, ldf      device output, n x n written (zeros below the diagonal), column-major
+ *   n, dtype, stream, info as for signtri() (info: path SIGNTRI_PATH_PH, tile 32)
+ * The diagonal entries of T must be distinct: a repeated one divides by zero and
+ * leaves non-finite values in F (nothing checks for it); nearby ones amplify
+ * rounding errors as 1 / |t_ii - t_jj| (Section 2).  With info, the call waits
+ * and reports a dependency wait that gave up (SIGNTRI_EHIP).  Returns 0, -p for
+ * argument p (-4 also when F overlaps T or fdiag), SIGNTRI_ENOMEM, SIGNTRI_EHIP.
+ * phi = sign on a diagonal without zero real parts gives sign(T) through
+ * Eq. (1) alone; signtri() computes it with Eq. (2) where signs agree.
+ */
+int signtri_fun(const void *T, int64_t ldt, const void *fdiag, void *F, int64_t ldf, int64_t n,
+                signtri_dtype dtype, void *stream, signtri_info *info);
+
+/*
  * Batched form: U_b = sign(T_b) for b = 0 .. batch-1, matrices of uneven
  * order, in one graph-captured persistent launch.
  *   T, U        HOST arrays of `batch` DEVICE pointers (host arrays, so that

@@ -57,6 +57,10 @@ def _load():
                 f = getattr(lib, name)
                 f.argtypes = [i64, p, i64, p, i64, i32]
                 f.restype = i64
+            for name in ("oracle_parlett_d", "oracle_parlett_z"):
+                f = getattr(lib, name)
+                f.argtypes = [i64, p, i64, p, p, i64]
+                f.restype = i64
             for name in ("oracle_trsyl_d", "oracle_trsyl_z"):
                 f = getattr(lib, name)
                 f.argtypes = [i64, i64, p, i64, p, i64, p, i64, p, i64]
@@ -126,3 +130,27 @@ def trsyl(A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise ZeroDivisionError("singular Sylvester pivot at linear index %d" % (rc - 1))
     return X
+
+
+def parlett(T: np.ndarray, fdiag) -> np.ndarray:
+    """F = phi(T) by Parlett's recurrence (Algorithm 1) from phi's values on the
+    diagonal, fdiag[i] = phi(t_ii); T upper triangular with distinct diagonal
+    entries (only its upper triangle is read)."""
+    T = np.asarray(T)
+    if T.ndim != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    n = T.shape[0]
+    fd = np.asarray(fdiag)
+    if fd.shape != (n,):
+        raise ValueError("fdiag must have one value per diagonal entry")
+    cplx = np.iscomplexobj(T) or np.iscomplexobj(fd)
+    dt = np.complex128 if cplx else np.float64
+    Tf = _colmajor(T, dt)
+    fdc = np.ascontiguousarray(fd, dtype=dt)
+    F = np.zeros((n, n), dtype=dt, order="F")
+    lib = _load()
+    f = lib.oracle_parlett_z if cplx else lib.oracle_parlett_d
+    rc = f(n, Tf.ctypes.data, max(n, 1), fdc.ctypes.data, F.ctypes.data, max(n, 1))
+    if rc != 0:
+        raise ZeroDivisionError("repeated diagonal entries at linear index %d" % (rc - 1))
+    return F

@@ -36,6 +36,14 @@
  * exactly this equation with C = +-2 T_12 (Section 2, the paragraph on the
  * trivial diagonal blocks of the sign function).
  *
+ * The Parlett oracle computes F = phi(T) for a general function phi given
+ * its values on the diagonal, f_ii = phi(t_ii) (Algorithm 1): for every i < j,
+ * by column j ascending and row i descending,
+ *   f_ij = [t_ij (f_ii - f_jj) + sum_{k=i+1}^{j-1} (f_ik t_kj - t_ik f_kj)]
+ *          / (t_ii - t_jj),
+ * the element equation of TF = FT (Section 2); it needs distinct diagonal
+ * entries.
+ *
  * Storage: column-major with a leading dimension; complex numbers are
  * interleaved (re, im) pairs of doubles.  Only the upper triangle of the
  * inputs is read.
@@ -321,6 +329,55 @@ int64_t oracle_trsyl_z(int64_t m, int64_t p, const double *A, int64_t lda,
             cplx x = cdiv(sum, den);
             X[2 * (i + j * ldx)] = x.re;
             X[2 * (i + j * ldx) + 1] = x.im;
+        }
+#undef CZ
+    return 0;
+}
+
+/*
+ * F = phi(T) by Algorithm 1 (real): fd[i] = phi(t_ii) given; F n x n, zero
+ * below the diagonal.  Returns 0, or the 1-based linear index (i + j*n + 1) of
+ * the first pair with t_ii == t_jj (the recurrence is undefined there).
+ */
+int64_t oracle_parlett_d(int64_t n, const double *T, int64_t ldt, const double *fd,
+                         double *F, int64_t ldf)
+{
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) F[i + j * ldf] = i == j ? fd[i] : 0.0;
+    for (int64_t j = 1; j < n; ++j)
+        for (int64_t i = j - 1; i >= 0; --i) {
+            double sum = T[i + j * ldt] * (fd[i] - fd[j]);
+            for (int64_t k = i + 1; k < j; ++k)
+                sum = sum + (F[i + k * ldf] * T[k + j * ldt] - T[i + k * ldt] * F[k + j * ldf]);
+            const double den = T[i + i * ldt] - T[j + j * ldt];
+            if (den == 0.0) return i + j * n + 1;
+            F[i + j * ldf] = sum / den;
+        }
+    return 0;
+}
+
+/* Complex version of oracle_parlett_d (interleaved storage, fd interleaved too). */
+int64_t oracle_parlett_z(int64_t n, const double *T, int64_t ldt, const double *fd,
+                         double *F, int64_t ldf)
+{
+#define CZ(M, ld, r, c) (*(const cplx *)((M) + 2 * ((r) + (c) * (ld))))
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            F[2 * (i + j * ldf)] = i == j ? fd[2 * i] : 0.0;
+            F[2 * (i + j * ldf) + 1] = i == j ? fd[2 * i + 1] : 0.0;
+        }
+    for (int64_t j = 1; j < n; ++j)
+        for (int64_t i = j - 1; i >= 0; --i) {
+            const cplx fi = {fd[2 * i], fd[2 * i + 1]}, fj = {fd[2 * j], fd[2 * j + 1]};
+            cplx sum = cmul(CZ(T, ldt, i, j), csub(fi, fj));
+            for (int64_t k = i + 1; k < j; ++k)
+                sum = cadd(sum, csub(cmul(CZ(F, ldf, i, k), CZ(T, ldt, k, j)),
+                                     cmul(CZ(T, ldt, i, k), CZ(F, ldf, k, j))));
+            const cplx den = csub(CZ(T, ldt, i, i), CZ(T, ldt, j, j));
+            if (den.re == 0.0 && den.im == 0.0) return i + j * n + 1;
+            const cplx x = cdiv(sum, den);
+            F[2 * (i + j * ldf)] = x.re;
+            F[2 * (i + j * ldf) + 1] = x.im;
         }
 #undef CZ
     return 0;

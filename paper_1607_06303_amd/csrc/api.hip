@@ -725,6 +725,74 @@ int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, sig
     return SIGNTRI_OK;
 }
 
+// F = phi(T) for a general function phi given on the diagonal (Algorithm 1):
+// the FP64 dataflow sweep of the substitution with every pair of entries by the
+// element Parlett equation, diagonal blocks by the same equation element by
+// element.
+int signtri_fun_run(const void *T, int64_t ldt, const void *fdiag, void *F, int64_t ldf,
+                    int64_t n, signtri_dtype dtype, void *stream, signtri_info *info)
+{
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (n > 0 && !T) return -1;
+    if (ldt < std::max<int64_t>(1, n)) return -2;
+    if (n > 0 && !fdiag) return -3;
+    if (n > 0 && !F) return -4;
+    if (ldf < std::max<int64_t>(1, n)) return -5;
+    if (n < 0) return -6;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -7;
+    const bool cplx = dtype == SIGNTRI_C128;
+    const size_t es = cplx ? 16 : 8;
+    if (n > 0 && ranges_overlap(T, extent_bytes(n, ldt, es), F, extent_bytes(n, ldf, es))) return -4;
+    if (n > 0 && ranges_overlap(fdiag, (size_t)n * es, F, extent_bytes(n, ldf, es))) return -4;
+    if (n == 0) return SIGNTRI_OK;
+    const Layout L = layout_for(n, dtype, SIGNTRI_COL_MAJOR, SIGNTRI_FP64, 32, true);
+    void *ws = nullptr, *hostbuf = nullptr;
+    size_t run_host = 0;
+    run_sizes(&n, 1, false, cplx, nullptr, &run_host);
+    if (int rc = owned_workspace(L.total, &ws)) return rc;
+    if (int rc = owned_host(align_up(sizeof(ScanResult)) + align_up((size_t)n) + run_host, &hostbuf))
+        return rc;
+    char *w = (char *)ws;
+    void *hflow = (char *)hostbuf + align_up(sizeof(ScanResult)) + align_up((size_t)n);
+    hipStream_t st = (hipStream_t)stream;
+    int8_t *sgn = (int8_t *)(w + L.sgn);
+    double *dg = (double *)(w + L.dg);
+    // the diagonal (the divisors t_ii - t_jj); its signs are not used
+    if (launch_scan(T, ldt, n, cplx, sgn, dg, (ScanResult *)(w + L.scan), st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    signtri_options eo;
+    std::memset(&eo, 0, sizeof(eo));
+    eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
+    eo.tile = 32;
+    eo.wgs_per_cu = flow_max_wgs_per_cu(false, cplx);
+    std::vector<RealItem> items(1);
+    RealItem &it = items[0];
+    it.T = (const double *)T;
+    it.ldt = ldt;
+    it.U = (double *)F;
+    it.ldu = ldf;
+    it.n = n;
+    it.path = SIGNTRI_PATH_PH;
+    it.p = 0;
+    it.s = 0;
+    it.sgn = sgn;
+    it.dg = dg;
+    it.cplx = cplx;
+    it.info = info;
+    it.fd = (const double *)fdiag;
+    int rc = run_real(items, SIGNTRI_FP64, &eo, w + L.flow, hflow, prof_on(), nullptr, st);
+    if (rc != SIGNTRI_OK) return rc;
+    if (info) {
+        int herr = 0;
+        if ((rc = sweep_error(w + L.flow, &n, 1, false, cplx, hflow, st, &herr)) != 0) return rc;
+        info->path = SIGNTRI_PATH_PH;
+        info->tile = 32;
+        info->sweep = SIGNTRI_SWEEP_DATAFLOW;
+        info->wgs_per_cu = eo.wgs_per_cu;
+    }
+    return SIGNTRI_OK;
+}
+
 }  // namespace sgt
 
 extern "C" {
@@ -738,6 +806,12 @@ int sign_tri(const void *T, int64_t n, int64_t ld, signtri_dtype dtype, void *U)
                      0, nullptr, nullptr, &info);
     if (rc != SIGNTRI_OK) return rc;
     return hipStreamSynchronize(nullptr) == hipSuccess ? SIGNTRI_OK : SIGNTRI_EHIP;
+}
+
+int signtri_fun(const void *T, int64_t ldt, const void *fdiag, void *F, int64_t ldf, int64_t n,
+                signtri_dtype dtype, void *stream, signtri_info *info)
+{
+    return sgt::signtri_fun_run(T, ldt, fdiag, F, ldf, n, dtype, stream, info);
 }
 
 size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch, signtri_dtype dtype,

@@ -89,18 +89,27 @@ __global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats
         for (int q = 0; q < P; ++q) {
             sT[q * PL + i + j * LD] =
                 (in && i <= j) ? d.T[P * ((r0 + i) + (r0 + j) * d.ldt) + q] : 0.0;
-            sU[q * PL + i + j * LD] = (q == 0 && in && i == j) ? (double)d.sgn[r0 + i] : 0.0;
+            double u = 0.0;
+            if (in && i == j) {
+                if (d.fd) u = d.fd[P * (r0 + i) + q];
+                else if (q == 0) u = (double)d.sgn[r0 + i];
+            }
+            sU[q * PL + i + j * LD] = u;
         }
     }
-    if (threadIdx.x < TB) ss[threadIdx.x] = threadIdx.x < bt ? d.sgn[r0 + threadIdx.x] : 1;
+    // (a general function: every pair by Eq. (1)'s form, the element Parlett
+    // equation of Algorithm 1: distinct classes for the two ends of every pair)
+    if (threadIdx.x < TB) ss[threadIdx.x] = threadIdx.x < bt ? (d.fd ? 1 : d.sgn[r0 + threadIdx.x]) : 1;
+    const bool gen = d.fd != nullptr;
     __syncthreads();
     const int i = threadIdx.x / LPE, q = threadIdx.x % LPE;
     for (int dd = 1; dd < bt; ++dd) {
         const int j = i + dd;
         if (j < bt) {
             const int si = ss[i], sj = ss[j];
+            const bool opp = gen || si != sj;
             double sr = 0.0, sim = 0.0;
-            if (si != sj) {
+            if (opp) {
                 for (int k = i + 1 + q; k < j; k += LPE) {
                     const int ik = i + k * LD, kj = k + j * LD;
                     sr += sU[ik] * sT[kj] - sT[ik] * sU[kj];
@@ -124,12 +133,19 @@ __global__ __launch_bounds__(256) void k_diag_b(const PrepMat *__restrict__ mats
             if (P == 2) sim = group_sum<LPE>(sim);
             if (q == 0) {
                 double ur, ui = 0.0;
-                if (si != sj) {
-                    // Eq. (1): t_ij (u_ii - u_jj) = 2 s_i t_ij
-                    const double nr = 2.0 * si * sT[i + j * LD] + sr;
+                if (opp) {
+                    // Eq. (1): t_ij (u_ii - u_jj) = 2 s_i t_ij for the sign; for a general
+                    // function t_ij (f_ii - f_jj)
+                    double cr = 2.0 * si, ci = 0.0;
+                    if (gen) {
+                        cr = sU[i + i * LD] - sU[j + j * LD];
+                        if (P == 2) ci = sU[PL + i + i * LD] - sU[PL + j + j * LD];
+                    }
+                    const double tr = sT[i + j * LD], ti = P == 2 ? sT[PL + i + j * LD] : 0.0;
+                    const double nr = (cr * tr - ci * ti) + sr;
                     const double dr = sT[i + i * LD] - sT[j + j * LD];
                     if (P == 2) {
-                        const double ni = 2.0 * si * sT[PL + i + j * LD] + sim;
+                        const double ni = (cr * ti + ci * tr) + sim;
                         const double di = sT[PL + i + i * LD] - sT[PL + j + j * LD];
                         // (nr + i ni) / (dr + i di), scaled against overflow
                         const double s = fmax(fabs(dr), fabs(di));

@@ -379,6 +379,8 @@ template <typename F> struct FlowMat {
     int nbr, nbc;        // blocks in the row and column index spaces of the unknown
     int64_t flag0;       // this matrix's first completion flag (flags are I * nbc + J)
     double rhs_scale;    // SYL: 2 s
+    int general;         // MAIN: a general function (Algorithm 1): every pair of entries by
+                         // the element Parlett equation, V's diagonal blocks holding phi(T_II)
 };
 template <typename F> struct FlowArgs {
     FlowMat<F> m0;             // the matrix, when mats is null
@@ -505,6 +507,7 @@ struct PrepMat {
     int kind;   // 0: zero the strict lower triangle; 1: diag(s I_p, -s I_{n-p}); 2: s I
     int64_t p;
     double s;
+    const double *fd;  // a general function: phi(t_ii) (complex: re, im pairs); else null
 };
 hipError_t launch_scan_b(const ScanMat *mats, int nmat, hipStream_t st);
 hipError_t launch_prepare_b(const PrepMat *mats, int nmat, int64_t nmax, bool cplx, hipStream_t st);
@@ -525,6 +528,8 @@ struct RealItem {
     const double *dg;     // (complex: interleaved re, im pairs)
     bool cplx;            // complex entries (interleaved re, im); the same for every item
     signtri_info *info;   // optional host output
+    const double *fd = nullptr;  // a general function phi (path PH, FP64): phi(t_ii) on the
+                                 // device (complex: re, im pairs); null for the sign
 };
 // Device and pinned-host bytes a run over these orders needs.
 void run_sizes(const int64_t *ns, int nmat, bool mixed, bool cplx, size_t *dev_bytes,

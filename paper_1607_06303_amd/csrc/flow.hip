@@ -200,7 +200,9 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
         };
 
         if (tid < TB) {
-            if (syl) {
+            // (the Sylvester form and a general function: every entry by the
+            // opposite-class equations)
+            if (syl || M.general) {
                 rs[tid] = tid < bi ? 1 : 0;
                 cs[tid] = tid < bj ? -1 : 0;
             } else {

@@ -294,13 +294,14 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
         f0[m] = nflags;
         nflags += (int64_t)nbr[m] * nbc[m];
         hpm[m] = PrepMat{it.T, it.ldt, it.U, it.ldu, n, it.sgn, triv ? 2 : (ps ? 1 : 0), it.p,
-                         (double)it.s};
+                         (double)it.s, it.fd};
         if (ps)
             hf64[m] = syl_mat<double>(it.T, it.ldt, it.U, it.ldu, it.T, it.ldt, 2.0 * it.s, it.dg,
                                       n, it.p, f0[m]);
         else
             hf64[m] = ph_mat<double>(it.T, it.ldt, nullptr, 0, it.U, it.ldu, it.dg, it.sgn, n,
                                      f0[m]);
+        hf64[m].general = it.fd != nullptr;
         if (!triv && !ps)
             for (int64_t I = 0; I < nblocks(n); ++I) hdt[ndiag++] = make_int2(m, (int)I);
         if (mixed) {

@@ -28,7 +28,7 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
            "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
            "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear", "signtri_noalloc",
-           "signtri_autotune_batched")
+           "signtri_autotune_batched", "signtri_fun")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
             "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10, "proj": 11,
             "proj_out": 12}
@@ -126,6 +126,8 @@ def lib() -> ctypes.CDLL:
             L.signtri_autotune.argtypes = [p, i64, p, i64, i64, i32, i32, i32, p, i32,
                                            ctypes.POINTER(TuneEntry)]
             L.signtri_autotune.restype = i32
+            L.signtri_fun.argtypes = [p, i64, p, p, i64, i64, i32, p, ctypes.POINTER(Info)]
+            L.signtri_fun.restype = i32
             L.signtri_autotune_batched.argtypes = [ctypes.POINTER(p), ctypes.POINTER(i64),
                                                    ctypes.POINTER(p), ctypes.POINTER(i64),
                                                    ctypes.POINTER(i64), i64, i32, i32, p, i32,
@@ -271,6 +273,29 @@ def sign_tri_noalloc(T, out=None, stream=None):
     if rc != 0:
         raise SignTriError(rc, strerror(rc), info.as_dict())
     return U, info.as_dict()
+
+
+def fun_tri(T, fdiag, out=None, stream=None):
+    """F = phi(T) for a square upper-triangular column-major tensor T and phi's
+    values on the diagonal, fdiag[i] = phi(t_ii) (a tensor of n values on the same
+    device, same dtype), by Parlett's substitution (Algorithm 1).  Returns (F, info)."""
+    if T.dim() != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    n = T.shape[0]
+    lay = _layout(T)
+    if lay is None or (n > 1 and lay[0] != COL_MAJOR):
+        raise ValueError("fun_tri takes a column-major T")
+    if fdiag.shape != (n,) or fdiag.dtype != T.dtype or fdiag.device != T.device:
+        raise ValueError("fdiag must hold n values of T's dtype on T's device")
+    fd = fdiag.contiguous()
+    F = out if out is not None else empty_like_layout(T)
+    info = Info()
+    rc = lib().signtri_fun(T.data_ptr() if n else None, lay[1], fd.data_ptr() if n else None,
+                           F.data_ptr() if n else None, _layout(F)[1] if n else 1, n,
+                           _dtype_code(T), _stream_handle(T, stream), ctypes.byref(info))
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc), info.as_dict())
+    return F, info.as_dict()
 
 
 def _batch_args(Ts, outs):

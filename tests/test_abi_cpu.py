@@ -256,3 +256,20 @@ def test_batched_workspace_size():
     # complex: twice the diagonal and FP32 copies
     c = L.signtri_batched_workspace_size(I(32, 100, 1000), 3, 1, 1)
     assert c > b
+
+
+def test_fun_argument_validation_without_device_work():
+    L = signtri.lib()
+    p = ctypes.c_void_p
+    t, fd, f = p(0x1000), p(0x200000), p(0x400000)
+    call = lambda T, ldt, FD, F, ldf, n, dt=0: L.signtri_fun(T, ldt, FD, F, ldf, n, dt, None, None)
+    assert call(None, 4, fd, f, 4, 4) == -1
+    assert call(t, 3, fd, f, 4, 4) == -2
+    assert call(t, 4, None, f, 4, 4) == -3
+    assert call(t, 4, fd, None, 4, 4) == -4
+    assert call(t, 4, fd, f, 3, 4) == -5
+    assert call(t, 4, fd, f, 4, -1) == -6
+    assert call(t, 4, fd, f, 4, 4, dt=9) == -7
+    assert call(t, 4, fd, t, 4, 4) == -4        # F overlaps T
+    assert call(t, 4, fd, fd, 4, 4) == -4       # F overlaps the diagonal values
+    assert call(None, 1, None, None, 1, 0) == 0  # n = 0: nothing to do
