@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/signtri.h"
@@ -139,6 +140,38 @@ __device__ inline dx4 mfma_f64(double a, double b, dx4 c)
 __device__ inline fx4 mfma_f32(float a, float b, fx4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Accesses through a pointer that addresses device memory.  A pointer read
+// from a struct is generic to the compiler, which then emits flat loads; a
+// flat load counts against the LDS counter as well, so each wait for an LDS
+// read also waits for every flat load in flight and a prefetch into registers
+// stops overlapping the compute.  These casts make the loads global ones.
+template <typename V> using gmem = __attribute__((address_space(1))) V;
+template <typename V> __device__ inline V gload(const V *p)
+{
+    if constexpr (std::is_arithmetic<V>::value) {
+        return *(const gmem<V> *)p;
+    } else {  // a struct or vector type: word by word
+        static_assert(sizeof(V) % 4 == 0 && alignof(V) >= 4, "gload of a struct needs whole words");
+        V v;
+        const gmem<int> *s = (const gmem<int> *)p;
+        int *d = (int *)&v;
+#pragma unroll
+        for (unsigned i = 0; i < sizeof(V) / 4; ++i) d[i] = s[i];
+        return v;
+    }
+}
+template <typename V> __device__ inline void gstore(V *p, V v) { *(gmem<V> *)p = v; }
+// Device-coherent (agent scope) forms, for data another workgroup of the
+// running launch writes or reads.
+template <typename V> __device__ inline V gload_coherent(const V *p)
+{
+    return __hip_atomic_load((const gmem<V> *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V> __device__ inline void gstore_coherent(V *p, V v)
+{
+    __hip_atomic_store((gmem<V> *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------

@@ -103,18 +103,9 @@ struct TileRef {
 // (s_waitcnt) before its flag store is issued, and the consumer issues its loads
 // only after it has read the flag.  Inputs and blocks written before the launch
 // use ordinary cached loads.
-__device__ inline int flag_load(const int *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename F> __device__ inline F coherent_load(const F *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename F> __device__ inline void coherent_store(F *p, F v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ inline int flag_load(const int *p) { return gload_coherent(p); }
+template <typename F> __device__ inline F coherent_load(const F *p) { return gload_coherent(p); }
+template <typename F> __device__ inline void coherent_store(F *p, F v) { gstore_coherent(p, v); }
 
 // Global-to-LDS staging of one K step: each thread carries 4 consecutive rows
 // of one column of every operand tile the step needs (A side: unknown, -T, U0;
@@ -184,9 +175,9 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
     __syncthreads();
     int t = uniform(s_task);
     while (t < ntasks) {
-        const int2 tk = a.tasks[t];
+        const int2 tk = gload(a.tasks + t);
         const int mat = uniform(tk.x), ij = uniform(tk.y);
-        const FlowMat<F> M = a.mats ? a.mats[mat] : a.m0;
+        const FlowMat<F> M = a.mats ? gload(a.mats + mat) : a.m0;
         const int I = ij >> 16, J = ij & 0xffff;
         // row and column spaces of the unknown
         const int64_t ro = 0, co = syl ? M.split : 0;
@@ -206,8 +197,8 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 rs[tid] = tid < bi ? 1 : 0;
                 cs[tid] = tid < bj ? -1 : 0;
             } else {
-                rs[tid] = tid < bi ? M.sgn[gr0 + tid] : 0;
-                cs[tid] = tid < bj ? M.sgn[gc0 + tid] : 0;
+                rs[tid] = tid < bi ? gload(M.sgn + gr0 + tid) : 0;
+                cs[tid] = tid < bj ? gload(M.sgn + gc0 + tid) : 0;
             }
         }
         __syncthreads();
@@ -424,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     F v = 0;
-                    if (ok) v = coh ? coherent_load(p + at(r, c, ld, q)) : p[at(r, c, ld, q)];
+                    if (ok) v = coh ? coherent_load(p + at(r, c, ld, q)) : gload(p + at(r, c, ld, q));
                     dst[q][e] = v;
                 }
             }
@@ -583,9 +574,9 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             const int64_t gi = gr0 + li, gk = gr0 + k;
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                cu[q][u] = (up && !syl) ? (CORR ? M.C[at(gi, gk, M.ldc, q)] : M.V[at(gi, gk, M.ldv, q)])
+                cu[q][u] = (up && !syl) ? (CORR ? gload(M.C + at(gi, gk, M.ldc, q)) : gload(M.V + at(gi, gk, M.ldv, q)))
                                         : (F)0;
-                ct[q][u] = up ? M.T[at(gi, gk, M.ldt, q)] : (F)0;
+                ct[q][u] = up ? gload(M.T + at(gi, gk, M.ldt, q)) : (F)0;
             }
         }
         constexpr int RPT = TB * TB / NT;  // entries per thread of a 32 x 32 table
@@ -597,13 +588,13 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             const int64_t gi = gc0 + k, gk = gc0 + c;
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                rt[q][w] = in ? M.T[at(gi, gk, M.ldt, q)] : (F)0;
-                ru[q][w] = (in && !syl) ? (CORR ? M.C[at(gi, gk, M.ldc, q)] : M.V[at(gi, gk, M.ldv, q)])
+                rt[q][w] = in ? gload(M.T + at(gi, gk, M.ldt, q)) : (F)0;
+                ru[q][w] = (in && !syl) ? (CORR ? gload(M.C + at(gi, gk, M.ldc, q)) : gload(M.V + at(gi, gk, M.ldv, q)))
                                         : (F)0;
                 F v = 0;
                 if (k < bi && c < bj) {
-                    if (CORR) v = M.V[at(gr0 + k, gc0 + c, M.ldv, q)];
-                    if (syl) v = (F)M.rhs_scale * M.Rh[at(gr0 + k, gc0 + c, M.ldrh, q)];
+                    if (CORR) v = gload(M.V + at(gr0 + k, gc0 + c, M.ldv, q));
+                    if (syl) v = (F)M.rhs_scale * gload(M.Rh + at(gr0 + k, gc0 + c, M.ldrh, q));
                 }
                 r0v[q][w] = v;
             }
@@ -615,8 +606,8 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 double zr = 0.0, zi = 0.0;
                 if (opp) {
                     // 1 / (d_i - d_j) for a complex difference z: conj(z) / |z|^2
-                    const double dr = M.dg[2 * (gr0 + r)] - M.dg[2 * (gc0 + c)];
-                    const double di = M.dg[2 * (gr0 + r) + 1] - M.dg[2 * (gc0 + c) + 1];
+                    const double dr = gload(M.dg + 2 * (gr0 + r)) - gload(M.dg + 2 * (gc0 + c));
+                    const double di = gload(M.dg + 2 * (gr0 + r) + 1) - gload(M.dg + 2 * (gc0 + c) + 1);
                     const double s = fmax(fabs(dr), fabs(di));
                     const double xr = dr / s, xi = di / s;
                     const double den = s * (xr * xr + xi * xi);
@@ -626,7 +617,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
                 rcp[0][e] = zr;
                 rcp[1][e] = zi;
             } else {
-                rcp[0][e] = opp ? 1.0 / (M.dg[gr0 + r] - M.dg[gc0 + c]) : 0.0;
+                rcp[0][e] = opp ? 1.0 / (gload(M.dg + gr0 + r) - gload(M.dg + gc0 + c)) : 0.0;
             }
         }
 

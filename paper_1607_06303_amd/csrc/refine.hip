@@ -55,7 +55,7 @@ template <int P, typename S> __device__ inline double mag(const S *p, int64_t e)
     }
 }
 
-#define REF_MAT(a) (a.mats ? a.mats[blockIdx.z] : a.m0)
+#define REF_MAT(a) (a.mats ? gload(a.mats + blockIdx.z) : a.m0)
 
 // A kernel of a refinement step the device decided against: nothing to do.
 __device__ inline bool gated_off(const RefArgs &a) { return a.live && uniform(*a.live) == 0; }
@@ -73,11 +73,11 @@ template <int P> __global__ __launch_bounds__(NT) void k_to_f32(RefArgs a)
              i += (int64_t)gridDim.x * NT) {
             const int64_t et = i + j * d.ldt, e32 = i + j * d.ld32, eu = i + j * d.ldu;
 #pragma unroll
-            for (int q = 0; q < P; ++q) d.T32[P * e32 + q] = (float)d.T[P * et + q];
+            for (int q = 0; q < P; ++q) gstore(d.T32 + P * e32 + q, (float)gload(d.T + P * et + q));
             m = fmax(m, mag<P>(d.T, et));
             if (d.split == 0 && i / TB == j / TB)
 #pragma unroll
-                for (int q = 0; q < P; ++q) d.U32[P * e32 + q] = (float)d.U[P * eu + q];
+                for (int q = 0; q < P; ++q) gstore(d.U32 + P * e32 + q, (float)gload(d.U + P * eu + q));
         }
     m = block_max(m, red);
     if (threadIdx.x == 0) atomic_max_nonneg(&d.maxes[0], m);
@@ -103,7 +103,7 @@ template <int P> __global__ __launch_bounds__(NT) void k_widen(RefArgs a)
              i += (int64_t)gridDim.x * NT) {
             const int64_t e32 = i + j * d.ld32, eu = i + j * d.ldu;
 #pragma unroll
-            for (int q = 0; q < P; ++q) d.U[P * eu + q] = (double)d.U32[P * e32 + q];
+            for (int q = 0; q < P; ++q) gstore(d.U + P * eu + q, (double)gload(d.U32 + P * e32 + q));
             m = fmax(m, mag<P>(d.U32, e32));
         }
     }
@@ -124,7 +124,7 @@ template <int P> __global__ __launch_bounds__(NT) void k_add_correction(RefArgs 
              i += (int64_t)gridDim.x * NT) {
             const int64_t e32 = i + j * d.ld32, eu = i + j * d.ldu;
 #pragma unroll
-            for (int q = 0; q < P; ++q) d.U[P * eu + q] += (double)d.E32[P * e32 + q];
+            for (int q = 0; q < P; ++q) d.U[P * eu + q] += (double)gload(d.E32 + P * e32 + q);
             m = fmax(m, mag<P>(d.E32, e32));
         }
     }
@@ -136,7 +136,7 @@ __global__ void k_clear_correction_max(RefArgs a)
 {
     if (gated_off(a)) return;
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z < a.nmat) (a.mats ? a.mats[z] : a.m0).maxes[2] = 0;
+    if (z < a.nmat) (a.mats ? gload(a.mats + z) : a.m0).maxes[2] = 0;
 }
 
 // acc (P planes) += a * b for one MFMA operand pair (complex: four products)
@@ -172,8 +172,8 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
-    const int2 tk = tasks[ntasks - 1 - (int)blockIdx.x];
-    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int2 tk = gload(tasks + ntasks - 1 - (int)blockIdx.x);
+    const RefMat d = a.mats ? gload(a.mats + uniform(tk.x)) : a.m0;
     const int I = uniform(tk.y >> 16), J = uniform(tk.y & 0xffff);
     const int64_t n = uniform(d.n);
     const double *T = d.T, *U = d.U;
@@ -181,8 +181,8 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
     const int64_t r0 = (int64_t)I * TB, c0 = (int64_t)J * TB;
     const int bj = (int)min((int64_t)TB, n - c0);
     if (tid < TB) {
-        rs[tid] = d.sgn[r0 + tid];
-        cs[tid] = tid < bj ? d.sgn[c0 + tid] : 0;
+        rs[tid] = gload(d.sgn + r0 + tid);
+        cs[tid] = tid < bj ? gload(d.sgn + c0 + tid) : 0;
     }
     __syncthreads();
     bool needY = false, needX = false;
@@ -218,10 +218,10 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
             const bool okB = rb < n && cb < n && !(dB && rb > cb);
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                gaU[q][e] = okA ? U[P * (ra + ca * ldu) + q] : 0.0;
-                gaT[q][e] = (okA && any_x) ? T[P * (ra + ca * ldt) + q] : 0.0;
-                gbU[q][e] = okB ? U[P * (rb + cb * ldu) + q] : 0.0;
-                gbT[q][e] = (okB && any_x) ? T[P * (rb + cb * ldt) + q] : 0.0;
+                gaU[q][e] = okA ? gload(U + P * (ra + ca * ldu) + q) : 0.0;
+                gaT[q][e] = (okA && any_x) ? gload(T + P * (ra + ca * ldt) + q) : 0.0;
+                gbU[q][e] = okB ? gload(U + P * (rb + cb * ldu) + q) : 0.0;
+                gbT[q][e] = (okB && any_x) ? gload(T + P * (rb + cb * ldt) + q) : 0.0;
             }
         }
     };
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_resid(RefArgs a, const int2 *__restrict_
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 const double v = same ? accY[q][r] : accX[q][r];
-                d.E32[P * e + q] = (float)v;
+                gstore(d.E32 + P * e + q, (float)v);
                 ss += v * v;
             }
         }
@@ -308,11 +308,11 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
     __shared__ int8_t rs[RT], cs[RT];
 
     if (gated_off(a)) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int mg = lane >> 4, mt = lane & 15;
-    const int2 tk = tiles[ntiles - 1 - (int)blockIdx.x];
-    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int2 tk = gload(tiles + ntiles - 1 - (int)blockIdx.x);
+    const RefMat d = a.mats ? gload(a.mats + uniform(tk.x)) : a.m0;
     const int ta = uniform(tk.y >> 16), tb = uniform(tk.y & 0xffff);
     const int64_t n = uniform(d.n);
     const int nb = uniform(d.nbc);
@@ -322,12 +322,13 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
     const int I = 4 * ta + wr, J0 = 4 * tb + 2 * wc;
     const bool mine[2] = {I < J0 && J0 < nb, I < J0 + 1 && J0 + 1 < nb};
     if (tid < RT) {
-        rs[tid] = r0 + tid < n ? d.sgn[r0 + tid] : 0;
-        cs[tid] = c0 + tid < n ? d.sgn[c0 + tid] : 0;
+        rs[tid] = r0 + tid < n ? gload(d.sgn + r0 + tid) : 0;
+        cs[tid] = c0 + tid < n ? gload(d.sgn + c0 + tid) : 0;
     }
     __syncthreads();
-    bool nY[2][4], nX[2][4];
-    bool wx = false;
+    // which products each 16 x 16 piece needs, as wave-uniform bit masks (bit
+    // 4 ra + cb), so that the tests around the MFMAs are scalar branches
+    int ym = 0, xm = 0;
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
@@ -341,11 +342,12 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
                 cn |= vc < 0;
             }
             const bool m = mine[cb >> 1];
-            nY[ra][cb] = m && ((rp && cp) || (rn && cn));
-            nX[ra][cb] = m && ((rp && cn) || (rn && cp));
-            wx |= nX[ra][cb];
+            if (m && ((rp && cp) || (rn && cn))) ym |= 1 << (4 * ra + cb);
+            if (m && ((rp && cn) || (rn && cp))) xm |= 1 << (4 * ra + cb);
         }
-    const bool any_x = __syncthreads_or(wx);
+    ym = uniform(ym);
+    xm = uniform(xm);
+    const bool any_x = __syncthreads_or(xm != 0);
 
     dx4 accY[2][4], accX[2][4];
 #pragma unroll
@@ -366,10 +368,10 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
             const int64_t kb = k0 + 4 * bkq + e, cb = c0 + bcol;
             const bool okA = ra < n && ka < n && ra <= ka;
             const bool okB = kb < n && cb < n && kb <= cb;
-            gaU[e] = okA ? U[ra + ka * ldu] : 0.0;
-            gaT[e] = (okA && any_x) ? T[ra + ka * ldt] : 0.0;
-            gbU[e] = okB ? U[kb + cb * ldu] : 0.0;
-            gbT[e] = (okB && any_x) ? T[kb + cb * ldt] : 0.0;
+            gaU[e] = okA ? gload(U + ra + ka * ldu) : 0.0;
+            gaT[e] = (okA && any_x) ? gload(T + ra + ka * ldt) : 0.0;
+            gbU[e] = okB ? gload(U + kb + cb * ldu) : 0.0;
+            gbT[e] = (okB && any_x) ? gload(T + kb + cb * ldt) : 0.0;
         }
     };
     auto store = [&](int buf) {
@@ -419,8 +421,8 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
                     if (!live[ra][cb]) continue;
-                    if (nY[ra][cb]) accY[ra][cb] = mfma_f64(aU[ra], bU[cb], accY[ra][cb]);
-                    if (nX[ra][cb]) {
+                    if (ym >> (4 * ra + cb) & 1) accY[ra][cb] = mfma_f64(aU[ra], bU[cb], accY[ra][cb]);
+                    if (xm >> (4 * ra + cb) & 1) {
                         accX[ra][cb] = mfma_f64(aU[ra], bT[cb], accX[ra][cb]);
                         accX[ra][cb] = mfma_f64(aT[ra], bU[cb], accX[ra][cb]);
                     }
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
                     const int j = 64 * wc + 16 * cb + mt;
                     if (c0 + j < n) {
                         const double v = rs[i] == cs[j] ? accY[ra][cb][r] : accX[ra][cb][r];
-                        d.E32[(r0 + i) + (c0 + j) * d.ld32] = (float)v;
+                        gstore(d.E32 + (r0 + i) + (c0 + j) * d.ld32, (float)v);
                         ss += v * v;
                     }
                 }
@@ -471,8 +473,8 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int pr = wave >> 1, pc = wave & 1;
     const int lc = tid >> 3, lr = (tid & 7) * 4;
-    const int2 tk = tasks[ntasks - 1 - (int)blockIdx.x];
-    const RefMat d = a.mats ? a.mats[uniform(tk.x)] : a.m0;
+    const int2 tk = gload(tasks + ntasks - 1 - (int)blockIdx.x);
+    const RefMat d = a.mats ? gload(a.mats + uniform(tk.x)) : a.m0;
     const int I = uniform(tk.y >> 16), J = uniform(tk.y & 0xffff);
     const int64_t n = uniform(d.n), p = uniform(d.split);
     const double *T = d.T, *U = d.U;
@@ -512,8 +514,8 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
             const bool okB = rb < bend_r && cb < bend_c && !(bdiag && rb > cb);
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                ga[q][e] = okA ? sa * pa[P * (ra + ca * lda) + q] : 0.0;
-                gb[q][e] = okB ? pb[P * (rb + cb * ldb) + q] : 0.0;
+                ga[q][e] = okA ? sa * gload(pa + P * (ra + ca * lda) + q) : 0.0;
+                gb[q][e] = okB ? gload(pb + P * (rb + cb * ldb) + q) : 0.0;
             }
         }
     };
@@ -553,8 +555,8 @@ __global__ __launch_bounds__(NT) void k_resid_syl(RefArgs a, const int2 *__restr
         if (i < p && j < n) {
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                const double v = d.two_s * T[P * (i + j * ldt) + q] + acc[q][r];
-                d.E32[P * (i + j * d.ld32) + q] = (float)v;
+                const double v = d.two_s * gload(T + P * (i + j * ldt) + q) + acc[q][r];
+                gstore(d.E32 + P * (i + j * d.ld32) + q, (float)v);
                 ss += v * v;
             }
         }
