@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="block size 32 or 64 (0: library default)")
     ap.add_argument("--algo", default="auto", choices=["auto", "ph", "ps", "proj"],
                     help="the path (profiling runs of a path AUTO does not take; default auto)")
+    ap.add_argument("--products", default="masked", choices=["masked", "dense"],
+                    help="the dataflow sweeps' block products: per-piece masked (default) or "
+                         "both accumulators everywhere (for measuring what the masking saves)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the side measurement of the 2000-matrix batched workload")
     ap.add_argument("--no-tune", action="store_true",
@@ -209,7 +212,10 @@ def main():
         ref_s = time.perf_counter() - t0
         log("oracle: %.1f s" % ref_s)
 
-    opts = {"tile": args.tile} if args.tile else None
+    opts = {"tile": args.tile} if args.tile else {}
+    if args.products != "masked":
+        opts["products"] = args.products
+    opts = opts or None
     results = {}
     tuned = {}
     for mode in [m for m in args.modes.split(",") if m]:
@@ -308,7 +314,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "real upper-triangular n=%d, %d negative diagonal entries at random "
                                "positions (skewed inertia)" % (n, args.negatives),
-                   "n": n, "negatives": args.negatives, "headline_mode": headline},
+                   "n": n, "negatives": args.negatives, "headline_mode": headline,
+                   **({"products": args.products} if args.products != "masked" else {})},
         "modes": {m: {"ms_per_step": r["ms"], "gflops": r["gflops"],
                       "err_full": r.get("err_full"), "inv_u2": r.get("inv_u2"),
                       "inv_comm": r.get("inv_comm"), "path": r["info"]["path_name"],

@@ -166,7 +166,17 @@ typedef struct {
     int32_t wgs_per_cu;          /* dataflow sweep: persistent workgroups per compute unit,
                                     0 = tuned choice, else as many as fit; values above
                                     what fits are clamped to it                          */
+    int32_t products;            /* off-diagonal block products of the dataflow sweeps
+                                    (Section 5's accumulators X and Y): SIGNTRI_PRODUCTS_*;
+                                    other values -13                                     */
 } signtri_options;
+
+/* MASKED (0, the default): each 16 x 16 piece of a block's product forms only the
+ *   accumulator its entries need: Y (sums of u u) where some row and column share
+ *   a sign, X (sums of u t - t u) where some differ, as Section 5.3 proposes.
+ * DENSE: every piece forms both, as the recursion of Algorithms 4-6 does; the same
+ *   results up to rounding, kept for measuring what the masking saves. */
+enum { SIGNTRI_PRODUCTS_MASKED = 0, SIGNTRI_PRODUCTS_DENSE = 1 };
 
 /*
  * Compute U = sign(T).

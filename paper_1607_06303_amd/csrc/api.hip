@@ -97,6 +97,7 @@ int check_options(const signtri_options *o, signtri_dtype dtype, signtri_mode mo
     if (o->sweep < SIGNTRI_SWEEP_AUTO || o->sweep > SIGNTRI_SWEEP_SUPERDIAG) return -13;
     if (o->wgs_per_cu < 0) return -13;
     if (o->max_refine_steps > kMaxRefineSteps) return -13;
+    if (o->products != SIGNTRI_PRODUCTS_MASKED && o->products != SIGNTRI_PRODUCTS_DENSE) return -13;
     const bool cplx = dtype == SIGNTRI_C128;
     if (cplx && o->tile == 64) return SIGNTRI_ENOTSUP;
     if (mode != SIGNTRI_FP64 && (o->sweep == SIGNTRI_SWEEP_SUPERDIAG || o->tile == 64))
@@ -358,7 +359,7 @@ int launch_batch_graph(std::vector<RealItem> &items, signtri_mode mode,
     std::vector<int64_t> key{(int64_t)mode, (int64_t)device, (int64_t)(intptr_t)run_dev,
                              (int64_t)ws_generation().load(), (int64_t)items.size(),
                              (int64_t)(opts ? opts->wgs_per_cu : 0), (int64_t)cplx,
-                             (int64_t)flow_spin_limit()};
+                             (int64_t)flow_spin_limit(), (int64_t)(opts ? opts->products : 0)};
     if (mode == SIGNTRI_MIXED_REFINED) {
         // the refinement's options are part of what was captured
         int64_t stall_bits = 0;

@@ -414,6 +414,7 @@ template <typename F> struct FlowMat {
     double rhs_scale;    // SYL: 2 s
     int general;         // MAIN: a general function (Algorithm 1): every pair of entries by
                          // the element Parlett equation, V's diagonal blocks holding phi(T_II)
+    int dense;           // MAIN, CORR: every 16 x 16 piece forms both accumulators
 };
 template <typename F> struct FlowArgs {
     FlowMat<F> m0;             // the matrix, when mats is null

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
             }
             pneedY = uniform((rp && cp) || (rn && cn));  // the same in every lane of a wave
             pneedX = uniform((rp && cn) || (rn && cp));
+            if (M.dense && !syl && !M.general) pneedY = pneedX = true;
         }
         const bool any_x = uniform(__syncthreads_or(pneedX));
 

@@ -302,6 +302,8 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
             hf64[m] = ph_mat<double>(it.T, it.ldt, nullptr, 0, it.U, it.ldu, it.dg, it.sgn, n,
                                      f0[m]);
         hf64[m].general = it.fd != nullptr;
+        const int dense = opts && opts->products == SIGNTRI_PRODUCTS_DENSE;
+        hf64[m].dense = dense;
         if (!triv && !ps)
             for (int64_t I = 0; I < nblocks(n); ++I) hdt[ndiag++] = make_int2(m, (int)I);
         if (mixed) {
@@ -314,6 +316,7 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
             } else {
                 hf32[m] = ph_mat<float>(T32, ld, nullptr, 0, U32, ld, it.dg, it.sgn, n, f0[m]);
                 hfc[m] = ph_mat<float>(T32, ld, U32, ld, E32, ld, it.dg, it.sgn, n, f0[m]);
+                hf32[m].dense = hfc[m].dense = dense;
             }
             RefMat &r = hrm[m];
             std::memset(&r, 0, sizeof(r));

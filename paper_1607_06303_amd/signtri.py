@@ -21,6 +21,7 @@ MODES = {"fp64": 0, "mixed": 1, "fp32": 2}
 ALGOS = {"auto": 0, "ph": 1, "ps": 2, "proj": 3}
 PATH_NAMES = {0: "trivial", 1: "ph", 2: "ps", 3: "proj"}
 SWEEPS = {"auto": 0, "dataflow": 1, "superdiag": 2}
+PRODUCTS = {"masked": 0, "dense": 1}
 SWEEP_NAMES = {0: "-", 1: "dataflow", 2: "superdiag"}
 
 EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
@@ -59,6 +60,7 @@ class Options(ctypes.Structure):
         ("stall_ratio", ctypes.c_double), ("no_fallback", ctypes.c_int32),
         ("max_splits", ctypes.c_int32), ("force_stall", ctypes.c_int64),
         ("sweep", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+        ("products", ctypes.c_int32),
     ]
 
 
@@ -215,6 +217,8 @@ def _opts(options: dict | None):
     for k, v in options.items():
         if k == "sweep" and isinstance(v, str):
             v = SWEEPS[v]
+        if k == "products" and isinstance(v, str):
+            v = PRODUCTS[v]
         setattr(o, k, v)
     return ctypes.byref(o)
 

@@ -109,6 +109,8 @@ def test_option_validation_without_device_work(n):
     assert _call_opts(n, sweep=3) == -13
     assert _call_opts(n, sweep=-1) == -13
     assert _call_opts(n, wgs_per_cu=-2) == -13
+    assert _call_opts(n, products=2) == -13
+    assert _call_opts(n, products=-1) == -13
     # combinations no sweep implements
     assert _call_opts(n, dtype=1, tile=64) == 5          # complex with 64 x 64 blocks
     assert _call_opts(n, mode=1, sweep=2) == 5           # refinement on the superdiagonal sweep
@@ -120,7 +122,7 @@ def test_batched_option_validation_without_device_work():
     L = signtri.lib()
     P, I = ctypes.c_void_p * 1, ctypes.c_int64 * 1
     for opts, want in (({"sweep": 2}, 5), ({"tile": 64}, 5), ({"tile": 48}, -13),
-                       ({"wgs_per_cu": -1}, -13)):
+                       ({"wgs_per_cu": -1}, -13), ({"products": 3}, -13)):
         o = signtri.Options()
         for k, v in opts.items():
             setattr(o, k, v)

@@ -220,3 +220,37 @@ def test_repeated_diagonal_mixed(dev):
     rng = np.random.default_rng(7100)
     T = wl.schur_like(200, None, rng)
     check(T, dev, tol=1e-10, mode="mixed")
+
+
+# The products of the dataflow sweeps formed densely (both accumulators in every
+# 16 x 16 piece, as Algorithms 4-6 form X and Y) give the same U as the masked
+# default, up to rounding: FP64, refined and unrefined mixed, the batched form.
+@pytest.mark.parametrize("mode,tol", [("fp64", TOL_FP64), ("mixed", TOL_FP64),
+                                      ("fp32", TOL_FP32)])
+@pytest.mark.parametrize("neg", [None, 3])
+def test_dense_products_match(dev, mode, tol, neg):
+    rng = np.random.default_rng(6300 + (neg or 0))
+    n = 333
+    s = wl.signs_with_negatives(n, neg, rng) if neg else None
+    T = wl.make_T(n, rng, signs=s)
+    Ud, info, _ = check(T, dev, tol=tol, mode=mode, algo="ph",
+                        options={"products": "dense", "sweep": "dataflow"})
+    Um, _, _ = check(T, dev, tol=tol, mode=mode, algo="ph", options={"sweep": "dataflow"})
+    assert info["sweep"] == 1
+    assert rel_fro(Ud, Um) <= tol
+
+
+def test_dense_products_batched(dev):
+    import torch
+
+    import oracle
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(6400)
+    Ts = [wl.make_T(n, rng) for n in (40, 97, 200)]
+    Tg = [to_dev_colmajor(T, dev) for T in Ts]
+    for mode in ("fp64", "mixed"):
+        Us, _ = signtri.sign_tri_batched(Tg, mode=mode, options={"products": "dense"})
+        torch.cuda.synchronize()
+        for T, U in zip(Ts, Us):
+            assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
