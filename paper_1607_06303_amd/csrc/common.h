@@ -358,6 +358,9 @@ int wave_gemm_edge_slices(int D, int L);
 // task, completion flags between tasks.
 // ---------------------------------------------------------------------------
 constexpr int kFlowTile = 32;
+// A minority sign class of at most n / kStripDiv entries takes the residual's
+// entries of differing signs from strips over its rows and columns.
+constexpr int kStripDiv = 32;
 
 // ---------------------------------------------------------------------------
 // Projector form (proj.hip): the Parlett-Sylvester result for an ungrouped
@@ -479,9 +482,17 @@ hipError_t launch_widen(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t s
 hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipStream_t st);
 hipError_t launch_resid(const RefArgs &a, bool syl, bool cplx, const int2 *tasks, int ntasks,
                         double *norm2, hipStream_t st);
-// Real substitution form on 128 x 128 tiles (matrix, a << 16 | b), a <= b.
+// Real substitution form on 128 x 128 tiles (matrix, a << 16 | b), a <= b; yonly:
+// the entries of equal signs only (the others by launch_resid_strips, after it).
 hipError_t launch_resid128(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
-                           hipStream_t st);
+                           hipStream_t st, bool yonly = false);
+// The entries of differing signs of matrices with a small minority class: tasks
+// (matrix, kind, group g: minority indices minl[16 g .. 16 g + 15], start of a
+// 16-wide range); groups[g] = (matrix, 0, offset of its k-major copies in gbuf,
+// low and high word); nmax: the largest order.
+hipError_t launch_resid_strips(const RefArgs &a, const int4 *tasks, int ntasks, const int *minl,
+                               const int4 *groups, int ngroups, int64_t nmax, double *gbuf,
+                               double *norm2, hipStream_t st);
 
 // The refinement's decisions on the device, so that the whole refinement is
 // queued without a wait on the host (and can be captured in a graph).

@@ -300,11 +300,16 @@ constexpr int RAP = RT + 16;        // LDS: A as [k][row], padded
 constexpr int RBS = 4 * RT + 4;     // LDS: B as [k / 4][column][k % 4], padded
 constexpr int NT8 = 512;
 
+// YO: the entries of equal signs only (U^2 - I); the others come from
+// k_resid_strip, which runs after this kernel (norm2 is assigned here and added
+// to there).  T is then neither staged nor multiplied.
+template <bool YO>
 __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restrict__ tiles,
                                                   int ntiles, double *__restrict__ norm2)
 {
-    __shared__ double sAU[2][RK * RAP], sAT[2][RK * RAP];
-    __shared__ double sBU[2][(RK / 4) * RBS], sBT[2][(RK / 4) * RBS];
+    constexpr int TS = YO ? 1 : 2;  // T's LDS stages
+    __shared__ double sAU[2][RK * RAP], sAT[TS][YO ? 1 : RK * RAP];
+    __shared__ double sBU[2][(RK / 4) * RBS], sBT[TS][YO ? 1 : (RK / 4) * RBS];
     __shared__ int8_t rs[RT], cs[RT];
 
     if (gated_off(a)) return;
@@ -343,11 +348,11 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
             }
             const bool m = mine[cb >> 1];
             if (m && ((rp && cp) || (rn && cn))) ym |= 1 << (4 * ra + cb);
-            if (m && ((rp && cn) || (rn && cp))) xm |= 1 << (4 * ra + cb);
+            if (!YO && m && ((rp && cn) || (rn && cp))) xm |= 1 << (4 * ra + cb);
         }
     ym = uniform(ym);
-    xm = uniform(xm);
-    const bool any_x = __syncthreads_or(xm != 0);
+    xm = YO ? 0 : uniform(xm);
+    const bool any_x = YO ? false : __syncthreads_or(xm != 0);
 
     dx4 accY[2][4], accX[2][4];
 #pragma unroll
@@ -378,9 +383,11 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             sAU[buf][(4 * akh + e) * RAP + arow] = gaU[e];
-            sAT[buf][(4 * akh + e) * RAP + arow] = -gaT[e];
             sBU[buf][bkq * RBS + bcol * 4 + e] = gbU[e];
-            sBT[buf][bkq * RBS + bcol * 4 + e] = gbT[e];
+            if constexpr (!YO) {
+                sAT[buf][(4 * akh + e) * RAP + arow] = -gaT[e];
+                sBT[buf][bkq * RBS + bcol * 4 + e] = gbT[e];
+            }
         }
     };
     const int64_t kbeg = r0, kend = min(n, c0 + RT);
@@ -408,13 +415,13 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
             for (int ra = 0; ra < 2; ++ra) {
                 const int ao = (4 * k4 + mg) * RAP + 32 * wr + 16 * ra + mt;
                 aU[ra] = sAU[buf][ao];
-                aT[ra] = sAT[buf][ao];
+                aT[ra] = YO ? 0.0 : sAT[YO ? 0 : buf][YO ? 0 : ao];
             }
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 const int bo = k4 * RBS + (64 * wc + 16 * cb + mt) * 4 + mg;
                 bU[cb] = sBU[buf][bo];
-                bT[cb] = sBT[buf][bo];
+                bT[cb] = YO ? 0.0 : sBT[YO ? 0 : buf][YO ? 0 : bo];
             }
 #pragma unroll
             for (int ra = 0; ra < 2; ++ra)
@@ -444,7 +451,7 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
                 for (int r = 0; r < 4; ++r) {
                     const int i = 32 * wr + 16 * ra + mfma64_row(lane, r);
                     const int j = 64 * wc + 16 * cb + mt;
-                    if (c0 + j < n) {
+                    if (c0 + j < n && (!YO || rs[i] == cs[j])) {
                         const double v = rs[i] == cs[j] ? accY[ra][cb][r] : accX[ra][cb][r];
                         gstore(d.E32 + (r0 + i) + (c0 + j) * d.ld32, (float)v);
                         ss += v * v;
@@ -453,6 +460,162 @@ __global__ __launch_bounds__(NT8) void k_resid128(RefArgs a, const int2 *__restr
             }
         for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
         if (lane == 0) norm2[d.f0 + (int64_t)I * d.nbc + J0 + hb] = ss;
+    }
+}
+
+// FP64 residual (UT - TU)_ij of the entries whose signs differ, for a matrix
+// with a small minority sign class, on its minority rows and columns.  A task
+// (matrix, kind, group, tile start) takes 16 minority indices (minl[group ..
+// group + 15], ascending, -1 past the class's end) and a 16-wide range of the
+// other index:
+//   kind 0: rows i of the range against the group's columns c (i majority);
+//   kind 1: the group's rows r against columns j of the range (j majority).
+// Each entry is a sum over k from its row to its column, formed as FP64 MFMA
+// products (A = U or T on the piece's rows, B = T or U on its columns); the
+// four waves take every fourth batch of K steps and add their pieces in LDS.
+// Only entries in blocks above the diagonal are written (E32, and their squares
+// added to norm2 of their 32 x 32 block).
+constexpr int SKB = 8;  // K steps of 4 per batch of loads
+
+// The minority rows and columns of a group (16 indices of minl), copied k-major
+// so that the strips read them coalesced: for k < n and slot s (index x_s),
+//   G[0][k][s] = U[x_s, k], G[1][k][s] = T[x_s, k]   (rows)
+//   G[2][k][s] = T[k, x_s], G[3][k][s] = U[k, x_s]   (columns)
+// (zero for a padding slot).  groups[g] = (matrix, unused, offset of G in
+// doubles: low, high word); one workgroup per (group, 64 consecutive k).
+__global__ __launch_bounds__(256) void k_resid_gather(RefArgs a, const int4 *__restrict__ groups,
+                                                     const int *__restrict__ minl,
+                                                     double *__restrict__ gbuf)
+{
+    if (gated_off(a)) return;
+    const int4 gq = gload(groups + blockIdx.x);
+    const RefMat d = a.mats ? gload(a.mats + uniform(gq.x)) : a.m0;
+    const int64_t n = uniform(d.n);
+    const int64_t k0 = (int64_t)blockIdx.y * 64;
+    if (k0 >= n) return;
+    double *G = gbuf + (((int64_t)(unsigned)gq.w << 32) | (unsigned)gq.z);
+    const int s = threadIdx.x & 15;
+    const int x = gload(minl + 16 * (int64_t)blockIdx.x + s);
+    for (int e = threadIdx.x >> 4; e < 64; e += 16) {
+        const int64_t k = k0 + e;
+        if (k >= n) break;
+        const bool ok = x >= 0;
+        const double ru = ok ? gload(d.U + x + k * d.ldu) : 0.0;
+        const double rt = ok ? gload(d.T + x + k * d.ldt) : 0.0;
+        const double ct = ok ? gload(d.T + k + (int64_t)x * d.ldt) : 0.0;
+        const double cu = ok ? gload(d.U + k + (int64_t)x * d.ldu) : 0.0;
+        gstore(G + (0 * n + k) * 16 + s, ru);
+        gstore(G + (1 * n + k) * 16 + s, rt);
+        gstore(G + (2 * n + k) * 16 + s, ct);
+        gstore(G + (3 * n + k) * 16 + s, cu);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resid_strip(RefArgs a, const int4 *__restrict__ tasks,
+                                                    int ntasks, const int *__restrict__ minl,
+                                                    const int4 *__restrict__ groups,
+                                                    const double *__restrict__ gbuf,
+                                                    double *__restrict__ norm2)
+{
+    __shared__ double part[3][4][64];
+    if (gated_off(a)) return;
+    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
+    const int mg = lane >> 4, mt = lane & 15;
+    const int4 tk = gload(tasks + blockIdx.x);
+    const RefMat d = a.mats ? gload(a.mats + uniform(tk.x)) : a.m0;
+    const int kind = uniform(tk.y), gi = uniform(tk.z), t0 = uniform(tk.w);
+    const int grp = 16 * gi;  // the group's first entry in minl
+    const int4 gq = gload(groups + gi);
+    const double *G = gbuf + (((int64_t)(unsigned)gq.w << 32) | (unsigned)gq.z);
+    const int64_t n = uniform(d.n);
+    const double *T = d.T, *U = d.U;
+    const int64_t ldt = d.ldt, ldu = d.ldu;
+    // the group's indices (ascending; -1 past the end): its first and last
+    int gmin = gload(minl + grp), gmax = gmin;
+    for (int u = 1; u < 16; ++u) {
+        const int v = gload(minl + grp + u);
+        if (v >= 0) gmax = v;
+    }
+    gmin = uniform(gmin);
+    gmax = uniform(gmax);
+    const int gl = gload(minl + grp + mt);  // this lane's column (kind 0) or row (kind 1)
+    // K range, inclusive: from the piece's lowest row to its highest column
+    const int64_t kbeg = kind == 0 ? t0 : gmin;
+    const int64_t kend = kind == 0 ? gmax : min<int64_t>(n - 1, (int64_t)t0 + 15);
+    const int nk4 = kend >= kbeg ? uniform((int)((kend - kbeg) / 4 + 1)) : 0;
+    // this lane's A row and B column
+    const int64_t ar = kind == 0 ? (int64_t)t0 + mt : (int64_t)gl;
+    const int64_t bc = kind == 0 ? (int64_t)gl : (int64_t)t0 + mt;
+    const bool arok = ar >= 0 && ar < n, bcok = bc >= 0 && bc < n;
+    dx4 acc = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int s0 = SKB * wave; s0 < nk4; s0 += 4 * SKB) {
+        double au[SKB], at[SKB], bt[SKB], bu[SKB];
+#pragma unroll
+        for (int q = 0; q < SKB; ++q) {
+            const int64_t k = kbeg + 4 * (int64_t)(s0 + q) + mg;
+            const bool in = s0 + q < nk4 && k <= kend;
+            const bool oka = in && arok && k >= ar, okb = in && bcok && k <= bc;
+            // (the group's rows or columns from G, the other side from U and T)
+            if (kind == 0) {
+                au[q] = oka ? gload(U + ar + k * ldu) : 0.0;
+                at[q] = oka ? -gload(T + ar + k * ldt) : 0.0;
+                bt[q] = okb ? gload(G + (2 * n + k) * 16 + mt) : 0.0;
+                bu[q] = okb ? gload(G + (3 * n + k) * 16 + mt) : 0.0;
+            } else {
+                au[q] = oka ? gload(G + (0 * n + k) * 16 + mt) : 0.0;
+                at[q] = oka ? -gload(G + (1 * n + k) * 16 + mt) : 0.0;
+                bt[q] = okb ? gload(T + k + bc * ldt) : 0.0;
+                bu[q] = okb ? gload(U + k + bc * ldu) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SKB; ++q) {
+            acc = mfma_f64(au[q], bt[q], acc);
+            acc = mfma_f64(at[q], bu[q], acc);
+        }
+    }
+    // the four waves' pieces summed in a fixed order
+    if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[wave - 1][r][lane] = acc[r];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = ((acc[r] + part[0][r][lane]) + part[1][r][lane]) + part[2][r][lane];
+    // entry (row slot mg + 4 r, column slot mt)
+    double colsum = 0.0;  // kind 0: this lane's column (one block column)
+    double rowsum[4];     // kind 1: per row slot (one block row each)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rs = mg + 4 * r;
+        const int64_t i = kind == 0 ? (int64_t)t0 + rs : (int64_t)gload(minl + grp + rs);
+        const int64_t j = kind == 0 ? (int64_t)gl : (int64_t)t0 + mt;
+        bool ok = i >= 0 && j >= 0 && i < n && j < n && (i >> 5) < (j >> 5);
+        if (ok) ok = gload(d.sgn + i) != gload(d.sgn + j);
+        const double v = acc[r];
+        rowsum[r] = 0.0;
+        if (ok) {
+            gstore(d.E32 + i + j * d.ld32, (float)v);
+            if (kind == 0) colsum += v * v;
+            else rowsum[r] = v * v;
+        }
+    }
+    if (kind == 0) {
+        // lanes mt, mt + 16, mt + 32, mt + 48: the 16 rows (one block row) of column slot mt
+        colsum += __shfl_xor(colsum, 16, 64);
+        colsum += __shfl_xor(colsum, 32, 64);
+        const int64_t i0 = t0, j = gl;
+        if (mg == 0 && j >= 0 && i0 < n && (i0 >> 5) < (j >> 5) && colsum != 0.0)
+            atomicAdd(norm2 + d.f0 + (i0 >> 5) * d.nbc + (j >> 5), colsum);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // the 16 columns (one block column) of row slot mg + 4 r
+            const double v = group_sum<16>(rowsum[r]);
+            const int64_t i = gload(minl + grp + mg + 4 * r), j0 = t0;
+            if (mt == 0 && i >= 0 && j0 < n && v != 0.0)
+                atomicAdd(norm2 + d.f0 + (i >> 5) * d.nbc + (j0 >> 5), v);
+        }
     }
 }
 
@@ -719,10 +882,25 @@ hipError_t launch_add_correction(const RefArgs &a, int64_t nmax, bool cplx, hipS
 }
 
 hipError_t launch_resid128(const RefArgs &a, const int2 *tiles, int ntiles, double *norm2,
-                           hipStream_t st)
+                           hipStream_t st, bool yonly)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid128, dim3(ntiles), dim3(NT8), 0, st, a, tiles, ntiles, norm2);
+    if (yonly)
+        hipLaunchKernelGGL(k_resid128<true>, dim3(ntiles), dim3(NT8), 0, st, a, tiles, ntiles, norm2);
+    else
+        hipLaunchKernelGGL(k_resid128<false>, dim3(ntiles), dim3(NT8), 0, st, a, tiles, ntiles, norm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_strips(const RefArgs &a, const int4 *tasks, int ntasks, const int *minl,
+                               const int4 *groups, int ngroups, int64_t nmax, double *gbuf,
+                               double *norm2, hipStream_t st)
+{
+    if (ntasks <= 0 || ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_gather, dim3(ngroups, (unsigned)((nmax + 63) / 64)), dim3(256), 0, st,
+                       a, groups, minl, gbuf);
+    hipLaunchKernelGGL(k_resid_strip, dim3(ntasks), dim3(256), 0, st, a, tasks, ntasks, minl, groups,
+                       gbuf, norm2);
     return hipGetLastError();
 }
 

@@ -126,10 +126,10 @@ size_t sum_bytes(int nm) { return al(kSumInts * sizeof(int)) + (size_t)nm * size
 // them); the rest of each buffer is its own.  Sizes are upper bounds valid for
 // any diagonal: a matrix has at most nb^2 blocks in either form.
 struct Lay {
-    size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, rtiles, shared;   // shared part
-    size_t ctrl, flags, ftasks, norms0, norms1, maxes, rinit, okf, hop, rowmin, sum, f32, dev;
+    size_t fm64, fm32, fmc, rm, pm, dtasks, tasks, rtiles, minl, stasks, sgroups, shared;  // shared
+    size_t ctrl, flags, ftasks, norms0, norms1, maxes, rinit, okf, hop, rowmin, sum, f32, gbuf, dev;
     size_t h_err, h_sum, h_maxes, host;
-    int64_t nflags_max, ntasks_max, ndiag_max, nrows;
+    int64_t nflags_max, ntasks_max, ndiag_max, nrows, nminl_max, nstasks_max, ngroups_max, ngbuf_max;
     std::vector<int64_t> off32;  // per matrix, in floats, of its three FP32 n x n arrays
                                  // (complex: interleaved pairs, twice the floats)
 };
@@ -137,13 +137,19 @@ struct Lay {
 Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
 {
     Lay L;
-    int64_t sq = 0, sq4 = 0, nbsum = 0, f32 = 0;
+    int64_t sq = 0, sq4 = 0, nbsum = 0, f32 = 0, nminl = 0, nstasks = 0, ngroups = 0, ngbuf = 0;
     L.off32.resize(nm);
     for (int m = 0; m < nm; ++m) {
         const int64_t nb = nblocks(ns[m]), nb4 = (nb + 3) / 4;
         sq += nb * nb;
         sq4 += nb4 * nb4;
         nbsum += nb;
+        // the residual's strips (a minority class of at most n / kStripDiv entries)
+        const int64_t groups = (ns[m] / kStripDiv + 15) / 16;
+        nminl += 16 * groups;
+        nstasks += 2 * groups * ((ns[m] + 15) / 16);
+        ngroups += groups;
+        ngbuf += groups * 64 * ns[m];  // four k-major copies of 16 rows or columns
         L.off32[m] = f32;
         if (mixed) f32 += (cplx ? 6 : 3) * ns[m] * ns[m];
     }
@@ -159,6 +165,13 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     L.dtasks = o; o += al(L.ndiag_max * sizeof(int2));
     L.tasks = o; o += al(L.ntasks_max * sizeof(int2));
     L.rtiles = o; o += al((mixed ? std::max<int64_t>(sq4, 1) : 0) * sizeof(int2));
+    L.nminl_max = mixed && !cplx ? nminl : 0;
+    L.nstasks_max = mixed && !cplx ? nstasks : 0;
+    L.ngroups_max = mixed && !cplx ? ngroups : 0;
+    L.ngbuf_max = mixed && !cplx ? ngbuf : 0;
+    L.minl = o; o += al((size_t)L.nminl_max * sizeof(int));
+    L.stasks = o; o += al((size_t)L.nstasks_max * sizeof(int4));
+    L.sgroups = o; o += al((size_t)L.ngroups_max * sizeof(int4));
     L.shared = o;
     size_t d = o;
     L.ctrl = d; d += al(64 * sizeof(int));
@@ -173,6 +186,7 @@ Lay make_lay(const int64_t *ns, int nm, bool mixed, bool cplx)
     L.rowmin = d; d += al(mixed ? L.nrows * sizeof(int) : 0);
     L.sum = d; d += al(mixed ? sum_bytes(nm) : 0);
     L.f32 = d; d += al((size_t)f32 * sizeof(float));
+    L.gbuf = d; d += al((size_t)L.ngbuf_max * sizeof(double));
     L.dev = d;
     size_t h = o;
     L.h_err = h; h += al(64);
@@ -369,21 +383,77 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
                 }
     // 128 x 128 tiles (four blocks a side) of the real substitution form's
     // residual, shortest first (the kernel takes them in reverse); a diagonal
-    // tile only if it holds a block above the diagonal
-    int64_t nrt = 0;
+    // tile only if it holds a block above the diagonal.  A matrix whose minority
+    // sign class has at most n / kStripDiv entries (known from the host's copy of
+    // the signs) takes its entries of equal signs from the tiles (its tiles
+    // after the others', for the tile kernel's equal-signs form) and those of
+    // differing signs from strips over the minority rows and columns.
+    int64_t nrt = 0, nrty = 0, nstr = 0, ngr = 0;
     if (mixed && !cplx) {
+        std::vector<char> strips(nm, 0);
+        int *hminl = (int *)(H + L.minl);
+        int4 *hst = (int4 *)(H + L.stasks);
+        int4 *hgr = (int4 *)(H + L.sgroups);
+        int64_t nminl = 0, goff = 0;
+        for (int m = 0; m < nm && host_signs; ++m) {
+            const RealItem &it = items[m];
+            if (it.path != SIGNTRI_PATH_PH || it.fd || it.n < 2 * kFlowTile) continue;
+            const int8_t *hs = host_signs[m];
+            int64_t npos = 0;
+            for (int64_t i = 0; i < it.n; ++i) npos += hs[i] > 0;
+            const int64_t nneg = it.n - npos, mc = std::min(npos, nneg);
+            if (mc == 0 || mc > it.n / kStripDiv) continue;
+            const int8_t ms = nneg <= npos ? -1 : 1;  // the minority sign (ties: negative)
+            const int64_t o0 = nminl;
+            for (int64_t i = 0; i < it.n; ++i)
+                if (hs[i] == ms) hminl[nminl++] = (int)i;
+            while ((nminl - o0) % 16) hminl[nminl++] = -1;
+            for (int64_t go = o0; go < nminl; go += 16, ++ngr) {
+                const int gmin = hminl[go];
+                int gmax = gmin;
+                for (int u = 1; u < 16; ++u)
+                    if (hminl[go + u] >= 0) gmax = hminl[go + u];
+                hgr[ngr] = make_int4(m, 0, (int)(uint32_t)goff, (int)(uint32_t)(goff >> 32));
+                goff += 64 * it.n;
+                // rows of blocks above the group's last column's block, nearest the top
+                // (longest) first; columns of blocks past its first row's block, farthest first
+                for (int t0 = 0; t0 < (gmax >> 5) << 5; t0 += 16) hst[nstr++] = make_int4(m, 0, (int)ngr, t0);
+                for (int64_t t0 = (it.n - 1) / 16 * 16; t0 >= (int64_t)((gmin >> 5) + 1) << 5; t0 -= 16)
+                    hst[nstr++] = make_int4(m, 1, (int)ngr, (int)t0);
+            }
+            strips[m] = 1;
+        }
+        // longest K range first (the strips are taken in launch order)
+        auto klen = [&](const int4 &t) {
+            const int *g = hminl + 16 * (int64_t)t.z;
+            int gmax = g[0];
+            for (int u = 1; u < 16; ++u)
+                if (g[u] >= 0) gmax = g[u];
+            return t.y == 0 ? (int64_t)gmax - t.w
+                            : std::min<int64_t>(items[t.x].n - 1, (int64_t)t.w + 15) - g[0];
+        };
+        std::stable_sort(hst, hst + nstr, [&](const int4 &a, const int4 &b) { return klen(a) > klen(b); });
         int2 *hrt = (int2 *)(H + L.rtiles);
         const int nb4max = (int)((nblocks(nmax) + 3) / 4);
-        for (int dd = 0; dd < nb4max; ++dd)
-            for (auto it = order.rbegin(); it != order.rend(); ++it) {
-                const int m = *it;
-                if (items[m].path != SIGNTRI_PATH_PH) continue;
-                const int nb4 = (nbc[m] + 3) / 4;
-                for (int ta = 0; ta + dd < nb4; ++ta)
-                    if (dd > 0 || 4 * ta + 1 < nbc[m]) hrt[nrt++] = make_int2(m, (ta << 16) | (ta + dd));
-            }
+        int64_t k = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int dd = 0; dd < nb4max; ++dd)
+                for (auto it = order.rbegin(); it != order.rend(); ++it) {
+                    const int m = *it;
+                    if (items[m].path != SIGNTRI_PATH_PH || strips[m] != pass) continue;
+                    const int nb4 = (nbc[m] + 3) / 4;
+                    for (int ta = 0; ta + dd < nb4; ++ta)
+                        if (dd > 0 || 4 * ta + 1 < nbc[m]) hrt[k++] = make_int2(m, (ta << 16) | (ta + dd));
+                }
+            if (pass == 0) nrt = k;
+        }
+        nrty = k - nrt;
     }
     const int2 *drt = (const int2 *)(D + L.rtiles);
+    const int *dminl = (const int *)(D + L.minl);
+    const int4 *dst = (const int4 *)(D + L.stasks);
+    const int4 *dgr = (const int4 *)(D + L.sgroups);
+    double *dgbuf = (double *)(D + L.gbuf);
     const int2 *dtk = (const int2 *)(D + L.tasks);
     const int2 *dtk_ps = dtk + nph;
     const int2 *ddt = (const int2 *)(D + L.dtasks);
@@ -441,6 +511,10 @@ int run_real(std::vector<RealItem> &items, signtri_mode mode, const signtri_opti
         return timed(st, PK_RESID, fl.resid, [&] {
             hipError_t r = cplx ? launch_resid(rg, false, cplx, dtk, (int)nph, norm2, st)
                                 : launch_resid128(rg, drt, (int)nrt, norm2, st);
+            // equal signs on the tiles, then the strips add the differing ones
+            if (r == hipSuccess) r = launch_resid128(rg, drt + nrt, (int)nrty, norm2, st, true);
+            if (r == hipSuccess)
+                r = launch_resid_strips(rg, dst, (int)nstr, dminl, dgr, (int)ngr, nmax, dgbuf, norm2, st);
             if (r == hipSuccess) r = launch_resid(rg, true, cplx, dtk_ps, (int)nps, norm2, st);
             return r;
         });

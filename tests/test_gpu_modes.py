@@ -254,3 +254,29 @@ def test_dense_products_batched(dev):
         torch.cuda.synchronize()
         for T, U in zip(Ts, Us):
             assert rel_fro(U.cpu().numpy(), oracle.sign_tri(T)) <= TOL_FP64
+
+
+# A minority sign class of at most n / 32 entries: the residual's entries of
+# differing signs come from strips over the minority rows and columns, the
+# others from the tiles' equal-signs form.  Placements that stress the strips'
+# ranges: the first and last index, one block, a ragged order, exactly n / 32,
+# a positive minority, two groups of 16 and a partial third.
+def _minority_cases():
+    yield "edges", 300, lambda n, rng: [0, n - 1], -1
+    yield "one_block", 333, lambda n, rng: list(range(64, 70)), -1
+    yield "ragged", 517, lambda n, rng: sorted(rng.choice(n, 9, replace=False).tolist()), -1
+    yield "exact", 512, lambda n, rng: sorted(rng.choice(n, 16, replace=False).tolist()), -1
+    yield "positive", 450, lambda n, rng: sorted(rng.choice(n, 11, replace=False).tolist()), 1
+    yield "groups", 1500, lambda n, rng: sorted(rng.choice(n, 40, replace=False).tolist()), -1
+
+
+@pytest.mark.parametrize("case,n,where,ms", list(_minority_cases()),
+                         ids=[c[0] for c in _minority_cases()])
+def test_mixed_refined_minority_strips(dev, case, n, where, ms):
+    rng = np.random.default_rng(6500 + n)
+    s = np.full(n, -float(ms))
+    s[where(n, rng)] = ms
+    assert (s == ms).sum() <= n // 32
+    _, info, _ = check(wl.make_T(n, rng, signs=s), dev, mode="mixed", algo="ph")
+    assert info["path_name"] == "ph" and info["refine_steps"] >= 1
+    assert info["fallback_tiles"] == 0
