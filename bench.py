@@ -56,12 +56,15 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_name(family, mode, tile):
-    """The kernel behind one of the library's timer families, as rocprofv3 names it."""
+def kernel_name(family, mode, tile, strips=False):
+    """The kernel behind one of the library's timer families, as rocprofv3 names it
+    (strips: a minority sign class of at most n/32 entries, whose residual runs on
+    the equal-signs tiles plus strips)."""
     fp = "double" if mode == "fp64" else "float"
     return {"flow": "k_flow<%s, 0, false>" % fp, "corr": "k_flow<float, 1, false>",
             "syl": "k_flow<%s, 2, false>" % fp,
-            "resid": "k_resid64", "gemm": "k_wave_gemm<double, %d>" % tile,
+            "resid": "k_resid128<%s>" % ("true" if strips else "false"),
+            "gemm": "k_wave_gemm<double, %d>" % tile,
             "solve": "k_solve_r<double, %d, 256>" % tile,
             "proj": "k_proj_run", "proj_out": "k_proj_u"}.get(family)
 
@@ -264,7 +267,8 @@ def main():
     # the reduced-precision modes run their sweeps on FP32 matrix cores, the residual in FP64
     precision = "fp32" if headline in ("mixed", "fp32") and fam in ("flow", "corr", "syl") else "fp64"
     achieved = flops / (ms_k * 1e-3) / 1e12 if ms_k > 0 else 0.0
-    kname = kernel_name(fam, headline, H["info"]["tile"])
+    kname = kernel_name(fam, headline, H["info"]["tile"],
+                        strips=min(args.negatives, n - args.negatives) <= n // 32)
     # the projector substitutions run mostly on FP64 vector FMAs (the chip's FP64 vector
     # and matrix peaks are the same 78.6 TFLOP/s): priced against the ALU peak
     bound = "alu" if fam == "proj" else "mfma"
