@@ -257,7 +257,9 @@ constexpr int GC = 64 / NQ;       // columns per group (one wave)
 constexpr int NU = PB / NQ;       // block-row terms per lane
 constexpr int MPM = kProjMaxMinorityReal;  // minority columns at most (real T)
 constexpr int MAXG = MPM / GC;    // groups at most
-constexpr int CG = 64 / GC;       // groups per 64-column chunk (an owner task's columns)
+constexpr int OC = 32;            // columns of an owner task (a chunk)
+constexpr int CG = OC / GC;       // groups per chunk
+constexpr int NPO = OC / 16;      // 16-column MFMA pieces of a chunk
 constexpr int NT = 256;           // threads of a workgroup (four waves)
 constexpr int TP = PB + 1;        // LDS pitch of the T block, the window values and the panel
 constexpr int ZCP = PB + NQ;      // LDS pitch of a group column (conflict-free column reads)
@@ -348,9 +350,11 @@ struct Win {
 
 // Owner: tasks (row block i, chunk c of CG groups) of basis `beta`, in the order
 // of i, then c, every nown-th one; one task at a time.  A task keeps block i's
-// sums over the blocks j <= i - 2 for the chunk's 64 columns in MFMA
-// accumulators (four waves, each 16 rows x 64 columns: four 16 x 16 pieces, a
-// group's eight columns in half a piece).  The groups run at their own pace and
+// sums over the blocks j <= i - 2 for the chunk's OC columns in MFMA
+// accumulators (four waves, each 16 rows x OC columns: 16 x 16 pieces, a
+// group's eight columns in half a piece).  Chunks of four groups: at the top of
+// the matrix every group publishes a block per block time, and a task serving
+// more groups than that would fall behind (the groups then wait for their sums).  The groups run at their own pace and
 // each is followed on its own: thread 0 takes the lowest block j that some group
 // of the chunk has published and the task has not yet added, with every group
 // that has published it, and the workgroup adds T[block i, block j] Z[block j,
@@ -378,9 +382,9 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
         __syncthreads();  // the previous task's last reads of s_next are done
         if (t < CG) s_next[t] = (t < gn && bst[g0 + t] <= i - 2) ? bst[g0 + t] : i - 1;
         const int64_t r0 = blk_r0(n, i), r1 = blk_r1(n, i);
-        dx4 d[4];
+        dx4 d[NPO];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) d[y] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < NPO; ++y) d[y] = dx4{0.0, 0.0, 0.0, 0.0};
         for (;;) {
             __syncthreads();
             if (t == 0) {
@@ -427,11 +431,11 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
             const int64_t k0 = blk_r0(n, j), k1 = blk_r1(n, j);
             // the step's loads: block j's rows of the groups in the mask (coherent: they
             // were published in this launch), and T's tile [block i, block j]
-            double zb[16], ta[16];
+            double zb[OC / 4], ta[16];
 #pragma unroll
-            for (int x = 0; x < 16; ++x) {
+            for (int x = 0; x < OC / 4; ++x) {
                 const int cl = wv + 4 * x;  // column within the chunk
-                const int col = 64 * c + cl;
+                const int col = OC * c + cl;
                 const bool live = col < m && ((mask >> (cl / GC)) & 1) && k0 + lane < k1;
                 zb[x] = live ? coherent_load(B.Z + (k0 + lane) + (int64_t)col * n) : 0.0;
             }
@@ -447,17 +451,18 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
                                                             : 0.0;
                 }
             }
-            // Bs[kk * OP + cl] = Z[k0 + kk, 64 c + cl]; As[kk * OP + r] = entry (r0 + r, k0 + kk)
+            // Bs[kk * OP + cl] = Z[k0 + kk, OC c + cl]; As[kk * OP + r] = entry (r0 + r, k0 + kk)
+#pragma unroll
+            for (int x = 0; x < OC / 4; ++x) Bs[lane * OP + wv + 4 * x] = zb[x];
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 const int y = wv + 4 * x;
-                Bs[lane * OP + y] = zb[x];
                 if (B.flip) As[lane * OP + y] = ta[x];
                 else As[y * OP + lane] = ta[x];
             }
             __syncthreads();
 #pragma unroll
-            for (int y = 0; y < 4; ++y) {
+            for (int y = 0; y < NPO; ++y) {
                 if (!((mask >> (2 * y)) & 3)) continue;  // no group of this piece (uniform)
                 for (int kk = 0; kk < 64; kk += 4)
                     d[y] = mfma_f64(As[(kk + kr) * OP + rb + cc], Bs[(kk + kr) * OP + 16 * y + cc],
@@ -467,11 +472,11 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
                 // block j is the last below block i: publish the mask's groups' sums
                 // of block i
 #pragma unroll
-                for (int y = 0; y < 4; ++y)
+                for (int y = 0; y < NPO; ++y)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int64_t row = r0 + rb + mfma64_row(lane, e);
-                        const int cl = 16 * y + cc, col = 64 * c + cl;
+                        const int cl = 16 * y + cc, col = OC * c + cl;
                         if (row < r1 && col < m && ((mask >> (cl / GC)) & 1))
                             coherent_store(B.acc + row + (int64_t)col * n, d[y][e]);
                     }
