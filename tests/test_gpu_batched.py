@@ -210,3 +210,30 @@ def test_batched_mixed_graph_replays(dev):
         signtri.sign_tri_batched(Tg, outs=Us, mode="mixed",
                                  options={"force_stall": -1, "no_fallback": 1})
     assert ei.value.code == 4
+
+
+def test_batched_mixed_strips_without_graph(dev):
+    # The timers switch the batched form from its captured graph to direct
+    # launches, which take the host's copy of the signs: matrices whose minority
+    # sign class has at most n / 32 entries then take the residual's entries of
+    # differing signs from strips (the others from the equal-signs tiles), next
+    # to matrices that keep the combined tiles.
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(8700)
+    Ts = []
+    for k, n in enumerate([300, 520, 96, 700, 64, 450]):
+        if k % 2 == 0:
+            s = -np.ones(n) if k == 4 else np.ones(n)
+            pick = rng.choice(n, max(1, n // 40), replace=False)
+            s[pick] = -s[pick]
+        else:
+            s = wl.random_signs(n, rng)
+        Ts.append(wl.make_T(n, rng, signs=s))
+    signtri.profile_enable(True)
+    try:
+        Us, infos, _, _ = run_batch(Ts, dev, mode="mixed")
+    finally:
+        signtri.profile_enable(False)
+    check_all(Ts, Us, TOL_FP64)
+    assert all(i["fallback_tiles"] == 0 for i in infos)
