@@ -493,7 +493,8 @@ __device__ void proj_owner(const ProjArgs &a, const ProjSync &S, double *As, dou
 
 __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
 {
-    __shared__ double arena[3 * PB * TP + GC * ZCP + 2 * PB * ABP + MPM * LFP];
+    __shared__ double arena[3 * PB * TP + GC * ZCP + 3 * PB * ABP + MPM * LFP + 2 * GC * GC];
+    __shared__ int yok;  // the eigenvector form is taken from block by on
     if ((int)blockIdx.x >= 2 * S.G) {
         proj_owner(a, S, arena, arena + PB * OP);
         return;
@@ -509,6 +510,9 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                                            // with the columns of the blocks below
     double *const Cf = Ab + PB * ABP;      // Cf[r * ABP + k]: the coupling with the far columns
     double *const Lf = Cf + PB * ABP;      // Lf[l * LFP + k] = L[l, c0 + k], earlier columns l < c0
+    double *const AbY = Lf + MPM * LFP;    // AbY[r * ABP + k] = (Ab V)[r, k] (eigenvector form)
+    double *const Vg = AbY + PB * ABP;     // Vg[k * GC + l] = V[k, l]: L_gg V = V diag(L_gg)
+    double *const Wg = Vg + GC * GC;       // Wg = V^-1
 
     const int beta = (int)blockIdx.x & 1, g = uniform((int)blockIdx.x >> 1);
     const ProjBasis B = a.b[beta];
@@ -522,6 +526,30 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
     const int t = threadIdx.x, wv = uniform(t >> 6);
     const bool fl = B.flip != 0;
     int *const zdone = S.zdone + (beta * S.G + g) * S.nb;
+    // The eigenvector form.  Above the group's topmost minority row (b_c0, in
+    // block by - 1) the group's block L_gg of L is final; with L_gg V = V Lambda
+    // (V unit upper triangular, Lambda its diagonal, the group's minority
+    // eigenvalues), Y = Z_g V satisfies row by row
+    //   (t_ii - lambda_l) y_il = (d V)_l,
+    // d the coupling with the other columns minus the sums over the rows below:
+    // the columns no longer couple to one another, so the chain of the row step
+    // drops out.  In those blocks the group's sums Ab enter as Ab V, the walk
+    // keeps Y in Zc and the near window's coefficients as L[l', g] V, and both go
+    // back with V^-1 after the block.  Taken only when V is well conditioned
+    // (max |V| max |V^-1| <= 1e3; distinct minority eigenvalues), else the
+    // substitution keeps its chain to the top.
+    const int by = uniform(B.pos[c0] >= 0 ? (int)((n - 1 - B.pos[c0]) / PB) + 1 : S.nb);
+    if (t == 0) yok = 0;
+    // Ab V into AbY (all waves, between the boundary's third and fourth barriers)
+    auto ab_to_y = [&]() {
+        for (int e = t; e < PB * GC; e += NT) {
+            const int r = e >> 3, l = e & 7;
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < GC; ++k) v = fma(Ab[r * ABP + k], Vg[k * GC + l], v);
+            AbY[r * ABP + l] = v;
+        }
+    };
 
     // The earlier columns by where their minority row lies: in block b (near), in
     // block b - 1 (prev), further down (far).  Columns are ordered by their row,
@@ -721,6 +749,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             __syncthreads();  // (3)
             for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
             put_win(b, near(b), hN, have_c, false);
+            if (b >= by && uniform(yok) != 0) ab_to_y();
             __syncthreads();  // (4)
             have_c = have_a = false;
             if (b + 1 < S.nb) {
@@ -778,6 +807,8 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         if (b > bs) below_product(b);
         __syncthreads();  // (3)
         for (int e = t; e < GC * ZCP; e += NT) Zc[e] = 0.0;
+        const bool yf = b >= by && uniform(yok) != 0;  // the eigenvector form (uniform)
+        if (yf) ab_to_y();
         __syncthreads();  // (4)
 #pragma unroll
         for (int u = 0; u < NU; ++u) lreg[u] = 0.0;
@@ -801,9 +832,10 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         // barrier.
         const int plr = pl < r0 ? -1 : (int)(pl - r0 < PB ? pl - r0 : PB);
         const int rhi = kw < cw ? (plr < nr - 1 ? plr : nr - 1) : -1;  // last row it computes
-        auto front = [&](auto gtag, auto guardtag) {
+        auto front = [&](auto gtag, auto guardtag, auto ytag) {
         constexpr int NCU = decltype(gtag)::value;  // coupling chunks: the near window's
         constexpr bool GUARD = decltype(guardtag)::value;  // reciprocals checked for range
+        constexpr bool YF = decltype(ytag)::value;  // the eigenvector form: no chain
         // Row r's prepared state: dpart = coupling - sum without row r + 1's term,
         // tnext = t[r][r+1] (that term's coefficient; 0 when already included or
         // outside the block), t_rr and 1 / (t_rr - L[l, l]).
@@ -830,7 +862,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             const double tn = trow[r + 1 < PB ? r + 1 : r];
             P.tnext = (!included && r + 1 < nr) ? tn : 0.0;
             // (the group's sum of the row, read by all the column's lanes: a broadcast)
-            const double ab = Ab[r * ABP + kw];
+            const double ab = (YF ? AbY : Ab)[r * ABP + kw];
             // 1 / (t_ii - L[l, l]): the hardware estimate (relative error below 5e-8)
             // and one Newton step, which squares it (below 2.3e-15).  The signs of
             // t_ii and L[l, l] differ, so |dx| >= min |t_kk| and |dx| <= 2 max |t_kk|;
@@ -885,8 +917,10 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
 #pragma unroll
             for (int kp = 0; kp < GC - 1; ++kp) lwr[kp] = lw[kp] * Pc.rcp;
             double z = act ? d * Pc.rcp : 0.0;
+            if constexpr (!YF) {
 #pragma unroll
-            for (int kp = 0; kp < GC - 1; ++kp) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+                for (int kp = 0; kp < GC - 1; ++kp) z = fma(readlane_f64(z, kp * NQ), lwr[kp], z);
+            }
             const int typ = __builtin_amdgcn_readlane(rtl, r);
             const bool minority = typ >= 0;  // (uniform)
             if (minority) {
@@ -931,43 +965,41 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         if (s2 < nr) step(nr - 1 - s2, P0, P1);
         };
         static_assert(NU == 8, "one instance per chunk count");
+        // (one instance per chunk count, reciprocal check and form)
+        auto front2 = [&](auto gtag) {
+            if (S.rcp_guard) {
+                if (yf) front(gtag, std::true_type{}, std::true_type{});
+                else front(gtag, std::true_type{}, std::false_type{});
+            } else {
+                if (yf) front(gtag, std::false_type{}, std::true_type{});
+                else front(gtag, std::false_type{}, std::false_type{});
+            }
+        };
         switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
-            case 0:
-                if (S.rcp_guard) front(std::integral_constant<int, 0>{}, std::true_type{});
-                else front(std::integral_constant<int, 0>{}, std::false_type{});
-                break;
-            case 1:
-                if (S.rcp_guard) front(std::integral_constant<int, 1>{}, std::true_type{});
-                else front(std::integral_constant<int, 1>{}, std::false_type{});
-                break;
-            case 2:
-                if (S.rcp_guard) front(std::integral_constant<int, 2>{}, std::true_type{});
-                else front(std::integral_constant<int, 2>{}, std::false_type{});
-                break;
-            case 3:
-                if (S.rcp_guard) front(std::integral_constant<int, 3>{}, std::true_type{});
-                else front(std::integral_constant<int, 3>{}, std::false_type{});
-                break;
-            case 4:
-                if (S.rcp_guard) front(std::integral_constant<int, 4>{}, std::true_type{});
-                else front(std::integral_constant<int, 4>{}, std::false_type{});
-                break;
-            case 5:
-                if (S.rcp_guard) front(std::integral_constant<int, 5>{}, std::true_type{});
-                else front(std::integral_constant<int, 5>{}, std::false_type{});
-                break;
-            case 6:
-                if (S.rcp_guard) front(std::integral_constant<int, 6>{}, std::true_type{});
-                else front(std::integral_constant<int, 6>{}, std::false_type{});
-                break;
-            case 7:
-                if (S.rcp_guard) front(std::integral_constant<int, 7>{}, std::true_type{});
-                else front(std::integral_constant<int, 7>{}, std::false_type{});
-                break;
-            default:
-                if (S.rcp_guard) front(std::integral_constant<int, 8>{}, std::true_type{});
-                else front(std::integral_constant<int, 8>{}, std::false_type{});
-                break;
+            case 0: front2(std::integral_constant<int, 0>{}); break;
+            case 1: front2(std::integral_constant<int, 1>{}); break;
+            case 2: front2(std::integral_constant<int, 2>{}); break;
+            case 3: front2(std::integral_constant<int, 3>{}); break;
+            case 4: front2(std::integral_constant<int, 4>{}); break;
+            case 5: front2(std::integral_constant<int, 5>{}); break;
+            case 6: front2(std::integral_constant<int, 6>{}); break;
+            case 7: front2(std::integral_constant<int, 7>{}); break;
+            default: front2(std::integral_constant<int, 8>{}); break;
+        }
+        const int lane = t & 63;
+        if (yf) {
+            // the block's rows back from Y to Z = Y V^-1 (lane i: row i; V^-1 unit upper)
+            double yv[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) yv[k] = Zc[k * ZCP + lane];
+#pragma unroll
+            for (int l = 0; l < GC; ++l) {
+                double v = yv[l];
+#pragma unroll
+                for (int k = 0; k < l; ++k) v = fma(yv[k], Wg[k * GC + l], v);
+                Zc[l * ZCP + lane] = v;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
         store_rows(b);
         // the near window's coefficients, for the products of the blocks above
@@ -976,6 +1008,77 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         for (int u = 0; u < NU; ++u) {
             const int c = NQ * u + q;
             if (c < nw.cnt) Lf[(nw.lo + c) * LFP + kw] = lreg[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (yf && lane < nw.cnt) {
+            // L[l', g] V back to L[l', g] (lane c: window column lo + c)
+            double lv[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) lv[k] = Lf[(nw.lo + lane) * LFP + k];
+#pragma unroll
+            for (int l = 0; l < GC; ++l) {
+                double v = lv[l];
+#pragma unroll
+                for (int k = 0; k < l; ++k) v = fma(lv[k], Wg[k * GC + l], v);
+                Lf[(nw.lo + lane) * LFP + l] = v;
+            }
+        }
+        if (b == by - 1 && by < S.nb) {
+            // L_gg is final: V (L_gg V = V Lambda, unit upper), V^-1, and whether
+            // the form is well conditioned.  L_gg goes through Wg; column kw of V and
+            // of V^-1 in the registers of column kw's lanes.
+            if (q == 0)
+#pragma unroll
+                for (int kp = 0; kp < GC; ++kp)
+                    Wg[kp * GC + kw] = kp < kw ? lw[kp] : (kp == kw ? lamll : 0.0);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const bool on = kw < cw;
+            double vc[GC], wc[GC];
+#pragma unroll
+            for (int k = 0; k < GC; ++k) vc[k] = k == kw ? 1.0 : 0.0;
+            const double lam = Wg[kw * GC + kw];
+#pragma unroll
+            for (int k = GC - 2; k >= 0; --k) {
+                double sum = 0.0;
+#pragma unroll
+                for (int j = k + 1; j < GC; ++j) sum = fma(Wg[k * GC + j], vc[j], sum);
+                if (on && k < kw) vc[k] = sum / (lam - Wg[k * GC + k]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (q == 0)
+#pragma unroll
+                for (int k = 0; k < GC; ++k) Vg[k * GC + kw] = vc[k];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int k = 0; k < GC; ++k) wc[k] = k == kw ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = GC - 2; k >= 0; --k) {
+                double sum = 0.0;
+#pragma unroll
+                for (int j = k + 1; j < GC; ++j) sum = fma(Vg[k * GC + j], wc[j], sum);
+                if (on && k < kw) wc[k] = -sum;
+            }
+            double vmax = 0.0, wmax = 0.0;
+#pragma unroll
+            for (int k = 0; k < GC; ++k) {
+                vmax = fmax(vmax, fabs(vc[k]));  // (fmax drops a NaN: tested below)
+                wmax = fmax(wmax, fabs(wc[k]));
+            }
+            bool fin = true;
+#pragma unroll
+            for (int k = 0; k < GC; ++k) fin = fin && isfinite(vc[k]) && isfinite(wc[k]);
+            const bool good = __builtin_amdgcn_ballot_w64(!(fin && vmax * wmax <= 1e3)) == 0;
+            double vm = vmax, wm = wmax;
+#pragma unroll
+            for (int kp = 0; kp < GC; ++kp) {
+                vm = fmax(vm, readlane_f64(vmax, kp * NQ));
+                wm = fmax(wm, readlane_f64(wmax, kp * NQ));
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (q == 0)
+#pragma unroll
+                for (int k = 0; k < GC; ++k) Wg[k * GC + kw] = wc[k];
+            if (t == 0) yok = (good && vm * wm <= 1e3) ? 1 : 0;
         }
     }
     __syncthreads();

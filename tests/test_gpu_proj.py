@@ -342,3 +342,31 @@ def test_proj_wide_auto_and_repeat(dev):
     assert np.array_equal(U1, U2)
     assert rel_fro(U1, oracle.sign_tri(T)) <= TOL_FP64
 
+
+
+# Above a group's topmost minority row the substitution runs in the basis of
+# the eigenvectors of the group's block of L (no coupling chain), when they are
+# well conditioned; with equal or nearly equal minority eigenvalues, or a
+# strongly coupled block, it keeps the chain.  Every case matches the oracle.
+@pytest.mark.parametrize("kind", ["repeated", "near", "cluster", "spread", "strong"])
+def test_proj_eigenvector_form_and_fallback(dev, kind):
+    import oracle
+
+    n, m = 700, 16
+    rng = np.random.default_rng(9100)
+    where = np.sort(rng.choice(n, size=m, replace=False))
+    T = skewed(n, m, 9100, -1, where)
+    d = np.diag(T).copy()
+    if kind == "repeated":
+        d[where] = -1.0
+    elif kind == "near":
+        d[where] = -1.0 - 1e-9 * np.arange(m)
+    elif kind == "cluster":
+        d[where] = -1.0 - 0.02 * np.arange(m)
+    elif kind == "strong":
+        T = T + np.triu(rng.standard_normal((n, n)), 1) * 0.5
+    T[np.arange(n), np.arange(n)] = d
+    U, info = run_gpu(T, dev, algo="proj")
+    assert info["path_name"] == "proj", info
+    err = rel_fro(U, oracle.sign_tri(T))
+    assert err <= TOL_FP64, (kind, err)
