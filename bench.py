@@ -56,13 +56,19 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_name(family, mode, tile, strips=False):
+def kernel_name(family, mode, tile, strips=False, wgs_per_cu=0):
     """The kernel behind one of the library's timer families, as rocprofv3 names it
     (strips: a minority sign class of at most n/32 entries, whose residual runs on
-    the equal-signs tiles plus strips)."""
+    the equal-signs tiles plus strips; wgs_per_cu: the sweep's grid, which picks
+    the build of the real sweep kernels fitting three FP64 or four FP32
+    workgroups per compute unit)."""
     fp = "double" if mode == "fp64" else "float"
-    return {"flow": "k_flow<%s, 0, false>" % fp, "corr": "k_flow<float, 1, false>",
-            "syl": "k_flow<%s, 2, false>" % fp,
+    w64 = 3 if wgs_per_cu >= 3 else 0
+    w32 = 4 if wgs_per_cu >= 4 else 0
+    wf = w64 if fp == "double" else w32
+    return {"flow": "k_flow<%s, 0, false, %d>" % (fp, wf),
+            "corr": "k_flow<float, 1, false, %d>" % w32,
+            "syl": "k_flow<%s, 2, false, %d>" % (fp, wf),
             "resid": "k_resid128<%s>" % ("true" if strips else "false"),
             "gemm": "k_wave_gemm<double, %d>" % tile,
             "solve": "k_solve_r<double, %d, 256>" % tile,
@@ -268,7 +274,8 @@ def main():
     precision = "fp32" if headline in ("mixed", "fp32") and fam in ("flow", "corr", "syl") else "fp64"
     achieved = flops / (ms_k * 1e-3) / 1e12 if ms_k > 0 else 0.0
     kname = kernel_name(fam, headline, H["info"]["tile"],
-                        strips=min(args.negatives, n - args.negatives) <= n // 32)
+                        strips=min(args.negatives, n - args.negatives) <= n // 32,
+                        wgs_per_cu=H["info"]["wgs_per_cu"])
     # the projector substitutions run mostly on FP64 vector FMAs (the chip's FP64 vector
     # and matrix peaks are the same 78.6 TFLOP/s): priced against the ALU peak
     bound = "alu" if fam == "proj" else "mfma"

@@ -129,8 +129,18 @@ __device__ inline void cmma(F ar, F ai, F br, F bi, A &cr, A &ci)
 
 // C selects complex entries: every array then holds interleaved (re, im)
 // pairs and every leading dimension counts complex elements.
-template <typename F, int KIND, bool C>
-__global__ __launch_bounds__(NT) void k_flow(FlowArgs<F> a)
+// Two builds of the real kernels: as the compiler allocates registers (two
+// workgroups per compute unit for FP64, three for FP32), and within the
+// registers of one more workgroup (WPE waves per SIMD; the LDS allows it, the
+// few values spilled for it are read once per block, outside the K and solve
+// loops).  The launch takes the second when the grid asks for that many.
+template <typename F, bool C> struct FlowWaves { static constexpr int value = 0; };
+template <> struct FlowWaves<double, false> { static constexpr int value = 3; };
+template <> struct FlowWaves<float, false> { static constexpr int value = 4; };
+
+template <typename F, int KIND, bool C, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_flow(FlowArgs<F> a)
 {
     typedef typename mm<F>::acc acc_t;
     constexpr bool CORR = KIND == FLOW_CORR;
@@ -847,7 +857,7 @@ struct FlowFit {
 };
 
 // Compute units of the current device and resident workgroups of this kernel per unit.
-template <typename F, int KIND, bool C> static FlowFit flow_fit()
+template <typename F, int KIND, bool C, int WPE> static FlowFit flow_fit()
 {
     FlowFit f;
     int dev = 0;
@@ -855,17 +865,28 @@ template <typename F, int KIND, bool C> static FlowFit flow_fit()
         hipDeviceGetAttribute(&f.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         f.cus <= 0)
         f.cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.per, k_flow<F, KIND, C>, NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.per, k_flow<F, KIND, C, WPE>, NT, 0) !=
             hipSuccess ||
         f.per <= 0)
         f.per = 1;
     return f;
 }
 
-template <typename F, int KIND, bool C> static const FlowFit &flow_fit_cached()
+template <typename F, int KIND, bool C, int WPE> static const FlowFit &flow_fit_cached()
 {
-    static const FlowFit f = flow_fit<F, KIND, C>();
+    static const FlowFit f = flow_fit<F, KIND, C, WPE>();
     return f;
+}
+
+// Resident workgroups per compute unit: of the build as allocated (lo) and the
+// most of any build (hi).
+template <typename F, int KIND, bool C> static int flow_per(bool hi)
+{
+    const int lo = flow_fit_cached<F, KIND, C, 0>().per;
+    if constexpr (FlowWaves<F, C>::value > 0) {
+        if (hi) return std::max(lo, flow_fit_cached<F, KIND, C, FlowWaves<F, C>::value>().per);
+    }
+    return lo;
 }
 
 // The persistent grid: wgs_per_cu workgroups on every compute unit (0, or more
@@ -875,10 +896,18 @@ template <typename F, int KIND, bool C>
 hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st)
 {
     if (a.ntasks <= 0) return hipSuccess;
-    const FlowFit &f = flow_fit_cached<F, KIND, C>();
-    const int per = (wgs_per_cu > 0 && wgs_per_cu < f.per) ? wgs_per_cu : f.per;
-    const int g = std::min(f.cus * per, a.ntasks);
-    hipLaunchKernelGGL((k_flow<F, KIND, C>), dim3(g), dim3(NT), 0, st, a);
+    const int cus = flow_fit_cached<F, KIND, C, 0>().cus;
+    const int lo = flow_per<F, KIND, C>(false), hi = flow_per<F, KIND, C>(true);
+    const int per = (wgs_per_cu > 0 && wgs_per_cu < hi) ? wgs_per_cu : hi;
+    const int g = std::min(cus * per, a.ntasks);
+    if constexpr (FlowWaves<F, C>::value > 0) {
+        if (per > lo) {
+            hipLaunchKernelGGL((k_flow<F, KIND, C, FlowWaves<F, C>::value>), dim3(g), dim3(NT), 0,
+                               st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_flow<F, KIND, C, 0>), dim3(g), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -886,18 +915,18 @@ int flow_max_wgs_per_cu(bool fp32, bool cplx)
 {
     if (cplx) {
         if (fp32)
-            return std::min({flow_fit_cached<float, FLOW_MAIN, true>().per,
-                             flow_fit_cached<float, FLOW_CORR, true>().per,
-                             flow_fit_cached<float, FLOW_SYL, true>().per});
-        return std::min(flow_fit_cached<double, FLOW_MAIN, true>().per,
-                        flow_fit_cached<double, FLOW_SYL, true>().per);
+            return std::min({flow_per<float, FLOW_MAIN, true>(true),
+                             flow_per<float, FLOW_CORR, true>(true),
+                             flow_per<float, FLOW_SYL, true>(true)});
+        return std::min(flow_per<double, FLOW_MAIN, true>(true),
+                        flow_per<double, FLOW_SYL, true>(true));
     }
     if (fp32)
-        return std::min({flow_fit_cached<float, FLOW_MAIN, false>().per,
-                         flow_fit_cached<float, FLOW_CORR, false>().per,
-                         flow_fit_cached<float, FLOW_SYL, false>().per});
-    return std::min(flow_fit_cached<double, FLOW_MAIN, false>().per,
-                    flow_fit_cached<double, FLOW_SYL, false>().per);
+        return std::min({flow_per<float, FLOW_MAIN, false>(true),
+                         flow_per<float, FLOW_CORR, false>(true),
+                         flow_per<float, FLOW_SYL, false>(true)});
+    return std::min(flow_per<double, FLOW_MAIN, false>(true),
+                    flow_per<double, FLOW_SYL, false>(true));
 }
 
 #define SGT_FLOW(F, K, C) \

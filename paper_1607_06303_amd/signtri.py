@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+from collections.abc import Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # SIGNTRI_LIB: another build of the same library (the host-sanitizer build of
@@ -339,36 +340,66 @@ def autotune_batched(Ts, mode: str = "fp64", reps: int = 3, outs=None, stream=No
     return best.as_dict()
 
 
+class InfoList(Sequence):
+    """The infos of a batched call, each turned into a dict when it is read (a
+    batch of thousands of matrices would otherwise spend milliseconds on dicts
+    nobody reads)."""
+
+    def __init__(self, infos):
+        self._infos = infos
+
+    def __len__(self):
+        return len(self._infos)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self._infos[k].as_dict() for k in range(*i.indices(len(self._infos)))]
+        return self._infos[i].as_dict()
+
+
 def sign_tri_batched(Ts, mode: str = "fp64", outs=None, workspace=None, stream=None,
                      options: dict | None = None):
     """Batched form: list of square upper-triangular tensors (same dtype, device
-    and storage order).  Returns (list of U, list of info dicts)."""
+    and storage order).  Returns (list of U, sequence of info dicts)."""
     if not Ts:
         return [], []
     dt = _dtype_code(Ts[0])
-    layouts = [_layout(t) if t.shape[0] else (COL_MAJOR, 1) for t in Ts]
-    if any(l is None for l in layouts):
-        raise ValueError("every T must be column- or row-major strided")
-    nonempty = [l for t, l in zip(Ts, layouts) if t.shape[0] > 1]
-    layout = nonempty[0][0] if nonempty else COL_MAJOR
     Us = outs if outs is not None else [empty_like_layout(t) for t in Ts]
     B = len(Ts)
-    P = ctypes.c_void_p * B
-    I = ctypes.c_int64 * B
-    tp = P(*[t.data_ptr() if t.shape[0] else None for t in Ts])
-    up = P(*[u.data_ptr() if u.shape[0] else None for u in Us])
-    ldt = I(*[l[1] for l in layouts])
-    ldu = I(*[_layout(u)[1] if u.shape[0] else 1 for u in Us])
-    ns = I(*[t.shape[0] for t in Ts])
+    if len(Us) != B:
+        raise ValueError("outs must hold one tensor per T")
+    tp, up = (ctypes.c_void_p * B)(), (ctypes.c_void_p * B)()
+    ldt, ldu, ns = (ctypes.c_int64 * B)(), (ctypes.c_int64 * B)(), (ctypes.c_int64 * B)()
+    layout = None
+    # one pass over the tensors: each attribute read costs a fraction of a
+    # microsecond, which adds up over a large batch
+    for b in range(B):
+        t, u = Ts[b], Us[b]
+        n = t.shape[0]
+        ns[b] = n
+        if n == 0:
+            ldt[b] = ldu[b] = 1
+            continue
+        lt, lu = _layout(t), _layout(u)
+        if lt is None or lu is None:
+            raise ValueError("every T and U must be column- or row-major strided")
+        if n > 1:
+            if layout is None:
+                layout = lt[0]
+            if lt[0] != layout or lu[0] != layout:
+                raise ValueError("every T and U of more than one row must share one storage order")
+        tp[b], up[b] = t.data_ptr(), u.data_ptr()
+        ldt[b], ldu[b] = lt[1], lu[1]
     infos = (Info * B)()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-    rc = lib().signtri_batched(tp, ldt, up, ldu, ns, B, dt, layout, MODES[mode], ws_ptr,
+    rc = lib().signtri_batched(tp, ldt, up, ldu, ns, B, dt,
+                               COL_MAJOR if layout is None else layout, MODES[mode], ws_ptr,
                                ws_bytes, _stream_handle(Ts[0], stream), _opts(options), infos)
     if rc != 0:
         raise SignTriError(rc, strerror(rc))
-    return Us, [infos[b].as_dict() for b in range(B)]
+    return Us, InfoList(infos)
 
 
 def release() -> None:
