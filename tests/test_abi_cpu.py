@@ -248,6 +248,32 @@ def test_batched_argument_validation_without_device_work():
     assert call(T, ld, U, ld, n, 2, lay=1) == 5
 
 
+def test_batched_binding_marshalling_checks():
+    # rejected by the binding before any library call (host tensors suffice)
+    import torch
+
+    col = torch.zeros(3, 3, dtype=torch.float64).t()
+    row = torch.zeros(3, 3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="storage order"):
+        signtri.sign_tri_batched([col, row])
+    with pytest.raises(ValueError, match="one tensor per T"):
+        signtri.sign_tri_batched([col], outs=[])
+    strided = torch.zeros(3, 6, dtype=torch.float64)[:, ::2]
+    with pytest.raises(ValueError, match="strided"):
+        signtri.sign_tri_batched([strided])
+
+
+def test_batched_info_list_converts_on_read():
+    infos = (signtri.Info * 3)()
+    infos[1].path = 3
+    infos[2].n_neg = 7
+    lst = signtri.InfoList(infos)
+    assert len(lst) == 3
+    assert lst[1]["path_name"] == "proj" and lst[-1]["n_neg"] == 7
+    assert [d["path"] for d in lst] == [0, 3, 0]
+    assert [d["n_neg"] for d in lst[1:]] == [0, 7]
+
+
 def test_batched_workspace_size():
     I = ctypes.c_int64 * 3
     L = signtri.lib()
