@@ -164,8 +164,11 @@ typedef struct {
                                     when 0                                               */
     int32_t sweep;               /* SIGNTRI_SWEEP_*; 0 = tuned choice or default           */
     int32_t wgs_per_cu;          /* dataflow sweep: persistent workgroups per compute unit,
-                                    0 = tuned choice, else as many as fit; values above
-                                    what fits are clamped to it                          */
+                                    0 = tuned choice, else as many as fit with the
+                                    registers the compiler gives the sweep (a batch: as
+                                    many as fit at all); a value above that takes the
+                                    sweep's build for one more workgroup per compute unit
+                                    (real T), values above what fits are clamped to it  */
     int32_t products;            /* off-diagonal block products of the dataflow sweeps
                                     (Section 5's accumulators X and Y): SIGNTRI_PRODUCTS_*;
                                     other values -13                                     */

@@ -126,8 +126,10 @@ signtri_options resolve_options(const signtri_options *opts, signtri_dtype dtype
     if (o.sweep == 0) o.sweep = o.tile == 64 ? SIGNTRI_SWEEP_SUPERDIAG : SIGNTRI_SWEEP_DATAFLOW;
     if (o.tile == 0) o.tile = 32;
     if (o.sweep == SIGNTRI_SWEEP_DATAFLOW) {
-        const int mx = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, dtype == SIGNTRI_C128);
-        if (o.wgs_per_cu <= 0 || o.wgs_per_cu > mx) o.wgs_per_cu = mx;
+        const bool f32 = mode != SIGNTRI_FP64, cx = dtype == SIGNTRI_C128;
+        const int mx = flow_max_wgs_per_cu(f32, cx);
+        if (o.wgs_per_cu <= 0) o.wgs_per_cu = flow_default_wgs_per_cu(f32, cx);
+        if (o.wgs_per_cu > mx) o.wgs_per_cu = mx;
     } else {
         o.wgs_per_cu = 0;
     }
@@ -646,7 +648,7 @@ int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, sig
         // no captured graph: the dataflow sweep, whatever the tuning table recorded
         eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
         eo.tile = 32;
-        eo.wgs_per_cu = flow_max_wgs_per_cu(false, cplx);
+        eo.wgs_per_cu = flow_default_wgs_per_cu(false, cplx);
     }
     if (path == SIGNTRI_PATH_PS && eo.sweep != SIGNTRI_SWEEP_DATAFLOW) {
         // the Sylvester form runs on the dataflow sweeps only
@@ -657,7 +659,7 @@ int signtri_run(const void *T, int64_t ldt, void *U, int64_t ldu, int64_t n, sig
         } else {
             eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
             eo.tile = 32;
-            eo.wgs_per_cu = flow_max_wgs_per_cu(mode != SIGNTRI_FP64, cplx);
+            eo.wgs_per_cu = flow_default_wgs_per_cu(mode != SIGNTRI_FP64, cplx);
         }
     }
     const bool flow = eo.sweep == SIGNTRI_SWEEP_DATAFLOW;
@@ -765,7 +767,7 @@ int signtri_fun_run(const void *T, int64_t ldt, const void *fdiag, void *F, int6
     std::memset(&eo, 0, sizeof(eo));
     eo.sweep = SIGNTRI_SWEEP_DATAFLOW;
     eo.tile = 32;
-    eo.wgs_per_cu = flow_max_wgs_per_cu(false, cplx);
+    eo.wgs_per_cu = flow_default_wgs_per_cu(false, cplx);
     std::vector<RealItem> items(1);
     RealItem &it = items[0];
     it.T = (const double *)T;

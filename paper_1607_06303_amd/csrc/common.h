@@ -440,6 +440,7 @@ hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st);
 // Most workgroups per compute unit that fit, over the sweeps of one precision
 // (wgs_per_cu above a kernel's own limit is clamped at launch).
 int flow_max_wgs_per_cu(bool fp32, bool cplx);
+int flow_default_wgs_per_cu(bool fp32, bool cplx);
 hipError_t launch_fill_int(int *p, int64_t n, int v, hipStream_t st);
 hipError_t launch_tasks_tri(int nb, int mat, int2 *out, hipStream_t st);
 hipError_t launch_tasks_rect(int nbr, int nbc, int mat, int2 *out, hipStream_t st);

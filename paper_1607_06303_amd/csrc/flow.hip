@@ -889,16 +889,17 @@ template <typename F, int KIND, bool C> static int flow_per(bool hi)
     return lo;
 }
 
-// The persistent grid: wgs_per_cu workgroups on every compute unit (0, or more
-// than fit: as many as fit), never more than there are tasks.  Tasks are taken
-// by ticket in dependency order, so any grid size is deadlock-free.
+// The persistent grid: wgs_per_cu workgroups on every compute unit (0: as many
+// as the first build fits; more than any build fits: as many as fit), never
+// more than there are tasks.  Tasks are taken by ticket in dependency order, so
+// any grid size is deadlock-free.
 template <typename F, int KIND, bool C>
 hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st)
 {
     if (a.ntasks <= 0) return hipSuccess;
     const int cus = flow_fit_cached<F, KIND, C, 0>().cus;
     const int lo = flow_per<F, KIND, C>(false), hi = flow_per<F, KIND, C>(true);
-    const int per = (wgs_per_cu > 0 && wgs_per_cu < hi) ? wgs_per_cu : hi;
+    const int per = wgs_per_cu <= 0 ? lo : std::min(wgs_per_cu, hi);
     const int g = std::min(cus * per, a.ntasks);
     if constexpr (FlowWaves<F, C>::value > 0) {
         if (per > lo) {
@@ -911,23 +912,31 @@ hipError_t launch_flow(const FlowArgs<F> &a, int wgs_per_cu, hipStream_t st)
     return hipGetLastError();
 }
 
-int flow_max_wgs_per_cu(bool fp32, bool cplx)
+// Workgroups per compute unit: the most any build of a mode's sweeps fits (hi,
+// the autotuner's range and the batched form's default), or the most the first
+// build fits (the default of a single call, whose large blocks gain nothing
+// from the second build's extra workgroup).
+static int flow_wgs_per_cu(bool fp32, bool cplx, bool hi)
 {
     if (cplx) {
         if (fp32)
-            return std::min({flow_per<float, FLOW_MAIN, true>(true),
-                             flow_per<float, FLOW_CORR, true>(true),
-                             flow_per<float, FLOW_SYL, true>(true)});
-        return std::min(flow_per<double, FLOW_MAIN, true>(true),
-                        flow_per<double, FLOW_SYL, true>(true));
+            return std::min({flow_per<float, FLOW_MAIN, true>(hi),
+                             flow_per<float, FLOW_CORR, true>(hi),
+                             flow_per<float, FLOW_SYL, true>(hi)});
+        return std::min(flow_per<double, FLOW_MAIN, true>(hi),
+                        flow_per<double, FLOW_SYL, true>(hi));
     }
     if (fp32)
-        return std::min({flow_per<float, FLOW_MAIN, false>(true),
-                         flow_per<float, FLOW_CORR, false>(true),
-                         flow_per<float, FLOW_SYL, false>(true)});
-    return std::min(flow_per<double, FLOW_MAIN, false>(true),
-                    flow_per<double, FLOW_SYL, false>(true));
+        return std::min({flow_per<float, FLOW_MAIN, false>(hi),
+                         flow_per<float, FLOW_CORR, false>(hi),
+                         flow_per<float, FLOW_SYL, false>(hi)});
+    return std::min(flow_per<double, FLOW_MAIN, false>(hi),
+                    flow_per<double, FLOW_SYL, false>(hi));
 }
+
+int flow_max_wgs_per_cu(bool fp32, bool cplx) { return flow_wgs_per_cu(fp32, cplx, true); }
+
+int flow_default_wgs_per_cu(bool fp32, bool cplx) { return flow_wgs_per_cu(fp32, cplx, false); }
 
 #define SGT_FLOW(F, K, C) \
     template hipError_t launch_flow<F, K, C>(const FlowArgs<F> &, int, hipStream_t);
