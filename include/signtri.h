@@ -263,6 +263,38 @@ size_t signtri_batched_workspace_size(const int64_t *n, int64_t batch,
                                       signtri_dtype dtype, signtri_mode mode);
 
 /*
+ * sign(A) for general square matrices of small order (Section 1: a complex
+ * Schur decomposition A = Q T Q*, the first step of Algorithm 3, then
+ * U = sign(T) by Algorithm 3's substitution, then sign(A) = Q U Q*).  Each
+ * matrix is reduced on one wave with its Hessenberg/Schur form and Q in LDS:
+ * Householder reduction to Hessenberg form, the shifted QR iteration (implicit
+ * single shifts, plane rotations) to the Schur form, Algorithm 3 on T, and the
+ * two products.  FP64 / complex128 throughout.
+ *   A, lda      host array of `batch` device pointers (column-major inputs, read
+ *               only) and their leading dimensions
+ *   S, lds      host array of device pointers to the outputs (n x n, column-major,
+ *               same dtype as A; a real A gets a real sign(A)); must not overlap A
+ *   n           host array of orders, 0 .. 64 (0: nothing done)
+ *   dtype       SIGNTRI_R64 or SIGNTRI_C128 for every matrix
+ *   stream      HIP stream (NULL: the default stream); the call waits for it
+ *   status      optional host array of `batch` codes: SIGNTRI_OK, SIGNTRI_EDOMAIN
+ *               (an eigenvalue on the imaginary axis, i.e. with |Re t_ii| at most
+ *               n u ||A||_F in the computed Schur form (u = 2^-52), where rounding
+ *               decides its sign, or a non-finite entry met on the way: that S is
+ *               left untouched), SIGNTRI_ENOCONV (the QR iteration
+ *               did not reach the Schur form within 30 max(10, n) sweeps: S left
+ *               untouched)
+ * Returns SIGNTRI_OK, the first failing matrix's code (in batch order),
+ * SIGNTRI_ENOTSUP for an order above 64, SIGNTRI_ENOMEM, SIGNTRI_EHIP, or -p for
+ * argument p (-3 also when some S overlaps its A).  sign(A) is ill-conditioned
+ * when eigenvalues lie near the imaginary axis (Section 1): the result is then
+ * as accurate as that conditioning allows, and nothing checks it.
+ */
+int signtri_signm_batched(const void *const *A, const int64_t *lda, void *const *S,
+                          const int64_t *lds, const int64_t *n, int64_t batch,
+                          signtri_dtype dtype, void *stream, int32_t *status);
+
+/*
  * The entry point that allocates nothing: for callers that cannot allocate
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation).  Computes what signtri() computes for FP64 mode,

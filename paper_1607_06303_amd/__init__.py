@@ -8,6 +8,7 @@ from .signtri import (  # noqa: F401
     SignTriError,
     plan_host,
     release,
+    sign_general_batched,
     sign_tri,
     sign_tri_batched,
     strerror,

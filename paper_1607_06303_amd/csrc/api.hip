@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "common.h"
+#include "signm.h"
 
 using namespace sgt;
 
@@ -966,6 +967,76 @@ int signtri_batched(const void *const *T, const int64_t *ldt, void *const *U, co
     if (mode == SIGNTRI_MIXED_REFINED) return refine_finish(items, &eo, run_dev, run_host, st);
     return sweep_error(run_dev, ns.data(), (int)ns.size(), mode != SIGNTRI_FP64, cplx, run_host, st,
                        nullptr);
+}
+
+int signtri_signm_batched(const void *const *A, const int64_t *lda, void *const *S,
+                          const int64_t *lds, const int64_t *n, int64_t batch,
+                          signtri_dtype dtype, void *stream, int32_t *status)
+{
+    if (batch > 0 && !A) return -1;
+    if (batch > 0 && !lda) return -2;
+    if (batch > 0 && !S) return -3;
+    if (batch > 0 && !lds) return -4;
+    if (batch > 0 && !n) return -5;
+    if (batch < 0 || batch > (1 << 24)) return -6;
+    if (dtype != SIGNTRI_R64 && dtype != SIGNTRI_C128) return -7;
+    const size_t es = dtype == SIGNTRI_C128 ? 16 : 8;
+    for (int64_t b = 0; b < batch; ++b) {
+        if (status) status[b] = SIGNTRI_OK;
+        if (n[b] < 0) return -5;
+        if (n[b] > 0 && (!A[b] || !S[b])) return A[b] ? -3 : -1;
+        if (lda[b] < std::max<int64_t>(1, n[b])) return -2;
+        if (lds[b] < std::max<int64_t>(1, n[b])) return -4;
+        if (n[b] > 0 && ranges_overlap(A[b], extent_bytes(n[b], lda[b], es), S[b],
+                                       extent_bytes(n[b], lds[b], es)))
+            return -3;
+    }
+    for (int64_t b = 0; b < batch; ++b)
+        if (n[b] > sgt::kSignmMaxOrder) return SIGNTRI_ENOTSUP;
+    // the table: orders up to 32 first (the smaller kernel), then the rest
+    std::vector<sgt::SignmMat> tab;
+    tab.reserve((size_t)batch);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t b = 0; b < batch; ++b) {
+            if (n[b] == 0 || (pass == 0) != (n[b] <= 32)) continue;
+            tab.push_back(sgt::SignmMat{(const double *)A[b], (double *)S[b], lda[b], lds[b],
+                                        (int32_t)n[b], (int32_t)b});
+        }
+    if (tab.empty()) return SIGNTRI_OK;
+    int n32 = 0;
+    while (n32 < (int)tab.size() && tab[n32].n <= 32) ++n32;
+    const size_t tb = align_up(tab.size() * sizeof(sgt::SignmMat));
+    const size_t bytes = tb + align_up((size_t)batch * sizeof(int32_t));
+    void *dev = nullptr, *host = nullptr;
+    if (int rc = owned_workspace(bytes, &dev)) return rc;
+    if (int rc = owned_host(bytes, &host)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::memcpy(host, tab.data(), tab.size() * sizeof(sgt::SignmMat));
+    int32_t *dstatus = (int32_t *)((char *)dev + tb), *hstatus = (int32_t *)((char *)host + tb);
+    if (hipMemcpyAsync(dev, host, tab.size() * sizeof(sgt::SignmMat), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        sgt::launch_signm((const sgt::SignmMat *)dev, (int)tab.size(), n32,
+                          dtype == SIGNTRI_C128, dstatus, st) != hipSuccess ||
+        hipMemcpyAsync(hstatus, dstatus, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SIGNTRI_EHIP;
+    int rc = SIGNTRI_OK;
+    for (const sgt::SignmMat &m : tab) {
+        const int v = hstatus[m.index];
+        const int code = v == sgt::SIGNM_EDOMAIN ? SIGNTRI_EDOMAIN
+                         : v == sgt::SIGNM_ENOCONV ? SIGNTRI_ENOCONV
+                                                   : SIGNTRI_OK;
+        if (status) status[m.index] = code;
+    }
+    for (int64_t b = 0; b < batch && rc == SIGNTRI_OK; ++b)
+        if (n[b] > 0) {
+            const int v = hstatus[b];
+            rc = v == sgt::SIGNM_EDOMAIN ? SIGNTRI_EDOMAIN
+                 : v == sgt::SIGNM_ENOCONV ? SIGNTRI_ENOCONV
+                                           : SIGNTRI_OK;
+        }
+    return rc;
 }
 
 void signtri_release(void)

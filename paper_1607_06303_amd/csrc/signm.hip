@@ -1,0 +1,330 @@
+// sign(A) for a general square A of small order (Section 1): a complex Schur
+// decomposition A = Q T Q* (the first step of Algorithm 3), U = sign(T) by the
+// element substitution of Algorithm 3 (Eq. (1) where the signs of Re t_ii and
+// Re t_jj differ, Eq. (2) where they agree), and sign(A) = Q U Q*.
+//
+// One workgroup of one wave per matrix; the matrix, reduced in place, and Q
+// stay in LDS (orders up to 64: 2 x 64 x 65 complex entries, 133 KB).
+//   1. Hessenberg form by Householder reflections P = I - 2 w w* / (w* w)
+//      (Hermitian and unitary), H <- P H P and Q <- Q P, one column at a time;
+//      lane j updates column j from the left, lane i row i from the right.
+//   2. The shifted QR iteration on the Hessenberg matrix, one implicit single
+//      shift per sweep (the eigenvalue of the trailing 2 x 2 block nearer its
+//      last diagonal entry; an exceptional shift after 10 and 20 sweeps
+//      without deflation), the bulge chased by plane rotations
+//      G = [c s; -conj(s) c] applied to the whole rows and columns (the full
+//      Schur form, not only the eigenvalues) and to Q.  A subdiagonal entry is
+//      set to zero when it is at most the unit roundoff times the two diagonal
+//      entries beside it (or below the smallest normal number scaled by n / u).
+//      At most 30 max(10, n) sweeps, else the matrix is reported as not
+//      converged.
+//   3. U = sign(T), superdiagonal by superdiagonal (lane i: entry (i, i + d)),
+//      kept in the strict lower triangle of the same LDS array (U_ij at
+//      position (j, i)), which the Schur form leaves free.
+//   4. sign(A) = (Q U) Q*, a row at a time: row i of Q U into an LDS row, then
+//      lane j forms entry (i, j) against row j of Q.  A real A gets the real
+//      part (sign of a real matrix is real; its imaginary part is rounding).
+// An eigenvalue on the imaginary axis leaves S untouched and reports
+// SIGNM_EDOMAIN.  The computed Schur form moves eigenvalues by rounding, so
+// "on the axis" means |Re t_ii| <= n u ||A||_F (u the unit roundoff), where the
+// sign of Re t_ii is not determined by A; a non-finite t_ii counts too.
+#include <cfloat>
+
+#include "common.h"
+#include "signm.h"
+
+namespace sgt {
+
+namespace {
+
+constexpr int NT = 64;  // one wave
+
+__device__ inline cd cconj(cd a) { return {a.re, -a.im}; }
+__device__ inline double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ inline double cabsv(cd a) { return hypot(a.re, a.im); }
+__device__ inline double cabs1(cd a) { return fabs(a.re) + fabs(a.im); }
+
+// principal square root
+__device__ inline cd csqrt_p(cd z)
+{
+    const double r = hypot(z.re, z.im);
+    if (r == 0.0) return {0.0, 0.0};
+    const double t = sqrt(0.5 * (r + fabs(z.re)));
+    if (z.re >= 0.0) return {t, z.im / (2.0 * t)};
+    return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// sum over the wave
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NM, bool CPLX>
+__global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
+                                              int32_t *__restrict__ status)
+{
+    constexpr int P = NM + 1;  // LDS pitch in complex entries
+    __shared__ cd H[NM * P];   // row-major: H[r * P + c]
+    __shared__ cd Q[NM * P];
+    __shared__ cd w[NM];       // Householder vector; then a row of Q U
+    const int lane = threadIdx.x;
+    const SignmMat M = mats[blockIdx.x];
+    const int n = uniform(M.n);
+    auto h = [&](int r, int c) -> cd & { return H[r * P + c]; };
+    auto q = [&](int r, int c) -> cd & { return Q[r * P + c]; };
+
+    double fro2 = 0.0;
+    for (int e = lane; e < n * n; e += NT) {
+        const int r = e % n, c = e / n;
+        const int64_t off = r + (int64_t)c * M.lda;
+        cd v;
+        if (CPLX) v = {gload(M.A + 2 * off), gload(M.A + 2 * off + 1)};
+        else v = {gload(M.A + off), 0.0};
+        h(r, c) = v;
+        q(r, c) = cd{r == c ? 1.0 : 0.0, 0.0};
+        fro2 += cabs2(v);
+    }
+    // an eigenvalue whose real part is within rounding of zero has no defined sign
+    const double axis_tol = (double)n * DBL_EPSILON * sqrt(wave_sum(fro2));
+    __syncthreads();
+
+    // ---- 1. Hessenberg form
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;  // rows k+1 .. n-1 of column k
+        const cd xl = lane < m ? h(k + 1 + lane, k) : cd{0.0, 0.0};
+        const double below = wave_sum(lane >= 1 && lane < m ? cabs2(xl) : 0.0);
+        if (uniform(below > 0.0 ? 1 : 0) == 0) continue;  // column already reduced
+        const cd x0 = h(k + 1, k);
+        const double a0 = cabsv(x0);
+        const cd ph = a0 > 0.0 ? x0 * (1.0 / a0) : cd{1.0, 0.0};
+        const double alpha = sqrt(a0 * a0 + below);
+        // w = x + ph alpha e1: P x = -ph alpha e1
+        if (lane < m) w[lane] = lane == 0 ? x0 + ph * alpha : xl;
+        const double wn2 = (a0 + alpha) * (a0 + alpha) + below;
+        const double beta = 2.0 / wn2;
+        __syncthreads();
+        // from the left, columns k+1 .. n-1 (column k is set below)
+        if (lane > k && lane < n) {
+            const int j = lane;
+            cd s = {0.0, 0.0};
+            for (int i = 0; i < m; ++i) s = s + cconj(w[i]) * h(k + 1 + i, j);
+            s = s * beta;
+            for (int i = 0; i < m; ++i) h(k + 1 + i, j) = h(k + 1 + i, j) - w[i] * s;
+        }
+        __syncthreads();
+        // from the right, every row; and Q <- Q P
+        if (lane < n) {
+            const int i = lane;
+            cd t = {0.0, 0.0}, u = {0.0, 0.0};
+            for (int l = 0; l < m; ++l) {
+                t = t + h(i, k + 1 + l) * w[l];
+                u = u + q(i, k + 1 + l) * w[l];
+            }
+            t = t * beta;
+            u = u * beta;
+            for (int l = 0; l < m; ++l) {
+                h(i, k + 1 + l) = h(i, k + 1 + l) - t * cconj(w[l]);
+                q(i, k + 1 + l) = q(i, k + 1 + l) - u * cconj(w[l]);
+            }
+        }
+        __syncthreads();
+        if (lane < m) h(k + 1 + lane, k) = lane == 0 ? -(ph * alpha) : cd{0.0, 0.0};
+        __syncthreads();
+    }
+
+    // ---- 2. shifted QR iteration to the Schur form
+    const double ulp = DBL_EPSILON;
+    const double smlnum = DBL_MIN * ((double)n / ulp);
+    const int itmax = 30 * max(10, n);
+    int ihi = n - 1, its = 0, total = 0;
+    bool fail = false;
+    while (ihi >= 1) {
+        // the lowest l such that H[l, l-1] is negligible (0: none)
+        int l = 0;
+        for (int k = ihi; k >= 1; --k) {
+            const double a = cabs1(h(k, k - 1));
+            double tst = cabs1(h(k - 1, k - 1)) + cabs1(h(k, k));
+            if (tst == 0.0) {
+                if (k - 2 >= 0) tst += fabs(h(k - 1, k - 2).re);
+                if (k + 1 <= ihi) tst += fabs(h(k + 1, k).re);
+            }
+            if (a <= smlnum || a <= ulp * tst) {
+                l = k;
+                break;
+            }
+        }
+        l = uniform(l);
+        __syncthreads();
+        if (l > 0) {
+            if (lane == 0) h(l, l - 1) = cd{0.0, 0.0};
+            __syncthreads();
+        }
+        if (l == ihi) {
+            // a 1 x 1 block has converged
+            ihi = uniform(ihi - 1);
+            its = 0;
+            continue;
+        }
+        if (uniform(++total > itmax ? 1 : 0)) {
+            fail = true;
+            break;
+        }
+        ++its;
+        cd mu;
+        if (its == 10) {
+            mu = h(l, l) + cd{0.75 * fabs(h(l + 1, l).re), 0.0};
+        } else if (its == 20) {
+            mu = h(ihi, ihi) + cd{0.75 * fabs(h(ihi, ihi - 1).re), 0.0};
+        } else {
+            // the eigenvalue of the trailing 2 x 2 block nearer its last diagonal entry
+            const cd a = h(ihi - 1, ihi - 1), b = h(ihi - 1, ihi), c = h(ihi, ihi - 1),
+                     d = h(ihi, ihi);
+            const cd hm = (a - d) * 0.5;
+            const cd disc = csqrt_p(hm * hm + b * c);
+            const cd mid = (a + d) * 0.5;
+            const cd e1 = mid + disc, e2 = mid - disc;
+            mu = cabs2(e1 - d) <= cabs2(e2 - d) ? e1 : e2;
+        }
+        for (int k = l; k < ihi; ++k) {
+            cd x, y;
+            if (k == l) {
+                x = h(l, l) - mu;
+                y = h(l + 1, l);
+            } else {
+                x = h(k, k - 1);
+                y = h(k + 1, k - 1);
+            }
+            // G [x; y] = [r; 0] with G = [c s; -conj(s) c], c real
+            const double ax = cabsv(x), ay = cabsv(y);
+            const double nu = hypot(ax, ay);
+            double c = 1.0;
+            cd s = {0.0, 0.0}, r = x;
+            if (nu > 0.0) {
+                if (ax == 0.0) {
+                    c = 0.0;
+                    s = {1.0, 0.0};
+                    r = y;
+                } else {
+                    const cd px = x * (1.0 / ax);
+                    c = ax / nu;
+                    s = px * cconj(y) * (1.0 / nu);
+                    r = px * nu;
+                }
+            }
+            __syncthreads();  // every lane has read x and y
+            // rows k, k+1 from column jlo on
+            const int jlo = k == l ? l : k;
+            if (lane >= jlo && lane < n) {
+                const int j = lane;
+                const cd h1 = h(k, j), h2 = h(k + 1, j);
+                h(k, j) = h1 * c + s * h2;
+                h(k + 1, j) = h2 * c - cconj(s) * h1;
+            }
+            if (k > l && lane == 0) {
+                h(k, k - 1) = r;
+                h(k + 1, k - 1) = cd{0.0, 0.0};
+            }
+            __syncthreads();
+            // columns k, k+1 of rows 0 .. min(k + 2, ihi), and of Q
+            const int ilast = min(k + 2, ihi);
+            if (lane < n) {
+                const int i = lane;
+                if (i <= ilast) {
+                    const cd h1 = h(i, k), h2 = h(i, k + 1);
+                    h(i, k) = h1 * c + h2 * cconj(s);
+                    h(i, k + 1) = h2 * c - h1 * s;
+                }
+                const cd q1 = q(i, k), q2 = q(i, k + 1);
+                q(i, k) = q1 * c + q2 * cconj(s);
+                q(i, k + 1) = q2 * c - q1 * s;
+            }
+            __syncthreads();
+        }
+    }
+    if (fail) {
+        if (lane == 0) status[M.index] = SIGNM_ENOCONV;
+        return;
+    }
+
+    // ---- 3. U = sign(T)
+    bool bad = false;
+    if (lane < n) {
+        const cd t = h(lane, lane);
+        bad = !(fabs(t.re) > axis_tol) || !isfinite(t.re) || !isfinite(t.im);
+    }
+    if (__builtin_amdgcn_ballot_w64(bad) != 0) {
+        if (lane == 0) status[M.index] = SIGNM_EDOMAIN;
+        return;
+    }
+    auto sgn = [&](int i) -> double { return h(i, i).re > 0.0 ? 1.0 : -1.0; };
+    for (int d = 1; d < n; ++d) {
+        if (lane + d < n) {
+            const int i = lane, j = lane + d;
+            const double si = sgn(i), sj = sgn(j);
+            cd sum = {0.0, 0.0};
+            cd u;
+            if (si != sj) {
+                // Eq. (1): u_ii - u_jj = 2 si
+                for (int k = i + 1; k < j; ++k) sum = sum + h(k, i) * h(k, j) - h(i, k) * h(j, k);
+                u = (h(i, j) * (2.0 * si) + sum) / (h(i, i) - h(j, j));
+            } else {
+                // Eq. (2): u_ii + u_jj = 2 si
+                for (int k = i + 1; k < j; ++k) sum = sum + h(k, i) * h(j, k);
+                u = sum * (-0.5 * si);
+            }
+            h(j, i) = u;
+        }
+        __syncthreads();
+    }
+
+    // ---- 4. S = (Q U) Q*, row by row
+    for (int i = 0; i < n; ++i) {
+        if (lane < n) {
+            const int j = lane;
+            cd acc = q(i, j) * sgn(j);
+            for (int k = 0; k < j; ++k) acc = acc + q(i, k) * h(j, k);
+            w[j] = acc;
+        }
+        __syncthreads();
+        if (lane < n) {
+            const int j = lane;
+            cd acc = {0.0, 0.0};
+            for (int k = 0; k < n; ++k) acc = acc + w[k] * cconj(q(j, k));
+            const int64_t off = i + (int64_t)j * M.lds;
+            if (CPLX) {
+                gstore(M.S + 2 * off, acc.re);
+                gstore(M.S + 2 * off + 1, acc.im);
+            } else {
+                gstore(M.S + off, acc.re);
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) status[M.index] = SIGNM_OK;
+}
+
+template <bool CPLX>
+hipError_t launch_signm_t(const SignmMat *mats, int count, int n32, int32_t *status,
+                          hipStream_t st)
+{
+    if (n32 > 0) hipLaunchKernelGGL((k_signm<32, CPLX>), dim3(n32), dim3(NT), 0, st, mats, status);
+    if (count > n32)
+        hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX>), dim3(count - n32), dim3(NT), 0, st,
+                           mats + n32, status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_signm(const SignmMat *mats, int count, int n32, bool cplx, int32_t *status,
+                        hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    return cplx ? launch_signm_t<true>(mats, count, n32, status, st)
+                : launch_signm_t<false>(mats, count, n32, status, st);
+}
+
+}  // namespace sgt

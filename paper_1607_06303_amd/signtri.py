@@ -30,7 +30,7 @@ EXPORTS = ("signtri", "signtri_workspace_size", "signtri_batched",
            "signtri_plan_host", "signtri_release", "signtri_profile_enable",
            "signtri_profile_read", "signtri_autotune", "signtri_tune_lookup",
            "signtri_tune_save", "signtri_tune_load", "signtri_tune_clear", "signtri_noalloc",
-           "signtri_autotune_batched", "signtri_fun")
+           "signtri_autotune_batched", "signtri_fun", "signtri_signm_batched")
 FAMILIES = {"scan": 0, "diag": 1, "gemm": 2, "solve": 3, "aux": 4, "resid": 5,
             "corr": 6, "syl": 7, "flow": 8, "batched": 9, "convert": 10, "proj": 11,
             "proj_out": 12}
@@ -111,6 +111,11 @@ def lib() -> ctypes.CDLL:
             L.signtri_batched.restype = i32
             L.signtri_batched_workspace_size.argtypes = [ctypes.POINTER(i64), i64, i32, i32]
             L.signtri_batched_workspace_size.restype = sz
+            L.signtri_signm_batched.argtypes = [ctypes.POINTER(p), ctypes.POINTER(i64),
+                                                ctypes.POINTER(p), ctypes.POINTER(i64),
+                                                ctypes.POINTER(i64), i64, i32, p,
+                                                ctypes.POINTER(ctypes.c_int32)]
+            L.signtri_signm_batched.restype = i32
             L.signtri_strerror.argtypes = [i32]
             L.signtri_strerror.restype = ctypes.c_char_p
             L.sign_tri.argtypes = [p, i64, i64, i32, p]
@@ -400,6 +405,46 @@ def sign_tri_batched(Ts, mode: str = "fp64", outs=None, workspace=None, stream=N
     if rc != 0:
         raise SignTriError(rc, strerror(rc))
     return Us, InfoList(infos)
+
+
+def sign_general_batched(As, outs=None, stream=None):
+    """sign(A) for a list of square column-major tensors of order at most 64 (all
+    float64 or all complex128, on one device): a Schur decomposition, the
+    triangular sign and the back-transformation, in the library's kernels.
+    Returns (list of S, list of status codes); raises SignTriError when the
+    call fails as a whole (argument errors) or, after filling every S it could,
+    with the first failing matrix's code."""
+    if not As:
+        return [], []
+    dt = _dtype_code(As[0])
+    Ss = outs if outs is not None else [empty_like_layout(a) for a in As]
+    B = len(As)
+    if len(Ss) != B:
+        raise ValueError("outs must hold one tensor per A")
+    ap, sp = (ctypes.c_void_p * B)(), (ctypes.c_void_p * B)()
+    lda, lds, ns = (ctypes.c_int64 * B)(), (ctypes.c_int64 * B)(), (ctypes.c_int64 * B)()
+    for b in range(B):
+        a, o = As[b], Ss[b]
+        if a.dim() != 2 or a.shape[0] != a.shape[1] or _dtype_code(a) != dt:
+            raise ValueError("every A must be square with the first one's dtype")
+        nb = a.shape[0]
+        ns[b] = nb
+        if nb == 0:
+            lda[b] = lds[b] = 1
+            continue
+        la, lo = _layout(a), _layout(o)
+        if nb > 1 and (la is None or lo is None or la[0] != COL_MAJOR or lo[0] != COL_MAJOR):
+            raise ValueError("every A and S must be column-major strided")
+        ap[b], sp[b] = a.data_ptr(), o.data_ptr()
+        lda[b] = la[1] if la else 1
+        lds[b] = lo[1] if lo else 1
+    st = (ctypes.c_int32 * B)()
+    rc = lib().signtri_signm_batched(ap, lda, sp, lds, ns, B, dt, _stream_handle(As[0], stream),
+                                     st)
+    codes = [int(st[b]) for b in range(B)]
+    if rc != 0:
+        raise SignTriError(rc, strerror(rc), {"status": codes})
+    return Ss, codes
 
 
 def release() -> None:

@@ -144,3 +144,46 @@ def schur_like(n: int, n_neg: int | None, rng: np.random.Generator) -> np.ndarra
         s = signs_with_negatives(n, n_neg, rng)
         T[np.arange(n), np.arange(n)] = s * d
     return np.asfortranarray(T)
+
+
+def general_A(n: int, rng: np.random.Generator, *, complex_: bool = False, gap: float = 0.5,
+              pairs: int | None = None, coupling: float = 0.3) -> np.ndarray:
+    """A general square matrix with known, well separated eigenvalues: A = V B V*,
+    V a random orthogonal (unitary) matrix, B block upper triangular with
+    eigenvalues whose real parts lie in +-[gap, 2] (random signs) and coupling
+    entries of size coupling / sqrt(n) above the diagonal blocks.  A real A gets
+    `pairs` complex-conjugate pairs (2 x 2 blocks [[a, b], [-b, a]], eigenvalues
+    a +- ib; default n // 4), the rest real eigenvalues; a complex A gets complex
+    eigenvalues with imaginary parts in [-1, 1]."""
+    dt = np.complex128 if complex_ else np.float64
+    B = np.zeros((n, n), dtype=dt)
+    re = rng.uniform(gap, 2.0, n) * rng.choice([-1.0, 1.0], n)
+    if complex_:
+        B[np.arange(n), np.arange(n)] = re + 1j * rng.uniform(-1.0, 1.0, n)
+        step = np.ones(n, dtype=int)
+    else:
+        k = n // 4 if pairs is None else min(pairs, n // 2)
+        i = 0
+        for p in range(k):
+            a, b = re[i], rng.uniform(0.2, 1.0)
+            B[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
+            i += 2
+        B[np.arange(i, n), np.arange(i, n)] = re[i:]
+    upper = np.triu(rng.standard_normal((n, n)), 1)
+    if complex_:
+        upper = upper + 1j * np.triu(rng.standard_normal((n, n)), 1)
+    # above the 2 x 2 blocks only: keep the block structure of B
+    mask = np.triu(np.ones((n, n), dtype=bool), 1)
+    if not complex_:
+        for j in range(0, 2 * (n // 4 if pairs is None else min(pairs, n // 2)), 2):
+            mask[j, j + 1] = False
+    B = B + np.where(mask, upper, 0.0) * (coupling / np.sqrt(max(n, 1)))
+    G = rng.standard_normal((n, n)) + (1j * rng.standard_normal((n, n)) if complex_ else 0.0)
+    V, R = np.linalg.qr(G)
+    V = V * (np.diag(R) / np.abs(np.diag(R)))  # a Haar-distributed factor
+    return np.asfortranarray(V @ B @ V.conj().T)
+
+
+def uniform_A(n: int, rng: np.random.Generator) -> np.ndarray:
+    """The paper's test matrices before their Schur form: U[-50, 50] entries."""
+    return np.asfortranarray(rng.uniform(-50.0, 50.0, (n, n)))

@@ -274,6 +274,33 @@ def test_batched_info_list_converts_on_read():
     assert [d["n_neg"] for d in lst[1:]] == [0, 7]
 
 
+def test_signm_argument_validation_without_device_work():
+    L = signtri.lib()
+    P = ctypes.c_void_p * 2
+    I = ctypes.c_int64 * 2
+    A = P(0x1000, 0x2000)
+    S = P(0x100000, 0x200000)
+    n = I(4, 4)
+    ld = I(4, 4)
+    st = (ctypes.c_int32 * 2)()
+    call = lambda a, la, s, ls, nn, b, dt=0: L.signtri_signm_batched(a, la, s, ls, nn, b, dt,
+                                                                      None, st)
+    assert call(None, ld, S, ld, n, 2) == -1
+    assert call(A, None, S, ld, n, 2) == -2
+    assert call(A, ld, None, ld, n, 2) == -3
+    assert call(A, ld, S, None, n, 2) == -4
+    assert call(A, ld, S, ld, None, 2) == -5
+    assert call(A, ld, S, ld, n, -1) == -6
+    assert call(A, ld, S, ld, n, 2, dt=9) == -7
+    assert call(A, I(4, 3), S, ld, n, 2) == -2
+    assert call(A, ld, S, I(3, 4), n, 2) == -4
+    assert call(A, ld, S, ld, I(4, -2), 2) == -5
+    assert call(A, ld, P(0x1000, 0x200000), ld, n, 2) == -3  # S overlaps A
+    assert call(A, ld, S, ld, n, 0) == 0
+    # orders above 64: not implemented (before any device work)
+    assert call(A, I(65, 4), S, I(65, 4), I(65, 4), 2) == 5
+
+
 def test_batched_workspace_size():
     I = ctypes.c_int64 * 3
     L = signtri.lib()

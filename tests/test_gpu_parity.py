@@ -184,6 +184,23 @@ def test_deterministic(dev):
     assert np.array_equal(U1, U2)
 
 
+@pytest.mark.parametrize("mode,grids", [("fp64", (2, 3)), ("mixed", (3, 4))])
+def test_sweep_builds_agree_bitwise(dev, mode, grids):
+    # the real sweeps' second build (one more workgroup per compute unit, a few
+    # values spilled) runs the same arithmetic in the same order as the first:
+    # the grid that picks it changes no bit of U, and both match the oracle
+    import oracle
+
+    rng = np.random.default_rng(4750)
+    T = wl.make_T(450, rng)
+    opts = lambda w: {"sweep": "dataflow", "wgs_per_cu": w}
+    Ua, ia = run_gpu(T, dev, mode=mode, algo="ph", options=opts(grids[0]))
+    Ub, ib = run_gpu(T, dev, mode=mode, algo="ph", options=opts(grids[1]))
+    assert ia["wgs_per_cu"] == grids[0] and ib["wgs_per_cu"] == grids[1]
+    assert np.array_equal(Ua, Ub)
+    assert rel_fro(Ua, oracle.sign_tri(T)) <= TOL_FP64
+
+
 def test_workspace_argument(dev):
     import torch
 
