@@ -49,6 +49,8 @@ def parse():
                          "both accumulators everywhere (for measuring what the masking saves)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the side measurement of the 2000-matrix batched workload")
+    ap.add_argument("--no-signm", action="store_true",
+                    help="skip the side measurement of sign(A) for a batch of general matrices")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default: tune each mode before its warm-up)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -130,6 +132,43 @@ def bench_batched(signtri, torch, workloads, oracle_mod, steps):
         out[mode] = {"ms": ms, "gflops": n3 / ms / 1e6, "err_max": err}
         log("batched %s: %.3f ms, %.1f GFLOP/s (sum n^3/3), worst rel err over the 2000 %s"
             % (mode, ms, n3 / ms / 1e6, "-" if err is None else "%.2e" % err))
+    return out
+
+
+def bench_signm(signtri, torch, workloads, oracle_signm, steps, count=2048, n=64, check=64):
+    """Side measurement (not the headline): sign(A) of `count` general real matrices
+    of order n (eigenvalues with real parts in +-[0.5, 2], a quarter of them in
+    complex pairs) in one batched call; the first `check` matrices are compared
+    with the oracle, which is also timed on them (the CPU rate)."""
+    import numpy as np
+
+    rng = workloads.rng_for(6)
+    As = [workloads.general_A(n, rng) for _ in range(count)]
+    Ag = [torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t() for A in As]
+    outs = [signtri.empty_like_layout(a) for a in Ag]
+    signtri.sign_general_batched(Ag, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        signtri.sign_general_batched(Ag, outs=outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = {"workload": "%d real general matrices of order %d, eigenvalue real parts in "
+                       "+-[0.5, 2], n/4 complex pairs" % (count, n),
+           "ms": ms, "matrices_per_s": count / ms * 1e3, "err_max": None,
+           "cpu_oracle_matrices_per_s": None}
+    if oracle_signm is not None:
+        err = 0.0
+        t0 = time.perf_counter()
+        refs = [oracle_signm.sign_general(A) for A in As[:check]]
+        dt = time.perf_counter() - t0
+        for S, ref in zip(outs[:check], refs):
+            err = max(err, float(np.linalg.norm(S.cpu().numpy() - ref) / np.linalg.norm(ref)))
+        out["err_max"] = err
+        out["cpu_oracle_matrices_per_s"] = check / dt
+    log("signm: %d matrices of order %d in %.3f ms (%.0f /s), worst rel err over %d %s"
+        % (count, n, ms, count / ms * 1e3, check,
+           "-" if out["err_max"] is None else "%.2e" % out["err_max"]))
     return out
 
 
@@ -292,6 +331,13 @@ def main():
         batched = bench_batched(signtri, torch, workloads, None if args.no_check else oracle_mod,
                                 max(1, min(args.steps, 5)))
 
+    signm = None
+    if not args.no_signm:
+        import oracle.signm as oracle_signm
+
+        signm = bench_signm(signtri, torch, workloads, None if args.no_check else oracle_signm,
+                            max(1, min(args.steps, 5)))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -340,6 +386,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "signm": signm,
     }
     print(json.dumps(out), flush=True)
 
