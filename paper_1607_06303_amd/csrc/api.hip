@@ -1011,12 +1011,16 @@ int signtri_signm_batched(const void *const *A, const int64_t *lda, void *const 
     if (int rc = owned_workspace(bytes, &dev)) return rc;
     if (int rc = owned_host(bytes, &host)) return rc;
     hipStream_t st = (hipStream_t)stream;
+    // testing hook: SIGNTRI_DEBUG_SIGNM_SWEEPS=k limits the QR iteration to k sweeps
+    // per matrix, so that its not-converged report can be exercised
+    int max_sweeps = 0;
+    if (const char *e = getenv("SIGNTRI_DEBUG_SIGNM_SWEEPS")) max_sweeps = std::max(0, atoi(e));
     std::memcpy(host, tab.data(), tab.size() * sizeof(sgt::SignmMat));
     int32_t *dstatus = (int32_t *)((char *)dev + tb), *hstatus = (int32_t *)((char *)host + tb);
     if (hipMemcpyAsync(dev, host, tab.size() * sizeof(sgt::SignmMat), hipMemcpyHostToDevice, st) !=
             hipSuccess ||
         sgt::launch_signm((const sgt::SignmMat *)dev, (int)tab.size(), n32,
-                          dtype == SIGNTRI_C128, dstatus, st) != hipSuccess ||
+                          dtype == SIGNTRI_C128, dstatus, max_sweeps, st) != hipSuccess ||
         hipMemcpyAsync(hstatus, dstatus, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToHost,
                        st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

@@ -29,7 +29,9 @@ enum { SIGNM_OK = 0, SIGNM_EDOMAIN = 1, SIGNM_ENOCONV = 4 };
 // first (smaller LDS, more workgroups per compute unit), then the rest; the
 // table must be sorted that way, with n32 of them of order at most 32.
 // status[index] receives each matrix's outcome.
+// max_sweeps > 0 replaces the QR iteration's limit of 30 max(10, n) sweeps (a
+// testing hook: a tiny limit makes the not-converged report reachable).
 hipError_t launch_signm(const SignmMat *mats, int count, int n32, bool cplx, int32_t *status,
-                        hipStream_t st);
+                        int max_sweeps, hipStream_t st);
 
 }  // namespace sgt

@@ -54,6 +54,59 @@ __device__ inline cd csqrt_p(cd z)
     return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
 }
 
+// 1 / sqrt(a) for a > 0: the hardware estimate and two Newton steps (each
+// squares the relative error; the estimate's is below 2^-22)
+__device__ inline double rsqrt_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// The plane rotation G = [c s; -conj(s) c] (c real) with G [x; y] = [r; 0]:
+// c = |x| / nu, s = (x / |x|) conj(y) / nu, r = (x / |x|) nu, nu = |(x, y)|
+// (x = 0: c = 0, s = 1, r = y).  The operands are scaled by a power of two so
+// that their squares neither overflow nor underflow.
+__device__ inline void givens(cd x, cd y, double &c, cd &s, cd &r)
+{
+    const double mx = fmax(fmax(fabs(x.re), fabs(x.im)), fmax(fabs(y.re), fabs(y.im)));
+    if (!(mx > 0.0)) {
+        c = 1.0;
+        s = {0.0, 0.0};
+        r = x;
+        return;
+    }
+    const int e = ilogb(mx);
+    const double sc = ldexp(1.0, -e);
+    const cd xs = {x.re * sc, x.im * sc}, ys = {y.re * sc, y.im * sc};
+    const double ax2 = xs.re * xs.re + xs.im * xs.im;
+    const double nu2 = ax2 + (ys.re * ys.re + ys.im * ys.im);
+    if (ax2 == 0.0) {
+        c = 0.0;
+        s = {1.0, 0.0};
+        r = y;
+        return;
+    }
+    const double iax = rsqrt_nr(ax2), inu = rsqrt_nr(nu2);
+    const cd px = {xs.re * iax, xs.im * iax};  // x / |x|
+    c = ax2 * iax * inu;
+    s = px * cd{ys.re * inu, -ys.im * inu};
+    const double nu = ldexp(nu2 * inu, e);
+    r = {px.re * nu, px.im * nu};
+}
+
+// Lane src's complex value, held by every lane
+__device__ inline double readlane_d(double v, int src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ inline cd readlane_c(cd v, int src) { return {readlane_d(v.re, src), readlane_d(v.im, src)}; }
+
 // sum over the wave
 __device__ inline double wave_sum(double v)
 {
@@ -64,7 +117,7 @@ __device__ inline double wave_sum(double v)
 
 template <int NM, bool CPLX>
 __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
-                                              int32_t *__restrict__ status)
+                                              int32_t *__restrict__ status, int max_sweeps)
 {
     constexpr int P = NM + 1;  // LDS pitch in complex entries
     __shared__ cd H[NM * P];   // row-major: H[r * P + c]
@@ -138,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
     // ---- 2. shifted QR iteration to the Schur form
     const double ulp = DBL_EPSILON;
     const double smlnum = DBL_MIN * ((double)n / ulp);
-    const int itmax = 30 * max(10, n);
+    const int itmax = max_sweeps > 0 ? max_sweeps : 30 * max(10, n);
     int ihi = n - 1, its = 0, total = 0;
     bool fail = false;
     while (ihi >= 1) {
@@ -188,33 +241,14 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
             const cd e1 = mid + disc, e2 = mid - disc;
             mu = cabs2(e1 - d) <= cabs2(e2 - d) ? e1 : e2;
         }
+        // The entries that define rotation k (k > l) are those the column update of
+        // rotation k - 1 has just formed in lanes k and k + 1: taken from there
+        // by readlane rather than through LDS.
+        cd x = h(l, l) - mu, y = h(l + 1, l);
         for (int k = l; k < ihi; ++k) {
-            cd x, y;
-            if (k == l) {
-                x = h(l, l) - mu;
-                y = h(l + 1, l);
-            } else {
-                x = h(k, k - 1);
-                y = h(k + 1, k - 1);
-            }
-            // G [x; y] = [r; 0] with G = [c s; -conj(s) c], c real
-            const double ax = cabsv(x), ay = cabsv(y);
-            const double nu = hypot(ax, ay);
-            double c = 1.0;
-            cd s = {0.0, 0.0}, r = x;
-            if (nu > 0.0) {
-                if (ax == 0.0) {
-                    c = 0.0;
-                    s = {1.0, 0.0};
-                    r = y;
-                } else {
-                    const cd px = x * (1.0 / ax);
-                    c = ax / nu;
-                    s = px * cconj(y) * (1.0 / nu);
-                    r = px * nu;
-                }
-            }
-            __syncthreads();  // every lane has read x and y
+            double c;
+            cd s, r;
+            givens(x, y, c, s, r);
             // rows k, k+1 from column jlo on
             const int jlo = k == l ? l : k;
             if (lane >= jlo && lane < n) {
@@ -230,16 +264,22 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
             __syncthreads();
             // columns k, k+1 of rows 0 .. min(k + 2, ihi), and of Q
             const int ilast = min(k + 2, ihi);
+            cd nk = {0.0, 0.0};
             if (lane < n) {
                 const int i = lane;
                 if (i <= ilast) {
                     const cd h1 = h(i, k), h2 = h(i, k + 1);
-                    h(i, k) = h1 * c + h2 * cconj(s);
+                    nk = h1 * c + h2 * cconj(s);
+                    h(i, k) = nk;
                     h(i, k + 1) = h2 * c - h1 * s;
                 }
                 const cd q1 = q(i, k), q2 = q(i, k + 1);
                 q(i, k) = q1 * c + q2 * cconj(s);
                 q(i, k + 1) = q2 * c - q1 * s;
+            }
+            if (k + 1 < ihi) {
+                x = readlane_c(nk, k + 1);
+                y = readlane_c(nk, k + 2);
             }
             __syncthreads();
         }
@@ -308,23 +348,25 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
 
 template <bool CPLX>
 hipError_t launch_signm_t(const SignmMat *mats, int count, int n32, int32_t *status,
-                          hipStream_t st)
+                          int max_sweeps, hipStream_t st)
 {
-    if (n32 > 0) hipLaunchKernelGGL((k_signm<32, CPLX>), dim3(n32), dim3(NT), 0, st, mats, status);
+    if (n32 > 0)
+        hipLaunchKernelGGL((k_signm<32, CPLX>), dim3(n32), dim3(NT), 0, st, mats, status,
+                           max_sweeps);
     if (count > n32)
         hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX>), dim3(count - n32), dim3(NT), 0, st,
-                           mats + n32, status);
+                           mats + n32, status, max_sweeps);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_signm(const SignmMat *mats, int count, int n32, bool cplx, int32_t *status,
-                        hipStream_t st)
+                        int max_sweeps, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    return cplx ? launch_signm_t<true>(mats, count, n32, status, st)
-                : launch_signm_t<false>(mats, count, n32, status, st);
+    return cplx ? launch_signm_t<true>(mats, count, n32, status, max_sweeps, st)
+                : launch_signm_t<false>(mats, count, n32, status, max_sweeps, st);
 }
 
 }  // namespace sgt

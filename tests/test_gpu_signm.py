@@ -136,3 +136,23 @@ def test_imaginary_eigenvalues_leave_the_output_untouched(dev):
     assert np.all(Ss[1] == 7.0)
     assert rel_fro(Ss[0], sign_general(good)) <= TOL
     assert rel_fro(Ss[2], sign_general(good)) <= TOL
+
+
+def test_not_converged_is_reported_and_leaves_the_output(dev, monkeypatch):
+    # the library's testing hook limits the QR iteration to one sweep per matrix:
+    # an order-16 matrix needs more, an order-1 matrix none
+    from oracle.signm import sign_general
+
+    from paper_1607_06303_amd import signtri
+
+    rng = np.random.default_rng(5500)
+    A = wl.general_A(16, rng)
+    one = np.array([[-0.5]])
+    monkeypatch.setenv("SIGNTRI_DEBUG_SIGNM_SWEEPS", "1")
+    Ss, codes, err = run([A, one], dev, sentinel=3.0)
+    assert isinstance(err, signtri.SignTriError) and err.code == 4
+    assert codes == [4, 0]
+    assert np.all(Ss[0] == 3.0) and Ss[1].tolist() == [[-1.0]]
+    monkeypatch.delenv("SIGNTRI_DEBUG_SIGNM_SWEEPS")
+    Ss, codes, err = run([A], dev)
+    assert err is None and rel_fro(Ss[0], sign_general(A)) <= TOL
