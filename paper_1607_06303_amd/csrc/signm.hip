@@ -3,8 +3,10 @@
 // element substitution of Algorithm 3 (Eq. (1) where the signs of Re t_ii and
 // Re t_jj differ, Eq. (2) where they agree), and sign(A) = Q U Q*.
 //
-// One workgroup of one wave per matrix; the matrix, reduced in place, and Q
-// stay in LDS (orders up to 64: 2 x 64 x 65 complex entries, 133 KB).
+// One workgroup of one wave per matrix; the matrix, reduced in place, stays in
+// LDS, and so does Q for orders up to 32 (2 x 32 x 33 complex entries, 34 KB);
+// for orders 33 to 64 Q lives in global memory (the matrix alone is 64 x 65
+// complex entries, 67 KB, so that two workgroups fit on a compute unit).
 //   1. Hessenberg form by Householder reflections P = I - 2 w w* / (w* w)
 //      (Hermitian and unitary), H <- P H P and Q <- Q P, one column at a time;
 //      lane j updates column j from the left, lane i row i from the right.
@@ -115,19 +117,44 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-template <int NM, bool CPLX>
+// QG: Q in global memory (M.Q, row-major, pitch n) instead of LDS, so that two
+// workgroups of the larger instance fit on a compute unit; the rotations of a
+// QR sweep are then logged in LDS and applied to Q after the sweep, each lane
+// running its row through them with the next entries loaded ahead.
+template <int NM, bool CPLX, bool QG>
 __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
                                               int32_t *__restrict__ status, int max_sweeps)
 {
     constexpr int P = NM + 1;  // LDS pitch in complex entries
     __shared__ cd H[NM * P];   // row-major: H[r * P + c]
-    __shared__ cd Q[NM * P];
+    __shared__ cd Q[QG ? 1 : NM * P];
     __shared__ cd w[NM];       // Householder vector; then a row of Q U
+    __shared__ cd qr[QG ? NM : 1];   // QG: a row of Q
+    __shared__ double rc[QG ? NM : 1];  // QG: the sweep's rotations
+    __shared__ cd rs[QG ? NM : 1];
     const int lane = threadIdx.x;
     const SignmMat M = mats[blockIdx.x];
     const int n = uniform(M.n);
     auto h = [&](int r, int c) -> cd & { return H[r * P + c]; };
     auto q = [&](int r, int c) -> cd & { return Q[r * P + c]; };
+    cd *const Qg = M.Q;
+    auto qget = [&](int r, int c) -> cd {
+        if constexpr (QG) {
+            const double *d = (const double *)(Qg + (int64_t)r * n + c);
+            return {gload(d), gload(d + 1)};
+        } else {
+            return Q[r * P + c];
+        }
+    };
+    auto qset = [&](int r, int c, cd v) {
+        if constexpr (QG) {
+            double *d = (double *)(Qg + (int64_t)r * n + c);
+            gstore(d, v.re);
+            gstore(d + 1, v.im);
+        } else {
+            Q[r * P + c] = v;
+        }
+    };
 
     double fro2 = 0.0;
     for (int e = lane; e < n * n; e += NT) {
@@ -137,8 +164,14 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
         if (CPLX) v = {gload(M.A + 2 * off), gload(M.A + 2 * off + 1)};
         else v = {gload(M.A + off), 0.0};
         h(r, c) = v;
-        q(r, c) = cd{r == c ? 1.0 : 0.0, 0.0};
+        if constexpr (!QG) q(r, c) = cd{r == c ? 1.0 : 0.0, 0.0};
         fro2 += cabs2(v);
+    }
+    if constexpr (QG) {
+        for (int e = lane; e < n * n; e += NT) {
+            const int r = e / n, c = e % n;
+            qset(r, c, cd{r == c ? 1.0 : 0.0, 0.0});
+        }
     }
     // an eigenvalue whose real part is within rounding of zero has no defined sign
     const double axis_tol = (double)n * DBL_EPSILON * sqrt(wave_sum(fro2));
@@ -174,13 +207,13 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
             cd t = {0.0, 0.0}, u = {0.0, 0.0};
             for (int l = 0; l < m; ++l) {
                 t = t + h(i, k + 1 + l) * w[l];
-                u = u + q(i, k + 1 + l) * w[l];
+                u = u + qget(i, k + 1 + l) * w[l];
             }
             t = t * beta;
             u = u * beta;
             for (int l = 0; l < m; ++l) {
                 h(i, k + 1 + l) = h(i, k + 1 + l) - t * cconj(w[l]);
-                q(i, k + 1 + l) = q(i, k + 1 + l) - u * cconj(w[l]);
+                qset(i, k + 1 + l, qget(i, k + 1 + l) - u * cconj(w[l]));
             }
         }
         __syncthreads();
@@ -273,13 +306,44 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
                     h(i, k) = nk;
                     h(i, k + 1) = h2 * c - h1 * s;
                 }
-                const cd q1 = q(i, k), q2 = q(i, k + 1);
-                q(i, k) = q1 * c + q2 * cconj(s);
-                q(i, k + 1) = q2 * c - q1 * s;
+                if constexpr (!QG) {
+                    const cd q1 = q(i, k), q2 = q(i, k + 1);
+                    q(i, k) = q1 * c + q2 * cconj(s);
+                    q(i, k + 1) = q2 * c - q1 * s;
+                }
+            }
+            if constexpr (QG) {
+                if (lane == 0) {
+                    rc[k - l] = c;
+                    rs[k - l] = s;
+                }
             }
             if (k + 1 < ihi) {
                 x = readlane_c(nk, k + 1);
                 y = readlane_c(nk, k + 2);
+            }
+            __syncthreads();
+        }
+        if constexpr (QG) {
+            // the sweep's rotations, in order, on columns l .. ihi of every row of Q
+            if (lane < n) {
+                const int i = lane;
+                cd carry = qget(i, l);
+                for (int k0 = l; k0 < ihi; k0 += 8) {
+                    cd nx[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < ihi) nx[u] = qget(i, k0 + u + 1);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < ihi) {
+                            const double c = rc[k0 + u - l];
+                            const cd s = rs[k0 + u - l];
+                            qset(i, k0 + u, carry * c + nx[u] * cconj(s));
+                            carry = nx[u] * c - carry * s;
+                        }
+                }
+                qset(i, ihi, carry);
             }
             __syncthreads();
         }
@@ -321,18 +385,29 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
     }
 
     // ---- 4. S = (Q U) Q*, row by row
+    // (QG: every lane's stores of Q reach the other lanes' loads below)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     for (int i = 0; i < n; ++i) {
+        if constexpr (QG) {
+            if (lane < n) qr[lane] = qget(i, lane);
+            __syncthreads();
+        }
+        auto qi = [&](int k) -> cd {
+            if constexpr (QG) return qr[k];
+            else return q(i, k);
+        };
         if (lane < n) {
             const int j = lane;
-            cd acc = q(i, j) * sgn(j);
-            for (int k = 0; k < j; ++k) acc = acc + q(i, k) * h(j, k);
+            cd acc = qi(j) * sgn(j);
+            for (int k = 0; k < j; ++k) acc = acc + qi(k) * h(j, k);
             w[j] = acc;
         }
         __syncthreads();
         if (lane < n) {
             const int j = lane;
             cd acc = {0.0, 0.0};
-            for (int k = 0; k < n; ++k) acc = acc + w[k] * cconj(q(j, k));
+#pragma unroll 8
+            for (int k = 0; k < n; ++k) acc = acc + w[k] * cconj(qget(j, k));
             const int64_t off = i + (int64_t)j * M.lds;
             if (CPLX) {
                 gstore(M.S + 2 * off, acc.re);
@@ -351,11 +426,11 @@ hipError_t launch_signm_t(const SignmMat *mats, int count, int n32, int32_t *sta
                           int max_sweeps, hipStream_t st)
 {
     if (n32 > 0)
-        hipLaunchKernelGGL((k_signm<32, CPLX>), dim3(n32), dim3(NT), 0, st, mats, status,
+        hipLaunchKernelGGL((k_signm<32, CPLX, false>), dim3(n32), dim3(NT), 0, st, mats, status,
                            max_sweeps);
     if (count > n32)
-        hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX>), dim3(count - n32), dim3(NT), 0, st,
-                           mats + n32, status, max_sweeps);
+        hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX, true>), dim3(count - n32), dim3(NT), 0,
+                           st, mats + n32, status, max_sweeps);
     return hipGetLastError();
 }
 
