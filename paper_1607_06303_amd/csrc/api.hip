@@ -1007,20 +1007,18 @@ int signtri_signm_batched(const void *const *A, const int64_t *lda, void *const 
     while (n32 < (int)tab.size() && tab[n32].n <= 32) ++n32;
     const size_t tb = align_up(tab.size() * sizeof(sgt::SignmMat));
     const size_t sb = align_up((size_t)batch * sizeof(int32_t));
-    // orders above 32 keep Q (n x n complex) in the workspace
+    // every matrix keeps Q (n x n complex) in the workspace
     size_t qb = 0;
-    for (const sgt::SignmMat &m : tab)
-        if (m.n > 32) qb += (size_t)m.n * m.n * 16;
+    for (const sgt::SignmMat &m : tab) qb += (size_t)m.n * m.n * 16;
     void *dev = nullptr, *host = nullptr;
     if (int rc = owned_workspace(tb + sb + align_up(qb), &dev)) return rc;
     if (int rc = owned_host(tb + sb, &host)) return rc;
     {
         char *qp = (char *)dev + tb + sb;
-        for (sgt::SignmMat &m : tab)
-            if (m.n > 32) {
-                m.Q = (sgt::cd *)qp;
-                qp += (size_t)m.n * m.n * 16;
-            }
+        for (sgt::SignmMat &m : tab) {
+            m.Q = (sgt::cd *)qp;
+            qp += (size_t)m.n * m.n * 16;
+        }
     }
     hipStream_t st = (hipStream_t)stream;
     // testing hook: SIGNTRI_DEBUG_SIGNM_SWEEPS=k limits the QR iteration to k sweeps

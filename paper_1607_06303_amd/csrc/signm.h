@@ -10,8 +10,8 @@ namespace sgt {
 
 struct cd;  // complex double (re, im)
 
-// Largest order the one-wave Schur kernels take (A's Hessenberg form and Q
-// both in LDS).
+// Largest order the one-wave Schur kernels take (A's Hessenberg and Schur
+// forms in LDS).
 constexpr int kSignmMaxOrder = 64;
 
 // One matrix of a batch: device pointers, column-major, leading dimensions.
@@ -22,7 +22,7 @@ struct SignmMat {
     int64_t lda, lds;
     int32_t n;
     int32_t index;  // position in the caller's batch (for the status word)
-    cd *Q;          // orders above 32: n x n complex workspace for Q (row-major)
+    cd *Q;          // n x n complex workspace for Q (row-major)
 };
 
 // Per-matrix outcome written by the kernels.

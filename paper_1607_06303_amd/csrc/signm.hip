@@ -4,9 +4,8 @@
 // Re t_jj differ, Eq. (2) where they agree), and sign(A) = Q U Q*.
 //
 // One workgroup of one wave per matrix; the matrix, reduced in place, stays in
-// LDS, and so does Q for orders up to 32 (2 x 32 x 33 complex entries, 34 KB);
-// for orders 33 to 64 Q lives in global memory (the matrix alone is 64 x 65
-// complex entries, 67 KB, so that two workgroups fit on a compute unit).
+// LDS (64 x 65 complex entries, 67 KB, for orders 33 to 64: two workgroups per
+// compute unit; 32 x 33 for orders up to 32), Q in a global workspace.
 //   1. Hessenberg form by Householder reflections P = I - 2 w w* / (w* w)
 //      (Hermitian and unitary), H <- P H P and Q <- Q P, one column at a time;
 //      lane j updates column j from the left, lane i row i from the right.
@@ -15,7 +14,7 @@
 //      last diagonal entry; an exceptional shift after 10 and 20 sweeps
 //      without deflation), the bulge chased by plane rotations
 //      G = [c s; -conj(s) c] applied to the whole rows and columns (the full
-//      Schur form, not only the eigenvalues) and to Q.  A subdiagonal entry is
+//      Schur form, not only the eigenvalues) and, after each sweep, to Q.  A subdiagonal entry is
 //      set to zero when it is at most the unit roundoff times the two diagonal
 //      entries beside it (or below the smallest normal number scaled by n / u).
 //      At most 30 max(10, n) sweeps, else the matrix is reported as not
@@ -117,43 +116,34 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// QG: Q in global memory (M.Q, row-major, pitch n) instead of LDS, so that two
-// workgroups of the larger instance fit on a compute unit; the rotations of a
-// QR sweep are then logged in LDS and applied to Q after the sweep, each lane
-// running its row through them with the next entries loaded ahead.
-template <int NM, bool CPLX, bool QG>
+// Q lives in global memory (M.Q, row-major, pitch n), so that LDS holds only
+// the matrix (two workgroups of the larger instance fit on a compute unit);
+// the rotations of a QR sweep are logged in LDS and applied to Q after the
+// sweep, each lane running its row through them with the next entries loaded
+// ahead.
+template <int NM, bool CPLX>
 __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
                                               int32_t *__restrict__ status, int max_sweeps)
 {
     constexpr int P = NM + 1;  // LDS pitch in complex entries
     __shared__ cd H[NM * P];   // row-major: H[r * P + c]
-    __shared__ cd Q[QG ? 1 : NM * P];
     __shared__ cd w[NM];       // Householder vector; then a row of Q U
-    __shared__ cd qr[QG ? NM : 1];   // QG: a row of Q
-    __shared__ double rc[QG ? NM : 1];  // QG: the sweep's rotations
-    __shared__ cd rs[QG ? NM : 1];
+    __shared__ cd qr[NM];      // a row of Q
+    __shared__ double rc[NM];  // the sweep's rotations
+    __shared__ cd rs[NM];
     const int lane = threadIdx.x;
     const SignmMat M = mats[blockIdx.x];
     const int n = uniform(M.n);
     auto h = [&](int r, int c) -> cd & { return H[r * P + c]; };
-    auto q = [&](int r, int c) -> cd & { return Q[r * P + c]; };
     cd *const Qg = M.Q;
     auto qget = [&](int r, int c) -> cd {
-        if constexpr (QG) {
-            const double *d = (const double *)(Qg + (int64_t)r * n + c);
-            return {gload(d), gload(d + 1)};
-        } else {
-            return Q[r * P + c];
-        }
+        const double *d = (const double *)(Qg + (int64_t)r * n + c);
+        return {gload(d), gload(d + 1)};
     };
     auto qset = [&](int r, int c, cd v) {
-        if constexpr (QG) {
-            double *d = (double *)(Qg + (int64_t)r * n + c);
-            gstore(d, v.re);
-            gstore(d + 1, v.im);
-        } else {
-            Q[r * P + c] = v;
-        }
+        double *d = (double *)(Qg + (int64_t)r * n + c);
+        gstore(d, v.re);
+        gstore(d + 1, v.im);
     };
 
     double fro2 = 0.0;
@@ -164,14 +154,11 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
         if (CPLX) v = {gload(M.A + 2 * off), gload(M.A + 2 * off + 1)};
         else v = {gload(M.A + off), 0.0};
         h(r, c) = v;
-        if constexpr (!QG) q(r, c) = cd{r == c ? 1.0 : 0.0, 0.0};
         fro2 += cabs2(v);
     }
-    if constexpr (QG) {
-        for (int e = lane; e < n * n; e += NT) {
-            const int r = e / n, c = e % n;
-            qset(r, c, cd{r == c ? 1.0 : 0.0, 0.0});
-        }
+    for (int e = lane; e < n * n; e += NT) {
+        const int r = e / n, c = e % n;
+        qset(r, c, cd{r == c ? 1.0 : 0.0, 0.0});
     }
     // an eigenvalue whose real part is within rounding of zero has no defined sign
     const double axis_tol = (double)n * DBL_EPSILON * sqrt(wave_sum(fro2));
@@ -295,7 +282,7 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
                 h(k + 1, k - 1) = cd{0.0, 0.0};
             }
             __syncthreads();
-            // columns k, k+1 of rows 0 .. min(k + 2, ihi), and of Q
+            // columns k, k+1 of rows 0 .. min(k + 2, ihi) (Q: after the sweep)
             const int ilast = min(k + 2, ihi);
             cd nk = {0.0, 0.0};
             if (lane < n) {
@@ -306,17 +293,10 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
                     h(i, k) = nk;
                     h(i, k + 1) = h2 * c - h1 * s;
                 }
-                if constexpr (!QG) {
-                    const cd q1 = q(i, k), q2 = q(i, k + 1);
-                    q(i, k) = q1 * c + q2 * cconj(s);
-                    q(i, k + 1) = q2 * c - q1 * s;
-                }
             }
-            if constexpr (QG) {
-                if (lane == 0) {
-                    rc[k - l] = c;
-                    rs[k - l] = s;
-                }
+            if (lane == 0) {
+                rc[k - l] = c;
+                rs[k - l] = s;
             }
             if (k + 1 < ihi) {
                 x = readlane_c(nk, k + 1);
@@ -324,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
             }
             __syncthreads();
         }
-        if constexpr (QG) {
+        {
             // the sweep's rotations, in order, on columns l .. ihi of every row of Q
             if (lane < n) {
                 const int i = lane;
@@ -385,21 +365,15 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
     }
 
     // ---- 4. S = (Q U) Q*, row by row
-    // (QG: every lane's stores of Q reach the other lanes' loads below)
+    // (every lane's stores of Q reach the other lanes' loads below)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     for (int i = 0; i < n; ++i) {
-        if constexpr (QG) {
-            if (lane < n) qr[lane] = qget(i, lane);
-            __syncthreads();
-        }
-        auto qi = [&](int k) -> cd {
-            if constexpr (QG) return qr[k];
-            else return q(i, k);
-        };
+        if (lane < n) qr[lane] = qget(i, lane);
+        __syncthreads();
         if (lane < n) {
             const int j = lane;
-            cd acc = qi(j) * sgn(j);
-            for (int k = 0; k < j; ++k) acc = acc + qi(k) * h(j, k);
+            cd acc = qr[j] * sgn(j);
+            for (int k = 0; k < j; ++k) acc = acc + qr[k] * h(j, k);
             w[j] = acc;
         }
         __syncthreads();
@@ -426,11 +400,11 @@ hipError_t launch_signm_t(const SignmMat *mats, int count, int n32, int32_t *sta
                           int max_sweeps, hipStream_t st)
 {
     if (n32 > 0)
-        hipLaunchKernelGGL((k_signm<32, CPLX, false>), dim3(n32), dim3(NT), 0, st, mats, status,
+        hipLaunchKernelGGL((k_signm<32, CPLX>), dim3(n32), dim3(NT), 0, st, mats, status,
                            max_sweeps);
     if (count > n32)
-        hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX, true>), dim3(count - n32), dim3(NT), 0,
-                           st, mats + n32, status, max_sweeps);
+        hipLaunchKernelGGL((k_signm<kSignmMaxOrder, CPLX>), dim3(count - n32), dim3(NT), 0, st,
+                           mats + n32, status, max_sweeps);
     return hipGetLastError();
 }
 
