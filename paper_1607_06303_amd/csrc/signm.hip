@@ -25,10 +25,12 @@
 //   4. sign(A) = (Q U) Q*, a row at a time: row i of Q U into an LDS row, then
 //      lane j forms entry (i, j) against row j of Q.  A real A gets the real
 //      part (sign of a real matrix is real; its imaginary part is rounding).
-// An eigenvalue on the imaginary axis leaves S untouched and reports
-// SIGNM_EDOMAIN.  The computed Schur form moves eigenvalues by rounding, so
-// "on the axis" means |Re t_ii| <= n u ||A||_F (u the unit roundoff), where the
-// sign of Re t_ii is not determined by A; a non-finite t_ii counts too.
+// A is first scaled by a power of two (exactly; the sign is unchanged) so that
+// its largest entry lies in [1, 2).  An eigenvalue on the imaginary axis leaves
+// S untouched and reports SIGNM_EDOMAIN.  The computed Schur form moves
+// eigenvalues by rounding, so "on the axis" means |Re t_ii| <= n u ||A||_F (u
+// the unit roundoff), where the sign of Re t_ii is not determined by A; a
+// non-finite t_ii counts too.
 #include <cfloat>
 
 #include "common.h"
@@ -146,13 +148,27 @@ __global__ __launch_bounds__(NT) void k_signm(const SignmMat *__restrict__ mats,
         gstore(d + 1, v.im);
     };
 
-    double fro2 = 0.0;
+    // sign(c A) = sign(A) for c > 0: A is scaled by the power of two that brings its
+    // largest entry to [1, 2), exactly, so that no square in the reduction or the
+    // rotations overflows or underflows, whatever A's magnitude
+    double amax = 0.0;
     for (int e = lane; e < n * n; e += NT) {
         const int r = e % n, c = e / n;
         const int64_t off = r + (int64_t)c * M.lda;
         cd v;
         if (CPLX) v = {gload(M.A + 2 * off), gload(M.A + 2 * off + 1)};
         else v = {gload(M.A + off), 0.0};
+        h(r, c) = v;
+        amax = fmax(amax, fmax(fabs(v.re), fabs(v.im)));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+    const double ascale = (amax > 0.0 && isfinite(amax)) ? ldexp(1.0, -ilogb(amax)) : 1.0;
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int e = lane; e < n * n; e += NT) {
+        const int r = e % n, c = e / n;
+        const cd v = h(r, c) * ascale;
         h(r, c) = v;
         fro2 += cabs2(v);
     }

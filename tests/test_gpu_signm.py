@@ -156,3 +156,17 @@ def test_not_converged_is_reported_and_leaves_the_output(dev, monkeypatch):
     monkeypatch.delenv("SIGNTRI_DEBUG_SIGNM_SWEEPS")
     Ss, codes, err = run([A], dev)
     assert err is None and rel_fro(Ss[0], sign_general(A)) <= TOL
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_power_of_two_scaling_passes_through_exactly(dev, cplx):
+    # sign(c A) = sign(A) for c > 0; the kernel scales A by a power of two to
+    # [1, 2) first, so 2^600 A and 2^-600 A run the same arithmetic as A
+    from oracle.signm import sign_general
+
+    rng = np.random.default_rng(5600 + cplx)
+    A = wl.general_A(40, rng, complex_=cplx)
+    Ss, codes, err = run([A, A * 2.0 ** 600, A * 2.0 ** -600], dev)
+    assert err is None
+    assert np.array_equal(Ss[0], Ss[1]) and np.array_equal(Ss[0], Ss[2])
+    assert rel_fro(Ss[0], sign_general(A)) <= TOL
