@@ -161,86 +161,113 @@ __global__ __launch_bounds__(kThreads) void k_gemm_c128(const cd *__restrict__ T
     const int am = tid & 31, akq = tid >> 5;   // A: row am, k = akq + 8t
     const int bkk = tid & 15, bjq = tid >> 4;  // B: k = bkk, col = bjq + 16t
 
-    auto run = [&](int kind, int K) {
-        int64_t acol = 0, brow = 0;
-        int klim = TB;
-        if (kind == K_MID) {
-            acol = (int64_t)K * TB;
-            brow = (int64_t)K * TB;
-        } else if (kind == K_SPEC_I) {
-            acol = r0;
-            brow = r0;
+    // The products run over a sequence of 16-deep chunks: two per middle block K
+    // in [kb, ke), then (the last split of a tile with X entries) two of each
+    // diagonal-block term.  Chunk c + 1 is loaded into registers while chunk c is
+    // multiplied from LDS.
+    const int nmc = uniform(2 * max(0, ke - kb));
+    const int nch = uniform(nmc + (specials ? 4 : 0));
+    struct Chunk {
+        int kind, klim, k0;
+        int64_t acol, brow;
+    };
+    auto chunk_at = [&](int c) {
+        Chunk d;
+        if (c < nmc) {
+            d.kind = K_MID;
+            d.acol = d.brow = (int64_t)(kb + (c >> 1)) * TB;
+            d.klim = TB;
         } else {
-            acol = c0;
-            brow = c0;
-            klim = bj;
+            const int sp = c - nmc;
+            d.kind = sp < 2 ? K_SPEC_I : K_SPEC_J;
+            d.acol = d.brow = d.kind == K_SPEC_I ? r0 : c0;
+            d.klim = d.kind == K_SPEC_I ? TB : bj;
         }
-        for (int k0 = 0; k0 < klim; k0 += KC) {
-            for (int kk = akq; kk < KC; kk += 8) {
-                bool ok = (k0 + kk) < klim;
-                int64_t col = acol + k0 + kk;
-                if (kind != K_SPEC_J) {
-                    cd v = ldg_or_zero(U + (r0 + am) + col * ldu, ok);
-                    sAUr[kk][am] = v.re;
-                    sAUi[kk][am] = v.im;
-                }
-                if ((kind == K_MID && any_x) || kind == K_SPEC_J) {
-                    cd v = ldg_or_zero(T + (r0 + am) + col * ldt, ok);
-                    sATr[kk][am] = v.re;
-                    sATi[kk][am] = v.im;
-                }
-            }
-            for (int j = bjq; j < TB; j += 16) {
-                bool ok = (j < bj) && (k0 + bkk) < klim;
-                int64_t row = brow + k0 + bkk;
-                if (kind != K_SPEC_I) {
-                    cd v = ldg_or_zero(U + row + (c0 + j) * ldu, ok);
-                    sBUr[bkk][j] = v.re;
-                    sBUi[bkk][j] = v.im;
-                }
-                if ((kind == K_MID && any_x) || kind == K_SPEC_I) {
-                    cd v = ldg_or_zero(T + row + (c0 + j) * ldt, ok);
-                    sBTr[bkk][j] = v.re;
-                    sBTi[bkk][j] = v.im;
-                }
-            }
-            __syncthreads();
+        d.k0 = (c & 1) * KC;
+        return d;
+    };
+    struct Regs {
+        cd au[KC / 8], at[KC / 8], bu[TB / 16], bt[TB / 16];
+    };
+    auto load = [&](const Chunk &d, Regs &R) {
 #pragma unroll
-            for (int k4 = 0; k4 < KC / 4; ++k4) {
-                const int kr = k4 * 4 + (lane >> 4);
-                const int ai = wr + (lane & 15), bi = wc + (lane & 15);
-                double aUr = sAUr[kr][ai], aUi = sAUi[kr][ai];
-                double aTr = -sATr[kr][ai], aTi = -sATi[kr][ai];
-                double bUr = sBUr[kr][bi], bUi = sBUi[kr][bi];
-                double bTr = sBTr[kr][bi], bTi = sBTi[kr][bi];
-                if (kind == K_MID && needY) {
-                    yR = mfma_f64(aUr, bUr, yR);
-                    yR = mfma_f64(-aUi, bUi, yR);
-                    yI = mfma_f64(aUr, bUi, yI);
-                    yI = mfma_f64(aUi, bUr, yI);
-                }
-                if (needX && (kind == K_MID || kind == K_SPEC_I)) {
-                    xR = mfma_f64(aUr, bTr, xR);
-                    xR = mfma_f64(-aUi, bTi, xR);
-                    xI = mfma_f64(aUr, bTi, xI);
-                    xI = mfma_f64(aUi, bTr, xI);
-                }
-                if (needX && (kind == K_MID || kind == K_SPEC_J)) {
-                    xR = mfma_f64(aTr, bUr, xR);
-                    xR = mfma_f64(-aTi, bUi, xR);
-                    xI = mfma_f64(aTr, bUi, xI);
-                    xI = mfma_f64(aTi, bUr, xI);
-                }
-            }
-            __syncthreads();
+        for (int t = 0; t < KC / 8; ++t) {
+            const int kk = akq + 8 * t;
+            const bool ok = (d.k0 + kk) < d.klim;
+            const int64_t col = d.acol + d.k0 + kk;
+            R.au[t] = d.kind != K_SPEC_J ? ldg_or_zero(U + (r0 + am) + col * ldu, ok) : cd{0.0, 0.0};
+            R.at[t] = ((d.kind == K_MID && any_x) || d.kind == K_SPEC_J)
+                          ? ldg_or_zero(T + (r0 + am) + col * ldt, ok) : cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int t = 0; t < TB / 16; ++t) {
+            const int jj = bjq + 16 * t;
+            const bool ok = (jj < bj) && (d.k0 + bkk) < d.klim;
+            const int64_t row = d.brow + d.k0 + bkk;
+            R.bu[t] = d.kind != K_SPEC_I ? ldg_or_zero(U + row + (c0 + jj) * ldu, ok) : cd{0.0, 0.0};
+            R.bt[t] = ((d.kind == K_MID && any_x) || d.kind == K_SPEC_I)
+                          ? ldg_or_zero(T + row + (c0 + jj) * ldt, ok) : cd{0.0, 0.0};
         }
     };
-
-    for (int K = kb; K < ke; ++K) run(K_MID, K);
-    if (specials) {
-        run(K_SPEC_I, I);
-        run(K_SPEC_J, J);
+    auto store = [&](const Regs &R) {
+#pragma unroll
+        for (int t = 0; t < KC / 8; ++t) {
+            const int kk = akq + 8 * t;
+            sAUr[kk][am] = R.au[t].re;
+            sAUi[kk][am] = R.au[t].im;
+            sATr[kk][am] = R.at[t].re;
+            sATi[kk][am] = R.at[t].im;
+        }
+#pragma unroll
+        for (int t = 0; t < TB / 16; ++t) {
+            const int jj = bjq + 16 * t;
+            sBUr[bkk][jj] = R.bu[t].re;
+            sBUi[bkk][jj] = R.bu[t].im;
+            sBTr[bkk][jj] = R.bt[t].re;
+            sBTi[bkk][jj] = R.bt[t].im;
+        }
+    };
+    auto compute = [&](int kind) {
+#pragma unroll
+        for (int k4 = 0; k4 < KC / 4; ++k4) {
+            const int kr = k4 * 4 + (lane >> 4);
+            const int ai = wr + (lane & 15), bi = wc + (lane & 15);
+            double aUr = sAUr[kr][ai], aUi = sAUi[kr][ai];
+            double aTr = -sATr[kr][ai], aTi = -sATi[kr][ai];
+            double bUr = sBUr[kr][bi], bUi = sBUi[kr][bi];
+            double bTr = sBTr[kr][bi], bTi = sBTi[kr][bi];
+            if (kind == K_MID && needY) {
+                yR = mfma_f64(aUr, bUr, yR);
+                yR = mfma_f64(-aUi, bUi, yR);
+                yI = mfma_f64(aUr, bUi, yI);
+                yI = mfma_f64(aUi, bUr, yI);
+            }
+            if (needX && (kind == K_MID || kind == K_SPEC_I)) {
+                xR = mfma_f64(aUr, bTr, xR);
+                xR = mfma_f64(-aUi, bTi, xR);
+                xI = mfma_f64(aUr, bTi, xI);
+                xI = mfma_f64(aUi, bTr, xI);
+            }
+            if (needX && (kind == K_MID || kind == K_SPEC_J)) {
+                xR = mfma_f64(aTr, bUr, xR);
+                xR = mfma_f64(-aTi, bUi, xR);
+                xI = mfma_f64(aTr, bUi, xI);
+                xI = mfma_f64(aTi, bUr, xI);
+            }
+        }
+    };
+    Regs cur, nxt;
+    if (nch > 0) load(chunk_at(0), cur);
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();  // the previous chunk's products are done with LDS
+        store(cur);
+        __syncthreads();
+        const int kind = chunk_at(c).kind;
+        if (c + 1 < nch) load(chunk_at(c + 1), nxt);
+        compute(kind);
+        cur = nxt;
     }
+
     cd *Zt = Z + ((int64_t)blockIdx.x * nsplit + split) * TB * TB;
     for (int r = 0; r < 4; ++r) {
         int i = wr + mfma64_row(lane, r);

@@ -33,6 +33,16 @@ def test_real_fp64_sweep_variants(dev, clean_table, n, sweep, tile):
     assert (info["wgs_per_cu"] > 0) == (sweep == "dataflow")
 
 
+@pytest.mark.parametrize("n", [77, 300, 517])
+def test_complex_fp64_superdiag_sweep(dev, clean_table, n):
+    # the complex superdiagonal sweep's products (K chunks pipelined through
+    # registers, split over several workgroups for long superdiagonals) against
+    # the oracle, ragged last block included
+    rng = np.random.default_rng(9050 + n)
+    _, info, _ = check(wl.make_T(n, rng, complex_=True), dev, options={"sweep": "superdiag"})
+    assert info["sweep_name"] == "superdiag" and info["tile"] == 32
+
+
 @pytest.mark.parametrize("mode,tol", [("fp64", TOL_FP64), ("mixed", TOL_FP64), ("fp32", TOL_FP32)])
 @pytest.mark.parametrize("wgs", [1, 2, 3, 50])
 def test_dataflow_grid_sizes(dev, clean_table, mode, tol, wgs):
