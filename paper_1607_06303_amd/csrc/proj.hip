@@ -79,6 +79,18 @@ struct ProjArgs {
     int m;
 };
 
+// The double of lane Q of each group of eight lanes, held by the whole group
+// (a swizzle in bitmask mode: source lane = (lane & 0x18) | Q within each half
+// of the wave).
+template <int Q> __device__ inline double bcast8_f64(double v)
+{
+    constexpr int pat = 0x18 | (Q << 5);
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)b, pat);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), pat);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Lane src's double, as a value every lane holds.
 __device__ inline double readlane_f64(double v, int src)
 {
@@ -964,6 +976,62 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         }
         if (s2 < nr) step(nr - 1 - s2, P0, P1);
         };
+        // The eigenvector form on a block without minority rows: the group's
+        // columns are independent triangular systems (T_bb - lambda_l I) y_l =
+        // -AbY_l over the block's rows.  Column-oriented: lane (kw, q) keeps the
+        // running sums s_i = AbY[i] + sum_{j > i} t_ij y_j of its rows i = q + 8u
+        // in registers; row r's owner (q = r mod 8) forms y_r = -s_r / (t_rr -
+        // lambda_l), the column's lanes receive it by a swizzle and add t_ir y_r to
+        // the rows above.  Only the owner's multiply, the swizzle and the next
+        // row's multiply-add are on the chain from row to row (no reduction).
+        auto walk_y0 = [&]() {
+            const bool on = kw < cw;
+            double sv[NU], rv[NU], yv[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int i = NQ * u + q;
+                sv[u] = (on && i < nr) ? AbY[i * ABP + kw] : 0.0;
+                rv[u] = (on && i < nr) ? 1.0 / (Tt[i * TP + i] - lamll) : 0.0;
+                yv[u] = 0.0;
+            }
+            auto row = [&](auto ut, auto qt) {
+                constexpr int u = decltype(ut)::value, qq = decltype(qt)::value;
+                constexpr int r = NQ * u + qq;
+                if (r >= nr) return;  // (uniform: the top block may be short)
+                const double y = bcast8_f64<qq>(-sv[u] * rv[u]);
+                if (q == qq) yv[u] = y;
+#pragma unroll
+                for (int v = 0; v <= u; ++v) {
+                    const int i = NQ * v + q;
+                    if (v < u || q < qq) sv[v] = fma(Tt[i * TP + r], y, sv[v]);
+                }
+            };
+            auto rows8 = [&](auto ut) {
+                row(ut, std::integral_constant<int, 7>{});
+                row(ut, std::integral_constant<int, 6>{});
+                row(ut, std::integral_constant<int, 5>{});
+                row(ut, std::integral_constant<int, 4>{});
+                row(ut, std::integral_constant<int, 3>{});
+                row(ut, std::integral_constant<int, 2>{});
+                row(ut, std::integral_constant<int, 1>{});
+                row(ut, std::integral_constant<int, 0>{});
+            };
+            rows8(std::integral_constant<int, 7>{});
+            rows8(std::integral_constant<int, 6>{});
+            rows8(std::integral_constant<int, 5>{});
+            rows8(std::integral_constant<int, 4>{});
+            rows8(std::integral_constant<int, 3>{});
+            rows8(std::integral_constant<int, 2>{});
+            rows8(std::integral_constant<int, 1>{});
+            rows8(std::integral_constant<int, 0>{});
+            if (on)
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int i = NQ * u + q;
+                    if (i < nr) Zc[kw * ZCP + i] = yv[u];
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        };
         static_assert(NU == 8, "one instance per chunk count");
         // (one instance per chunk count, reciprocal check and form)
         auto front2 = [&](auto gtag) {
@@ -975,7 +1043,8 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 else front(gtag, std::false_type{}, std::false_type{});
             }
         };
-        switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
+        if (yf && uniform(nw.cnt) == 0) walk_y0();
+        else switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
             case 0: front2(std::integral_constant<int, 0>{}); break;
             case 1: front2(std::integral_constant<int, 1>{}); break;
             case 2: front2(std::integral_constant<int, 2>{}); break;
