@@ -976,15 +976,18 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         }
         if (s2 < nr) step(nr - 1 - s2, P0, P1);
         };
-        // The eigenvector form on a block without minority rows: the group's
-        // columns are independent triangular systems (T_bb - lambda_l I) y_l =
-        // -AbY_l over the block's rows.  Column-oriented: lane (kw, q) keeps the
-        // running sums s_i = AbY[i] + sum_{j > i} t_ij y_j of its rows i = q + 8u
-        // in registers; row r's owner (q = r mod 8) forms y_r = -s_r / (t_rr -
-        // lambda_l), the column's lanes receive it by a swizzle and add t_ir y_r to
-        // the rows above.  Only the owner's multiply, the swizzle and the next
-        // row's multiply-add are on the chain from row to row (no reduction).
-        auto walk_y0 = [&]() {
+        // The eigenvector form, column-oriented: the group's columns are
+        // independent triangular systems (T_bb - lambda_l I) y_l = -AbY_l + (the
+        // coupling with the near window's columns) over the block's rows.  Lane
+        // (kw, q) keeps the running sums s_i = AbY[i] + sum_{j > i} t_ij y_j -
+        // sum_c Zr[i][c] L[c] of its rows i = q + 8u in registers; row r's owner
+        // (q = r mod 8) forms y_r = -s_r / (t_rr - lambda_l), the column's lanes
+        // receive it by a swizzle and add t_ir y_r to the rows above.  Only the
+        // owner's multiply, the swizzle and the next row's multiply-add are on the
+        // chain from row to row (no reduction).  A minority row of a near-window
+        // column c instead sets that column's coefficient L[c] = s_r (the group's
+        // y_r is zero there) and subtracts Zr[i][c] L[c] from the rows above.
+        auto walk_y = [&]() {
             const bool on = kw < cw;
             double sv[NU], rv[NU], yv[NU];
 #pragma unroll
@@ -998,6 +1001,22 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 constexpr int u = decltype(ut)::value, qq = decltype(qt)::value;
                 constexpr int r = NQ * u + qq;
                 if (r >= nr) return;  // (uniform: the top block may be short)
+                const int typ = __builtin_amdgcn_readlane(rtl, r);
+                if (typ >= 0) {
+                    // a near-window column's minority row (uniform branch)
+                    const int cn = typ - nw.lo;
+                    const double lc = bcast8_f64<qq>(sv[u]);
+                    if (on)
+#pragma unroll
+                        for (int w = 0; w < NU; ++w)
+                            if (NQ * w + q == cn) lreg[w] = lc;
+#pragma unroll
+                    for (int v = 0; v <= u; ++v) {
+                        const int i = NQ * v + q;
+                        if (v < u || q < qq) sv[v] = fma(-Zr[i * TP + cn], lc, sv[v]);
+                    }
+                    return;
+                }
                 const double y = bcast8_f64<qq>(-sv[u] * rv[u]);
                 if (q == qq) yv[u] = y;
 #pragma unroll
@@ -1043,7 +1062,7 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 else front(gtag, std::false_type{}, std::false_type{});
             }
         };
-        if (yf && uniform(nw.cnt) == 0) walk_y0();
+        if (yf) walk_y();
         else switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
             case 0: front2(std::integral_constant<int, 0>{}); break;
             case 1: front2(std::integral_constant<int, 1>{}); break;
