@@ -990,16 +990,26 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         auto walk_y = [&]() {
             const bool on = kw < cw;
             double sv[NU], rv[NU], yv[NU];
+            // T's column of the next row, loaded one row ahead (two register sets
+            // in turn, chosen by the row's parity)
+            double ta[NU], tb[NU];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = NQ * u + q;
                 sv[u] = (on && i < nr) ? AbY[i * ABP + kw] : 0.0;
                 rv[u] = (on && i < nr) ? 1.0 / (Tt[i * TP + i] - lamll) : 0.0;
                 yv[u] = 0.0;
+                ta[u] = Tt[i * TP + (PB - 1)];
             }
             auto row = [&](auto ut, auto qt) {
                 constexpr int u = decltype(ut)::value, qq = decltype(qt)::value;
                 constexpr int r = NQ * u + qq;
+                double(&tc)[NU] = (qq & 1) ? ta : tb;  // row r's column (row 63: ta)
+                double(&tn)[NU] = (qq & 1) ? tb : ta;
+                if constexpr (r > 0) {
+#pragma unroll
+                    for (int v = 0; v < NU; ++v) tn[v] = Tt[(NQ * v + q) * TP + (r - 1)];
+                }
                 if (r >= nr) return;  // (uniform: the top block may be short)
                 const int typ = __builtin_amdgcn_readlane(rtl, r);
                 if (typ >= 0) {
@@ -1020,10 +1030,8 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 const double y = bcast8_f64<qq>(-sv[u] * rv[u]);
                 if (q == qq) yv[u] = y;
 #pragma unroll
-                for (int v = 0; v <= u; ++v) {
-                    const int i = NQ * v + q;
-                    if (v < u || q < qq) sv[v] = fma(Tt[i * TP + r], y, sv[v]);
-                }
+                for (int v = 0; v <= u; ++v)
+                    if (v < u || q < qq) sv[v] = fma(tc[v], y, sv[v]);
             };
             auto rows8 = [&](auto ut) {
                 row(ut, std::integral_constant<int, 7>{});
