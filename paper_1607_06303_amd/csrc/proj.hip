@@ -987,20 +987,29 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
         // chain from row to row (no reduction).  A minority row of a near-window
         // column c instead sets that column's coefficient L[c] = s_r (the group's
         // y_r is zero there) and subtracts Zr[i][c] L[c] from the rows above.
-        auto walk_y = [&]() {
+        auto walk_y = [&](auto mintag) {
+            constexpr bool MIN = decltype(mintag)::value;  // the block holds minority rows
             const bool on = kw < cw;
-            double sv[NU], rv[NU], yv[NU];
-            // T's column of the next row, loaded one row ahead (two register sets
-            // in turn, chosen by the row's parity)
-            double ta[NU], tb[NU];
+            double sv[NU], rv[NU];
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = NQ * u + q;
                 sv[u] = (on && i < nr) ? AbY[i * ABP + kw] : 0.0;
                 rv[u] = (on && i < nr) ? 1.0 / (Tt[i * TP + i] - lamll) : 0.0;
-                yv[u] = 0.0;
-                ta[u] = Tt[i * TP + (PB - 1)];
             }
+            // T's diagonal now lives in the reciprocals: zero it, so that row r's
+            // update may run over every slot of every lane (t_ir = 0 for i >= r; the
+            // owner's own slot keeps s_r, from which y_r is formed again at the end)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (kw == 0)
+#pragma unroll
+                for (int u = 0; u < NU; ++u) Tt[(NQ * u + q) * (TP + 1)] = 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            // T's column of the next row, loaded one row ahead (two register sets
+            // in turn, chosen by the row's parity)
+            double ta[NU], tb[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) ta[u] = Tt[(NQ * u + q) * TP + (PB - 1)];
             auto row = [&](auto ut, auto qt) {
                 constexpr int u = decltype(ut)::value, qq = decltype(qt)::value;
                 constexpr int r = NQ * u + qq;
@@ -1011,27 +1020,28 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                     for (int v = 0; v < NU; ++v) tn[v] = Tt[(NQ * v + q) * TP + (r - 1)];
                 }
                 if (r >= nr) return;  // (uniform: the top block may be short)
-                const int typ = __builtin_amdgcn_readlane(rtl, r);
-                if (typ >= 0) {
-                    // a near-window column's minority row (uniform branch)
-                    const int cn = typ - nw.lo;
-                    const double lc = bcast8_f64<qq>(sv[u]);
-                    if (on)
+                if constexpr (MIN) {
+                    const int typ = __builtin_amdgcn_readlane(rtl, r);
+                    if (typ >= 0) {
+                        // a near-window column's minority row (uniform branch); that
+                        // column's z is zero below the row and one at it, where the
+                        // owner's slot is then reset (the group's y_r is zero)
+                        const int cn = typ - nw.lo;
+                        const double lc = bcast8_f64<qq>(sv[u]);
+                        if (on)
 #pragma unroll
-                        for (int w = 0; w < NU; ++w)
-                            if (NQ * w + q == cn) lreg[w] = lc;
+                            for (int w = 0; w < NU; ++w)
+                                if (NQ * w + q == cn) lreg[w] = lc;
 #pragma unroll
-                    for (int v = 0; v <= u; ++v) {
-                        const int i = NQ * v + q;
-                        if (v < u || q < qq) sv[v] = fma(-Zr[i * TP + cn], lc, sv[v]);
+                        for (int v = 0; v <= u; ++v)
+                            sv[v] = fma(-Zr[(NQ * v + q) * TP + cn], lc, sv[v]);
+                        if (q == qq) sv[u] = 0.0;
+                        return;
                     }
-                    return;
                 }
                 const double y = bcast8_f64<qq>(-sv[u] * rv[u]);
-                if (q == qq) yv[u] = y;
 #pragma unroll
-                for (int v = 0; v <= u; ++v)
-                    if (v < u || q < qq) sv[v] = fma(tc[v], y, sv[v]);
+                for (int v = 0; v <= u; ++v) sv[v] = fma(tc[v], y, sv[v]);
             };
             auto rows8 = [&](auto ut) {
                 row(ut, std::integral_constant<int, 7>{});
@@ -1051,11 +1061,13 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
             rows8(std::integral_constant<int, 2>{});
             rows8(std::integral_constant<int, 1>{});
             rows8(std::integral_constant<int, 0>{});
+            // y of each lane's rows from their final sums (the value the row's
+            // broadcast carried; +0 at a minority row, whose sum was reset)
             if (on)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
                     const int i = NQ * u + q;
-                    if (i < nr) Zc[kw * ZCP + i] = yv[u];
+                    if (i < nr) Zc[kw * ZCP + i] = fma(-sv[u], rv[u], 0.0);
                 }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         };
@@ -1070,8 +1082,10 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 else front(gtag, std::false_type{}, std::false_type{});
             }
         };
-        if (yf) walk_y();
-        else switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
+        if (yf) {
+            if (uniform(nw.cnt) > 0) walk_y(std::true_type{});
+            else walk_y(std::false_type{});
+        } else switch (uniform(nw.cnt > 0 ? (nw.cnt + NQ - 1) / NQ : 0)) {
             case 0: front2(std::integral_constant<int, 0>{}); break;
             case 1: front2(std::integral_constant<int, 1>{}); break;
             case 2: front2(std::integral_constant<int, 2>{}); break;
