@@ -25,31 +25,50 @@ __global__ __launch_bounds__(1024) void k_scan(const double *__restrict__ T, int
     }
     __syncthreads();
     unsigned long long my_pos = 0, my_min = ~0ull, my_max = 0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        double re, im = 0.0;
-        if (cplx) {
-            const double *p = T + 2 * (i + i * ldt);
-            re = p[0];
-            im = p[1];
-        } else {
-            re = T[i + i * ldt];
+    // The diagonal entries lie a column apart (a separate line, often a separate
+    // page, each): every thread issues the loads of eight of them before using
+    // any, so that their latencies overlap.
+    constexpr int BATCH = 8;
+    const int64_t stride = blockDim.x;
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += BATCH * stride) {
+        double vre[BATCH], vim[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int64_t i = i0 + k * stride;
+            vre[k] = 0.0;
+            vim[k] = 0.0;
+            if (i < n) {
+                if (cplx) {
+                    const double *p = T + 2 * (i + i * ldt);
+                    vre[k] = p[0];
+                    vim[k] = p[1];
+                } else {
+                    vre[k] = T[i + i * ldt];
+                }
+            }
         }
-        int s = 0;
-        if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
-        sgn[i] = (int8_t)s;
-        // the divisors t_ii - t_jj of the sweeps, in FP64 (complex: re, im pairs)
-        if (dg && cplx) {
-            dg[2 * i] = re;
-            dg[2 * i + 1] = im;
-        } else if (dg) {
-            dg[i] = re;
-        }
-        if (s == 0) atomicMin(&bad, (unsigned long long)i);
-        my_pos += (s > 0);
-        if (s != 0) {
-            const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(re));
-            my_min = a < my_min ? a : my_min;
-            my_max = a > my_max ? a : my_max;
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i >= n) break;
+            const double re = vre[k], im = vim[k];
+            int s = 0;
+            if (isfinite(re) && isfinite(im)) s = re > 0.0 ? 1 : (re < 0.0 ? -1 : 0);
+            sgn[i] = (int8_t)s;
+            // the divisors t_ii - t_jj of the sweeps, in FP64 (complex: re, im pairs)
+            if (dg && cplx) {
+                dg[2 * i] = re;
+                dg[2 * i + 1] = im;
+            } else if (dg) {
+                dg[i] = re;
+            }
+            if (s == 0) atomicMin(&bad, (unsigned long long)i);
+            my_pos += (s > 0);
+            if (s != 0) {
+                const unsigned long long a = (unsigned long long)__double_as_longlong(fabs(re));
+                my_min = a < my_min ? a : my_min;
+                my_max = a > my_max ? a : my_max;
+            }
         }
     }
     atomicAdd(&npos, my_pos);
