@@ -266,11 +266,15 @@ CLUSTERS = [
     # blocks are cut from the bottom, so the top block is short)
     (1000, list(range(0, 64))),
     (1000, list(range(936, 1000))),
+    # a bottom group whose eigenvector-form column walk meets earlier columns'
+    # minority rows in its blocks, the short top block (40 rows) included
+    (1000, [5, 20, 33, 300, 301, 650, 651, 652] + list(range(992, 1000))),
 ]
 
 
 @pytest.mark.parametrize("n,where", CLUSTERS,
-                         ids=["one-block", "run64", "wave-edges", "spread", "top64", "bottom64"])
+                         ids=["one-block", "run64", "wave-edges", "spread", "top64", "bottom64",
+                              "walk-windows"])
 @pytest.mark.parametrize("minority", [-1, 1])
 def test_proj_clustered_minority(dev, n, where, minority):
     """Minority rows clustered within blocks and across wave boundaries of the column order."""
