@@ -1015,17 +1015,23 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                 constexpr int r = NQ * u + qq;
                 double(&tc)[NU] = (qq & 1) ? ta : tb;  // row r's column (row 63: ta)
                 double(&tn)[NU] = (qq & 1) ? tb : ta;
-                if constexpr (r > 0) {
+                auto prefetch = [&] {
+                    if constexpr (r > 0) {
 #pragma unroll
-                    for (int v = 0; v < NU; ++v) tn[v] = Tt[(NQ * v + q) * TP + (r - 1)];
+                        for (int v = 0; v < NU; ++v) tn[v] = Tt[(NQ * v + q) * TP + (r - 1)];
+                    }
+                };
+                if (r >= nr) {  // (uniform: the top block may be short)
+                    prefetch();
+                    return;
                 }
-                if (r >= nr) return;  // (uniform: the top block may be short)
                 if constexpr (MIN) {
                     const int typ = __builtin_amdgcn_readlane(rtl, r);
                     if (typ >= 0) {
                         // a near-window column's minority row (uniform branch); that
                         // column's z is zero below the row and one at it, where the
                         // owner's slot is then reset (the group's y_r is zero)
+                        prefetch();
                         const int cn = typ - nw.lo;
                         const double lc = bcast8_f64<qq>(sv[u]);
                         if (on)
@@ -1039,9 +1045,16 @@ __global__ __launch_bounds__(NT) void k_proj_run(ProjArgs a, ProjSync S)
                         return;
                     }
                 }
+                // the broadcast ahead of the next column's loads (LDS returns in
+                // order), and first the update of row r - 1's own slot, which the next
+                // row's broadcast waits for
                 const double y = bcast8_f64<qq>(-sv[u] * rv[u]);
+                prefetch();
+                constexpr int vn = qq > 0 ? u : u - 1;
+                if constexpr (vn >= 0) sv[vn] = fma(tc[vn], y, sv[vn]);
 #pragma unroll
-                for (int v = 0; v <= u; ++v) sv[v] = fma(tc[v], y, sv[v]);
+                for (int v = 0; v <= u; ++v)
+                    if (v != vn) sv[v] = fma(tc[v], y, sv[v]);
             };
             auto rows8 = [&](auto ut) {
                 row(ut, std::integral_constant<int, 7>{});
